@@ -1,0 +1,293 @@
+"""FP64 CPU oracle for the retarded-time imaging operator and its drivers.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  It shares no code
+with the GPU library.
+
+* ``forward`` / ``adjoint``: A and A^T of Sec. 3.1 eq. (2)-(3) and App. A.2
+  eq. (47), evaluated row by row in FP64 by the plain C code in
+  ``rtt_oracle.c``.
+* ``dense``: the dense matrix of A, column by column (tiny grids only).
+* ``rsvd``: randomized subspace iteration (Halko, Martinsson & Tropp, SIAM
+  Review 2011, Alg. 4.4) followed by the direct SVD of the projected matrix
+  (their Alg. 5.1), FP64, LAPACK QR/SVD.
+* ``block_lanczos``: block Golub-Kahan bidiagonalisation with full
+  one-sided reorthogonalisation, FP64.
+* ``tsvd_solve``, ``ridge_solve``, ``ridge_gradient``: the TSVD and ridge
+  estimators of Sec. 9 and the ridge objective gradient.
+* ``s_ref`` and ``operational_rank``: eq. (17)-(18) and eq. (31).
+
+Every function here is pinned by the "not gpu" tests against facts that do
+not come from this module (see the tests' docstrings).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rtt_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_rtt_oracle.so")
+_lib = None
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_orders", ctypes.c_int), ("n_frames", ctypes.c_int),
+                ("t0", ctypes.c_double), ("dt_obs", ctypes.c_double),
+                ("n_r", ctypes.c_int), ("n_phi", ctypes.c_int),
+                ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
+                ("n_hat", ctypes.c_int), ("s0", ctypes.c_double), ("dt_src", ctypes.c_double)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc into oracle/_rtt_oracle.so."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        for name in ("ora_forward", "ora_adjoint"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.POINTER(_Grid), i64p, dp, dp, dp, dp, dp, dp, ctypes.c_uint]
+        lib.ora_stencil.restype = ctypes.c_int
+        lib.ora_stencil.argtypes = [ctypes.POINTER(_Grid), ctypes.c_double, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_int), dp]
+        _lib = lib
+    return _lib
+
+
+def _cgrid(g) -> _Grid:
+    return _Grid(g.n_orders, g.n_frames, g.t0, g.dt_obs, g.n_r, g.n_phi, g.r_in, g.r_out,
+                 g.n_hat, g.s0, g.dt_src)
+
+
+class _Packed:
+    """Ray maps of a geometry concatenated over orders (caller ray order)."""
+
+    def __init__(self, geom):
+        self.grid = geom.grid
+        self.counts = np.array(geom.rays_per_order, dtype=np.int64)
+        cat = lambda attr: np.ascontiguousarray(
+            np.concatenate([getattr(m, attr) for m in geom.maps]) if geom.maps else np.zeros(0))
+        self.r, self.phi, self.delay, self.weight = (cat(a) for a in ("r", "phi", "delay", "weight"))
+        self.n_rays = int(self.counts.sum())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _mask(geom, order_mask):
+    return (1 << geom.grid.n_orders) - 1 if order_mask is None else int(order_mask)
+
+
+def forward(geom, x, order_mask=None, out=None):
+    """y = A x (FP64).  x: [S*K] or [B][S*K]; y rows (n, p, f), frames fastest.
+
+    Rows of orders outside ``order_mask`` are returned as zeros.
+    """
+    lib = _load()
+    pk = _Packed(geom)
+    g = pk.grid
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    single = x.ndim == 1
+    xb = x.reshape(1, -1) if single else x
+    if xb.shape[1] != g.n_cols:
+        raise ValueError("x has wrong length")
+    y = np.zeros((xb.shape[0], pk.n_rays * g.n_frames))
+    cg = _cgrid(g)
+    for b in range(xb.shape[0]):
+        xv = np.ascontiguousarray(xb[b])
+        yv = np.zeros(pk.n_rays * g.n_frames)
+        rc = lib.ora_forward(ctypes.byref(cg), pk.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             _ptr(pk.r), _ptr(pk.phi), _ptr(pk.delay), _ptr(pk.weight),
+                             _ptr(xv), _ptr(yv), _mask(geom, order_mask))
+        if rc:
+            raise ValueError("oracle forward rejected its inputs")
+        y[b] = yv
+    return y[0] if single else y
+
+
+def adjoint(geom, y, order_mask=None):
+    """x = A^T y (FP64), same layouts as ``forward``."""
+    lib = _load()
+    pk = _Packed(geom)
+    g = pk.grid
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    single = y.ndim == 1
+    yb = y.reshape(1, -1) if single else y
+    if yb.shape[1] != pk.n_rays * g.n_frames:
+        raise ValueError("y has wrong length")
+    x = np.zeros((yb.shape[0], g.n_cols))
+    cg = _cgrid(g)
+    for b in range(yb.shape[0]):
+        yv = np.ascontiguousarray(yb[b])
+        xv = np.zeros(g.n_cols)
+        rc = lib.ora_adjoint(ctypes.byref(cg), pk.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             _ptr(pk.r), _ptr(pk.phi), _ptr(pk.delay), _ptr(pk.weight),
+                             _ptr(yv), _ptr(xv), _mask(geom, order_mask))
+        if rc:
+            raise ValueError("oracle adjoint rejected its inputs")
+        x[b] = xv
+    return x[0] if single else x
+
+
+def stencil(grid, r, phi):
+    """(cells[4], weights[4]) of the bilinear spatial basis at (r, phi)."""
+    lib = _load()
+    cells = (ctypes.c_int * 4)()
+    w = np.zeros(4)
+    lib.ora_stencil(ctypes.byref(_cgrid(grid)), float(r), float(phi), cells, _ptr(w))
+    return np.array(list(cells)), w
+
+
+def dense(geom, order_mask=None):
+    """Dense A (rows x cols) built column by column from ``forward``: tiny grids only."""
+    n = geom.grid.n_cols
+    if n * geom.n_rows > 5e7:
+        raise ValueError("dense oracle is for tiny grids")
+    eye = np.eye(n)
+    return forward(geom, eye, order_mask).T.copy()
+
+
+# ----------------------------------------------------------------------------------------------
+# Linear algebra drivers (FP64)
+# ----------------------------------------------------------------------------------------------
+
+def _orth(Y):
+    """Orthonormal basis of range(Y): LAPACK Householder QR."""
+    q, _ = np.linalg.qr(Y, mode="reduced")
+    return q
+
+
+def rsvd(geom, omega, q=2, order_mask=None, want_u=False):
+    """Randomized SVD of A (HMT 2011 Alg. 4.4 + Alg. 5.1), FP64.
+
+    ``omega``: test block [l][S*K] (one row per test vector, the layout of a
+    block of coefficient vectors).  Returns (sigma[l], V[l][S*K], U or None),
+    where the rows of V (and of U) are right (left) singular vectors.
+    """
+    Om = np.asarray(omega, dtype=np.float64)
+    Q = _orth(forward(geom, Om, order_mask).T)               # rows x l
+    for _ in range(q):
+        Qt = _orth(adjoint(geom, Q.T, order_mask).T)           # cols x l
+        Q = _orth(forward(geom, Qt.T, order_mask).T)
+    Bt = adjoint(geom, Q.T, order_mask).T                      # cols x l   (= (Q^T A)^T)
+    Qb, Rb = np.linalg.qr(Bt, mode="reduced")                   # B = Rb^T Qb^T
+    Ur, s, Wt = np.linalg.svd(Rb.T)                             # Rb^T = Ur diag(s) Wt
+    V = Qb @ Wt.T                                               # cols x l
+    U = Q @ Ur if want_u else None
+    return s, V.T.copy(), (U.T.copy() if want_u else None)
+
+
+def block_lanczos(geom, start, steps, order_mask=None):
+    """Block Golub-Kahan bidiagonalisation, one-sided reorthogonalisation, FP64.
+
+    ``start``: [b][S*K] start block.  With V_1 = orth(start) it runs, for
+    j = 1..steps,
+        A V_j - U_{j-1} R_{j-1}^T = U_j L_j          (QR, L_j upper triangular)
+        A^T U_j - V_j L_j^T       = V_{j+1} R_j      (QR after reorthogonalising
+                                                      against every stored V)
+    so that A [V_1..V_s] = [U_1..U_s] T with T block upper bidiagonal (L_j on
+    the diagonal, R_j^T above it).  Only the right (coefficient-space) basis is
+    stored and reorthogonalised (two classical Gram-Schmidt passes); left
+    blocks are kept one step back.  Returns (ritz_sigma, ritz_V[m][S*K],
+    residual_estimates) with m = b * steps, where the residual of Ritz pair i
+    is || R_s (last block of the left singular vector of T) ||, the norm of
+    A^T u_i - sigma_i v_i implied by the recurrence.
+    """
+    X = np.asarray(start, dtype=np.float64).T                   # cols x b
+    b = X.shape[1]
+    V, _ = np.linalg.qr(X, mode="reduced")
+    Vs = [V]
+    m = b * steps
+    T = np.zeros((m, m))
+    U_prev, R_prev = None, None
+    for j in range(steps):
+        W = forward(geom, Vs[j].T, order_mask).T                  # rows x b
+        if U_prev is not None:
+            W = W - U_prev @ R_prev.T
+        U, L = np.linalg.qr(W, mode="reduced")
+        T[j * b:(j + 1) * b, j * b:(j + 1) * b] = L
+        Z = adjoint(geom, U.T, order_mask).T - Vs[j] @ L.T        # cols x b
+        for _ in range(2):
+            for Vo in Vs:
+                Z = Z - Vo @ (Vo.T @ Z)
+        Vn, Rn = np.linalg.qr(Z, mode="reduced")
+        if j + 1 < steps:
+            T[j * b:(j + 1) * b, (j + 1) * b:(j + 2) * b] = Rn.T
+            Vs.append(Vn)
+        U_prev, R_prev = U, Rn
+    Vall = np.concatenate(Vs, axis=1)                                # cols x m
+    Pu, s, Pvt = np.linalg.svd(T)
+    ritz_V = Vall @ Pvt.T
+    res = np.linalg.norm(R_prev @ Pu[m - b:, :], axis=0)
+    return s, ritz_V.T.copy(), res
+
+
+def tsvd_solve(geom, V, sigma, y, t, order_mask=None):
+    """TSVD estimate x = sum_{i<t} v_i (v_i . A^T y) / sigma_i^2 (rows of V are v_i)."""
+    g = adjoint(geom, y, order_mask)
+    single = g.ndim == 1
+    G = g.reshape(1, -1) if single else g                         # [nrhs][S*K]
+    Vt = np.asarray(V, dtype=np.float64)[:t]                      # [t][S*K]
+    c = (G @ Vt.T) / (np.asarray(sigma, dtype=np.float64)[:t] ** 2)   # [nrhs][t]
+    x = c @ Vt
+    return x[0] if single else x
+
+
+def ridge_gradient(geom, x, y, lam, order_mask=None):
+    """Gradient of 1/2 ||A x - y||^2 + lam/2 ||x||^2: A^T (A x - y) + lam x."""
+    return adjoint(geom, forward(geom, x, order_mask) - y, order_mask) + lam * np.asarray(x, dtype=np.float64)
+
+
+def ridge_solve(geom, y, lam, tol=1e-12, maxit=10000, order_mask=None):
+    """Ridge estimate: conjugate gradients on (A^T A + lam I) x = A^T y, FP64.
+
+    Stops when ||r|| <= tol * ||A^T y||.  Returns (x, iterations).
+    """
+    rhs = adjoint(geom, y, order_mask)
+    x = np.zeros_like(rhs)
+    r = rhs.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    stop = tol * math.sqrt(float(rhs @ rhs))
+    it = 0
+    while math.sqrt(rr) > stop and it < maxit:
+        Ap = adjoint(geom, forward(geom, p, order_mask), order_mask) + lam * p
+        alpha = rr / float(p @ Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    return x, it
+
+
+def s_ref(geom):
+    """eq. (17): RMS direct-order response to the constant reference emissivity."""
+    ones = np.ones(geom.grid.n_cols)
+    y0 = forward(geom, ones, order_mask=1)
+    m0 = geom.maps[0].n_rays * geom.grid.n_frames
+    return math.sqrt(float(y0[:m0] @ y0[:m0]) / m0)
+
+
+def operational_rank(sigma, s_reference, snr0=100.0, rho=1.0):
+    """eq. (31) with C = sigma_Omega^2 I, sigma_Omega = s_ref/SNR0 (eq. (18))."""
+    thr = rho * s_reference / snr0
+    return int(np.count_nonzero(np.asarray(sigma) >= thr))

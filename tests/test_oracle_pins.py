@@ -1,0 +1,320 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+* spatial factor: scipy's RegularGridInterpolator (bilinear on the cell-centre
+  grid, periodic in phi, constant continuation in r) evaluated at each ray's
+  source point (eq. (47), psi_l(r, phi));
+* temporal factor: numpy.interp on the hat nodes padded by one zero node on
+  each side -- piecewise-linear interpolation is exactly the span of the
+  degree-one B-splines of Sec. 7 (eq. (47), tau_k(t_o - Delta));
+* Thm 4.1 / Cor 4.2: the blind hats are computed from the footprint eq. (23)
+  alone, and the oracle must return exact (bitwise) zeros on them;
+* adjoint identity, Gram monotonicity eq. (21), split/merge Gram invariance
+  of the whitened rows eq. (16) (paper's criterion 1e-10);
+* LAPACK: rSVD and block Lanczos reduce to the SVD when the sketch spans the
+  range, TSVD to the truncated pseudo-inverse, ridge CG to a dense solve;
+* the ridge gradient against central finite differences of the objective.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import RegularGridInterpolator
+
+import oracle
+import synth
+from tinygeo import tiny_geometry
+
+GEOMS = {
+    "ratio1": dict(seed=11, rays=(12, 6, 5)),
+    "ratio_half": dict(seed=12, rays=(10, 5, 4), dt_obs=2.0, n_frames=9),
+    "ratio2": dict(seed=13, rays=(9, 4, 3), dt_obs=8.0, n_frames=4),
+    "direct_only": dict(seed=14, rays=(15,)),
+}
+
+
+def packed(geo):
+    r = np.concatenate([m.r for m in geo.maps])
+    phi = np.concatenate([m.phi for m in geo.maps])
+    delay = np.concatenate([m.delay for m in geo.maps])
+    w = np.concatenate([m.weight for m in geo.maps])
+    return r, phi, delay, w
+
+
+def spatial_interp(grid, field, r, phi):
+    """Bilinear interpolation of a cell-centred field via scipy (periodic phi, clamped r)."""
+    dr = (grid.r_out - grid.r_in) / grid.n_r
+    dphi = 2 * math.pi / grid.n_phi
+    rc = grid.r_in + (np.arange(grid.n_r) + 0.5) * dr
+    pc = (np.arange(grid.n_phi) + 0.5) * dphi
+    f2 = field.reshape(grid.n_r, grid.n_phi)
+    pcp = np.concatenate([[pc[-1] - 2 * math.pi], pc, [pc[0] + 2 * math.pi]])
+    f2p = np.concatenate([f2[:, -1:], f2, f2[:, :1]], axis=1)
+    rgi = RegularGridInterpolator((rc, pcp), f2p, method="linear")
+    q = np.stack([np.clip(r, rc[0], rc[-1]), np.mod(phi, 2 * math.pi)], axis=1)
+    return rgi(q)
+
+
+def temporal_interp(grid, h, t):
+    nodes = grid.s0 + grid.dt_src * np.arange(-1, grid.n_hat + 1)
+    vals = np.concatenate([[0.0], h, [0.0]])
+    return np.interp(t, nodes, vals, left=0.0, right=0.0)
+
+
+def frame_times(grid):
+    return grid.t0 + grid.dt_obs * np.arange(grid.n_frames)
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_separable_field_matches_library_interpolation(name):
+    geo = tiny_geometry(**GEOMS[name])
+    g = geo.grid
+    rng = np.random.default_rng(5)
+    gs = rng.standard_normal(g.n_cells)
+    hk = rng.standard_normal(g.n_hat)
+    x = np.outer(gs, hk).ravel()
+    y = oracle.forward(geo, x).reshape(geo.n_rays, g.n_frames)
+    r, phi, delay, w = packed(geo)
+    G = spatial_interp(g, gs, r, phi)
+    H = temporal_interp(g, hk, frame_times(g)[None, :] - delay[:, None])
+    expect = w[:, None] * G[:, None] * H
+    assert np.max(np.abs(y - expect)) <= 1e-13 * np.max(np.abs(expect))
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_spatial_and_temporal_factors_separately(name):
+    geo = tiny_geometry(**GEOMS[name])
+    g = geo.grid
+    r, phi, delay, w = packed(geo)
+    rng = np.random.default_rng(6)
+    # spatial only: x constant in time -> hats sum to one inside [s_0, s_{K-1}]
+    gs = rng.standard_normal(g.n_cells)
+    y = oracle.forward(geo, np.repeat(gs, g.n_hat)).reshape(geo.n_rays, g.n_frames)
+    tret = frame_times(g)[None, :] - delay[:, None]
+    inside = (tret >= g.s0) & (tret <= g.s0 + (g.n_hat - 1) * g.dt_src)
+    expect = (w * spatial_interp(g, gs, r, phi))[:, None] * np.ones_like(tret)
+    assert inside.all()
+    assert np.max(np.abs(y - expect)) <= 1e-13 * np.max(np.abs(expect))
+    # temporal only: x constant over cells -> bilinear weights sum to one
+    hk = rng.standard_normal(g.n_hat)
+    y = oracle.forward(geo, np.tile(hk, g.n_cells)).reshape(geo.n_rays, g.n_frames)
+    expect = w[:, None] * temporal_interp(g, hk, tret)
+    assert np.max(np.abs(y - expect)) <= 1e-13 * np.max(np.abs(expect))
+
+
+def test_partition_of_unity_and_sref_closed_form():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    g = geo.grid
+    y = oracle.forward(geo, np.ones(g.n_cols)).reshape(geo.n_rays, g.n_frames)
+    w = packed(geo)[3]
+    assert np.max(np.abs(y - w[:, None])) <= 1e-15
+    # eq. (17): with every direct row inside the hat window, s_ref^2 = mean(w_0^2)
+    w0 = geo.maps[0].weight
+    assert oracle.s_ref(geo) == pytest.approx(math.sqrt(np.mean(w0 ** 2)), rel=1e-14)
+
+
+def test_window_edges_ramp_like_unclamped_hats():
+    """Retarded times beyond the last node ramp down over one hat width."""
+    geo = tiny_geometry(seed=21, rays=(20,), delay_hi=10.0, extra_hats=-3)
+    g = geo.grid
+    y = oracle.forward(geo, np.ones(g.n_cols)).reshape(geo.n_rays, g.n_frames)
+    r, phi, delay, w = packed(geo)
+    tret = frame_times(g)[None, :] - delay[:, None]
+    top = g.s0 + (g.n_hat - 1) * g.dt_src
+    ramp = np.clip(1.0 - (tret - top) / g.dt_src, 0.0, 1.0)
+    expect = w[:, None] * np.where(tret > top, ramp, 1.0)
+    assert (tret > top).any()
+    assert np.max(np.abs(y - expect)) <= 1e-14
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_adjoint_identity(name):
+    geo = tiny_geometry(**GEOMS[name])
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(geo.grid.n_cols)
+    y = rng.standard_normal(geo.n_rows)
+    lhs = float(oracle.forward(geo, x) @ y)
+    rhs = float(x @ oracle.adjoint(geo, y))
+    assert abs(lhs - rhs) <= 1e-13 * (np.linalg.norm(oracle.forward(geo, x)) * np.linalg.norm(y))
+
+
+def direct_blind_hats(geo):
+    """Hats whose open support misses the discrete direct footprint eq. (23)."""
+    g = geo.grid
+    W0 = (frame_times(g)[None, :] - geo.maps[0].delay[:, None]).ravel()
+    sk = g.s0 + g.dt_src * np.arange(g.n_hat)
+    return np.array([k for k in range(g.n_hat) if not np.any(np.abs(W0 - sk[k]) < g.dt_src)])
+
+
+def test_direct_old_epoch_blindness_theorem():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    g = geo.grid
+    Z0 = direct_blind_hats(geo)
+    assert len(Z0) >= 3                      # the old-anchored window has direct-blind hats
+    rng = np.random.default_rng(8)
+    x = np.zeros((g.n_cells, g.n_hat))
+    x[:, Z0] = rng.standard_normal((g.n_cells, len(Z0)))
+    y = oracle.forward(geo, x.ravel()).reshape(geo.n_rays, g.n_frames)
+    P0 = geo.maps[0].n_rays
+    assert np.all(y[:P0] == 0.0)                              # eq. (24): bitwise zero block
+    # converse: hats reached by an added order make the stacked column nonzero
+    Wr = (frame_times(g)[None, :] - np.concatenate([m.delay for m in geo.maps[1:]])[:, None]).ravel()
+    sk = g.s0 + g.dt_src * np.arange(g.n_hat)
+    lifted = [k for k in Z0 if np.any(np.abs(Wr - sk[k]) < g.dt_src)]
+    assert lifted and np.any(y[P0:] != 0.0)
+    # transpose: A_0^T y vanishes on the blind block
+    xb = oracle.adjoint(geo, rng.standard_normal(geo.n_rows), order_mask=1).reshape(g.n_cells, g.n_hat)
+    assert np.all(xb[:, Z0] == 0.0)
+    # Cor. 4.2: nullity(A_0) >= m * d_s
+    D0 = oracle.dense(geo, order_mask=1)[: P0 * g.n_frames]
+    assert D0.shape[1] - np.linalg.matrix_rank(D0) >= len(Z0) * g.n_cells
+
+
+def test_zero_columns_are_the_support_based_set():
+    """Column (s,k) of A_0 is zero iff no (ray, frame) has psi_s > 0 and tau_k > 0."""
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    g = geo.grid
+    P0 = geo.maps[0].n_rays
+    D0 = oracle.dense(geo, order_mask=1)[: P0 * g.n_frames]
+    r, phi, delay = geo.maps[0].r, geo.maps[0].phi, geo.maps[0].delay
+    psi = np.stack([spatial_interp(g, np.eye(g.n_cells)[s], r, phi) for s in range(g.n_cells)], 1)
+    tret = frame_times(g)[None, :] - delay[:, None]
+    tau = np.stack([temporal_interp(g, np.eye(g.n_hat)[k], tret) for k in range(g.n_hat)], -1)
+    touched = np.einsum("ps,pfk->sk", (psi > 1e-15).astype(float), (tau > 1e-15).astype(float)) > 0
+    zero_cols = np.all(D0 == 0.0, axis=0).reshape(g.n_cells, g.n_hat)
+    assert np.array_equal(zero_cols, ~touched)
+
+
+def test_gram_monotonicity_and_order_blocks():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    g = geo.grid
+    D = oracle.dense(geo)
+    P = [m.n_rays * g.n_frames for m in geo.maps]
+    prev = None
+    for N in range(len(P)):
+        DN = D[: sum(P[: N + 1])]
+        s = np.linalg.svd(DN, compute_uv=False)
+        if prev is not None:
+            assert np.all(s[: len(prev)] >= prev[: len(s)] - 1e-14 * s[0])   # eq. (21)
+        prev = s
+    # masked rows are not produced, unmasked blocks are the stacked blocks of eq. (3)
+    x = np.random.default_rng(9).standard_normal(g.n_cols)
+    y12 = oracle.forward(geo, x, order_mask=0b110)
+    assert np.all(y12[: P[0]] == 0.0)
+    assert np.allclose(y12[P[0]:], (D @ x)[P[0]:], rtol=0, atol=1e-15)
+
+
+def test_split_merge_gram_invariance():
+    """eq. (15)-(16): four equal-area children with identical transfer values keep A^T A."""
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    kids = []
+    for m in geo.maps:
+        rep = lambda a: np.repeat(a, 4)
+        kids.append(synth.RayMap(r=rep(m.r), phi=rep(m.phi), delay=rep(m.delay),
+                                 weight=rep(m.weight) * math.sqrt(0.25)))
+    geo4 = synth.Geometry(grid=geo.grid, maps=kids)
+    D, D4 = oracle.dense(geo), oracle.dense(geo4)
+    G, G4 = D.T @ D, D4.T @ D4
+    assert np.linalg.norm(G4 - G) / np.linalg.norm(G) <= 1e-10
+
+
+def test_rsvd_equals_lapack_when_sketch_spans_range():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    D = oracle.dense(geo)
+    s_ref_ = np.linalg.svd(D, compute_uv=False)
+    om = np.random.default_rng(10).standard_normal((D.shape[1], D.shape[1]))
+    s, V, U = oracle.rsvd(geo, om, q=2, want_u=True)
+    k = int(np.sum(s_ref_ > 1e-12 * s_ref_[0]))
+    assert np.max(np.abs(s[:k] - s_ref_[:k])) <= 1e-12 * s_ref_[0]
+    # the factors reproduce A on the numerical range
+    approx = (U[:k].T * s[:k]) @ V[:k]
+    assert np.linalg.norm(approx - D) <= 1e-11 * np.linalg.norm(D)
+
+
+def test_rsvd_partial_sketch_converges_with_power_iterations():
+    """A partial sketch: Ritz values lie below the true ones and approach them as q grows.
+
+    The tiny operator's spectrum is flat (sigma_1/sigma_40 ~ 1.4), so the error
+    decays like (sigma_{l+1}/sigma_j)^(2q+1) (HMT 2011, Sec. 10.4) and needs q ~ 16.
+    """
+    geo = tiny_geometry(seed=15, rays=(40, 12, 10), n_r=6, n_phi=8, n_frames=10)
+    D = oracle.dense(geo)
+    s_true = np.linalg.svd(D, compute_uv=False)
+    om = np.random.default_rng(16).standard_normal((40, D.shape[1]))
+    errs = []
+    for q in (0, 2, 8, 16):
+        s, V, _ = oracle.rsvd(geo, om, q=q)
+        assert np.all(s <= s_true[: len(s)] * (1 + 1e-12))
+        errs.append(abs(s[0] - s_true[0]) / s_true[0])
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] <= 1e-8
+
+
+def test_block_lanczos_equals_lapack_when_space_exhausted():
+    geo = tiny_geometry(**GEOMS["ratio_half"])
+    D = oracle.dense(geo)
+    s_true = np.linalg.svd(D, compute_uv=False)
+    b = 4
+    steps = D.shape[0] // b
+    start = np.random.default_rng(17).standard_normal((b, D.shape[1]))
+    s, V, res = oracle.block_lanczos(geo, start, steps)
+    k = int(np.sum(s_true > 1e-10 * s_true[0]))
+    assert np.max(np.abs(s[:k] - s_true[:k])) <= 1e-10 * s_true[0]
+    assert np.max(res[:k]) <= 1e-8 * s_true[0]
+    # Ritz vectors are right singular vectors: ||A v|| = sigma
+    Av = D @ V[:k].T
+    assert np.allclose(np.linalg.norm(Av, axis=0), s[:k], rtol=1e-9, atol=1e-12 * s[0])
+
+
+def test_tsvd_is_truncated_pseudoinverse():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    D = oracle.dense(geo)
+    U, s, Vt = np.linalg.svd(D, full_matrices=False)
+    y = np.random.default_rng(18).standard_normal(D.shape[0])
+    for t in (1, 5, 20):
+        expect = Vt[:t].T @ ((U[:, :t].T @ y) / s[:t])
+        got = oracle.tsvd_solve(geo, Vt, s, y, t)
+        assert np.linalg.norm(got - expect) <= 1e-10 * np.linalg.norm(expect)
+
+
+def test_ridge_cg_matches_dense_solve():
+    geo = tiny_geometry(**GEOMS["ratio_half"])
+    D = oracle.dense(geo)
+    y = np.random.default_rng(19).standard_normal(D.shape[0])
+    lam = 1e-3
+    expect = np.linalg.solve(D.T @ D + lam * np.eye(D.shape[1]), D.T @ y)
+    got, it = oracle.ridge_solve(geo, y, lam, tol=1e-13)
+    assert np.linalg.norm(got - expect) <= 1e-9 * np.linalg.norm(expect)
+
+
+def test_ridge_gradient_against_finite_differences():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    g = geo.grid
+    rng = np.random.default_rng(20)
+    x = rng.random(g.n_cols)
+    y = rng.standard_normal(geo.n_rows)
+    lam = 1e-3
+
+    def loss(v):
+        res = oracle.forward(geo, v) - y
+        return 0.5 * float(res @ res) + 0.5 * lam * float(v @ v)
+
+    grad = oracle.ridge_gradient(geo, x, y, lam)
+    h = 1e-3
+    for i in rng.choice(g.n_cols, 16, replace=False):
+        e = np.zeros(g.n_cols)
+        e[i] = h
+        fd = (loss(x + e) - loss(x - e)) / (2 * h)
+        assert fd == pytest.approx(grad[i], rel=1e-7, abs=1e-9)
+
+
+def test_operational_rank_threshold():
+    s = np.array([3.0, 1.0, 0.02, 0.01, 0.005])
+    assert oracle.operational_rank(s, s_reference=1.0, snr0=100.0) == 4   # sigma >= 0.01
+    assert oracle.operational_rank(s, s_reference=1.0, snr0=100.0, rho=3.0) == 2
+
+
+def test_oracle_rejects_bad_grid():
+    geo = tiny_geometry(**GEOMS["ratio1"])
+    bad = synth.Geometry(grid=synth.Grid(**{**geo.grid.as_dict(), "n_r": 1}), maps=geo.maps)
+    with pytest.raises(ValueError):
+        oracle.forward(bad, np.zeros(bad.grid.n_cols))
