@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark of the retarded-time operator pair A / A^T on one MI355X.
+
+Workload (default): the Kerr a=0.5, i=50 deg geometry with orders n=0,1,2 on a
+128^2 screen, 128 frames at 4M cadence, 64x64 polar cells x 96 hats, and a
+block of l = k + p = 256 + 8 = 264 coefficient vectors (the randomized-SVD
+block).  One step = one block application of A (264 vectors) followed by one
+block application of A^T (264 vectors): 528 applies.  Inputs are synthetic,
+seeded, and resident in HBM before the timed region starts.
+
+Printed: one JSON line with the throughput (applies/s), the roofline of the
+dominant kernel (algorithmic bytes / measured kernel time vs the 8 TB/s HBM
+peak), the plain per-vector throughput beside the batched one, parity against
+the FP64 oracle on sampled vectors, and the oracle's own CPU throughput on
+one full step of the same work.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A+A^T applies/sec and HBM GB/s; batched vs plain at 1e-5 rel err"
+HBM_PEAK_GBPS = 8000.0
+RAY_RECORD_BYTES = 32
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_rows, n_cols, n_rays, n_cells, n_orders, nvec, adjoint):
+    """Bytes the method must move per launch: y (write or read) + x + ray tables (+ CSR)."""
+    b = 4 * nvec * (n_rows + n_cols) + RAY_RECORD_BYTES * n_rays
+    if adjoint:
+        b += 4 * (n_cells + 1)
+    return b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--nvec", type=int, default=264)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2609_05528_amd as rtt
+    import synth
+
+    rtt.require_native()
+    dev = torch.device("cuda:0")
+    p = synth.config(args.workload)
+    geo = synth.geometry_for(p)
+    g = geo.grid
+    G = rtt.Geometry(geo)
+    nvec = args.nvec
+    log("workload %s: rays %s, rows %d, cols %d, nvec %d" % (args.workload, geo.rays_per_order, G.n_rows,
+                                                             G.n_cols, nvec))
+    om = synth.gaussian_block(G.n_cols, nvec, seed=p["seed"] + 1)
+    X = torch.from_numpy(om).to(dev)
+    del om
+    Y = torch.empty((nvec, G.n_rows), dtype=torch.float32, device=dev)
+    XT = torch.empty((nvec, G.n_cols), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record()
+        rtt.op_apply(G, X, Y)
+        if evs is not None:
+            evs[1].record()
+        rtt.op_apply_adjoint(G, Y, XT)
+        if evs is not None:
+            evs[2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    t_a = [e[0].elapsed_time(e[1]) for e in events]
+    t_at = [e[1].elapsed_time(e[2]) for e in events]
+    ms_a, ms_at = float(np.mean(t_a)), float(np.mean(t_at))
+    applies = 2 * nvec * args.steps
+    value = applies / wall
+    log("A %.3f ms, A^T %.3f ms per block launch; step %.3f ms" % (ms_a, ms_at, 1e3 * wall / args.steps))
+
+    nc = g.n_cells
+    b_a = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, nc, g.n_orders, nvec, False)
+    b_at = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, nc, g.n_orders, nvec, True)
+    gbps_a = b_a / (ms_a * 1e-3) / 1e9
+    gbps_at = b_at / (ms_at * 1e-3) / 1e9
+    dom = "op_apply_adjoint" if ms_at >= ms_a else "op_apply"
+    dom_gbps = gbps_at if ms_at >= ms_a else gbps_a
+    dom_bytes = b_at if ms_at >= ms_a else b_a
+
+    # parity of two vectors of the block against the FP64 oracle
+    import oracle
+    par = {}
+    for b in (0, nvec - 1):
+        xb = X[b].double().cpu().numpy()
+        yr = oracle.forward(geo, xb)
+        ya = Y[b].double().cpu().numpy()
+        par.setdefault("A", []).append(float(np.linalg.norm(ya - yr) / np.linalg.norm(yr)))
+        xr = oracle.adjoint(geo, Y[b].double().cpu().numpy())
+        xa = XT[b].double().cpu().numpy()
+        par.setdefault("AT", []).append(float(np.linalg.norm(xa - xr) / np.linalg.norm(xr)))
+    parity = {"A_max_rel_err": max(par["A"]), "AT_max_rel_err": max(par["AT"]), "vectors": [0, nvec - 1],
+              "tol": 1e-5}
+
+    # plain per-instance loop on the same GPU (one vector per call)
+    plain = None
+    if not args.no_plain:
+        xs = [X[b] for b in range(nvec)]
+        ys = [Y[b] for b in range(nvec)]
+        xts = [XT[b] for b in range(nvec)]
+        for b in range(min(nvec, 8)):
+            rtt.op_apply(G, xs[b], ys[b])
+            rtt.op_apply_adjoint(G, ys[b], xts[b])
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for b in range(nvec):
+            rtt.op_apply(G, xs[b], ys[b])
+            rtt.op_apply_adjoint(G, ys[b], xts[b])
+        torch.cuda.synchronize()
+        plain = 2 * nvec / (time.perf_counter() - tp0)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_s = nvec
+        xs = X[:n_s].double().cpu().numpy()
+        tc0 = time.perf_counter()
+        yo = oracle.forward(geo, xs)
+        oracle.adjoint(geo, yo)
+        tc = time.perf_counter() - tc0
+        cpu = {"value": 2 * n_s / tc, "unit": "applies/s", "cores": 1, "kind": "oracle",
+               "sample": "one full step: %d A + %d A^T FP64 applies (plain C, single thread), %.1f s"
+                         % (n_s, n_s, tc)}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%s: %s; block of %d vectors (rSVD l=k+p); step = A + A^T on the block"
+                               % (args.workload, p["label"], nvec),
+                   "rays_per_order": geo.rays_per_order, "rows": G.n_rows, "cols": G.n_cols, "nvec": nvec},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": dom_gbps / HBM_PEAK_GBPS, "traffic": None, "bytes_per_launch": dom_bytes},
+        "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a},
+                    "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at}},
+        "hbm_gbps": (b_a + b_at) / ((ms_a + ms_at) * 1e-3) / 1e9,
+        "plain_value": plain,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

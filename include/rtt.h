@@ -1,0 +1,214 @@
+/*
+ * rtt.h -- C ABI of the MI355X retarded-time tomography library.
+ *
+ * The library evaluates the order-resolved retarded-time imaging operator of
+ * "Photon-Ring Retarded-Time Tomography" (Sec. 3.1, eq. (2)-(3); App. A.2,
+ * eq. (47)) and its transpose on one GPU, and builds the spectral quantities
+ * and estimators on top of it: randomized SVD / block Lanczos singular values
+ * (Sec. 3.6 eq. (19), Sec. 4.4 eq. (31)) and the TSVD and ridge estimates of
+ * Sec. 9.
+ *
+ * Discretisation.  A source history is a coefficient vector x[s][k] over
+ * n_r x n_phi polar cells (s = i*n_phi + j; nodal bilinear basis on the cell
+ * centres, uniform in r over [r_in, r_out], periodic in phi, constant over the
+ * half cells next to r_in and r_out) times n_hat degree-one B-spline hats
+ * centred at s_k = s0 + k*dt_src with half-width dt_src (Sec. 7).  A datum is
+ * indexed by (order n, ray p, frame f) with t_f = t0 + f*dt_obs and equals
+ *     w_{n,p} * sum_s psi_s(r_{n,p}, phi_{n,p}) * sum_k tau_k(t_f - Delta_{n,p}) * x[s][k].
+ *
+ * Conventions shared by every entry point:
+ *  - All float arrays passed to compute calls are DEVICE pointers to FP32,
+ *    contiguous and 4-byte aligned (16-byte alignment of data rows lets the
+ *    forward kernel use vector stores); they stay owned by the caller.
+ *  - A coefficient block is [nvec][n_cols] with n_cols = n_r*n_phi*n_hat
+ *    (k fastest).  A data block is [nvec][n_rows] with rows ordered
+ *    (order n, caller ray p, frame f), frames fastest.  For a handle holding
+ *    G > 1 geometries the operator is block diagonal: columns and rows are the
+ *    per-geometry blocks concatenated in geometry order (offsets from
+ *    geometry_info).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Compute calls are
+ *    asynchronous on it unless stated otherwise.
+ *  - Return value 0 (RTT_OK) or a negative RTT_E* code; on error nothing has
+ *    been launched and last_error() holds a message for the calling thread.
+ *    No C++ exception crosses this boundary.
+ *  - The ratio dt_obs/dt_src must be a rational P/Q with Q <= 64, P <= 4096.
+ */
+#ifndef RTT_H
+#define RTT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RTT_OK = 0,
+    RTT_EINVAL = -1,   /* bad argument, shape or value                         */
+    RTT_ENOMEM = -2,   /* device or host allocation failed                     */
+    RTT_EDEVICE = -3,  /* a HIP runtime call failed                             */
+    RTT_ENOCONV = -4,  /* an iteration stopped before reaching its tolerance    */
+    RTT_ESTATE = -5    /* object in the wrong state (e.g. freed, no factors)    */
+};
+
+typedef struct rtt_geometry rtt_geometry; /* opaque; owns the device ray tables */
+typedef struct rtt_svd rtt_svd;           /* opaque; owns device singular factors */
+
+/* Observer frames, polar source cells and source-time hats of one geometry. */
+typedef struct {
+    int32_t n_orders;  /* image orders 0..n_orders-1 (1..8)                    */
+    int32_t n_frames;  /* observer frames, t_f = t0 + f*dt_obs                  */
+    double t0, dt_obs;
+    int32_t n_r, n_phi;/* polar cells, n_r >= 2, n_phi >= 1                      */
+    double r_in, r_out;
+    int32_t n_hat;     /* hats at s_k = s0 + k*dt_src, n_hat >= 2                */
+    double s0, dt_src;
+} rtt_grid;
+
+/* Retained rays of one order (Sec. 3.1: chi = 1 rays only).  Host FP64
+ * arrays, caller-owned, copied by geometry_load. */
+typedef struct {
+    int64_t n_rays;
+    const double* r_src;      /* source radius r_{n,p}                            */
+    const double* phi_src;    /* source azimuth phi_{n,p} (any real; folded mod 2 pi) */
+    const double* delay;      /* coordinate-time delay Delta_{n,p}                 */
+    const double* weight;     /* transfer weight w_{n,p} (incl. order weight, g^3) */
+    const double* pixel_area; /* nullable: solid angle dOmega_p for whitening     */
+} rtt_raymap;
+
+typedef struct {
+    double sigma_omega;   /* noise density of eq. (15); with pixel_area set, rows
+                             are whitened by sqrt(dOmega_p)/sigma_omega (eq. (16));
+                             0 means 1                                            */
+    int32_t drop_invalid; /* 1: rays with r_src outside [r_in, r_out] get chi = 0
+                             (their rows are written as zeros); 0: RTT_EINVAL     */
+    int32_t reserved[5];
+} rtt_load_opts;
+
+typedef struct {
+    int32_t n_geometries;
+    int64_t n_rows;        /* total rows (all geometries, all orders)          */
+    int64_t n_cols;        /* total columns                                    */
+    int64_t n_rays;        /* total retained rays                              */
+    int64_t table_bytes;   /* device bytes held by the handle                  */
+} rtt_geometry_info;
+
+/* Per-geometry layout inside a handle (geometry g of geometry_info). */
+typedef struct {
+    rtt_grid grid;
+    int64_t row_offset, n_rows;  /* rows of this geometry inside a data vector */
+    int64_t col_offset, n_cols;  /* columns inside a coefficient vector       */
+    int64_t rays_per_order[8];
+} rtt_member_info;
+
+/*
+ * geometry_load -- validate ray maps, build the device ray tables.
+ * grids[G], maps[sum_g grids[g].n_orders] (maps of geometry 0 first, by order).
+ * Per ray, in FP64 on the host: the bilinear stencil of (r, phi) and the hat
+ * index/fraction of t0 - Delta; rays are then sorted by base cell and cast to
+ * a 32-byte device record (eq. (47) row data).  Blocking: ends with the tables
+ * resident on the current device.  opts may be NULL.  *out receives a handle
+ * to release with geometry_free.
+ * Errors: RTT_EINVAL (sizes, NaN/Inf, r outside range without drop_invalid,
+ * unsupported dt_obs/dt_src ratio), RTT_ENOMEM, RTT_EDEVICE.
+ */
+int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int32_t n_geometries,
+                  const rtt_load_opts* opts, rtt_geometry** out);
+int geometry_free(rtt_geometry* geom);
+int geometry_info(const rtt_geometry* geom, rtt_geometry_info* info);
+int geometry_member(const rtt_geometry* geom, int32_t g, rtt_member_info* info);
+
+/*
+ * op_apply -- y = A x (Sec. 3.1 eq. (2)-(3), App. A.2 eq. (47)).
+ * x: device [nvec][n_cols]; y: device [nvec][n_rows].  Rows of orders whose
+ * bit is clear in order_mask (bit n = order n) are neither written nor read;
+ * order_mask = 0 selects all orders.  Deterministic.
+ */
+int op_apply(const rtt_geometry* geom, const float* x, float* y, int32_t nvec,
+             uint32_t order_mask, void* stream);
+
+/*
+ * op_apply_adjoint -- x = A^T y, the exact transpose of op_apply (the
+ * transposed action whose consistency Sec. 5 validates), computed
+ * owner-by-owner without atomics; x is overwritten.  Bitwise reproducible
+ * for fixed inputs.
+ */
+int op_apply_adjoint(const rtt_geometry* geom, const float* y, float* x, int32_t nvec,
+                     uint32_t order_mask, void* stream);
+
+/* ------------------------------------------------------------------ spectra */
+enum { RTT_SVD_RSVD = 0, RTT_SVD_BLOCK_LANCZOS = 1 };
+
+typedef struct {
+    int32_t method;     /* RTT_SVD_RSVD or RTT_SVD_BLOCK_LANCZOS                 */
+    int32_t k;          /* wanted singular triplets                              */
+    int32_t p;          /* oversampling (rSVD): block l = k + p                   */
+    int32_t q;          /* power iterations (rSVD)                                */
+    int32_t block;      /* Lanczos block size b                                   */
+    int32_t steps;      /* Lanczos steps (b*steps right vectors)                  */
+    uint32_t order_mask;/* rows used (0 = all)                                    */
+    int32_t geometry;   /* member geometry for G > 1 handles (-1 = whole operator) */
+    uint64_t seed;      /* used when omega == NULL (counter-based normal draws)   */
+    int32_t keep_u;     /* 1: also store left vectors (rSVD)                       */
+    int32_t reserved[3];
+} rtt_svd_opts;
+
+/*
+ * rsvd -- leading singular triplets of A (Sec. 3.6 eq. (19) with C = I).
+ * rSVD: randomized subspace iteration (Halko, Martinsson & Tropp 2011,
+ * Alg. 4.4) with block l = k + p, q power iterations, orthonormalisation by
+ * Cholesky QR (FP32 MFMA Gram, FP64 factor) after every application, and the
+ * FP64 SVD of the projected l x l factor.  Block Lanczos: block Golub-Kahan
+ * with one-sided FP64 reorthogonalisation.  omega: device FP32 [l][n_cols]
+ * start block (NULL: drawn from seed).  Blocking (returns after the small SVD).
+ */
+int rsvd(const rtt_geometry* geom, const rtt_svd_opts* opts, const float* omega,
+         rtt_svd** out, void* stream);
+int svd_free(rtt_svd* s);
+/* sigma_host[k] (FP64 host, descending), *V_dev = device [k][n_cols] FP32
+ * right vectors, *U_dev = device [k][n_rows] left vectors or NULL. Any output
+ * pointer may be NULL.  *k_out receives k.  Pointers stay owned by s. */
+int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, const float** V_dev,
+            const float** U_dev, double* resid_host);
+
+/*
+ * tsvd_solve -- TSVD estimate of Sec. 9: x = V_t diag(sigma_t^-2) V_t^T A^T y
+ * (= sum_{i<t} v_i (u_i . y)/sigma_i for an exact factorisation).
+ * y: device [nrhs][n_rows]; x: device [nrhs][n_cols].  t <= k; t <= 0 means
+ * t = #{sigma_i >= sigma_min} with sigma_min given.
+ */
+int tsvd_solve(const rtt_geometry* geom, const rtt_svd* s, const float* y, int32_t nrhs,
+               int32_t t, double sigma_min, float* x, void* stream);
+
+typedef struct {
+    float tol;          /* stop when ||r|| <= tol ||A^T y|| (per right-hand side) */
+    int32_t maxit;      /* iteration cap                                           */
+    uint32_t order_mask;
+    int32_t reserved[5];
+} rtt_cg_opts;
+
+typedef struct {
+    int32_t iterations;  /* largest iteration count over right-hand sides        */
+    int32_t converged;   /* number of right-hand sides that met tol               */
+    float rel_residual;  /* largest final ||r||/||A^T y||                         */
+    int32_t reserved;
+} rtt_solve_info;
+
+/*
+ * ridge_solve -- ridge (Tikhonov) estimate of Sec. 9:
+ * argmin 1/2||A x - y||^2 + lambda/2 ||x||^2, by conjugate gradients on
+ * (A^T A + lambda I) x = A^T y with independent scalars per right-hand side.
+ * y: device [nrhs][n_rows]; x: device [nrhs][n_cols] (overwritten; the
+ * start is x = 0).  info may be NULL.  Blocking.  Returns RTT_ENOCONV if some
+ * right-hand side did not reach tol within maxit (x still holds the iterate).
+ */
+int ridge_solve(const rtt_geometry* geom, const float* y, int32_t nrhs, float lambda,
+                const rtt_cg_opts* opts, float* x, rtt_solve_info* info, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTT_H */

@@ -1,0 +1,84 @@
+// Internal declarations of the retarded-time tomography library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rtt.h"
+
+namespace rtt {
+
+// Device record of one retained ray (32 bytes), built in FP64 on the host from
+// (r, phi, delay, weight) and cast once (the row data of eq. (47)).
+struct alignas(16) RayRec {
+    int32_t cell;   // base cell s = i*n_phi + j0 of the 2x2 bilinear stencil
+    float fr;       // radial fraction: weights (1-fr) on row i, fr on row i+1
+    float fphi;     // azimuthal fraction: (1-fphi) on column j0, fphi on j0+1 (periodic)
+    float w;        // transfer weight (chi * w * optional whitening)
+    int32_t k0;     // floor(u0), u0 = (t0 - delay - s0)/dt_src
+    float th0;      // u0 - k0 in [0, 1)
+    int32_t row;    // caller ray index inside the geometry (row block row*n_frames)
+    int32_t order;  // image order n
+};
+static_assert(sizeof(RayRec) == 32, "RayRec must be 32 bytes");
+
+// One geometry of a handle, as the kernels see it.
+struct Member {
+    rtt_grid grid;
+    int32_t P, Q;          // dt_obs/dt_src = P/Q exactly (1/1 when n_frames == 1)
+    int64_t ray_begin;     // first record of this geometry in the sorted ray array
+    int64_t n_rays;
+    int64_t row_offset, n_rows;
+    int64_t col_offset, n_cols;
+    int64_t cell_begin;    // first CSR entry (n_cells + 1 entries)
+    int64_t rays_per_order[8];
+    int32_t adj_variant;   // adjoint tile variant picked by the tuner
+    int32_t apply_variant; // forward launch variant picked by the tuner
+};
+
+}  // namespace rtt
+
+struct rtt_geometry {
+    std::vector<rtt::Member> members;
+    rtt::RayRec* d_rays = nullptr;      // all members, each sorted by base cell
+    int32_t* d_cell_start = nullptr;    // per member CSR over base cells (relative to ray_begin)
+    int64_t n_rows = 0, n_cols = 0, n_rays = 0;
+    int64_t table_bytes = 0;
+    int device = 0;
+    uint32_t magic = 0x52545447u;
+};
+
+namespace rtt {
+
+// thread-local error reporting ---------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define RTT_HIP(call)                                            \
+    do {                                                         \
+        hipError_t e__ = (call);                                 \
+        if (e__ != hipSuccess) return ::rtt::hip_fail(e__, #call); \
+    } while (0)
+
+bool valid_handle(const rtt_geometry* g);
+
+// launchers (operator.hip) ---------------------------------------------------------------------
+int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* y, int nvec,
+                 int64_t x_stride, int64_t y_stride, uint32_t mask, hipStream_t s, int variant);
+int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float* x, int nvec,
+                   int64_t y_stride, int64_t x_stride, uint32_t mask, hipStream_t s, int variant);
+int n_adjoint_variants();
+int n_apply_variants();
+const char* adjoint_variant_name(int v);
+const char* apply_variant_name(int v);
+int default_adjoint_variant(const Member& m);
+int default_apply_variant(const Member& m);
+
+uint32_t effective_mask(const Member& m, uint32_t mask);
+
+}  // namespace rtt

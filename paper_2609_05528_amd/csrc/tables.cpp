@@ -1,0 +1,256 @@
+// geometry_load: host-side FP64 table build (stencils, hat origins, base-cell sort, CSR).
+//
+// Every ray's spatial stencil and time origin is evaluated once here in FP64
+// and rounded to FP32 once; the kernels then step from frame to frame with
+// exact integer arithmetic.  This keeps the retarded-time positions exact to
+// FP64 accuracy even where absolute times reach 10^3 M.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <sstream>
+
+#include "rtt_internal.h"
+
+namespace rtt {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    if (std::getenv("RTT_LOG")) std::fprintf(stderr, "[rtt] error %d: %s\n", code, msg.c_str());
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    std::ostringstream os;
+    os << what << ": " << hipGetErrorString(e);
+    return fail(e == hipErrorOutOfMemory ? RTT_ENOMEM : RTT_EDEVICE, os.str());
+}
+
+bool valid_handle(const rtt_geometry* g) { return g && g->magic == 0x52545447u && g->d_rays; }
+
+uint32_t effective_mask(const Member& m, uint32_t mask)
+{
+    uint32_t all = (m.grid.n_orders >= 32) ? 0xffffffffu : ((1u << m.grid.n_orders) - 1u);
+    return mask == 0 ? all : (mask & all);
+}
+
+// dt_obs/dt_src as an exact small rational P/Q
+static bool exact_ratio(double dt_obs, double dt_src, int n_frames, int32_t* P, int32_t* Q)
+{
+    if (n_frames <= 1) { *P = 1; *Q = 1; return true; }  // only f = 0 exists
+    double ratio = dt_obs / dt_src;
+    if (!(ratio > 0.0) || !std::isfinite(ratio)) return false;
+    for (int q = 1; q <= 64; ++q) {
+        double p = std::round(ratio * q);
+        if (p < 1.0 || p > 4096.0) continue;
+        if (std::fabs(p / q - ratio) <= 1e-12 * ratio) {
+            int pi = (int)p, g = std::gcd(pi, q);
+            *P = pi / g; *Q = q / g;
+            return true;
+        }
+    }
+    return false;
+}
+
+static int check_grid(const rtt_grid& g, int idx)
+{
+    std::ostringstream os;
+    os << "geometry " << idx << ": ";
+    if (g.n_orders < 1 || g.n_orders > 8) return fail(RTT_EINVAL, os.str() + "n_orders must be 1..8");
+    if (g.n_frames < 1 || g.n_frames > 65536) return fail(RTT_EINVAL, os.str() + "n_frames must be 1..65536");
+    if (g.n_r < 2 || g.n_phi < 1) return fail(RTT_EINVAL, os.str() + "need n_r >= 2 and n_phi >= 1");
+    if (g.n_hat < 2) return fail(RTT_EINVAL, os.str() + "need n_hat >= 2");
+    if ((int64_t)g.n_r * g.n_phi > (1 << 26) || (int64_t)g.n_r * g.n_phi * g.n_hat > (1ll << 31) - 1)
+        return fail(RTT_EINVAL, os.str() + "coefficient space too large");
+    if (!std::isfinite(g.r_in) || !std::isfinite(g.r_out) || !(g.r_out > g.r_in))
+        return fail(RTT_EINVAL, os.str() + "need finite r_in < r_out");
+    if (!std::isfinite(g.s0) || !std::isfinite(g.t0) || !std::isfinite(g.dt_obs) || !(g.dt_src > 0.0) ||
+        !std::isfinite(g.dt_src))
+        return fail(RTT_EINVAL, os.str() + "need finite t0, s0, dt_obs and dt_src > 0");
+    if (g.n_frames > 1 && !(g.dt_obs > 0.0)) return fail(RTT_EINVAL, os.str() + "need dt_obs > 0");
+    int32_t P, Q;
+    if (!exact_ratio(g.dt_obs, g.dt_src, g.n_frames, &P, &Q))
+        return fail(RTT_EINVAL, os.str() + "dt_obs/dt_src must be a rational P/Q with Q <= 64, P <= 4096");
+    if ((int64_t)(g.n_frames - 1) * P > (1 << 30))
+        return fail(RTT_EINVAL, os.str() + "n_frames * P too large");
+    return RTT_OK;
+}
+
+}  // namespace rtt
+
+using namespace rtt;
+
+extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int32_t n_geometries,
+                             const rtt_load_opts* opts, rtt_geometry** out)
+{
+    if (!out) return fail(RTT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grids || !maps) return fail(RTT_EINVAL, "grids/maps is NULL");
+    if (n_geometries < 1 || n_geometries > 4096) return fail(RTT_EINVAL, "n_geometries must be 1..4096");
+    const double sigma = (opts && opts->sigma_omega > 0.0) ? opts->sigma_omega : 1.0;
+    const bool drop_invalid = opts && opts->drop_invalid;
+    if (opts && !(opts->sigma_omega >= 0.0)) return fail(RTT_EINVAL, "sigma_omega must be >= 0");
+
+    std::vector<Member> members(n_geometries);
+    std::vector<RayRec> recs;
+    std::vector<int32_t> cstart;
+    int64_t row_off = 0, col_off = 0, map_idx = 0;
+    const double two_pi = 6.283185307179586476925286766559;
+
+    for (int gi = 0; gi < n_geometries; ++gi) {
+        const rtt_grid& g = grids[gi];
+        int rc = check_grid(g, gi);
+        if (rc) return rc;
+        Member& m = members[gi];
+        std::memset(&m, 0, sizeof(m));
+        m.grid = g;
+        exact_ratio(g.dt_obs, g.dt_src, g.n_frames, &m.P, &m.Q);
+        const double dr = (g.r_out - g.r_in) / g.n_r;
+        const double dphi = two_pi / g.n_phi;
+        const int64_t n_cells = (int64_t)g.n_r * g.n_phi;
+
+        std::vector<RayRec> gr;
+        int64_t caller = 0;
+        for (int n = 0; n < g.n_orders; ++n, ++map_idx) {
+            const rtt_raymap& rm = maps[map_idx];
+            if (rm.n_rays < 0 || rm.n_rays > (1ll << 30)) return fail(RTT_EINVAL, "n_rays out of range");
+            if (rm.n_rays > 0 && (!rm.r_src || !rm.phi_src || !rm.delay || !rm.weight))
+                return fail(RTT_EINVAL, "ray map array is NULL");
+            m.rays_per_order[n] = rm.n_rays;
+            for (int64_t p = 0; p < rm.n_rays; ++p, ++caller) {
+                double r = rm.r_src[p], phi = rm.phi_src[p], dl = rm.delay[p], w = rm.weight[p];
+                if (!std::isfinite(r) || !std::isfinite(phi) || !std::isfinite(dl) || !std::isfinite(w)) {
+                    std::ostringstream os;
+                    os << "geometry " << gi << " order " << n << " ray " << p << ": non-finite value";
+                    return fail(RTT_EINVAL, os.str());
+                }
+                if (rm.pixel_area) {
+                    double a = rm.pixel_area[p];
+                    if (!(a >= 0.0) || !std::isfinite(a)) return fail(RTT_EINVAL, "pixel_area must be finite and >= 0");
+                    w *= std::sqrt(a) / sigma;
+                }
+                if (r < g.r_in || r > g.r_out) {
+                    if (!drop_invalid) {
+                        std::ostringstream os;
+                        os << "geometry " << gi << " order " << n << " ray " << p << ": r_src=" << r
+                           << " outside [r_in, r_out]";
+                        return fail(RTT_EINVAL, os.str());
+                    }
+                    w = 0.0;  // chi = 0: the row is kept and reads as zero
+                    r = std::min(std::max(r, g.r_in), g.r_out);
+                }
+                // bilinear stencil on cell centres (uniform in r, periodic in phi)
+                double ur = (r - g.r_in) / dr - 0.5;
+                ur = std::min(std::max(ur, 0.0), (double)(g.n_r - 1));
+                int i = std::min((int)std::floor(ur), g.n_r - 2);
+                double fr = ur - i;
+                double pf = std::fmod(phi, two_pi);
+                if (pf < 0.0) pf += two_pi;
+                double up = pf / dphi - 0.5;
+                double jf = std::floor(up);
+                double fp = up - jf;
+                int j0 = (int)(((int64_t)jf % g.n_phi + g.n_phi) % g.n_phi);
+                // hat origin of frame 0
+                double u0 = (g.t0 - dl - g.s0) / g.dt_src;
+                double k0 = std::floor(u0);
+                if (std::fabs(k0) > (double)(1 << 29)) return fail(RTT_EINVAL, "delay too far from the hat window");
+                RayRec rr;
+                rr.cell = i * g.n_phi + j0;
+                rr.fr = (float)fr;
+                rr.fphi = (float)fp;
+                rr.w = (float)w;
+                rr.k0 = (int32_t)k0;
+                rr.th0 = (float)(u0 - k0);
+                rr.row = (int32_t)caller;
+                rr.order = n;
+                gr.push_back(rr);
+            }
+        }
+        // sort by base cell (stable: keeps (order, caller) order inside a cell)
+        std::stable_sort(gr.begin(), gr.end(), [](const RayRec& a, const RayRec& b) { return a.cell < b.cell; });
+        m.ray_begin = (int64_t)recs.size();
+        m.n_rays = (int64_t)gr.size();
+        m.cell_begin = (int64_t)cstart.size();
+        std::vector<int32_t> cs(n_cells + 1, 0);
+        for (const RayRec& rr : gr) cs[rr.cell + 1]++;
+        for (int64_t c = 0; c < n_cells; ++c) cs[c + 1] += cs[c];
+        cstart.insert(cstart.end(), cs.begin(), cs.end());
+        recs.insert(recs.end(), gr.begin(), gr.end());
+        m.n_rows = m.n_rays * g.n_frames;
+        m.n_cols = n_cells * g.n_hat;
+        m.row_offset = row_off;
+        m.col_offset = col_off;
+        row_off += m.n_rows;
+        col_off += m.n_cols;
+        m.adj_variant = default_adjoint_variant(m);
+        m.apply_variant = default_apply_variant(m);
+    }
+    if (recs.empty()) return fail(RTT_EINVAL, "no rays");
+
+    rtt_geometry* h = new (std::nothrow) rtt_geometry();
+    if (!h) return fail(RTT_ENOMEM, "host allocation failed");
+    h->members = std::move(members);
+    h->n_rows = row_off;
+    h->n_cols = col_off;
+    h->n_rays = (int64_t)recs.size();
+    hipGetDevice(&h->device);
+    size_t rb = recs.size() * sizeof(RayRec), cb = cstart.size() * sizeof(int32_t);
+    hipError_t e = hipMalloc((void**)&h->d_rays, rb);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->d_cell_start, cb);
+    if (e == hipSuccess) e = hipMemcpy(h->d_rays, recs.data(), rb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_cell_start, cstart.data(), cb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "geometry_load upload");
+        if (h->d_rays) hipFree(h->d_rays);
+        if (h->d_cell_start) hipFree(h->d_cell_start);
+        delete h;
+        return rc;
+    }
+    h->table_bytes = (int64_t)(rb + cb);
+    *out = h;
+    return RTT_OK;
+}
+
+extern "C" int geometry_free(rtt_geometry* g)
+{
+    if (!g) return RTT_OK;
+    if (g->magic != 0x52545447u) return fail(RTT_ESTATE, "not a geometry handle");
+    if (g->d_rays) hipFree(g->d_rays);
+    if (g->d_cell_start) hipFree(g->d_cell_start);
+    g->magic = 0;
+    delete g;
+    return RTT_OK;
+}
+
+extern "C" int geometry_info(const rtt_geometry* g, rtt_geometry_info* info)
+{
+    if (!valid_handle(g) || !info) return fail(RTT_EINVAL, "bad handle or info");
+    info->n_geometries = (int32_t)g->members.size();
+    info->n_rows = g->n_rows;
+    info->n_cols = g->n_cols;
+    info->n_rays = g->n_rays;
+    info->table_bytes = g->table_bytes;
+    return RTT_OK;
+}
+
+extern "C" int geometry_member(const rtt_geometry* g, int32_t idx, rtt_member_info* info)
+{
+    if (!valid_handle(g) || !info) return fail(RTT_EINVAL, "bad handle or info");
+    if (idx < 0 || idx >= (int32_t)g->members.size()) return fail(RTT_EINVAL, "member index out of range");
+    const Member& m = g->members[idx];
+    info->grid = m.grid;
+    info->row_offset = m.row_offset;
+    info->n_rows = m.n_rows;
+    info->col_offset = m.col_offset;
+    info->n_cols = m.n_cols;
+    for (int n = 0; n < 8; ++n) info->rays_per_order[n] = m.rays_per_order[n];
+    return RTT_OK;
+}
+
+extern "C" const char* last_error(void) { return g_err.c_str(); }

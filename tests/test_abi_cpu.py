@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI that need no GPU: exports and input validation."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2609_05528_amd as rtt
+import synth
+from tinygeo import tiny_geometry
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "rtt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rtt.require_native()
+    names = declared_functions()
+    assert {"geometry_load", "op_apply", "op_apply_adjoint", "rsvd", "tsvd_solve", "ridge_solve"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(rtt.EXPORTED) == set(names)
+
+
+def _load_err(geo, **kw):
+    with pytest.raises(rtt.RttError) as ei:
+        rtt.Geometry(geo, **kw)
+    return ei.value
+
+
+def test_validation_rejects_bad_inputs_before_device_work():
+    geo = tiny_geometry(seed=3, rays=(6, 3))
+    g = geo.grid
+
+    def with_grid(**kw):
+        return synth.Geometry(grid=synth.Grid(**{**g.as_dict(), **kw}), maps=geo.maps)
+
+    for kw, frag in [(dict(n_r=1), "n_r"), (dict(n_hat=1), "n_hat"), (dict(n_frames=0), "n_frames"),
+                     (dict(r_out=5.0), "r_in < r_out"), (dict(dt_src=0.0), "dt_src"),
+                     (dict(dt_obs=4.0 * math.pi), "rational")]:
+        e = _load_err(with_grid(**kw))
+        assert e.code == rtt.RTT_EINVAL and frag in str(e), (kw, str(e))
+    bad = [synth.RayMap(r=m.r.copy(), phi=m.phi, delay=m.delay, weight=m.weight) for m in geo.maps]
+    bad[1].r[2] = 25.0
+    e = _load_err(synth.Geometry(grid=g, maps=bad))
+    assert e.code == rtt.RTT_EINVAL and "outside" in str(e) and "order 1 ray 2" in str(e)
+    bad[1].r[2] = np.nan
+    e = _load_err(synth.Geometry(grid=g, maps=bad))
+    assert e.code == rtt.RTT_EINVAL and "non-finite" in str(e)
+
+
+def test_drop_invalid_passes_validation():
+    geo = tiny_geometry(seed=3, rays=(6, 3))
+    bad = [synth.RayMap(r=m.r.copy(), phi=m.phi, delay=m.delay, weight=m.weight) for m in geo.maps]
+    bad[0].r[0] = 30.0
+    try:
+        rtt.Geometry(synth.Geometry(grid=geo.grid, maps=bad), drop_invalid=True)
+    except rtt.RttError as e:           # without a GPU the upload is what fails
+        assert e.code in (rtt.RTT_EDEVICE, rtt.RTT_ENOMEM)
+
+
+def test_null_arguments_are_errors():
+    lib = rtt.require_native()
+    assert lib.geometry_load(None, None, 1, None, None) == rtt.RTT_EINVAL
+    assert lib.op_apply(None, None, None, 1, 0, None) == rtt.RTT_EINVAL
+    assert lib.op_apply_adjoint(None, None, None, 1, 0, None) == rtt.RTT_EINVAL
+    assert b"invalid geometry handle" in lib.last_error()
+    assert lib.geometry_free(None) == rtt.RTT_OK
+    info = rtt.rtt_solve_info()
+    assert lib.ridge_solve(None, None, 1, 1e-3, None, None, ctypes.byref(info), None) == rtt.RTT_EINVAL
+
+
+def test_synthetic_workload_shapes():
+    """The synthetic geometries have the ray counts stated for the workloads."""
+    assert synth.geometry_for("cfg1").rays_per_order == [2944]
+    assert synth.geometry_for("cfg2").rays_per_order == [11732, 184, 164]
+    assert synth.geometry_for("cfg3").rays_per_order == [46840]
+    g5 = synth.geometry_for("cfg5")
+    assert g5.rays_per_order == [187348, 2720, 2696] and g5.n_rows == 98695168
+    gs = synth.batch_geometries()
+    assert len(gs) == 12 and sum(g.n_rays for g in gs) == 295508
+    assert [g.grid.s0 for g in (synth.geometry_for(c) for c in ("cfg1", "cfg2", "cfg5"))] == [-32.0, -72.0, -76.0]

@@ -1,0 +1,256 @@
+"""GPU parity of A and A^T (HIP, FP32) against the FP64 oracle.
+
+Tolerance: relative L2 error <= 1e-5 per output and per order block, against
+the oracle evaluated on the same FP32-rounded inputs.  Full-size workloads are
+checked on sampled rays and cells (the oracle evaluated on the rays that can
+reach them) and by the adjoint identity.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tinygeo import tiny_geometry
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def block_rel(geo, got, ref):
+    out = []
+    F = geo.grid.n_frames
+    off = 0
+    for m in geo.maps:
+        n = m.n_rays * F
+        if n:
+            out.append(rel(got[off:off + n], ref[off:off + n]))
+        off += n
+    return out
+
+
+TINY = {
+    "ratio1": dict(seed=11, rays=(12, 6, 5)),
+    "ratio_half": dict(seed=12, rays=(10, 5, 4), dt_obs=2.0, n_frames=9),
+    "ratio2": dict(seed=13, rays=(9, 4, 3), dt_obs=8.0, n_frames=4),
+    "ratio3_4": dict(seed=22, rays=(30, 7), dt_obs=3.0, n_frames=11),
+    "direct_only": dict(seed=14, rays=(15,)),
+    "many_tiles": dict(seed=23, rays=(900, 200, 150), n_r=19, n_phi=21, n_frames=70),
+    "ring1": dict(seed=24, rays=(40, 10), n_r=5, n_phi=1, n_frames=5),
+    "single_frame": dict(seed=25, rays=(20,), n_frames=1),
+}
+
+
+@pytest.mark.parametrize("name", list(TINY))
+def test_apply_and_adjoint_match_oracle_tiny(gpu_lib, name):
+    rtt = gpu_lib
+    geo = tiny_geometry(**TINY[name])
+    say("case", name, geo.rays_per_order, geo.grid.n_frames)
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(100)
+    x = rng.random(geo.grid.n_cols).astype(np.float32)
+    y = rng.standard_normal(geo.n_rows).astype(np.float32)
+    ya = rtt.op_apply(G, to_dev(x)).cpu().numpy()
+    xa = rtt.op_apply_adjoint(G, to_dev(y)).cpu().numpy()
+    yr = oracle.forward(geo, x.astype(np.float64))
+    xr = oracle.adjoint(geo, y.astype(np.float64))
+    assert max(block_rel(geo, ya, yr)) <= TOL
+    assert rel(xa, xr) <= TOL
+
+
+def _cfg_case(name):
+    geo = synth.geometry_for(name)
+    x = synth.uniform_emissivity(geo.grid, seed=synth.config(name)["seed"]).astype(np.float32)
+    return geo, x
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_apply_and_adjoint_full_oracle(gpu_lib, name):
+    rtt = gpu_lib
+    geo, x = _cfg_case(name)
+    say("case", name)
+    G = rtt.Geometry(geo)
+    y = np.random.default_rng(7).standard_normal(geo.n_rows).astype(np.float32)
+    ya = rtt.op_apply(G, to_dev(x)).cpu().numpy()
+    xa = rtt.op_apply_adjoint(G, to_dev(y)).cpu().numpy()
+    yr = oracle.forward(geo, x.astype(np.float64))
+    xr = oracle.adjoint(geo, y.astype(np.float64))
+    assert max(block_rel(geo, ya, yr)) <= TOL
+    assert rel(xa, xr) <= TOL
+    # per-order adjoint blocks
+    for n in range(geo.grid.n_orders):
+        xa_n = rtt.op_apply_adjoint(G, to_dev(y), order_mask=1 << n).cpu().numpy()
+        assert rel(xa_n, oracle.adjoint(geo, y.astype(np.float64), order_mask=1 << n)) <= TOL
+
+
+def sub_geometry(geo, keep):
+    """The rays selected by boolean masks ``keep[n]`` (same grid)."""
+    maps = [synth.RayMap(r=m.r[k], phi=m.phi[k], delay=m.delay[k], weight=m.weight[k])
+            for m, k in zip(geo.maps, keep)]
+    return synth.Geometry(grid=geo.grid, maps=maps)
+
+
+def test_large_geometry_sampled_parity(gpu_lib):
+    """Full 512^2 x 512-frame workload: sampled rows, sampled cells, adjoint identity."""
+    import torch
+    rtt = gpu_lib
+    geo, x = _cfg_case("cfg5")
+    g = geo.grid
+    say("case cfg5 sampled")
+    G = rtt.Geometry(geo)
+    xd = to_dev(x)
+    yd = rtt.op_apply(G, xd)
+    rng = np.random.default_rng(55)
+    # rows: 64 random rays per order
+    F = g.n_frames
+    off = 0
+    keep = []
+    rows = []
+    for m in geo.maps:
+        k = np.zeros(m.n_rays, dtype=bool)
+        idx = rng.choice(m.n_rays, size=min(64, m.n_rays), replace=False)
+        k[idx] = True
+        keep.append(k)
+        for p in np.sort(idx):
+            rows.append(off + p)
+        off += m.n_rays
+    sub = sub_geometry(geo, keep)
+    yr = oracle.forward(sub, x.astype(np.float64)).reshape(-1, F)
+    ya = yd.view(-1, F)[torch.tensor(rows, device="cuda")].cpu().numpy()
+    assert rel(ya, yr) <= TOL
+    # columns: random cells; the oracle sees every ray within two cells of them
+    yv = rng.standard_normal(geo.n_rows).astype(np.float32)
+    xa = rtt.op_apply_adjoint(G, to_dev(yv)).cpu().numpy().reshape(g.n_cells, g.n_hat)
+    dr = (g.r_out - g.r_in) / g.n_r
+    dphi = 2 * math.pi / g.n_phi
+    cells = rng.choice(g.n_cells, size=6, replace=False)
+    yrow = yv.reshape(-1, F)
+    for c in cells:
+        ci, cj = divmod(int(c), g.n_phi)
+        rc = g.r_in + (ci + 0.5) * dr
+        pc = (cj + 0.5) * dphi
+        keep, sel = [], []
+        off = 0
+        for m in geo.maps:
+            dp = np.abs(np.angle(np.exp(1j * (m.phi - pc))))
+            k = (np.abs(m.r - rc) < 2 * dr) & (dp < 2 * dphi)
+            keep.append(k)
+            sel.append(off + np.nonzero(k)[0])
+            off += m.n_rays
+        sub = sub_geometry(geo, keep)
+        ysub = yrow[np.concatenate(sel)].astype(np.float64).ravel()
+        xr = oracle.adjoint(sub, ysub).reshape(g.n_cells, g.n_hat)[c]
+        assert rel(xa[c], xr) <= TOL, (c, rel(xa[c], xr))
+    # adjoint identity with FP64 accumulation of the GPU outputs
+    lhs = float(yd.double().cpu().numpy() @ yv.astype(np.float64))
+    rhs = float(x.astype(np.float64) @ xa.ravel().astype(np.float64))
+    assert abs(lhs - rhs) <= TOL * abs(lhs)
+
+
+def test_adjoint_identity_and_determinism(gpu_lib):
+    import torch
+    rtt = gpu_lib
+    geo, _ = _cfg_case("cfg2")
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(3)
+    x = to_dev(rng.standard_normal(geo.grid.n_cols))
+    y = to_dev(rng.standard_normal(geo.n_rows))
+    Ax = rtt.op_apply(G, x)
+    ATy = rtt.op_apply_adjoint(G, y)
+    lhs = float((Ax.double() * y.double()).sum())
+    rhs = float((x.double() * ATy.double()).sum())
+    assert abs(lhs - rhs) <= TOL * float(Ax.double().norm() * y.double().norm())
+    ATy2 = rtt.op_apply_adjoint(G, y)
+    Ax2 = rtt.op_apply(G, x)
+    assert torch.equal(ATy, ATy2) and torch.equal(Ax, Ax2)
+
+
+def test_blind_blocks_are_bitwise_zero(gpu_lib):
+    """Thm 4.1 on the GPU: x on direct-blind hats gives an exactly zero direct block."""
+    import torch
+    rtt = gpu_lib
+    geo, _ = _cfg_case("cfg2")
+    g = geo.grid
+    G = rtt.Geometry(geo)
+    W0 = (g.t0 + g.dt_obs * np.arange(g.n_frames))[None, :] - geo.maps[0].delay[:, None]
+    sk = g.s0 + g.dt_src * np.arange(g.n_hat)
+    lo, hi = W0.min(), W0.max()
+    blind = [k for k in range(g.n_hat) if sk[k] + g.dt_src <= lo or sk[k] - g.dt_src >= hi]
+    assert len(blind) >= 9
+    x = np.zeros((g.n_cells, g.n_hat), dtype=np.float32)
+    x[:, blind] = np.random.default_rng(4).random((g.n_cells, len(blind)))
+    y = rtt.op_apply(G, to_dev(x.ravel()))
+    P0 = geo.maps[0].n_rays * g.n_frames
+    assert torch.count_nonzero(y[:P0]).item() == 0
+    assert torch.count_nonzero(y[P0:]).item() > 0          # lifted by the higher orders
+    xb = rtt.op_apply_adjoint(G, to_dev(np.random.default_rng(5).random(geo.n_rows)), order_mask=1)
+    assert torch.count_nonzero(xb.view(g.n_cells, g.n_hat)[:, blind]).item() == 0
+
+
+def test_multi_vector_and_order_mask(gpu_lib):
+    import torch
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=31, rays=(300, 60, 50), n_r=9, n_phi=12, n_frames=33)
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(8)
+    X = to_dev(rng.random((3, geo.grid.n_cols)))
+    Y = rtt.op_apply(G, X)
+    for b in range(3):
+        assert torch.equal(Y[b], rtt.op_apply(G, X[b].contiguous()))
+    Yt = to_dev(rng.standard_normal((3, geo.n_rows)))
+    XT = rtt.op_apply_adjoint(G, Yt)
+    for b in range(3):
+        assert torch.equal(XT[b], rtt.op_apply_adjoint(G, Yt[b].contiguous()))
+    # masked-out rows are not written
+    ys = torch.full((geo.n_rows,), 7.0, device="cuda")
+    rtt.op_apply(G, X[0].contiguous(), y=ys, order_mask=0b010)
+    P = [m.n_rays * geo.grid.n_frames for m in geo.maps]
+    assert torch.all(ys[: P[0]] == 7.0) and torch.all(ys[P[0] + P[1]:] == 7.0)
+    ref = oracle.forward(geo, X[0].double().cpu().numpy(), order_mask=0b010)
+    assert rel(ys[P[0]:P[0] + P[1]].cpu().numpy(), ref[P[0]:P[0] + P[1]]) <= TOL
+
+
+def test_drop_invalid_rays_write_zero_rows(gpu_lib):
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=32, rays=(20, 5))
+    maps = [synth.RayMap(r=m.r.copy(), phi=m.phi, delay=m.delay, weight=m.weight) for m in geo.maps]
+    maps[0].r[3] = 25.0
+    bad = synth.Geometry(grid=geo.grid, maps=maps)
+    G = rtt.Geometry(bad, drop_invalid=True)
+    y = rtt.op_apply(G, to_dev(np.ones(geo.grid.n_cols))).cpu().numpy().reshape(-1, geo.grid.n_frames)
+    assert np.all(y[3] == 0.0) and np.all(y[4] != 0.0)
+
+
+def test_batched_handle_is_block_diagonal(gpu_lib):
+    rtt = gpu_lib
+    geos = [tiny_geometry(seed=40 + i, rays=(50 + 7 * i, 9, 4), n_frames=5 + 3 * i) for i in range(3)]
+    G = rtt.Geometry(geos)
+    rng = np.random.default_rng(9)
+    x = rng.random(G.n_cols).astype(np.float32)
+    y = rng.standard_normal(G.n_rows).astype(np.float32)
+    ya = rtt.op_apply(G, to_dev(x)).cpu().numpy()
+    xa = rtt.op_apply_adjoint(G, to_dev(y)).cpu().numpy()
+    for geo, m in zip(geos, G.members):
+        xs = x[m["col_offset"]:m["col_offset"] + m["n_cols"]].astype(np.float64)
+        ys = y[m["row_offset"]:m["row_offset"] + m["n_rows"]].astype(np.float64)
+        assert rel(ya[m["row_offset"]:m["row_offset"] + m["n_rows"]], oracle.forward(geo, xs)) <= TOL
+        assert rel(xa[m["col_offset"]:m["col_offset"] + m["n_cols"]], oracle.adjoint(geo, ys)) <= TOL
