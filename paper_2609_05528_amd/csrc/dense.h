@@ -1,0 +1,50 @@
+// Dense building blocks of the spectral drivers (device kernels in dense.hip,
+// small FP64 factorisations on the host in smallla.cpp).
+#pragma once
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "rtt_internal.h"
+
+namespace rtt {
+
+// Named, grow-only device scratch buffers owned by one driver call.
+struct Workspace {
+    std::map<std::string, std::pair<void*, size_t>> bufs;
+    void* get(const char* name, size_t bytes);
+    void release();
+    ~Workspace();
+};
+
+// G (device, FP64, M x N row-major) = A B^T with A: M rows, B: N rows of length L.
+int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb, int M, int N, int64_t L,
+         double* G_dev, hipStream_t s);
+// Out[m][l] = beta*Out[m][l] + sum_k C[k][m] Y[k][l]; C device FP32 K x M row-major.
+int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Out, int64_t ldo, int64_t L,
+            float beta, hipStream_t s);
+// out[v] = <a_v, b_v> in FP64 for nvec vectors of length n.
+int dots(Workspace& ws, const float* a, int64_t lda, const float* b, int64_t ldb, int64_t n, int nvec,
+         double* out_dev, hipStream_t s);
+// N(0,1) FP32 draws from Philox-4x32-10 counters (seeded).
+int normal_fill(float* out, int64_t n, uint64_t seed, hipStream_t s);
+
+// host FP64 small dense linear algebra (column-major n x n unless stated)
+// Cholesky G = R^T R of a symmetric n x n (row-major) matrix; pivots below
+// dead_tol * max diag mark dependent columns (reported in dead[]): their
+// diagonal and row of R are zero and their projection coefficients R[k][j]
+// (k < j) are kept.  shift is added to the diagonal.  Returns the number of
+// dependent columns.
+int cholesky_upper(const std::vector<double>& G, int n, double shift, double dead_tol, std::vector<double>& R,
+                   std::vector<char>& dead);
+// Inverse of R on the independent columns: dependent rows/columns of the result are zero.
+void upper_inverse(const std::vector<double>& R, int n, const std::vector<char>& dead, std::vector<double>& Rinv);
+// One-sided Jacobi SVD of an n x n row-major matrix M = U diag(s) W^T, s descending.
+void jacobi_svd(const std::vector<double>& M, int n, std::vector<double>& U, std::vector<double>& s,
+                std::vector<double>& W);
+// C = A B for n x n row-major matrices.
+void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C);
+
+}  // namespace rtt

@@ -1,0 +1,293 @@
+// Dense kernels of the spectral drivers on gfx950: FP32 MFMA Gram and block
+// combination, deterministic FP64 reductions, and normal draws.
+//
+// Blocks of vectors are stored vector-major: V[i][0..L) with row stride ld.
+//
+//  gram:    G[i][j] = sum_l A[i][l] B[j][l]        (M x N, L long; e.g. Y^T Y)
+//           split over L into independent slices; each workgroup computes a
+//           64x64 output block of one slice with v_mfma_f32_32x32x2f32 (one
+//           32x32 tile per wave) and writes an FP32 partial; a second kernel
+//           sums the partials of every entry in FP64 in slice order, so the
+//           result does not depend on scheduling.
+//  combine: Out[m][l] = sum_k C[k][m] Y[k][l]      (Out = C^T Y; e.g. Q = Y R^-1)
+//           C (K x M, small) is staged in LDS 32 rows at a time; each wave
+//           owns 32 columns l and up to MG 32-row blocks of Out, so every
+//           element of Y is read once per pass.
+//
+// MFMA operand layout used (32x32x2 f32): lane t supplies A[t%32][t/32] and
+// B[t/32][t%32]; accumulator register r of lane t holds
+// C[8(r/4) + 4(t/32) + r%4][t%32].
+#include "rtt_internal.h"
+#include "dense.h"
+
+namespace rtt {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int GB = 64;   // gram output block
+constexpr int GK = 32;   // k-chunk staged in LDS
+
+__global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ A, int64_t lda,
+                                                      const float* __restrict__ B, int64_t ldb, int M, int N,
+                                                      int64_t L, int64_t slice, int nbn, int sym,
+                                                      float* __restrict__ part)
+{
+    __shared__ float As[GB][GK + 1];
+    __shared__ float Bs[GB][GK + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
+    const int s = blockIdx.y;
+    float* __restrict__ out = part + (int64_t)s * M * N;
+    if (sym && bn < bm) return;   // lower blocks are mirrored from the upper ones
+    const int64_t l0 = (int64_t)s * slice;
+    const int64_t l1 = min(L, l0 + slice);
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f16v acc = {};
+    for (int64_t lc = l0; lc < l1; lc += GK) {
+        // stage A[bm*64 .. +64][lc .. lc+32) and the same rows of B
+        for (int e = tid; e < GB * GK; e += 256) {
+            const int r = e / GK, c = e % GK;
+            const int64_t l = lc + c;
+            const int ia = bm * GB + r, ib = bn * GB + r;
+            As[r][c] = (ia < M && l < l1) ? A[(int64_t)ia * lda + l] : 0.f;
+            Bs[r][c] = (ib < N && l < l1) ? B[(int64_t)ib * ldb + l] : 0.f;
+        }
+        __syncthreads();
+        const int half = lane >> 5, row = lane & 31;
+#pragma unroll
+        for (int j = 0; j < GK / 2; ++j) {
+            // step j covers k = j and k = j + 16 (half selects which)
+            const float a = As[wm + row][16 * half + j];
+            const float b = Bs[wn + row][16 * half + j];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int col = lane & 31, hi = lane >> 5;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = bm * GB + wm + 8 * (r >> 2) + 4 * hi + (r & 3);
+        const int j = bn * GB + wn + col;
+        if (i < M && j < N) out[(int64_t)i * N + j] = acc[r];
+    }
+}
+
+__global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M, int N, int sym,
+                              double* __restrict__ G)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)M * N) return;
+    int i = (int)(e / N), j = (int)(e % N);
+    int si = i, sj = j;
+    if (sym && (j / GB) < (i / GB)) { si = j; sj = i; }   // read the mirrored upper block
+    double s = 0.0;
+    for (int t = 0; t < nsplit; ++t) s += (double)part[(int64_t)t * M * N + (int64_t)si * N + sj];
+    G[e] = s;
+}
+
+template <int MG>
+__global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, int K, int M, int m0,
+                                                 const float* __restrict__ Y, int64_t ldy,
+                                                 float* __restrict__ Out, int64_t ldo, int64_t L, float beta)
+{
+    __shared__ float Cs[32][MG * 32 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t lb = ((int64_t)blockIdx.x * 4 + wave) * 32;
+    const int col = lane & 31, half = lane >> 5;
+    const int64_t l = lb + col;
+    const bool lin = l < L;
+    f16v acc[MG];
+#pragma unroll
+    for (int g = 0; g < MG; ++g) acc[g] = (f16v){};
+    for (int kc = 0; kc < K; kc += 32) {
+        for (int e = tid; e < 32 * MG * 32; e += 256) {
+            const int kr = e / (MG * 32), mc = e % (MG * 32);
+            const int k = kc + kr, m = m0 + mc;
+            Cs[kr][mc] = (k < K && m < M) ? C[(int64_t)k * M + m] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const int kr = 2 * j + half;
+            const int k = kc + kr;
+            const float b = (lin && k < K) ? Y[(int64_t)k * ldy + l] : 0.f;
+#pragma unroll
+            for (int g = 0; g < MG; ++g) {
+                const float a = Cs[kr][g * 32 + col];
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[g], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (!lin) return;
+#pragma unroll
+    for (int g = 0; g < MG; ++g) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int m = m0 + g * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            if (m < M) {
+                float* o = Out + (int64_t)m * ldo + l;
+                *o = (beta == 0.f) ? acc[g][r] : beta * (*o) + acc[g][r];
+            }
+        }
+    }
+}
+
+// Philox-4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) and Box-Muller normals.
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[0] = n0; c[1] = (uint32_t)p1; c[2] = n2; c[3] = (uint32_t)p0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+}
+
+__global__ void k_normal(float* __restrict__ out, int64_t n, uint64_t seed, uint64_t offset)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t base = 4 * i;
+    if (base >= n) return;
+    uint32_t c[4] = {(uint32_t)(i + offset), (uint32_t)((i + offset) >> 32), 0u, 0u};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float two_pi = 6.2831853071795864769f;
+    const float inv = 2.3283064365386963e-10f;   // 2^-32
+    float u0 = ((float)c[0] + 0.5f) * inv, u1 = ((float)c[1] + 0.5f) * inv;
+    float u2 = ((float)c[2] + 0.5f) * inv, u3 = ((float)c[3] + 0.5f) * inv;
+    float r0 = sqrtf(-2.0f * logf(u0)), r1 = sqrtf(-2.0f * logf(u2));
+    float v[4] = {r0 * cosf(two_pi * u1), r0 * sinf(two_pi * u1), r1 * cosf(two_pi * u3), r1 * sinf(two_pi * u3)};
+    for (int t = 0; t < 4 && base + t < n; ++t) out[base + t] = v[t];
+}
+
+// per-vector dot products in FP64, deterministic: partials of fixed slices, then a fixed-order sum
+__global__ void k_dot_partial(const float* __restrict__ a, int64_t lda, const float* __restrict__ b,
+                              int64_t ldb, int64_t n, int64_t slice, double* __restrict__ part)
+{
+    __shared__ double red[256];
+    const int v = blockIdx.y, s = blockIdx.x;
+    const float* av = a + (int64_t)v * lda;
+    const float* bv = b + (int64_t)v * ldb;
+    const int64_t l0 = (int64_t)s * slice, l1 = min(n, l0 + slice);
+    double acc = 0.0;
+    for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) acc += (double)av[l] * (double)bv[l];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + s] = red[0];
+}
+
+__global__ void k_dot_final(const double* __restrict__ part, int nsplit, int nvec, double* __restrict__ out)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvec) return;
+    double s = 0.0;
+    for (int t = 0; t < nsplit; ++t) s += part[(int64_t)v * nsplit + t];
+    out[v] = s;
+}
+
+// --------------------------------------------------------------------------------- host side
+Workspace::~Workspace() { release(); }
+void Workspace::release()
+{
+    for (auto& kv : bufs) hipFree(kv.second.first);
+    bufs.clear();
+}
+void* Workspace::get(const char* name, size_t bytes)
+{
+    auto it = bufs.find(name);
+    if (it != bufs.end() && it->second.second >= bytes) return it->second.first;
+    if (it != bufs.end()) {
+        hipFree(it->second.first);
+        bufs.erase(it);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
+    bufs[name] = {p, bytes};
+    return p;
+}
+
+int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb, int M, int N, int64_t L,
+         double* G_dev, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return RTT_OK;
+    const int nbm = (M + GB - 1) / GB, nbn = (N + GB - 1) / GB;
+    const int sym = (A == B && lda == ldb && M == N) ? 1 : 0;
+    int nsplit = (int)std::min<int64_t>(std::max<int64_t>(1, L / 2048), 512);
+    const int64_t blocks_per_split = (int64_t)nbm * nbn;
+    if (blocks_per_split * nsplit > 8192) nsplit = (int)std::max<int64_t>(1, 8192 / blocks_per_split);
+    int64_t slice = (L + nsplit - 1) / nsplit;
+    slice = ((slice + GK - 1) / GK) * GK;
+    nsplit = (int)((L + slice - 1) / slice);
+    if (nsplit < 1) nsplit = 1;
+    float* part = (float*)ws.get("gram_part", sizeof(float) * (size_t)nsplit * M * N);
+    if (!part) return fail(RTT_ENOMEM, "gram workspace");
+    dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit);
+    hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part);
+    const int64_t tot = (int64_t)M * N;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit, M, N,
+                       sym, G_dev);
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+template <int MG>
+static void combine_launch(const float* C, int K, int M, int m0, const float* Y, int64_t ldy, float* Out,
+                           int64_t ldo, int64_t L, float beta, hipStream_t s)
+{
+    dim3 grid((unsigned)((L + 127) / 128));
+    hipLaunchKernelGGL((k_combine<MG>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta);
+}
+
+int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Out, int64_t ldo, int64_t L,
+            float beta, hipStream_t s)
+{
+    if (M <= 0 || L <= 0) return RTT_OK;
+    for (int m0 = 0; m0 < M; m0 += 9 * 32) {
+        const int mg = std::min(9, (M - m0 + 31) / 32);
+        switch (mg) {
+        case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 4: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 5: combine_launch<5>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 6: combine_launch<6>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 7: combine_launch<7>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 8: combine_launch<8>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        default: combine_launch<9>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        }
+    }
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+int normal_fill(float* out, int64_t n, uint64_t seed, hipStream_t s)
+{
+    const int64_t q = (n + 3) / 4;
+    hipLaunchKernelGGL(k_normal, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, out, n, seed, (uint64_t)0);
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+int dots(Workspace& ws, const float* a, int64_t lda, const float* b, int64_t ldb, int64_t n, int nvec,
+         double* out_dev, hipStream_t s)
+{
+    const int nsplit = (int)std::min<int64_t>(std::max<int64_t>(1, n / 4096), 256);
+    const int64_t slice = (n + nsplit - 1) / nsplit;
+    double* part = (double*)ws.get("dot_part", sizeof(double) * (size_t)nsplit * nvec);
+    if (!part) return fail(RTT_ENOMEM, "dot workspace");
+    hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)nsplit, (unsigned)nvec), dim3(256), 0, s, a, lda, b, ldb, n,
+                       slice, part);
+    hipLaunchKernelGGL(k_dot_final, dim3((unsigned)((nvec + 127) / 128)), dim3(128), 0, s, part, nsplit, nvec,
+                       out_dev);
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+}  // namespace rtt

@@ -377,8 +377,8 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
     a.P = m.P;
     a.Q = m.Q;
     a.invQ = 1.0f / (float)m.Q;
-    a.x = x + m.col_offset;
-    a.y = y + m.row_offset;
+    a.x = x;
+    a.y = y;
     a.x_stride = x_stride;
     a.y_stride = y_stride;
     a.mask = mask;
@@ -417,8 +417,8 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
     a.P = m.P;
     a.Q = m.Q;
     a.invQ = 1.0f / (float)m.Q;
-    a.y = y + m.row_offset;
-    a.x = x + m.col_offset;
+    a.y = y;
+    a.x = x;
     a.y_stride = y_stride;
     a.x_stride = x_stride;
     a.mask = mask;
@@ -429,6 +429,30 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
     default: adjoint_dispatch_tile<4, 4>(a, m.P, m.Q, nvec, s); break;
     }
     RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+}  // namespace rtt
+
+namespace rtt {
+
+int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, float* out, int nvec,
+             uint32_t mask, hipStream_t s)
+{
+    if (member >= 0) {
+        const Member& m = g->members[member];
+        const uint32_t em = effective_mask(m, mask);
+        return adjoint ? launch_adjoint(g, m, in, out, nvec, m.n_rows, m.n_cols, em, s, -1)
+                       : launch_apply(g, m, in, out, nvec, m.n_cols, m.n_rows, em, s, -1);
+    }
+    for (const Member& m : g->members) {
+        const uint32_t em = effective_mask(m, mask);
+        int rc = adjoint ? launch_adjoint(g, m, in + m.row_offset, out + m.col_offset, nvec, g->n_rows, g->n_cols,
+                                          em, s, -1)
+                         : launch_apply(g, m, in + m.col_offset, out + m.row_offset, nvec, g->n_cols, g->n_rows,
+                                        em, s, -1);
+        if (rc) return rc;
+    }
     return RTT_OK;
 }
 
@@ -451,12 +475,7 @@ extern "C" int op_apply(const rtt_geometry* g, const float* x, float* y, int32_t
 {
     int rc = check_call(g, x, y, nvec);
     if (rc) return rc;
-    for (const Member& m : g->members) {
-        rc = launch_apply(g, m, x, y, nvec, g->n_cols, g->n_rows, effective_mask(m, order_mask),
-                          (hipStream_t)stream, -1);
-        if (rc) return rc;
-    }
-    return RTT_OK;
+    return apply_op(g, -1, false, x, y, nvec, order_mask, (hipStream_t)stream);
 }
 
 extern "C" int op_apply_adjoint(const rtt_geometry* g, const float* y, float* x, int32_t nvec,
@@ -464,10 +483,5 @@ extern "C" int op_apply_adjoint(const rtt_geometry* g, const float* y, float* x,
 {
     int rc = check_call(g, y, x, nvec);
     if (rc) return rc;
-    for (const Member& m : g->members) {
-        rc = launch_adjoint(g, m, y, x, nvec, g->n_rows, g->n_cols, effective_mask(m, order_mask),
-                            (hipStream_t)stream, -1);
-        if (rc) return rc;
-    }
-    return RTT_OK;
+    return apply_op(g, -1, true, y, x, nvec, order_mask, (hipStream_t)stream);
 }

@@ -81,4 +81,10 @@ int default_apply_variant(const Member& m);
 
 uint32_t effective_mask(const Member& m, uint32_t mask);
 
+// A (adjoint = false) or A^T on one member (member-compact vectors of length
+// n_cols / n_rows of that member) or, with member = -1, on the whole
+// block-diagonal operator (full-length vectors).
+int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, float* out, int nvec,
+             uint32_t mask, hipStream_t s);
+
 }  // namespace rtt

@@ -1,0 +1,228 @@
+"""GPU parity of rSVD, block Lanczos, TSVD, ridge and the autograd path.
+
+Tolerances: singular values 1e-4 relative for sigma_i >= 1e-3 sigma_1;
+solutions 1e-5 relative against the oracle where the oracle evaluates the same
+arithmetic (TSVD from the same factors, gradients), and the FP64 normal
+equation residual for the ridge solve.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tinygeo import tiny_geometry
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def proj_dist(V1, V2):
+    """Distance between the row spaces of V1 and V2 (orthonormal rows): ||P1 - P2||_2."""
+    q1, _ = np.linalg.qr(np.asarray(V1, dtype=np.float64).T)
+    q2, _ = np.linalg.qr(np.asarray(V2, dtype=np.float64).T)
+    s = np.linalg.svd(q1.T @ q2, compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - s.min() ** 2)))
+
+
+def test_rsvd_equals_lapack_on_tiny_grid(gpu_lib):
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=51, rays=(60, 20, 15), n_r=5, n_phi=8, n_frames=12)
+    say("case rsvd tiny", geo.grid.n_cols, geo.n_rows)
+    G = rtt.Geometry(geo)
+    D = oracle.dense(geo)
+    s_true = np.linalg.svd(D, compute_uv=False)
+    k = 40
+    om = np.random.default_rng(1).standard_normal((k + 24, geo.grid.n_cols)).astype(np.float32)
+    sv = rtt.rsvd(G, k=k, p=24, q=2, omega=to_dev(om), keep_u=True)
+    sig = sv.sigma
+    ok = s_true[:k] >= 1e-3 * s_true[0]
+    # a sketch of 64 vectors with 2 power iterations vs the FP64 oracle on the same draw
+    s_o, V_o, _ = oracle.rsvd(geo, om.astype(np.float64), q=2)
+    assert np.max(np.abs(sig[ok] - s_o[:k][ok]) / s_o[:k][ok]) <= 1e-4
+    assert np.all(sig <= s_true[:k] * (1 + 1e-5))
+    V = sv.V().cpu().numpy()
+    assert np.allclose(np.linalg.norm(V, axis=1), 1.0, atol=1e-5)
+    U = sv.U().cpu().numpy()
+    assert U.shape == (k, geo.n_rows) and np.all(np.isfinite(sv.residual))
+    # the residuals || A v_i - sigma_i u_i || reported by the library match the factors
+    Av = D @ V.T.astype(np.float64)
+    res = np.linalg.norm(Av - U.T.astype(np.float64) * sig, axis=0)
+    assert np.allclose(sv.residual, res, rtol=1e-3, atol=1e-5 * s_true[0])
+
+
+def test_rsvd_full_sketch_reproduces_spectrum(gpu_lib):
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=52, rays=(30, 10, 8), n_r=4, n_phi=6, n_frames=8)
+    G = rtt.Geometry(geo)
+    D = oracle.dense(geo)
+    s_true = np.linalg.svd(D, compute_uv=False)
+    r = int(np.sum(s_true > 1e-6 * s_true[0]))
+    k = min(r, 64)
+    sv = rtt.rsvd(G, k=k, p=min(D.shape) - k, q=1, seed=7)
+    good = s_true[:k] >= 1e-3 * s_true[0]
+    assert np.max(np.abs(sv.sigma[good] - s_true[:k][good]) / s_true[:k][good]) <= 1e-4
+
+
+def test_rsvd_workload_block_matches_oracle(gpu_lib):
+    """128^2 geometry, orders 0-2: rSVD k=32, p=8, q=2 against the FP64 oracle on the same draw."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg2")
+    say("case rsvd cfg2 k=32")
+    G = rtt.Geometry(geo)
+    k, p = 32, 8
+    om = synth.gaussian_block(geo.grid.n_cols, k + p, seed=2001)
+    sv = rtt.rsvd(G, k=k, p=p, q=2, omega=to_dev(om))
+    s_o, V_o, _ = oracle.rsvd(geo, om.astype(np.float64), q=2)
+    assert np.max(np.abs(sv.sigma - s_o[:k]) / s_o[:k]) <= 1e-4
+    V = sv.V().cpu().numpy()
+    # subspace of well-separated leading directions
+    assert proj_dist(V[:8], V_o[:8]) <= 1e-2
+
+
+def test_block_lanczos_tiny_exhausts_space(gpu_lib):
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=53, rays=(40, 12, 10), n_r=4, n_phi=8, n_frames=8)
+    G = rtt.Geometry(geo)
+    D = oracle.dense(geo)
+    s_true = np.linalg.svd(D, compute_uv=False)
+    steps = min(D.shape) // 32
+    sv = rtt.rsvd(G, method="lanczos", k=32, block=32, steps=steps, seed=3)
+    good = s_true[:32] >= 1e-3 * s_true[0]
+    assert np.max(np.abs(sv.sigma[good] - s_true[:32][good]) / s_true[:32][good]) <= 1e-4
+
+
+def test_block_lanczos_matches_oracle(gpu_lib):
+    """Same start block: the GPU Ritz values follow the FP64 oracle's recurrence."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg1")
+    say("case lanczos cfg1")
+    G = rtt.Geometry(geo)
+    b, steps = 32, 8
+    start = synth.gaussian_block(geo.grid.n_cols, b, seed=77)
+    sv = rtt.rsvd(G, method="lanczos", k=b * steps, block=b, steps=steps, omega=to_dev(start))
+    s_o, V_o, res_o = oracle.block_lanczos(geo, start.astype(np.float64), steps)
+    say("gpu", sv.sigma[:6], "oracle", s_o[:6], "res", res_o[:6], sv.residual[:6])
+    top = 16
+    assert np.max(np.abs(sv.sigma[:top] - s_o[:top])) <= 1e-4 * s_o[0]
+    assert np.allclose(sv.residual[:top], res_o[:top], rtol=1e-2, atol=1e-4 * s_o[0])
+
+
+def test_tsvd_matches_oracle_and_pinv(gpu_lib):
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=54, rays=(30, 10, 8), n_r=4, n_phi=6, n_frames=8)
+    G = rtt.Geometry(geo)
+    D = oracle.dense(geo)
+    U, s, Vt = np.linalg.svd(D, full_matrices=False)
+    r = int(np.sum(s > 1e-6 * s[0]))
+    k = min(r, 64)
+    sv = rtt.rsvd(G, k=k, p=min(D.shape) - k, q=1, seed=11)
+    y = np.random.default_rng(2).standard_normal((3, geo.n_rows)).astype(np.float32)
+    t = 12
+    x = rtt.tsvd_solve(G, sv, to_dev(y), t=t).cpu().numpy()
+    # oracle TSVD from the same (GPU) factors
+    Vg = sv.V().double().cpu().numpy()
+    xo = oracle.tsvd_solve(geo, Vg, sv.sigma, y.astype(np.float64), t)
+    assert rel(x, xo) <= 1e-5
+    # exact truncated pseudo-inverse (a gap after sigma_t keeps it well defined)
+    xe = (Vt[:t].T @ ((U[:, :t].T @ y.T.astype(np.float64)) / s[:t, None])).T
+    assert rel(x, xe) <= 1e-3
+
+
+def test_ridge_matches_dense_solve_tiny(gpu_lib):
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=55, rays=(40, 12, 10), n_r=4, n_phi=6, n_frames=10)
+    G = rtt.Geometry(geo)
+    D = oracle.dense(geo)
+    lam = 1e-1
+    y = np.random.default_rng(3).standard_normal((2, geo.n_rows)).astype(np.float32)
+    x, info = rtt.ridge_solve(G, to_dev(y), lam, tol=1e-6, maxit=2000)
+    xe = np.linalg.solve(D.T @ D + lam * np.eye(D.shape[1]), D.T @ y.T.astype(np.float64)).T
+    assert info["converged"] == 2
+    assert rel(x.cpu().numpy(), xe) <= 1e-4
+
+
+def test_ridge_normal_equation_residual_workload(gpu_lib):
+    """64^2 workload, lambda = 1e-3 (absolute): FP64 residual of the normal equations."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg1")
+    say("case ridge cfg1")
+    G = rtt.Geometry(geo)
+    xt = synth.uniform_emissivity(geo.grid, seed=1000)
+    y = oracle.forward(geo, xt).astype(np.float32)
+    lam = 1e-3
+    x, info = rtt.ridge_solve(G, to_dev(y), lam, tol=1e-6, maxit=20000, raise_on_noconv=False)
+    xh = x.double().cpu().numpy()
+    rhs = oracle.adjoint(geo, y.astype(np.float64))
+    res = oracle.adjoint(geo, oracle.forward(geo, xh)) + lam * xh - rhs
+    say("ridge iterations", info)
+    assert np.linalg.norm(res) / np.linalg.norm(rhs) <= 1e-4
+
+
+def test_autograd_gradient_matches_oracle_and_fd(gpu_lib):
+    import torch
+    rtt = gpu_lib
+    from paper_2609_05528_amd.autograd import ridge_loss
+    geo = synth.geometry_for("cfg1")
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(3001)
+    xt = rng.random(geo.grid.n_cols).astype(np.float32)
+    y = oracle.forward(geo, xt.astype(np.float64)) + 0.01 * rng.standard_normal(geo.n_rows)
+    y32 = y.astype(np.float32)
+    x0 = rng.random(geo.grid.n_cols).astype(np.float32)
+    lam = 1e-3
+    xd = to_dev(x0).requires_grad_(True)
+    loss = ridge_loss(xd, to_dev(y32), G, lam)
+    loss.backward()
+    g = xd.grad.double().cpu().numpy()
+    go = oracle.ridge_gradient(geo, x0.astype(np.float64), y32.astype(np.float64), lam)
+    assert rel(g, go) <= 1e-5
+    # central differences of the FP64-accumulated loss on 64 coordinates
+    idx = rng.choice(geo.grid.n_cols, 64, replace=False)
+    h = 1e-3
+
+    def loss64(v):
+        r = rtt.op_apply(G, v).double() - torch.from_numpy(y32.astype(np.float64)).cuda()
+        return 0.5 * float((r * r).sum()) + 0.5 * lam * float((v.double() ** 2).sum())
+
+    errs = []
+    for i in idx:
+        xp = to_dev(x0)
+        xm = to_dev(x0)
+        xp[i] += h
+        xm[i] -= h
+        step = float(xp[i].double() - xm[i].double())
+        fd = (loss64(xp) - loss64(xm)) / step
+        errs.append(abs(fd - g[i]) / max(abs(g[i]), 1e-3 * np.abs(g).max()))
+    assert np.median(errs) <= 1e-3 and max(errs) <= 1e-2
+
+
+def test_double_backward_is_linear(gpu_lib):
+    import torch
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=56, rays=(30, 8, 6))
+    G = rtt.Geometry(geo)
+    x = to_dev(np.random.default_rng(4).random(geo.grid.n_cols)).requires_grad_(True)
+    y = rtt.retarded_time_apply(x, G)
+    w = to_dev(np.random.default_rng(5).standard_normal(geo.n_rows)).requires_grad_(True)
+    (gx,) = torch.autograd.grad((y * w).sum(), x, create_graph=True)   # gx = A^T w
+    v = to_dev(np.random.default_rng(6).standard_normal(geo.grid.n_cols))
+    (gw,) = torch.autograd.grad((gx * v).sum(), w)                     # d/dw <A^T w, v> = A v
+    ref = oracle.forward(geo, v.double().cpu().numpy())
+    assert rel(gw.cpu().numpy(), ref) <= 1e-5
