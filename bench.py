@@ -42,6 +42,32 @@ def algorithmic_bytes(n_rows, n_cols, n_rays, n_cells, n_orders, nvec, adjoint):
     return b
 
 
+def calibrate(torch, dev, gib=2):
+    """Streaming bandwidth of torch's plain copy and fill kernels on 2 GiB (HBM reference)."""
+    n = gib * (1 << 30) // 4
+    a = torch.empty(n, dtype=torch.float32, device=dev)
+    b = torch.empty(n, dtype=torch.float32, device=dev)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 5
+    e[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    e[1].record()
+    for _ in range(reps):
+        a.fill_(2.0)
+    e[2].record()
+    torch.cuda.synchronize()
+    t_copy = e[0].elapsed_time(e[1]) / reps * 1e-3
+    t_fill = e[1].elapsed_time(e[2]) / reps * 1e-3
+    out = {"copy_gbps": 2 * 4 * n / t_copy / 1e9, "fill_gbps": 4 * n / t_fill / 1e9, "bytes": 4 * n}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +77,7 @@ def main():
     ap.add_argument("--nvec", type=int, default=264)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -63,6 +90,8 @@ def main():
 
     rtt.require_native()
     dev = torch.device("cuda:0")
+    calib = calibrate(torch, dev)
+    log("calibration: %s" % calib)
     p = synth.config(args.workload)
     geo = synth.geometry_for(p)
     g = geo.grid
@@ -70,6 +99,10 @@ def main():
     nvec = args.nvec
     log("workload %s: rays %s, rows %d, cols %d, nvec %d" % (args.workload, geo.rays_per_order, G.n_rows,
                                                              G.n_cols, nvec))
+    if not args.no_tune:
+        choice = G.tune(nvec=nvec, reps=3)
+        log("autotuner choice (apply, adjoint): %s = %s" % (choice, [
+            (rtt.variant_names(False)[a], rtt.variant_names(True)[b]) for a, b in choice]))
     om = synth.gaussian_block(G.n_cols, nvec, seed=p["seed"] + 1)
     X = torch.from_numpy(om).to(dev)
     del om
@@ -169,7 +202,10 @@ def main():
         "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a},
                     "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at}},
         "hbm_gbps": (b_a + b_at) / ((ms_a + ms_at) * 1e-3) / 1e9,
+        "variants": {"op_apply": rtt.variant_names(False)[G.members[0]["apply_variant"]],
+                     "op_apply_adjoint": rtt.variant_names(True)[G.members[0]["adjoint_variant"]]},
         "plain_value": plain,
+        "calibration": calib,
         "parity": parity,
         "cpu_baseline": cpu,
     }

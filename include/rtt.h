@@ -99,6 +99,9 @@ typedef struct {
     int64_t row_offset, n_rows;  /* rows of this geometry inside a data vector */
     int64_t col_offset, n_cols;  /* columns inside a coefficient vector       */
     int64_t rays_per_order[8];
+    int32_t apply_variant;       /* kernel variant used by op_apply            */
+    int32_t adjoint_variant;     /* kernel variant used by op_apply_adjoint    */
+    uint64_t digest;             /* FNV-1a hash of the grid and device tables  */
 } rtt_member_info;
 
 /*
@@ -117,6 +120,25 @@ int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int32_t n_geome
 int geometry_free(rtt_geometry* geom);
 int geometry_info(const rtt_geometry* geom, rtt_geometry_info* info);
 int geometry_member(const rtt_geometry* geom, int32_t g, rtt_member_info* info);
+
+/*
+ * geometry_set_variant -- pin the kernel variant of op_apply / op_apply_adjoint
+ * for member g (-1: every member); -1 leaves a variant unchanged.  Variants
+ * compute the same operator with different tilings; names via
+ * variant_name().  Errors: RTT_EINVAL for an unknown index.
+ */
+int geometry_set_variant(rtt_geometry* geom, int32_t g, int32_t apply_variant, int32_t adjoint_variant);
+/* Name of variant v of the forward (adjoint = 0) or adjoint (1) kernel, NULL if out of range. */
+const char* variant_name(int32_t adjoint, int32_t v);
+
+/*
+ * geometry_tune -- autotuner: times every applicable variant of both kernels
+ * on nvec random vectors (HIP events on `stream`, median of `reps`) for each
+ * member, keeps the fastest, and records the choice in the text cache at
+ * cache_path (nullable; one "digest nvec apply adjoint" line per entry).  A
+ * cache hit skips the timing.  Blocking; allocates scratch vectors.
+ */
+int geometry_tune(rtt_geometry* geom, int32_t nvec, int32_t reps, const char* cache_path, void* stream);
 
 /*
  * op_apply -- y = A x (Sec. 3.1 eq. (2)-(3), App. A.2 eq. (47)).

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(_HERE, "librtt.so")
 RTT_OK, RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE, RTT_ENOCONV, RTT_ESTATE = 0, -1, -2, -3, -4, -5
 RTT_SVD_RSVD, RTT_SVD_BLOCK_LANCZOS = 0, 1
 
-EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "op_apply",
-            "op_apply_adjoint", "rsvd", "svd_free", "svd_get", "tsvd_solve", "ridge_solve",
-            "last_error")
+EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
+            "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
+            "tsvd_solve", "ridge_solve", "last_error")
 
 
 class RttError(RuntimeError):
@@ -64,7 +64,8 @@ class rtt_geometry_info(ctypes.Structure):
 class rtt_member_info(ctypes.Structure):
     _fields_ = [("grid", rtt_grid), ("row_offset", ctypes.c_int64), ("n_rows", ctypes.c_int64),
                 ("col_offset", ctypes.c_int64), ("n_cols", ctypes.c_int64),
-                ("rays_per_order", ctypes.c_int64 * 8)]
+                ("rays_per_order", ctypes.c_int64 * 8), ("apply_variant", ctypes.c_int32),
+                ("adjoint_variant", ctypes.c_int32), ("digest", ctypes.c_uint64)]
 
 
 class rtt_svd_opts(ctypes.Structure):
@@ -108,6 +109,8 @@ def require_native():
         "geometry_free": [vp],
         "geometry_info": [vp, ctypes.POINTER(rtt_geometry_info)],
         "geometry_member": [vp, i32, ctypes.POINTER(rtt_member_info)],
+        "geometry_set_variant": [vp, i32, i32, i32],
+        "geometry_tune": [vp, i32, i32, ctypes.c_char_p, vp],
         "op_apply": [vp, vp, vp, i32, u32, vp],
         "op_apply_adjoint": [vp, vp, vp, i32, u32, vp],
         "rsvd": [vp, ctypes.POINTER(rtt_svd_opts), vp, ctypes.POINTER(vp), vp],
@@ -121,6 +124,8 @@ def require_native():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.variant_name.argtypes = [i32, i32]
+    lib.variant_name.restype = ctypes.c_char_p
     lib.last_error.argtypes = []
     lib.last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -199,14 +204,32 @@ class Geometry:
         self.n_cols = info.n_cols
         self.n_rays = info.n_rays
         self.table_bytes = info.table_bytes
+        self._read_members()
+
+    def _read_members(self):
+        lib = require_native()
         self.members = []
         for gi in range(self.n_geometries):
             mi = rtt_member_info()
-            _check(lib.geometry_member(h, gi, ctypes.byref(mi)))
+            _check(lib.geometry_member(self._h, gi, ctypes.byref(mi)))
             self.members.append(dict(row_offset=mi.row_offset, n_rows=mi.n_rows,
                                      col_offset=mi.col_offset, n_cols=mi.n_cols,
                                      n_frames=mi.grid.n_frames, n_orders=mi.grid.n_orders,
-                                     rays_per_order=list(mi.rays_per_order)[: mi.grid.n_orders]))
+                                     rays_per_order=list(mi.rays_per_order)[: mi.grid.n_orders],
+                                     apply_variant=mi.apply_variant, adjoint_variant=mi.adjoint_variant,
+                                     digest=mi.digest))
+
+    def set_variant(self, apply=-1, adjoint=-1, member=-1):
+        """Pin kernel variants (indices as in variant_names())."""
+        _check(require_native().geometry_set_variant(self.handle, member, apply, adjoint))
+        self._read_members()
+
+    def tune(self, nvec=1, reps=5, cache_path=None, stream=None):
+        """Autotune the kernel variants of every member (see include/rtt.h)."""
+        cp = None if cache_path is None else str(cache_path).encode()
+        _check(require_native().geometry_tune(self.handle, nvec, reps, cp, _stream(stream)))
+        self._read_members()
+        return [(m["apply_variant"], m["adjoint_variant"]) for m in self.members]
 
     @property
     def handle(self):
@@ -224,6 +247,16 @@ class Geometry:
             self.free()
         except Exception:
             pass
+
+
+def variant_names(adjoint: bool):
+    lib = require_native()
+    out = []
+    while True:
+        n = lib.variant_name(int(bool(adjoint)), len(out))
+        if n is None:
+            return out
+        out.append(n.decode())
 
 
 def geometry_load(geoms, sigma_omega=0.0, drop_invalid=False) -> Geometry:

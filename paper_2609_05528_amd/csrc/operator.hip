@@ -27,6 +27,8 @@
 //     u_f = k0 + th0 + f P / Q,  kf = k0 + (fP div Q) + [th0 + (fP mod Q)/Q >= 1]
 // and the hat fraction th = th0 + (fP mod Q)/Q - carry.  Both kernels use the
 // same function, so A^T is the exact transpose of A.
+#include <algorithm>
+
 #include "rtt_internal.h"
 
 namespace rtt {
@@ -217,6 +219,43 @@ __device__ __forceinline__ float hat_gather(const float* __restrict__ yrow, int 
     return v;
 }
 
+// hat_gather with a fixed candidate count and clamped, unconditional loads (no divergent
+// branches around the loads, so a batch of rays keeps all its loads in flight).
+template <int TP, int TQ>
+__device__ __forceinline__ float hat_gather_clamped(const float* __restrict__ yrow, int k, int k0, float th0, int F,
+                                                    int P, int Q, float invQ)
+{
+    const int p = TP ? TP : P;
+    const int q = TQ ? TQ : Q;
+    const int d = k - k0;
+    auto ceil_div = [](int n, int dd) { return n >= 0 ? (n + dd - 1) / dd : -((-n) / dd); };
+    const int flo = ceil_div((d - 2) * q, p);
+    const int fhi = ceil_div((d + 1) * q, p) - 1;
+    float v = 0.f;
+    if (TP && TQ) {
+        constexpr int NC = (3 * (TQ > 0 ? TQ : 1) + (TP > 0 ? TP : 1) - 1) / (TP > 0 ? TP : 1) + 1;
+        float yv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) yv[c] = yrow[min(max(flo + c, 0), F - 1)];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int f = flo + c;
+            if (f > fhi || f < 0 || f >= F) continue;
+            const FrameStep st = frame_step<TP, TQ>(f, k0, th0, P, Q, invQ);
+            if (st.kf == k) v += (1.0f - st.th) * yv[c];
+            else if (st.kf == k - 1) v += st.th * yv[c];
+        }
+        return v;
+    }
+    for (int f = max(flo, 0); f <= min(fhi, F - 1); ++f) {
+        const FrameStep st = frame_step<TP, TQ>(f, k0, th0, P, Q, invQ);
+        const float yv = yrow[f];
+        if (st.kf == k) v += (1.0f - st.th) * yv;
+        else if (st.kf == k - 1) v += st.th * yv;
+    }
+    return v;
+}
+
 template <int TR, int TC, int TP, int TQ>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint(AdjArgs a)
 {
@@ -329,32 +368,771 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint(AdjArgs a)
 }
 
 // --------------------------------------------------------------------------------------------
+// A^T, batched tile form: the owner-computes LDS tile of k_adjoint, but each wave walks its
+// slice of the tile's ray ranges NB rays at a time: the range table lives in scalar registers,
+// all NB ray records and data loads are issued before any is consumed, then the NB
+// contributions are folded into the corner registers in order (flushing to the wave's LDS copy
+// whenever the base cell changes).
+// --------------------------------------------------------------------------------------------
+template <int TR, int TC, int TP, int TQ, int NB>
+__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_tb(AdjArgs a)
+{
+    constexpr int NR = 2 * (TR + 1);
+    __shared__ float acc[T_WAVES][TR * TC][KC];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int tiles_k = (a.K + KC - 1) / KC;
+    const int tiles_c = (a.n_phi + TC - 1) / TC;
+    const int tiles_r = (a.n_r + TR - 1) / TR;
+    const int64_t lin = xcd_remap(blockIdx.x, (int64_t)tiles_r * tiles_c * tiles_k);
+    const int tk = (int)(lin % tiles_k);
+    const int tcell = (int)(lin / tiles_k);
+    const int tc = tcell % tiles_c, tr = tcell / tiles_c;
+    const int i0 = tr * TR, jlo = tc * TC;
+    const int jhi = min(jlo + TC, a.n_phi);
+    const int kc = tk * KC;
+    const float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
+    float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
+
+    for (int e = threadIdx.x; e < T_WAVES * TR * TC * KC; e += blockDim.x) (&acc[0][0][0])[e] = 0.f;
+
+    // ray ranges of the base cells whose stencil reaches the tile (uniform, compile-time indexed)
+    int rlo[NR], rln[NR];
+    const bool full_ring = (jhi - jlo) == a.n_phi;
+#pragma unroll
+    for (int t = 0; t <= TR; ++t) {
+        const int ib = i0 - 1 + t;
+        rlo[2 * t] = rln[2 * t] = rlo[2 * t + 1] = rln[2 * t + 1] = 0;
+        if (ib < 0 || ib > a.n_r - 2) continue;
+        const int rowc = ib * a.n_phi;
+        if (full_ring) {
+            rlo[2 * t] = a.cstart[rowc];
+            rln[2 * t] = a.cstart[rowc + a.n_phi] - rlo[2 * t];
+        } else if (jlo == 0) {
+            rlo[2 * t] = a.cstart[rowc + a.n_phi - 1];
+            rln[2 * t] = a.cstart[rowc + a.n_phi] - rlo[2 * t];
+            rlo[2 * t + 1] = a.cstart[rowc];
+            rln[2 * t + 1] = a.cstart[rowc + jhi] - rlo[2 * t + 1];
+        } else {
+            rlo[2 * t] = a.cstart[rowc + jlo - 1];
+            rln[2 * t] = a.cstart[rowc + jhi] - rlo[2 * t];
+        }
+    }
+    int total = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) total += rln[r];
+    const int vlo = (int)(((int64_t)total * wave) / T_WAVES);
+    const int vhi = (int)(((int64_t)total * (wave + 1)) / T_WAVES);
+    __syncthreads();
+
+    float* accw = &acc[wave][0][0];
+    float a00 = 0.f, a10 = 0.f, a01 = 0.f, a11 = 0.f;
+    int l00 = -1, l10 = -1, l01 = -1, l11 = -1;
+    int cur_cell = -1;
+    const int k = kc + lane;
+    auto local_of = [&](int ci, int cj) -> int {
+        if (ci < i0 || ci >= i0 + TR || cj < jlo || cj >= jhi) return -1;
+        return (ci - i0) * TC + (cj - jlo);
+    };
+
+    for (int v0 = vlo; v0 < vhi; v0 += NB) {
+        // phase 1: ray indices (scalar) and records (independent scalar loads)
+        int ri[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int v = min(v0 + j, vhi - 1);
+            int r_ = rlo[0], off = 0;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (v >= off && v < off + rln[r]) r_ = rlo[r] + (v - off);
+                off += rln[r];
+            }
+            ri[j] = __builtin_amdgcn_readfirstlane(r_);
+        }
+        RayRec rr[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) rr[j] = a.rays[ri[j]];
+        // phase 2: every data load of the batch, unconditional (clamped indices)
+        float hv[NB];
+        if (TP == 1 && TQ == 1) {
+            float ya[NB], yb[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const float* __restrict__ yrow = y + (int64_t)rr[j].row * a.F;
+                const int f = k - rr[j].k0;
+                ya[j] = yrow[min(max(f, 0), a.F - 1)];
+                yb[j] = yrow[min(max(f - 1, 0), a.F - 1)];
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int f = k - rr[j].k0;
+                const float h = ((f >= 0 && f < a.F) ? (1.0f - rr[j].th0) * ya[j] : 0.f) +
+                                ((f >= 1 && f - 1 < a.F) ? rr[j].th0 * yb[j] : 0.f);
+                hv[j] = h;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const float* __restrict__ yrow = y + (int64_t)rr[j].row * a.F;
+                hv[j] = hat_gather_clamped<TP, TQ>(yrow, k, rr[j].k0, rr[j].th0, a.F, a.P, a.Q, a.invQ);
+            }
+        }
+        // phase 3: fold the batch into the corner registers in order
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const bool valid = v0 + j < vhi;
+            if (!valid) continue;
+            const int klast = frame_step<TP, TQ>(a.F - 1, rr[j].k0, rr[j].th0, a.P, a.Q, a.invQ).kf + 1;
+            const bool on = ((a.mask >> rr[j].order) & 1u) && !(rr[j].k0 > kc + KC - 1 || klast < kc) && k < a.K;
+            const float h = on ? hv[j] * rr[j].w : 0.f;
+            if (rr[j].cell != cur_cell) {
+                if (l00 >= 0) accw[l00 * KC + lane] += a00;
+                if (l10 >= 0) accw[l10 * KC + lane] += a10;
+                if (l01 >= 0) accw[l01 * KC + lane] += a01;
+                if (l11 >= 0) accw[l11 * KC + lane] += a11;
+                a00 = a10 = a01 = a11 = 0.f;
+                cur_cell = rr[j].cell;
+                const int ci = cur_cell / a.n_phi;
+                const int cj0 = cur_cell - ci * a.n_phi;
+                const int cj1 = (cj0 + 1 == a.n_phi) ? 0 : cj0 + 1;
+                l00 = local_of(ci, cj0);
+                l10 = local_of(ci + 1, cj0);
+                l01 = local_of(ci, cj1);
+                l11 = local_of(ci + 1, cj1);
+            }
+            const float fr = rr[j].fr, fp = rr[j].fphi;
+            a00 += (1.0f - fr) * (1.0f - fp) * h;
+            a10 += fr * (1.0f - fp) * h;
+            a01 += (1.0f - fr) * fp * h;
+            a11 += fr * fp * h;
+        }
+    }
+    if (l00 >= 0) accw[l00 * KC + lane] += a00;
+    if (l10 >= 0) accw[l10 * KC + lane] += a10;
+    if (l01 >= 0) accw[l01 * KC + lane] += a01;
+    if (l11 >= 0) accw[l11 * KC + lane] += a11;
+    __syncthreads();
+    for (int e = threadIdx.x; e < TR * TC * KC; e += blockDim.x) {
+        const int lc = e / KC, kk = kc + (e % KC);
+        const int ci = i0 + lc / TC, cj = jlo + lc % TC;
+        if (ci < a.n_r && cj < jhi && kk < a.K) {
+            float sum = acc[0][lc][e % KC];
+#pragma unroll
+            for (int w = 1; w < T_WAVES; ++w) sum += acc[w][lc][e % KC];
+            x[(int64_t)(ci * a.n_phi + cj) * a.K + kk] = sum;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// A, batched form: a wave owns NB consecutive (base-cell sorted) rays and one chunk of frames.
+// All ray records and x gathers of the batch are issued before any is consumed, the combined
+// series z of every ray goes to LDS, then the wave streams NB row segments with float4 stores
+// using all 64 lanes.  Used when frames are at least as dense as hats (P <= Q).
+// --------------------------------------------------------------------------------------------
+template <int TP, int TQ, int NB, int ZI>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_batch(ApplyArgs a, int fc)
+{
+    constexpr int ZW = ZI * WAVE + 4;
+    __shared__ float zs_all[A_WAVES][NB][ZW];
+    __shared__ int pi_all[A_WAVES][NB][4];     // klo, k0, row, active
+    __shared__ float pf_all[A_WAVES][NB][2];   // th0, w
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r0 = (blk * A_WAVES + wave) * NB;
+    if (r0 >= a.n_rays) return;   // no block-wide barrier below: a wave may leave early
+    const float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
+    float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
+    const int K = a.K, F = a.F;
+    const int f0 = blockIdx.z * fc;
+    const int fend = min(F, f0 + fc);
+    float (*zs)[ZW] = zs_all[wave];
+
+    float xv[NB][ZI][4];
+    float bw[NB][4];
+    int klo[NB], W[NB];
+    bool act[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int64_t ri = r0 + j;
+        act[j] = ri < a.n_rays;
+        const RayRec rr = a.rays[__builtin_amdgcn_readfirstlane((int)(act[j] ? ri : r0))];
+        act[j] = act[j] && ((a.mask >> rr.order) & 1u);
+        const int i = rr.cell / a.n_phi;
+        const int j0 = rr.cell - i * a.n_phi;
+        const int j1 = (j0 + 1 == a.n_phi) ? 0 : j0 + 1;
+        klo[j] = frame_step<TP, TQ>(f0, rr.k0, rr.th0, a.P, a.Q, a.invQ).kf;
+        const int khi = frame_step<TP, TQ>(fend - 1, rr.k0, rr.th0, a.P, a.Q, a.invQ).kf + 1;
+        W[j] = khi - klo[j] + 1;
+        bw[j][0] = (1.0f - rr.fr) * (1.0f - rr.fphi);
+        bw[j][1] = rr.fr * (1.0f - rr.fphi);
+        bw[j][2] = (1.0f - rr.fr) * rr.fphi;
+        bw[j][3] = rr.fr * rr.fphi;
+        const int64_t c00 = (int64_t)(i * a.n_phi + j0) * K, c10 = (int64_t)((i + 1) * a.n_phi + j0) * K;
+        const int64_t c01 = (int64_t)(i * a.n_phi + j1) * K, c11 = (int64_t)((i + 1) * a.n_phi + j1) * K;
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const int jj = lane + it * WAVE;
+            const int k = klo[j] + jj;
+            const bool ok = act[j] && jj < W[j] && k >= 0 && k < K;
+            const int kk = ok ? k : 0;
+            xv[j][it][0] = ok ? x[c00 + kk] : 0.f;
+            xv[j][it][1] = ok ? x[c10 + kk] : 0.f;
+            xv[j][it][2] = ok ? x[c01 + kk] : 0.f;
+            xv[j][it][3] = ok ? x[c11 + kk] : 0.f;
+        }
+        if (lane == 0) {
+            pi_all[wave][j][0] = klo[j];
+            pi_all[wave][j][1] = rr.k0;
+            pi_all[wave][j][2] = rr.row;
+            pi_all[wave][j][3] = act[j] ? 1 : 0;
+            pf_all[wave][j][0] = rr.th0;
+            pf_all[wave][j][1] = rr.w;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const int jj = lane + it * WAVE;
+            if (jj < W[j])
+                zs[j][jj] = bw[j][0] * xv[j][it][0] + bw[j][1] * xv[j][it][1] + bw[j][2] * xv[j][it][2] +
+                            bw[j][3] * xv[j][it][3];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const bool vec4 = ((F & 3) == 0) && ((fend - f0) & 3) == 0 && ((((uintptr_t)y) & 15) == 0);
+    if (vec4) {
+        const int ng = (fend - f0) >> 2;
+        for (int g = lane; g < NB * ng; g += WAVE) {
+            const int j = g / ng, q = g - j * ng;
+            if (!pi_all[wave][j][3]) continue;
+            const int kl = pi_all[wave][j][0], k0 = pi_all[wave][j][1];
+            const float th0 = pf_all[wave][j][0], w = pf_all[wave][j][1];
+            const int f = f0 + 4 * q;
+            f4 v;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const FrameStep st = frame_step<TP, TQ>(f + t, k0, th0, a.P, a.Q, a.invQ);
+                const int jz = st.kf - kl;
+                v[t] = w * ((1.0f - st.th) * zs[j][jz] + st.th * zs[j][jz + 1]);
+            }
+            __builtin_nontemporal_store(v, (f4*)(y + (int64_t)pi_all[wave][j][2] * F + f));
+        }
+    } else {
+        const int ng = fend - f0;
+        for (int g = lane; g < NB * ng; g += WAVE) {
+            const int j = g / ng, q = g - j * ng;
+            if (!pi_all[wave][j][3]) continue;
+            const int kl = pi_all[wave][j][0], k0 = pi_all[wave][j][1];
+            const float th0 = pf_all[wave][j][0], w = pf_all[wave][j][1];
+            const int f = f0 + q;
+            const FrameStep st = frame_step<TP, TQ>(f, k0, th0, a.P, a.Q, a.invQ);
+            const int jz = st.kf - kl;
+            __builtin_nontemporal_store(w * ((1.0f - st.th) * zs[j][jz] + st.th * zs[j][jz + 1]),
+                                        y + (int64_t)pi_all[wave][j][2] * F + f);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// A^T, visit-list form (dt_obs/dt_src = 1/Q).  A wave owns cell row ci and a segment of
+// VISIT_SEG columns, and all hats (V per lane).  Its visit list (built at load time) holds, in
+// sweep order, every ray that touches the row inside the segment with the row's weights
+// already folded in.  The wave fetches NB visit records with one vector load, reads each ray's
+// data row through a buffer descriptor whose range is exactly the row (out-of-range frames read
+// as 0; negative offsets are clamped to a large positive value first, so no offset can wrap
+// into range), applies the ray's fixed 2Q-tap hat filter
+// (frame f = Q (k - k0) + m, weight 1 - |th0 + m/Q|), and accumulates into two sliding
+// register accumulators (target columns u and u+1).  A finished column is written once.
+// --------------------------------------------------------------------------------------------
+struct VisitArgs {
+    const Visit* visits;
+    const int64_t* vtask;
+    int n_r, n_phi, K, F, nseg;
+    const float* y;
+    float* x;
+    int64_t y_stride, x_stride;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
+template <int Q, int V, int NB>
+__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
+{
+    constexpr int T = 2 * Q;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
+    const int64_t lin = xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg);
+    const int sg = (int)(lin % a.nseg), rg = (int)(lin / a.nseg);
+    const int ci = rg * T_WAVES + wave;
+    if (ci >= a.n_r) return;
+    const int64_t task = (int64_t)ci * a.nseg + sg;
+    const int64_t vbeg = a.vtask[task], vend = a.vtask[task + 1];
+    const int jlo = sg * VISIT_SEG;
+    const int jhi = min(jlo + VISIT_SEG, a.n_phi);
+    const int ncol = jhi - jlo + 1;
+    const float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
+    float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
+    const int rowbytes = a.F * 4;
+
+    float acc_a[V], acc_b[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc_a[v] = acc_b[v] = 0.f;
+    int col = 0;
+    auto emit = [&]() {
+        if (col >= 1) {
+            float* xr = x + (int64_t)(ci * a.n_phi + (jlo - 1 + col)) * a.K;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k = lane + WAVE * v;
+                if (k < a.K) xr[k] = acc_a[v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            acc_a[v] = acc_b[v];
+            acc_b[v] = 0.f;
+        }
+        ++col;
+    };
+
+    for (int64_t e0 = vbeg; e0 < vend; e0 += NB) {
+        // one visit record per lane j < NB
+        int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
+        if (lane < NB && e0 + lane < vend) {
+            const int4* vp = (const int4*)(a.visits + e0 + lane);
+            r0 = vp[0];
+            r1 = vp[1];
+        }
+        float yv[NB][V][T], tw[NB][T], wa[NB], wb[NB];
+        int vcol[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const bool valid = e0 + j < vend;
+            const int row = __builtin_amdgcn_readlane(r0.x, j);
+            const int k0 = __builtin_amdgcn_readlane(r0.y, j);
+            const float th0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(r0.z, j));
+            wa[j] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(r0.w, j));
+            wb[j] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(r1.x, j));
+            vcol[j] = valid ? __builtin_amdgcn_readlane(r1.y, j) : ncol;
+            const int order = __builtin_amdgcn_readlane(r1.z, j);
+            const bool on = valid && ((a.mask >> order) & 1u);
+            // a zero-sized range makes every load of a skipped visit return 0 without touching memory
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(y + (int64_t)row * a.F), (short)0, on ? rowbytes : 0,
+                                                  0x00020000);
+            const int mlo = (int)floorf(-(float)Q - (float)Q * th0) + 1;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                tw[j][t] = fmaxf(0.f, 1.0f - fabsf(th0 + (float)(mlo + t) * (1.0f / (float)Q)));
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int base = Q * (lane + WAVE * v - k0) + mlo;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    // frames before the row give negative offsets; clamp their unsigned value far
+                    // below 2^32 so that offset + 4 cannot wrap back into the row's range
+                    const unsigned off = min((unsigned)((base + t) * 4), 0x7FFFFFF0u);
+                    yv[j][v][t] = buf_load_f32(rs, (int)off);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            while (col < vcol[j]) emit();
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                float h = 0.f;
+#pragma unroll
+                for (int t = 0; t < T; ++t) h += tw[j][t] * yv[j][v][t];
+                acc_a[v] += wa[j] * h;
+                acc_b[v] += wb[j] * h;
+            }
+        }
+    }
+    while (col < ncol) emit();
+}
+
+// --------------------------------------------------------------------------------------------
+// A, persistent streaming form.  Work items are (vector, frame chunk, batch of NB rays); each
+// XCD owns a contiguous range of items and its waves stride through that range.  Per item the
+// wave forms z in LDS from the registers loaded for it, immediately issues the x gathers of its
+// next item, and only then streams the current item's rows, so gather latency hides behind the
+// stores.
+// --------------------------------------------------------------------------------------------
+template <int TP, int TQ, int NB, int ZI>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_stream(ApplyArgs a, int fc, int nch, int64_t nbatch,
+                                                                 int64_t total)
+{
+    constexpr int ZW = ZI * WAVE + 4;
+    __shared__ float zs_all[A_WAVES][NB][ZW];
+    __shared__ int pi_all[A_WAVES][NB][4];
+    __shared__ float pf_all[A_WAVES][NB][2];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    float (*zs)[ZW] = zs_all[wave];
+    const int K = a.K, F = a.F;
+    // XCD x (= blockIdx.x % 8) owns items [x*total/8, (x+1)*total/8)
+    const int xcd = blockIdx.x & 7;
+    const int64_t bpx = (gridDim.x + 7 - xcd) / 8;            // blocks on this XCD
+    const int64_t lw = (int64_t)(blockIdx.x >> 3) * A_WAVES + wave;
+    const int64_t nw = bpx * A_WAVES;
+    const int64_t beg = total * xcd / 8, end = total * (xcd + 1) / 8;
+    int64_t item = beg + lw;
+    if (item >= end) return;
+
+    float xv[NB][ZI][4];
+    float bw[NB][4];
+    int klo[NB], W[NB], k0s[NB], rows[NB];
+    float th0s[NB], ws[NB];
+    bool act[NB];
+    int64_t vec = 0;
+    int f0 = 0, fend = 0;
+
+    auto load_item = [&](int64_t it) {
+        const int64_t b = it % nbatch;
+        const int64_t vc = it / nbatch;
+        const int c = (int)(vc % nch);
+        vec = vc / nch;
+        f0 = c * fc;
+        fend = min(F, f0 + fc);
+        const float* __restrict__ x = a.x + vec * a.x_stride;
+        const int64_t r0 = b * NB;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int64_t ri = r0 + j;
+            act[j] = ri < a.n_rays;
+            const RayRec rr = a.rays[__builtin_amdgcn_readfirstlane((int)(act[j] ? ri : r0))];
+            act[j] = act[j] && ((a.mask >> rr.order) & 1u);
+            const int i = rr.cell / a.n_phi;
+            const int j0 = rr.cell - i * a.n_phi;
+            const int j1 = (j0 + 1 == a.n_phi) ? 0 : j0 + 1;
+            klo[j] = frame_step<TP, TQ>(f0, rr.k0, rr.th0, a.P, a.Q, a.invQ).kf;
+            W[j] = frame_step<TP, TQ>(fend - 1, rr.k0, rr.th0, a.P, a.Q, a.invQ).kf + 2 - klo[j];
+            k0s[j] = rr.k0;
+            th0s[j] = rr.th0;
+            ws[j] = rr.w;
+            rows[j] = rr.row;
+            bw[j][0] = (1.0f - rr.fr) * (1.0f - rr.fphi);
+            bw[j][1] = rr.fr * (1.0f - rr.fphi);
+            bw[j][2] = (1.0f - rr.fr) * rr.fphi;
+            bw[j][3] = rr.fr * rr.fphi;
+            const int64_t c00 = (int64_t)(i * a.n_phi + j0) * K, c10 = (int64_t)((i + 1) * a.n_phi + j0) * K;
+            const int64_t c01 = (int64_t)(i * a.n_phi + j1) * K, c11 = (int64_t)((i + 1) * a.n_phi + j1) * K;
+#pragma unroll
+            for (int q = 0; q < ZI; ++q) {
+                const int jj = lane + q * WAVE;
+                const int kk = min(max(klo[j] + jj, 0), K - 1);   // clamped: always a valid address
+                xv[j][q][0] = x[c00 + kk];
+                xv[j][q][1] = x[c10 + kk];
+                xv[j][q][2] = x[c01 + kk];
+                xv[j][q][3] = x[c11 + kk];
+            }
+        }
+    };
+
+    load_item(item);
+    for (;;) {
+        // z of the current item into LDS (zero outside the hat range and for inactive rays)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+#pragma unroll
+            for (int q = 0; q < ZI; ++q) {
+                const int jj = lane + q * WAVE;
+                const int k = klo[j] + jj;
+                const bool ok = act[j] && k >= 0 && k < K;
+                if (jj < W[j])
+                    zs[j][jj] = ok ? bw[j][0] * xv[j][q][0] + bw[j][1] * xv[j][q][1] + bw[j][2] * xv[j][q][2] +
+                                         bw[j][3] * xv[j][q][3]
+                                   : 0.f;
+            }
+            if (lane == 0) {
+                pi_all[wave][j][0] = klo[j];
+                pi_all[wave][j][1] = k0s[j];
+                pi_all[wave][j][2] = rows[j];
+                pi_all[wave][j][3] = act[j] ? 1 : 0;
+                pf_all[wave][j][0] = th0s[j];
+                pf_all[wave][j][1] = ws[j];
+            }
+        }
+        const int64_t cur_vec = vec;
+        const int cf0 = f0, cfend = fend;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t next = item + nw;
+        const bool has_next = next < end;
+        if (has_next) load_item(next);   // gathers of the next item fly while this one is stored
+        float* __restrict__ y = a.y + cur_vec * a.y_stride;
+        const bool vec4 = ((F & 3) == 0) && ((cfend - cf0) & 3) == 0 && ((((uintptr_t)y) & 15) == 0);
+        if (vec4) {
+            const int ng = (cfend - cf0) >> 2;
+            for (int g = lane; g < NB * ng; g += WAVE) {
+                const int j = g / ng, q = g - j * ng;
+                if (!pi_all[wave][j][3]) continue;
+                const int kl = pi_all[wave][j][0], k0 = pi_all[wave][j][1];
+                const float th0 = pf_all[wave][j][0], w = pf_all[wave][j][1];
+                const int f = cf0 + 4 * q;
+                f4 v;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const FrameStep st = frame_step<TP, TQ>(f + t, k0, th0, a.P, a.Q, a.invQ);
+                    const int jz = st.kf - kl;
+                    v[t] = w * ((1.0f - st.th) * zs[j][jz] + st.th * zs[j][jz + 1]);
+                }
+                __builtin_nontemporal_store(v, (f4*)(y + (int64_t)pi_all[wave][j][2] * F + f));
+            }
+        } else {
+            const int ng = cfend - cf0;
+            for (int g = lane; g < NB * ng; g += WAVE) {
+                const int j = g / ng, q = g - j * ng;
+                if (!pi_all[wave][j][3]) continue;
+                const int kl = pi_all[wave][j][0], k0 = pi_all[wave][j][1];
+                const float th0 = pf_all[wave][j][0], w = pf_all[wave][j][1];
+                const int f = cf0 + q;
+                const FrameStep st = frame_step<TP, TQ>(f, k0, th0, a.P, a.Q, a.invQ);
+                const int jz = st.kf - kl;
+                __builtin_nontemporal_store(w * ((1.0f - st.th) * zs[j][jz] + st.th * zs[j][jz + 1]),
+                                            y + (int64_t)pi_all[wave][j][2] * F + f);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (!has_next) break;
+        item = next;
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// A^T, sweep form.  A wave owns one cell row ci, a column segment [jlo, jhi) and 64*V hats.
+// The cells of row ci are corners of rays whose base row is ci-1 (their upper corners, radial
+// weight fr) or ci (lower corners, weight 1-fr).  The wave sweeps the base columns
+// u = jlo-1 .. jhi-1; the rays of base column u feed target columns u (azimuthal weight
+// 1-fphi) and u+1 (weight fphi).  Two register accumulators per hat hold target columns u and
+// u+1; when the sweep leaves base column u, column u is complete and written once.  Ray records
+// and data loads are issued NB rays at a time.  No atomics, no LDS, deterministic.
+// --------------------------------------------------------------------------------------------
+template <int TP, int TQ, int TC, int V, int NB>
+__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_sweep(AdjArgs a)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int segs = (a.n_phi + TC - 1) / TC;
+    const int kchunks = (a.K + WAVE * V - 1) / (WAVE * V);
+    const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
+    const int64_t lin = xcd_remap(blockIdx.x, (int64_t)rgroups * segs * kchunks);
+    const int kch = (int)(lin % kchunks);
+    const int64_t t2 = lin / kchunks;
+    const int seg = (int)(t2 % segs), rg = (int)(t2 / segs);
+    const int ci = rg * T_WAVES + wave;
+    if (ci >= a.n_r) return;
+    const int jlo = seg * TC, jhi = min(jlo + TC, a.n_phi);
+    const int ncol = jhi - jlo + 1;   // base columns jlo-1 .. jhi-1
+    const int kc = kch * WAVE * V;
+    const float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
+    float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
+
+    // per-lane column table: lane c describes base column u = jlo - 1 + c
+    int st0 = 0, ln0 = 0, st1 = 0, ln1 = 0;
+    if (lane < ncol) {
+        const int u = jlo - 1 + lane;
+        const int ub = (u + a.n_phi) % a.n_phi;
+        if (ci >= 1) {
+            const int c = (ci - 1) * a.n_phi + ub;
+            st0 = a.cstart[c];
+            ln0 = a.cstart[c + 1] - st0;
+        }
+        if (ci <= a.n_r - 2) {
+            const int c = ci * a.n_phi + ub;
+            st1 = a.cstart[c];
+            ln1 = a.cstart[c + 1] - st1;
+        }
+    }
+    const int cnt = ln0 + ln1;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int o = __shfl_up(incl, d, WAVE);
+        if (lane >= d) incl += o;
+    }
+    const int total = __shfl(incl, WAVE - 1, WAVE);
+
+    float acc_a[V], acc_b[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc_a[v] = acc_b[v] = 0.f;
+    int col = 0;   // base column index whose target columns acc_a (u) and acc_b (u+1) hold
+
+    auto emit = [&]() {
+        // target column u = jlo - 1 + col is complete
+        if (col >= 1) {
+            const int u = jlo - 1 + col;
+            float* xr = x + (int64_t)(ci * a.n_phi + u) * a.K;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k = kc + lane + WAVE * v;
+                if (k < a.K) xr[k] = acc_a[v];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            acc_a[v] = acc_b[v];
+            acc_b[v] = 0.f;
+        }
+        ++col;
+    };
+
+    for (int e0 = 0; e0 < total; e0 += NB) {
+        int cj[NB];
+        float hv[NB][V], wa[NB], wb[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int e = e0 + j;
+            const bool valid = e < total;
+            const int ee = valid ? e : total - 1;
+            const int c = __popcll(__ballot(incl <= ee));
+            const int inc_c = __shfl(incl, c, WAVE), cnt_c = __shfl(cnt, c, WAVE);
+            const int l0c = __shfl(ln0, c, WAVE);
+            const int o = ee - (inc_c - cnt_c);
+            const bool upper = o < l0c;   // base row ci-1
+            const int ri = upper ? __shfl(st0, c, WAVE) + o : __shfl(st1, c, WAVE) + (o - l0c);
+            const RayRec rr = a.rays[__builtin_amdgcn_readfirstlane(ri)];
+            const bool on = valid && ((a.mask >> rr.order) & 1u);
+            cj[j] = valid ? c : ncol;
+            const float wr = upper ? rr.fr : 1.0f - rr.fr;
+            wa[j] = on ? rr.w * wr * (1.0f - rr.fphi) : 0.f;
+            wb[j] = on ? rr.w * wr * rr.fphi : 0.f;
+            const float* __restrict__ yrow = y + (int64_t)rr.row * a.F;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k = kc + lane + WAVE * v;
+                hv[j][v] = 0.f;
+                if (TP == 1 && TQ == 1) {
+                    const int f = k - rr.k0;
+                    const bool ok1 = f >= 0 && f < a.F, ok2 = f >= 1 && f <= a.F;
+                    const float y1 = yrow[min(max(f, 0), a.F - 1)];
+                    const float y2 = yrow[min(max(f - 1, 0), a.F - 1)];
+                    hv[j][v] = (ok1 ? (1.0f - rr.th0) * y1 : 0.f) + (ok2 ? rr.th0 * y2 : 0.f);
+                } else {
+                    hv[j][v] = hat_gather<TP, TQ>(yrow, k, rr.k0, rr.th0, a.F, a.P, a.Q, a.invQ);
+                }
+                if (k >= a.K) hv[j][v] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            while (col < cj[j]) emit();
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                acc_a[v] += wa[j] * hv[j][v];
+                acc_b[v] += wb[j] * hv[j][v];
+            }
+        }
+    }
+    while (col < ncol) emit();
+}
+
+// --------------------------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------------------------
+// Adjoint variants: 0-2 LDS tile kernels, 3-6 sweep kernels (TC column segment, V hats per lane),
+// 7-10 batched LDS tile kernels, 11 visit-list kernel (dt_obs/dt_src = 1 or 1/2, n_hat <= 512).
 struct AdjVariant {
     const char* name;
-    int tr, tc;
+    int kind;   // 0 tile, 1 sweep, 2 batched tile
+    int a, b;   // tile: TR, TC; sweep: TC, V
 };
-static const AdjVariant kAdjVariants[] = {{"tile8x8", 8, 8}, {"tile4x8", 4, 8}, {"tile4x4", 4, 4}};
+static const AdjVariant kAdjVariants[] = {
+    {"tile8x8", 0, 8, 8},    {"tile4x8", 0, 4, 8},    {"tile4x4", 0, 4, 4},    {"sweep32v1", 1, 32, 1},
+    {"sweep32v2", 1, 32, 2}, {"sweep16v1", 1, 16, 1}, {"sweep16v2", 1, 16, 2}, {"tb8x8", 2, 8, 8},
+    {"tb4x8", 2, 4, 8},      {"tb4x4", 2, 4, 4},      {"tb2x4", 2, 2, 4},      {"visit", 3, 0, 0},
+};
+constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
-int n_adjoint_variants() { return 3; }
+int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 2; }
-const char* apply_variant_name(int v) { return v == 0 ? "rpw1" : "rpw2"; }
+int n_apply_variants() { return 4; }
+const char* apply_variant_name(int v)
+{
+    static const char* names[] = {"rpw1", "rpw2", "batch", "stream"};
+    return names[v];
+}
+
+bool visit_supported(const Member& m) { return m.P == 1 && (m.Q == 1 || m.Q == 2) && m.grid.n_hat <= 512; }
 
 int default_adjoint_variant(const Member& m)
 {
-    // small grids need smaller tiles to fill the chip
-    int64_t cells = (int64_t)m.grid.n_r * m.grid.n_phi;
-    if (cells >= 128 * 128) return 0;
-    if (cells >= 64 * 64) return 1;
+    if (visit_supported(m)) return 11;
     return 2;
 }
-int default_apply_variant(const Member& m) { return m.n_rays >= 65536 ? 1 : 0; }
+int default_apply_variant(const Member& m) { return m.P <= m.Q ? 3 : 1; }
+
+template <int TP, int TQ, int NB, int ZI>
+static void apply_batch_launch(const ApplyArgs& a, int nvec, hipStream_t s)
+{
+    // frames per chunk: the chunk's hat window (<= floor((fc-1)P/Q) + 4) must fit ZI*64
+    const int P = a.P, Q = a.Q;
+    int fc = a.F;
+    const int64_t span = (int64_t)(fc - 1) * P / Q + 4;
+    if (span > (int64_t)ZI * WAVE) {
+        fc = (int)(((int64_t)ZI * WAVE - 4) * Q / P) + 1;
+        fc &= ~3;
+    }
+    const int nch = (a.F + fc - 1) / fc;
+    const int64_t rays_per_block = (int64_t)A_WAVES * NB;
+    dim3 grid((unsigned)((a.n_rays + rays_per_block - 1) / rays_per_block), (unsigned)nvec, (unsigned)nch);
+    hipLaunchKernelGGL((k_apply_batch<TP, TQ, NB, ZI>), grid, dim3(A_WAVES * WAVE), 0, s, a, fc);
+}
+
+template <int TP, int TQ, int NB, int ZI>
+static void apply_stream_launch(const ApplyArgs& a, int nvec, hipStream_t s)
+{
+    const int P = a.P, Q = a.Q;
+    int fc = a.F;
+    const int64_t span = (int64_t)(fc - 1) * P / Q + 4;
+    if (span > (int64_t)ZI * WAVE) {
+        fc = (int)(((int64_t)ZI * WAVE - 4) * Q / P) + 1;
+        fc &= ~3;
+    }
+    const int nch = (a.F + fc - 1) / fc;
+    const int64_t nbatch = (a.n_rays + NB - 1) / NB;
+    const int64_t total = nbatch * nch * nvec;
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t blocks = std::min<int64_t>((int64_t)cus * 8, (total + A_WAVES - 1) / A_WAVES);
+    blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_apply_stream<TP, TQ, NB, ZI>), dim3((unsigned)blocks), dim3(A_WAVES * WAVE), 0, s, a, fc,
+                       nch, nbatch, total);
+}
 
 template <int TP, int TQ>
 static void apply_dispatch(const ApplyArgs& a, int nvec, int variant, hipStream_t s)
 {
+    if (variant == 3 && a.P <= a.Q) {
+        const int64_t span = (int64_t)(a.F - 1) * a.P / a.Q + 4;
+        if (span <= 2 * WAVE) apply_stream_launch<TP, TQ, 4, 2>(a, nvec, s);
+        else if (span <= 3 * WAVE) apply_stream_launch<TP, TQ, 4, 3>(a, nvec, s);
+        else apply_stream_launch<TP, TQ, 2, 5>(a, nvec, s);
+        return;
+    }
+    if (variant == 2 && a.P <= a.Q) {
+        const int64_t span = (int64_t)(a.F - 1) * a.P / a.Q + 4;
+        if (span <= 2 * WAVE) apply_batch_launch<TP, TQ, 4, 2>(a, nvec, s);
+        else if (span <= 3 * WAVE) apply_batch_launch<TP, TQ, 4, 3>(a, nvec, s);
+        else apply_batch_launch<TP, TQ, 2, 5>(a, nvec, s);
+        return;
+    }
     const int rpw = variant == 1 ? 2 : 1;
     const int64_t rays_per_block = (int64_t)A_WAVES * rpw;
     dim3 grid((unsigned)((a.n_rays + rays_per_block - 1) / rays_per_block), (unsigned)nvec);
@@ -403,6 +1181,53 @@ static void adjoint_dispatch_tile(const AdjArgs& a, int P, int Q, int nvec, hipS
         hipLaunchKernelGGL((k_adjoint<TR, TC, 0, 0>), grid, dim3(T_WAVES * WAVE), 0, s, a);
 }
 
+template <int TR, int TC>
+static void adjoint_dispatch_tb(const AdjArgs& a, int P, int Q, int nvec, hipStream_t s)
+{
+    constexpr int NB = 8;
+    const int64_t tiles = (int64_t)((a.n_r + TR - 1) / TR) * ((a.n_phi + TC - 1) / TC) * ((a.K + KC - 1) / KC);
+    dim3 grid((unsigned)tiles, (unsigned)nvec);
+    if (P == 1 && Q == 1)
+        hipLaunchKernelGGL((k_adjoint_tb<TR, TC, 1, 1, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+    else if (P == 1 && Q == 2)
+        hipLaunchKernelGGL((k_adjoint_tb<TR, TC, 1, 2, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adjoint_tb<TR, TC, 0, 0, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+}
+
+template <int TC, int V>
+static void adjoint_dispatch_sweep(const AdjArgs& a, int P, int Q, int nvec, hipStream_t s)
+{
+    constexpr int NB = 8;
+    const int64_t work = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * ((a.n_phi + TC - 1) / TC) *
+                         ((a.K + WAVE * V - 1) / (WAVE * V));
+    dim3 grid((unsigned)work, (unsigned)nvec);
+    if (P == 1 && Q == 1)
+        hipLaunchKernelGGL((k_adjoint_sweep<1, 1, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+    else if (P == 1 && Q == 2)
+        hipLaunchKernelGGL((k_adjoint_sweep<1, 2, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_adjoint_sweep<0, 0, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+}
+
+template <int Q, int V, int NB>
+static void visit_launch(const VisitArgs& a, int nvec, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg;
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB>), dim3((unsigned)blocks, (unsigned)nvec), dim3(T_WAVES * WAVE), 0, s,
+                       a);
+}
+
+template <int Q>
+static void visit_dispatch(const VisitArgs& a, int nvec, hipStream_t s)
+{
+    constexpr int NB1 = Q == 1 ? 8 : 4;
+    if (a.K <= 64) visit_launch<Q, 1, NB1>(a, nvec, s);
+    else if (a.K <= 128) visit_launch<Q, 2, NB1>(a, nvec, s);
+    else if (a.K <= 256) visit_launch<Q, 4, Q == 1 ? 4 : 2>(a, nvec, s);
+    else visit_launch<Q, 8, 2>(a, nvec, s);
+}
+
 int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float* x, int nvec,
                    int64_t y_stride, int64_t x_stride, uint32_t mask, hipStream_t s, int variant)
 {
@@ -423,10 +1248,38 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
     a.x_stride = x_stride;
     a.mask = mask;
     if (variant < 0 || variant >= n_adjoint_variants()) variant = m.adj_variant;
+    if (variant == 11 && !visit_supported(m)) variant = 2;
+    if (variant == 11) {
+        VisitArgs va;
+        va.visits = g->d_visits + m.visit_begin;
+        va.vtask = g->d_vtask + m.vtask_begin;
+        va.n_r = m.grid.n_r;
+        va.n_phi = m.grid.n_phi;
+        va.K = m.grid.n_hat;
+        va.F = m.grid.n_frames;
+        va.nseg = m.nseg;
+        va.y = y;
+        va.x = x;
+        va.y_stride = y_stride;
+        va.x_stride = x_stride;
+        va.mask = mask;
+        if (m.Q == 1) visit_dispatch<1>(va, nvec, s);
+        else visit_dispatch<2>(va, nvec, s);
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     switch (variant) {
     case 0: adjoint_dispatch_tile<8, 8>(a, m.P, m.Q, nvec, s); break;
     case 1: adjoint_dispatch_tile<4, 8>(a, m.P, m.Q, nvec, s); break;
-    default: adjoint_dispatch_tile<4, 4>(a, m.P, m.Q, nvec, s); break;
+    case 2: adjoint_dispatch_tile<4, 4>(a, m.P, m.Q, nvec, s); break;
+    case 3: adjoint_dispatch_sweep<32, 1>(a, m.P, m.Q, nvec, s); break;
+    case 4: adjoint_dispatch_sweep<32, 2>(a, m.P, m.Q, nvec, s); break;
+    case 5: adjoint_dispatch_sweep<16, 1>(a, m.P, m.Q, nvec, s); break;
+    case 6: adjoint_dispatch_sweep<16, 2>(a, m.P, m.Q, nvec, s); break;
+    case 7: adjoint_dispatch_tb<8, 8>(a, m.P, m.Q, nvec, s); break;
+    case 8: adjoint_dispatch_tb<4, 8>(a, m.P, m.Q, nvec, s); break;
+    case 9: adjoint_dispatch_tb<4, 4>(a, m.P, m.Q, nvec, s); break;
+    default: adjoint_dispatch_tb<2, 4>(a, m.P, m.Q, nvec, s); break;
     }
     RTT_HIP(hipGetLastError());
     return RTT_OK;

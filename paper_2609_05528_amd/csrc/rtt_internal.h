@@ -26,6 +26,23 @@ struct alignas(16) RayRec {
 };
 static_assert(sizeof(RayRec) == 32, "RayRec must be 32 bytes");
 
+// One visit of a ray by the wave that owns one cell row: the ray feeds two
+// cells of that row (target columns col-1 and col of the row's sweep, in the
+// segment's local numbering) with weights wa and wb (transfer weight x radial
+// weight of this row x azimuthal weights).  32 bytes.
+struct alignas(16) Visit {
+    int32_t row;    // caller ray index (data row block row * n_frames)
+    int32_t k0;     // hat origin of frame 0
+    float th0;      // fraction of frame 0
+    float wa;       // weight into target column (col - 1 + segment start)
+    float wb;       // weight into target column (col + segment start)
+    int32_t col;    // sweep position 0 .. ncol-1 (base column segment_start - 1 + col)
+    int32_t order;  // image order (for order masks)
+    int32_t pad;
+};
+static_assert(sizeof(Visit) == 32, "Visit must be 32 bytes");
+constexpr int VISIT_SEG = 16;   // columns per sweep segment
+
 // One geometry of a handle, as the kernels see it.
 struct Member {
     rtt_grid grid;
@@ -36,8 +53,12 @@ struct Member {
     int64_t col_offset, n_cols;
     int64_t cell_begin;    // first CSR entry (n_cells + 1 entries)
     int64_t rays_per_order[8];
-    int32_t adj_variant;   // adjoint tile variant picked by the tuner
-    int32_t apply_variant; // forward launch variant picked by the tuner
+    int32_t adj_variant;   // adjoint kernel variant (default heuristic or autotuner)
+    int32_t apply_variant; // forward kernel variant
+    uint64_t digest;       // FNV-1a of the grid and this member's device records
+    int64_t visit_begin;   // first visit record of this member
+    int64_t vtask_begin;   // first entry of the task offsets (n_r * nseg + 1 entries)
+    int32_t nseg;          // sweep segments per cell row
 };
 
 }  // namespace rtt
@@ -46,6 +67,8 @@ struct rtt_geometry {
     std::vector<rtt::Member> members;
     rtt::RayRec* d_rays = nullptr;      // all members, each sorted by base cell
     int32_t* d_cell_start = nullptr;    // per member CSR over base cells (relative to ray_begin)
+    rtt::Visit* d_visits = nullptr;     // per member visit lists (cell row x segment tasks)
+    int64_t* d_vtask = nullptr;         // per member task offsets into the visit lists
     int64_t n_rows = 0, n_cols = 0, n_rays = 0;
     int64_t table_bytes = 0;
     int device = 0;
@@ -66,6 +89,7 @@ int hip_fail(hipError_t e, const char* what);
     } while (0)
 
 bool valid_handle(const rtt_geometry* g);
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ull);
 
 // launchers (operator.hip) ---------------------------------------------------------------------
 int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* y, int nvec,
@@ -78,6 +102,7 @@ const char* adjoint_variant_name(int v);
 const char* apply_variant_name(int v);
 int default_adjoint_variant(const Member& m);
 int default_apply_variant(const Member& m);
+bool visit_supported(const Member& m);
 
 uint32_t effective_mask(const Member& m, uint32_t mask);
 

@@ -34,6 +34,16 @@ int hip_fail(hipError_t e, const char* what)
 
 bool valid_handle(const rtt_geometry* g) { return g && g->magic == 0x52545447u && g->d_rays; }
 
+uint64_t fnv1a(const void* data, size_t n, uint64_t h)
+{
+    const unsigned char* p = (const unsigned char*)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
 uint32_t effective_mask(const Member& m, uint32_t mask)
 {
     uint32_t all = (m.grid.n_orders >= 32) ? 0xffffffffu : ((1u << m.grid.n_orders) - 1u);
@@ -100,6 +110,8 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     std::vector<Member> members(n_geometries);
     std::vector<RayRec> recs;
     std::vector<int32_t> cstart;
+    std::vector<Visit> visits;
+    std::vector<int64_t> vtask;
     int64_t row_off = 0, col_off = 0, map_idx = 0;
     const double two_pi = 6.283185307179586476925286766559;
 
@@ -180,6 +192,43 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
         std::vector<int32_t> cs(n_cells + 1, 0);
         for (const RayRec& rr : gr) cs[rr.cell + 1]++;
         for (int64_t c = 0; c < n_cells; ++c) cs[c + 1] += cs[c];
+        // visit lists: for cell row ci and segment sg (columns [jlo, jhi)), sweep the base
+        // columns u = jlo-1 .. jhi-1; rays with base row ci-1 feed row ci with radial weight fr,
+        // rays with base row ci with 1 - fr; azimuthal weights (1-fphi) -> column u, fphi -> u+1.
+        const int nseg = (g.n_phi + VISIT_SEG - 1) / VISIT_SEG;
+        m.nseg = nseg;
+        m.visit_begin = (int64_t)visits.size();
+        m.vtask_begin = (int64_t)vtask.size();
+        for (int ci = 0; ci < g.n_r; ++ci) {
+            for (int sg = 0; sg < nseg; ++sg) {
+                vtask.push_back((int64_t)visits.size() - m.visit_begin);
+                const int jlo = sg * VISIT_SEG, jhi = std::min(jlo + VISIT_SEG, g.n_phi);
+                for (int c = 0; c <= jhi - jlo; ++c) {
+                    const int u = jlo - 1 + c;
+                    const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
+                    for (int part = 0; part < 2; ++part) {
+                        const int ib = part == 0 ? ci - 1 : ci;
+                        if (ib < 0 || ib > g.n_r - 2) continue;
+                        const int64_t cell = (int64_t)ib * g.n_phi + ub;
+                        for (int32_t q = cs[cell]; q < cs[cell + 1]; ++q) {
+                            const RayRec& rr = gr[q];
+                            const double wr = part == 0 ? (double)rr.fr : 1.0 - (double)rr.fr;
+                            Visit v;
+                            v.row = rr.row;
+                            v.k0 = rr.k0;
+                            v.th0 = rr.th0;
+                            v.wa = (float)((double)rr.w * wr * (1.0 - (double)rr.fphi));
+                            v.wb = (float)((double)rr.w * wr * (double)rr.fphi);
+                            v.col = c;
+                            v.order = rr.order;
+                            v.pad = 0;
+                            visits.push_back(v);
+                        }
+                    }
+                }
+            }
+        }
+        vtask.push_back((int64_t)visits.size() - m.visit_begin);
         cstart.insert(cstart.end(), cs.begin(), cs.end());
         recs.insert(recs.end(), gr.begin(), gr.end());
         m.n_rows = m.n_rays * g.n_frames;
@@ -190,6 +239,8 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
         col_off += m.n_cols;
         m.adj_variant = default_adjoint_variant(m);
         m.apply_variant = default_apply_variant(m);
+        m.digest = fnv1a(&g, sizeof(g));
+        m.digest = fnv1a(gr.data(), gr.size() * sizeof(RayRec), m.digest);
     }
     if (recs.empty()) return fail(RTT_EINVAL, "no rays");
 
@@ -201,18 +252,26 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     h->n_rays = (int64_t)recs.size();
     hipGetDevice(&h->device);
     size_t rb = recs.size() * sizeof(RayRec), cb = cstart.size() * sizeof(int32_t);
+    size_t vb = std::max<size_t>(visits.size(), 1) * sizeof(Visit), tb = vtask.size() * sizeof(int64_t);
     hipError_t e = hipMalloc((void**)&h->d_rays, rb);
     if (e == hipSuccess) e = hipMalloc((void**)&h->d_cell_start, cb);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->d_visits, vb);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->d_vtask, tb);
     if (e == hipSuccess) e = hipMemcpy(h->d_rays, recs.data(), rb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_cell_start, cstart.data(), cb, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !visits.empty())
+        e = hipMemcpy(h->d_visits, visits.data(), visits.size() * sizeof(Visit), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_vtask, vtask.data(), tb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "geometry_load upload");
         if (h->d_rays) hipFree(h->d_rays);
         if (h->d_cell_start) hipFree(h->d_cell_start);
+        if (h->d_visits) hipFree(h->d_visits);
+        if (h->d_vtask) hipFree(h->d_vtask);
         delete h;
         return rc;
     }
-    h->table_bytes = (int64_t)(rb + cb);
+    h->table_bytes = (int64_t)(rb + cb + vb + tb);
     *out = h;
     return RTT_OK;
 }
@@ -223,6 +282,8 @@ extern "C" int geometry_free(rtt_geometry* g)
     if (g->magic != 0x52545447u) return fail(RTT_ESTATE, "not a geometry handle");
     if (g->d_rays) hipFree(g->d_rays);
     if (g->d_cell_start) hipFree(g->d_cell_start);
+    if (g->d_visits) hipFree(g->d_visits);
+    if (g->d_vtask) hipFree(g->d_vtask);
     g->magic = 0;
     delete g;
     return RTT_OK;
@@ -250,7 +311,36 @@ extern "C" int geometry_member(const rtt_geometry* g, int32_t idx, rtt_member_in
     info->col_offset = m.col_offset;
     info->n_cols = m.n_cols;
     for (int n = 0; n < 8; ++n) info->rays_per_order[n] = m.rays_per_order[n];
+    info->apply_variant = m.apply_variant;
+    info->adjoint_variant = m.adj_variant;
+    info->digest = m.digest;
     return RTT_OK;
+}
+
+extern "C" int geometry_set_variant(rtt_geometry* g, int32_t idx, int32_t apply_variant, int32_t adjoint_variant)
+{
+    if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
+    if (idx < -1 || idx >= (int32_t)g->members.size()) return fail(RTT_EINVAL, "member index out of range");
+    if (apply_variant < -1 || apply_variant >= n_apply_variants()) return fail(RTT_EINVAL, "unknown apply variant");
+    if (adjoint_variant < -1 || adjoint_variant >= n_adjoint_variants())
+        return fail(RTT_EINVAL, "unknown adjoint variant");
+    for (int i = 0; i < (int)g->members.size(); ++i) {
+        if (idx >= 0 && i != idx) continue;
+        Member& m = g->members[i];
+        if ((apply_variant == 2 || apply_variant == 3) && m.P > m.Q)
+            return fail(RTT_EINVAL, "batch/stream forward variants need dt_obs <= dt_src");
+        if (apply_variant >= 0) m.apply_variant = apply_variant;
+        if (adjoint_variant == 11 && !visit_supported(m))
+            return fail(RTT_EINVAL, "visit adjoint variant needs dt_obs/dt_src = 1 or 1/2 and n_hat <= 512");
+        if (adjoint_variant >= 0) m.adj_variant = adjoint_variant;
+    }
+    return RTT_OK;
+}
+
+extern "C" const char* variant_name(int32_t adjoint, int32_t v)
+{
+    if (adjoint) return (v >= 0 && v < n_adjoint_variants()) ? adjoint_variant_name(v) : nullptr;
+    return (v >= 0 && v < n_apply_variants()) ? apply_variant_name(v) : nullptr;
 }
 
 extern "C" const char* last_error(void) { return g_err.c_str(); }

@@ -254,3 +254,59 @@ def test_batched_handle_is_block_diagonal(gpu_lib):
         ys = y[m["row_offset"]:m["row_offset"] + m["n_rows"]].astype(np.float64)
         assert rel(ya[m["row_offset"]:m["row_offset"] + m["n_rows"]], oracle.forward(geo, xs)) <= TOL
         assert rel(xa[m["col_offset"]:m["col_offset"] + m["n_cols"]], oracle.adjoint(geo, ys)) <= TOL
+
+
+VARIANT_CASES = {
+    "many_tiles": dict(seed=23, rays=(900, 200, 150), n_r=19, n_phi=21, n_frames=70),
+    "ratio_half": dict(seed=12, rays=(300, 50, 40), dt_obs=2.0, n_frames=90, n_r=7, n_phi=66),
+    "ratio3_4": dict(seed=22, rays=(300, 70), dt_obs=3.0, n_frames=41, n_r=5, n_phi=40),
+    "long_rows": dict(seed=26, rays=(200, 30, 20), n_frames=700, n_r=4, n_phi=9),
+    "ring1": dict(seed=24, rays=(40, 10), n_r=5, n_phi=1, n_frames=5),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANT_CASES))
+def test_every_kernel_variant_matches_oracle(gpu_lib, name):
+    rtt = gpu_lib
+    geo = tiny_geometry(**VARIANT_CASES[name])
+    say("case variants", name)
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(101)
+    X = rng.random((2, geo.grid.n_cols)).astype(np.float32)
+    Yv = rng.standard_normal((2, geo.n_rows)).astype(np.float32)
+    yr = oracle.forward(geo, X.astype(np.float64))
+    xr = oracle.adjoint(geo, Yv.astype(np.float64))
+    ratio_le1 = geo.grid.dt_obs <= geo.grid.dt_src or geo.grid.n_frames == 1
+    for v, vname in enumerate(rtt.variant_names(False)):
+        if vname in ("batch", "stream") and not ratio_le1:
+            continue
+        G.set_variant(apply=v)
+        ya = rtt.op_apply(G, to_dev(X)).cpu().numpy()
+        for b in range(2):
+            assert max(block_rel(geo, ya[b], yr[b])) <= TOL, (vname, b)
+    r = geo.grid.dt_obs / geo.grid.dt_src
+    visit_ok = (geo.grid.n_frames == 1 or abs(r - 1) < 1e-12 or abs(r - 0.5) < 1e-12) and geo.grid.n_hat <= 512
+    for v, vname in enumerate(rtt.variant_names(True)):
+        if vname == "visit" and not visit_ok:
+            continue
+        G.set_variant(adjoint=v)
+        xa = rtt.op_apply_adjoint(G, to_dev(Yv)).cpu().numpy()
+        xa2 = rtt.op_apply_adjoint(G, to_dev(Yv)).cpu().numpy()
+        assert np.array_equal(xa, xa2), vname
+        for b in range(2):
+            assert rel(xa[b], xr[b]) <= TOL, (vname, b)
+
+
+def test_autotuner_picks_a_valid_variant_and_caches(gpu_lib, tmp_path):
+    rtt = gpu_lib
+    geo, x = _cfg_case("cfg1")
+    G = rtt.Geometry(geo)
+    cache = tmp_path / "tune.txt"
+    choice = G.tune(nvec=2, reps=3, cache_path=cache)
+    assert len(choice) == 1 and 0 <= choice[0][0] < len(rtt.variant_names(False))
+    assert cache.read_text().strip()
+    G2 = rtt.Geometry(geo)
+    G2.set_variant(apply=0, adjoint=0)
+    assert G2.tune(nvec=2, reps=3, cache_path=cache) == choice      # cache hit
+    y = rtt.op_apply(G2, to_dev(x)).cpu().numpy()
+    assert rel(y, oracle.forward(geo, x.astype(np.float64))) <= TOL
