@@ -640,6 +640,164 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_batch(ApplyArgs a, int
 }
 
 // --------------------------------------------------------------------------------------------
+// A, lean form for dt_obs/dt_src = 1/Q (Q = 1, 2).  Per ray the wave reads a 48-byte record with
+// corner offsets and weights precomputed (no division, no weight arithmetic), stages the
+// combined series z over the chunk's hats in LDS (hats clamped into [0, K) for addressing and
+// masked with one compare; one buffer descriptor per x vector, the radial corner step in the
+// scalar offset), then writes the rows: 4 frames per lane from one 16-byte LDS read
+// plus one 4-byte read (Q = 1) or two 8-byte reads with the half-step weights of the ray
+// (Q = 2).  Frame chunks are 128 Q frames so the lane -> (ray, frame group) split is a shift.
+// --------------------------------------------------------------------------------------------
+struct LeanArgs {
+    const FwdRec* rec;
+    int64_t n_rays;
+    int K, F, nk;       // nk = n_phi * K (row offset of the i+1 corners)
+    const float* x;
+    float* y;
+    int64_t x_stride, y_stride;
+    int x_bytes;        // bytes of one coefficient vector
+    uint32_t mask;
+};
+
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
+{
+    constexpr int FC = 128 * Q;          // frames per chunk
+    constexpr int W = FC / Q + 4;        // hats staged per ray
+    constexpr int ZI = (W + WAVE - 1) / WAVE;
+    constexpr int ZS = ZI * WAVE;        // LDS row length (multiple of 4)
+    __shared__ __attribute__((aligned(16))) float zs_all[A_WAVES][NB][ZS];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r0 = (blk * A_WAVES + wave) * NB;
+    if (r0 >= a.n_rays) return;
+    const float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
+    float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
+    const int f0 = blockIdx.z * FC;
+    const int fend = min(a.F, f0 + FC);
+    float(*zs)[ZS] = zs_all[wave];
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
+
+    // phase 1: every record of the batch (independent scalar loads)
+    FwdRec rc[NB];
+    bool on[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int64_t ri = r0 + j;
+        rc[j] = a.rec[__builtin_amdgcn_readfirstlane((int)(ri < a.n_rays ? ri : r0))];
+    }
+    // phase 2: every gather of the batch
+    float xv[NB][ZI][4];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        on[j] = (r0 + j < a.n_rays) && ((a.mask >> rc[j].order) & 1u);
+        const int klo = rc[j].k0 + f0 / Q;
+        // The scalar offset is unsigned and not range checked: it only carries the
+        // non-negative row step n_phi*K.  The column step to the periodic neighbour can be
+        // negative (wrap at 2 pi), so it goes into the vector offset, which is an in-range
+        // element index of the x vector for every lane (hat clamped into [0, K)).
+        const int s10 = a.nk * 4;
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const int kc = min(max(klo + lane + it * WAVE, 0), a.K - 1);
+            const int off0 = (rc[j].c00k + kc) * 4;
+            const int off1 = off0 + rc[j].d01k * 4;
+            xv[j][it][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off0, 0, 0));
+            xv[j][it][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off0, s10, 0));
+            xv[j][it][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off1, 0, 0));
+            xv[j][it][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off1, s10, 0));
+        }
+    }
+    // phase 3: combined series into LDS (hats outside [0, K) and inactive rays give 0)
+    float th0[NB];
+    int row[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        th0[j] = rc[j].th0;
+        row[j] = rc[j].row;
+        const int klo = rc[j].k0 + f0 / Q;
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const int h = lane + it * WAVE;
+            const int k = klo + h;
+            const float z = rc[j].b00 * xv[j][it][0] + rc[j].b10 * xv[j][it][1] + rc[j].b01 * xv[j][it][2] +
+                            rc[j].b11 * xv[j][it][3];
+            const bool ok = on[j] && (unsigned)k < (unsigned)a.K;
+            if (h < W) zs[j][h] = ok ? z : 0.f;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    if (VEC4) {
+        constexpr int NG = FC / 4;               // frame groups per ray chunk: 32 (Q=1) or 64 (Q=2)
+        constexpr int RPP = WAVE / NG;           // rays per pass: 2 or 1
+#pragma unroll
+        for (int p = 0; p < NB / RPP; ++p) {
+            const int sub = (RPP == 2) ? (lane >> 5) : 0;
+            const int g = lane & (NG - 1);
+            const int jA = p * RPP, jB = p * RPP + RPP - 1;
+            const bool pickB = sub != 0;
+            const float th = pickB ? th0[jB] : th0[jA];
+            const int rw = pickB ? row[jB] : row[jA];
+            const bool active = pickB ? on[jB] : on[jA];
+            const int f = f0 + 4 * g;
+            const float* zr = &zs[0][0] + (pickB ? jB : jA) * ZS;
+            f4 v;
+            if (Q == 1) {
+                const f4 z4 = *(const f4*)(zr + 4 * g);
+                const float z5 = zr[4 * g + 4];
+                v[0] = z4[0] + th * (z4[1] - z4[0]);
+                v[1] = z4[1] + th * (z4[2] - z4[1]);
+                v[2] = z4[2] + th * (z4[3] - z4[2]);
+                v[3] = z4[3] + th * (z5 - z4[3]);
+            } else {
+                typedef float f2 __attribute__((ext_vector_type(2)));
+                const f2 za = *(const f2*)(zr + 2 * g);
+                const f2 zb = *(const f2*)(zr + 2 * g + 2);
+                const float z0 = za[0], z1 = za[1], z2 = zb[0], z3 = zb[1];
+                const bool c1 = th >= 0.5f;
+                const float th1 = c1 ? th - 0.5f : th + 0.5f;
+                const float a1 = c1 ? z1 : z0, b1 = c1 ? z2 : z1;
+                const float a3 = c1 ? z2 : z1, b3 = c1 ? z3 : z2;
+                v[0] = z0 + th * (z1 - z0);
+                v[1] = a1 + th1 * (b1 - a1);
+                v[2] = z1 + th * (z2 - z1);
+                v[3] = a3 + th1 * (b3 - a3);
+            }
+            if (active && f < fend) __builtin_nontemporal_store(v, (f4*)(y + (int64_t)rw * a.F + f));
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (!on[j]) continue;
+            float* yr = y + (int64_t)row[j] * a.F;
+#pragma unroll
+            for (int t = 0; t < FC / WAVE; ++t) {
+                const int q = lane + t * WAVE;
+                const int f = f0 + q;
+                if (f >= fend) continue;
+                int jz;
+                float th;
+                if (Q == 1) {
+                    jz = q;
+                    th = th0[j];
+                } else {
+                    const bool odd = q & 1;
+                    const bool c1 = th0[j] >= 0.5f;
+                    jz = (q >> 1) + ((odd && c1) ? 1 : 0);
+                    th = odd ? (c1 ? th0[j] - 0.5f : th0[j] + 0.5f) : th0[j];
+                }
+                const float za = zs[j][jz], zb = zs[j][jz + 1];
+                __builtin_nontemporal_store(za + th * (zb - za), yr + f);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------------------------
 // A^T, visit-list form (dt_obs/dt_src = 1/Q).  A wave owns cell row ci and a segment of
 // VISIT_SEG columns, and all hats (V per lane).  Its visit list (built at load time) holds, in
 // sweep order, every ray that touches the row inside the segment with the row's weights
@@ -665,10 +823,36 @@ __device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, int byte
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
-template <int Q, int V, int NB>
+// Tap weights of one visit: frame f = Q (k - k0) + MLO + t feeds hat k with weight
+// 1 - |th0 + (MLO + t)/Q| (zero outside the hat).  Q = 1: taps m = -1, 0.  Q = 2: taps
+// m = -4 .. 1 (six, the first always zero) so that frames come in aligned pairs.
+template <int Q>
+struct Taps {
+    static constexpr int MLO = Q == 1 ? -1 : -4;
+    static constexpr int T = Q == 1 ? 2 : 6;
+    __device__ __forceinline__ static void weights(float th0, float* w)
+    {
+        if (Q == 1) {
+            w[0] = th0;
+            w[1] = 1.0f - th0;
+        } else {
+            const bool hi = th0 >= 0.5f;
+            w[0] = 0.f;                                   // m = -4
+            w[1] = hi ? th0 - 0.5f : 0.f;                 // m = -3
+            w[2] = th0;                                   // m = -2
+            w[3] = hi ? 1.5f - th0 : 0.5f + th0;          // m = -1
+            w[4] = 1.0f - th0;                            // m =  0
+            w[5] = hi ? 0.f : 0.5f - th0;                 // m =  1
+        }
+    }
+};
+
+template <int Q, int V, int NB, bool PAIR>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
-    constexpr int T = 2 * Q;
+    typedef Taps<Q> TP_;
+    constexpr int T = TP_::T;
+    typedef float f2 __attribute__((ext_vector_type(2)));
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
@@ -684,6 +868,7 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
     const float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
     float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
     const int rowbytes = a.F * 4;
+    const int lane_off = Q * lane * 4;   // per-lane part of every frame offset
 
     float acc_a[V], acc_b[V];
 #pragma unroll
@@ -707,7 +892,6 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
     };
 
     for (int64_t e0 = vbeg; e0 < vend; e0 += NB) {
-        // one visit record per lane j < NB
         int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
         if (lane < NB && e0 + lane < vend) {
             const int4* vp = (const int4*)(a.visits + e0 + lane);
@@ -727,23 +911,30 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
             vcol[j] = valid ? __builtin_amdgcn_readlane(r1.y, j) : ncol;
             const int order = __builtin_amdgcn_readlane(r1.z, j);
             const bool on = valid && ((a.mask >> order) & 1u);
-            // a zero-sized range makes every load of a skipped visit return 0 without touching memory
+            // zero-sized range for skipped visits: their loads return 0 without touching memory
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc((void*)(y + (int64_t)row * a.F), (short)0, on ? rowbytes : 0,
                                                   0x00020000);
-            const int mlo = (int)floorf(-(float)Q - (float)Q * th0) + 1;
-#pragma unroll
-            for (int t = 0; t < T; ++t)
-                tw[j][t] = fmaxf(0.f, 1.0f - fabsf(th0 + (float)(mlo + t) * (1.0f / (float)Q)));
+            TP_::weights(th0, tw[j]);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int base = Q * (lane + WAVE * v - k0) + mlo;
+                const int ub = (Q * (WAVE * v - k0) + TP_::MLO) * 4;   // uniform part of the offset
+                if (PAIR) {
 #pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    // frames before the row give negative offsets; clamp their unsigned value far
-                    // below 2^32 so that offset + 4 cannot wrap back into the row's range
-                    const unsigned off = min((unsigned)((base + t) * 4), 0x7FFFFFF0u);
-                    yv[j][v][t] = buf_load_f32(rs, (int)off);
+                    for (int t = 0; t < T; t += 2) {
+                        // frames before the row: clamp the unsigned offset far below 2^32 so that
+                        // offset + 8 cannot wrap back into the row's range
+                        const unsigned off = min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u);
+                        const f2 p = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+                        yv[j][v][t] = p[0];
+                        yv[j][v][t + 1] = p[1];
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        const unsigned off = min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u);
+                        yv[j][v][t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                    }
                 }
             }
         }
@@ -1061,11 +1252,15 @@ constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 4; }
+int n_apply_variants() { return 6; }
 const char* apply_variant_name(int v)
 {
-    static const char* names[] = {"rpw1", "rpw2", "batch", "stream"};
+    static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8"};
     return names[v];
+}
+bool lean_supported(const Member& m)
+{
+    return m.P == 1 && (m.Q == 1 || m.Q == 2) && (int64_t)m.grid.n_r * m.grid.n_phi * m.grid.n_hat < (1ll << 29);
 }
 
 bool visit_supported(const Member& m) { return m.P == 1 && (m.Q == 1 || m.Q == 2) && m.grid.n_hat <= 512; }
@@ -1075,7 +1270,7 @@ int default_adjoint_variant(const Member& m)
     if (visit_supported(m)) return 11;
     return 2;
 }
-int default_apply_variant(const Member& m) { return m.P <= m.Q ? 3 : 1; }
+int default_apply_variant(const Member& m) { return lean_supported(m) ? 4 : (m.P <= m.Q ? 2 : 1); }
 
 template <int TP, int TQ, int NB, int ZI>
 static void apply_batch_launch(const ApplyArgs& a, int nvec, hipStream_t s)
@@ -1142,10 +1337,47 @@ static void apply_dispatch(const ApplyArgs& a, int nvec, int variant, hipStream_
         hipLaunchKernelGGL((k_apply<TP, TQ, 1>), grid, dim3(A_WAVES * WAVE), 0, s, a);
 }
 
+template <int Q, int NB>
+static void lean_launch(const LeanArgs& a, int nvec, bool vec4, hipStream_t s)
+{
+    const int64_t rays_per_block = (int64_t)A_WAVES * NB;
+    const int nch = (a.F + 128 * Q - 1) / (128 * Q);
+    dim3 grid((unsigned)((a.n_rays + rays_per_block - 1) / rays_per_block), (unsigned)nvec, (unsigned)nch);
+    if (vec4) hipLaunchKernelGGL((k_apply_lean<Q, NB, true>), grid, dim3(A_WAVES * WAVE), 0, s, a);
+    else hipLaunchKernelGGL((k_apply_lean<Q, NB, false>), grid, dim3(A_WAVES * WAVE), 0, s, a);
+}
+
 int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* y, int nvec,
                  int64_t x_stride, int64_t y_stride, uint32_t mask, hipStream_t s, int variant)
 {
     if (m.n_rays == 0 || nvec == 0) return RTT_OK;
+    if (variant < 0 || variant >= n_apply_variants()) variant = m.apply_variant;
+    if ((variant == 4 || variant == 5) && !lean_supported(m)) variant = m.P <= m.Q ? 2 : 1;
+    if (variant == 4 || variant == 5) {
+        LeanArgs la;
+        la.rec = g->d_fwd + m.ray_begin;
+        la.n_rays = m.n_rays;
+        la.K = m.grid.n_hat;
+        la.F = m.grid.n_frames;
+        la.nk = m.grid.n_phi * m.grid.n_hat;
+        la.x = x;
+        la.y = y;
+        la.x_stride = x_stride;
+        la.y_stride = y_stride;
+        la.x_bytes = (int)(m.n_cols * 4);
+        la.mask = mask;
+        // float4 rows need F % 4 == 0 and 16-byte aligned vectors
+        const bool vec4 = (la.F % 4) == 0 && (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (y_stride % 4) == 0);
+        if (m.Q == 1) {
+            if (variant == 4) lean_launch<1, 4>(la, nvec, vec4, s);
+            else lean_launch<1, 8>(la, nvec, vec4, s);
+        } else {
+            if (variant == 4) lean_launch<2, 4>(la, nvec, vec4, s);
+            else lean_launch<2, 8>(la, nvec, vec4, s);
+        }
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     ApplyArgs a;
     a.rays = g->d_rays + m.ray_begin;
     a.n_rays = m.n_rays;
@@ -1210,22 +1442,22 @@ static void adjoint_dispatch_sweep(const AdjArgs& a, int P, int Q, int nvec, hip
         hipLaunchKernelGGL((k_adjoint_sweep<0, 0, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, int V, int NB>
+template <int Q, int V, int NB, bool PAIR>
 static void visit_launch(const VisitArgs& a, int nvec, hipStream_t s)
 {
     const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB>), dim3((unsigned)blocks, (unsigned)nvec), dim3(T_WAVES * WAVE), 0, s,
-                       a);
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR>), dim3((unsigned)blocks, (unsigned)nvec),
+                       dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q>
+template <int Q, bool PAIR>
 static void visit_dispatch(const VisitArgs& a, int nvec, hipStream_t s)
 {
     constexpr int NB1 = Q == 1 ? 8 : 4;
-    if (a.K <= 64) visit_launch<Q, 1, NB1>(a, nvec, s);
-    else if (a.K <= 128) visit_launch<Q, 2, NB1>(a, nvec, s);
-    else if (a.K <= 256) visit_launch<Q, 4, Q == 1 ? 4 : 2>(a, nvec, s);
-    else visit_launch<Q, 8, 2>(a, nvec, s);
+    if (a.K <= 64) visit_launch<Q, 1, NB1, PAIR>(a, nvec, s);
+    else if (a.K <= 128) visit_launch<Q, 2, NB1, PAIR>(a, nvec, s);
+    else if (a.K <= 256) visit_launch<Q, 4, Q == 1 ? 4 : 2, PAIR>(a, nvec, s);
+    else visit_launch<Q, 8, 2, PAIR>(a, nvec, s);
 }
 
 int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float* x, int nvec,
@@ -1263,8 +1495,11 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         va.y_stride = y_stride;
         va.x_stride = x_stride;
         va.mask = mask;
-        if (m.Q == 1) visit_dispatch<1>(va, nvec, s);
-        else visit_dispatch<2>(va, nvec, s);
+        // frame pairs need 8-byte aligned rows: even n_frames and aligned data vectors
+        const bool pair = (va.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
+        if (m.Q == 1) visit_dispatch<1, false>(va, nvec, s);
+        else if (pair) visit_dispatch<2, true>(va, nvec, s);
+        else visit_dispatch<2, false>(va, nvec, s);
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }

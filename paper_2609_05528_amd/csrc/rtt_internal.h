@@ -43,6 +43,20 @@ struct alignas(16) Visit {
 static_assert(sizeof(Visit) == 32, "Visit must be 32 bytes");
 constexpr int VISIT_SEG = 16;   // columns per sweep segment
 
+// Forward record of one ray (48 bytes): corner offsets and weights precomputed so
+// the forward kernel does no integer division and no weight arithmetic.
+struct alignas(16) FwdRec {
+    int32_t c00k;   // (i*n_phi + j0) * n_hat: start of the x row of corner (i, j0)
+    int32_t d01k;   // (cell(i, j0+1) - cell(i, j0)) * n_hat (periodic wrap folded in)
+    float b00, b10, b01, b11;   // bilinear weights times the transfer weight
+    int32_t k0;     // hat origin of frame 0
+    float th0;      // fraction of frame 0
+    int32_t row;    // caller ray index
+    int32_t order;  // image order
+    int32_t pad0, pad1;
+};
+static_assert(sizeof(FwdRec) == 48, "FwdRec must be 48 bytes");
+
 // One geometry of a handle, as the kernels see it.
 struct Member {
     rtt_grid grid;
@@ -68,6 +82,7 @@ struct rtt_geometry {
     rtt::RayRec* d_rays = nullptr;      // all members, each sorted by base cell
     int32_t* d_cell_start = nullptr;    // per member CSR over base cells (relative to ray_begin)
     rtt::Visit* d_visits = nullptr;     // per member visit lists (cell row x segment tasks)
+    rtt::FwdRec* d_fwd = nullptr;       // forward records, same order as d_rays
     int64_t* d_vtask = nullptr;         // per member task offsets into the visit lists
     int64_t n_rows = 0, n_cols = 0, n_rays = 0;
     int64_t table_bytes = 0;
@@ -103,6 +118,7 @@ const char* apply_variant_name(int v);
 int default_adjoint_variant(const Member& m);
 int default_apply_variant(const Member& m);
 bool visit_supported(const Member& m);
+bool lean_supported(const Member& m);
 
 uint32_t effective_mask(const Member& m, uint32_t mask);
 

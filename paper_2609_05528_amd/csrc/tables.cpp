@@ -112,6 +112,7 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     std::vector<int32_t> cstart;
     std::vector<Visit> visits;
     std::vector<int64_t> vtask;
+    std::vector<FwdRec> fwd;
     int64_t row_off = 0, col_off = 0, map_idx = 0;
     const double two_pi = 6.283185307179586476925286766559;
 
@@ -229,6 +230,25 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
             }
         }
         vtask.push_back((int64_t)visits.size() - m.visit_begin);
+        for (const RayRec& rr : gr) {
+            const int i = rr.cell / g.n_phi, j0 = rr.cell % g.n_phi;
+            const int j1 = (j0 + 1 == g.n_phi) ? 0 : j0 + 1;
+            FwdRec f;
+            f.c00k = rr.cell * g.n_hat;
+            f.d01k = (j1 - j0) * g.n_hat;
+            const double fr = rr.fr, fp = rr.fphi, w = rr.w;
+            f.b00 = (float)(w * (1.0 - fr) * (1.0 - fp));
+            f.b10 = (float)(w * fr * (1.0 - fp));
+            f.b01 = (float)(w * (1.0 - fr) * fp);
+            f.b11 = (float)(w * fr * fp);
+            f.k0 = rr.k0;
+            f.th0 = rr.th0;
+            f.row = rr.row;
+            f.order = rr.order;
+            f.pad0 = f.pad1 = 0;
+            fwd.push_back(f);
+            (void)i;
+        }
         cstart.insert(cstart.end(), cs.begin(), cs.end());
         recs.insert(recs.end(), gr.begin(), gr.end());
         m.n_rows = m.n_rays * g.n_frames;
@@ -257,6 +277,9 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     if (e == hipSuccess) e = hipMalloc((void**)&h->d_cell_start, cb);
     if (e == hipSuccess) e = hipMalloc((void**)&h->d_visits, vb);
     if (e == hipSuccess) e = hipMalloc((void**)&h->d_vtask, tb);
+    const size_t fb = fwd.size() * sizeof(FwdRec);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->d_fwd, fb);
+    if (e == hipSuccess) e = hipMemcpy(h->d_fwd, fwd.data(), fb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_rays, recs.data(), rb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_cell_start, cstart.data(), cb, hipMemcpyHostToDevice);
     if (e == hipSuccess && !visits.empty())
@@ -268,10 +291,11 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
         if (h->d_cell_start) hipFree(h->d_cell_start);
         if (h->d_visits) hipFree(h->d_visits);
         if (h->d_vtask) hipFree(h->d_vtask);
+        if (h->d_fwd) hipFree(h->d_fwd);
         delete h;
         return rc;
     }
-    h->table_bytes = (int64_t)(rb + cb + vb + tb);
+    h->table_bytes = (int64_t)(rb + cb + vb + tb + fb);
     *out = h;
     return RTT_OK;
 }
@@ -284,6 +308,7 @@ extern "C" int geometry_free(rtt_geometry* g)
     if (g->d_cell_start) hipFree(g->d_cell_start);
     if (g->d_visits) hipFree(g->d_visits);
     if (g->d_vtask) hipFree(g->d_vtask);
+    if (g->d_fwd) hipFree(g->d_fwd);
     g->magic = 0;
     delete g;
     return RTT_OK;
@@ -329,6 +354,8 @@ extern "C" int geometry_set_variant(rtt_geometry* g, int32_t idx, int32_t apply_
         Member& m = g->members[i];
         if ((apply_variant == 2 || apply_variant == 3) && m.P > m.Q)
             return fail(RTT_EINVAL, "batch/stream forward variants need dt_obs <= dt_src");
+        if ((apply_variant == 4 || apply_variant == 5) && !lean_supported(m))
+            return fail(RTT_EINVAL, "lean forward variants need dt_obs/dt_src = 1 or 1/2");
         if (apply_variant >= 0) m.apply_variant = apply_variant;
         if (adjoint_variant == 11 && !visit_supported(m))
             return fail(RTT_EINVAL, "visit adjoint variant needs dt_obs/dt_src = 1 or 1/2 and n_hat <= 512");
