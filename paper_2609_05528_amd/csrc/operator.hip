@@ -798,8 +798,8 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
 }
 
 // --------------------------------------------------------------------------------------------
-// A^T, visit-list form (dt_obs/dt_src = 1/Q).  A wave owns cell row ci and a segment of
-// VISIT_SEG columns, and all hats (V per lane).  Its visit list (built at load time) holds, in
+// A^T, visit-list form (dt_obs/dt_src = 1/Q).  A wave owns cell row ci, a segment of vseg
+// columns and a chunk of 64 V hats (V per lane).  Its visit list (built at load time) holds, in
 // sweep order, every ray that touches the row inside the segment with the row's weights
 // already folded in.  The wave fetches NB visit records with one vector load, reads each ray's
 // data row through a buffer descriptor whose range is exactly the row (out-of-range frames read
@@ -811,7 +811,8 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
 struct VisitArgs {
     const Visit* visits;
     const int64_t* vtask;
-    int n_r, n_phi, K, F, nseg;
+    int n_r, n_phi, K, F, nseg, vseg;
+    int kchunks;        // hat chunks of 64*V hats (one per wave)
     const float* y;
     float* x;
     int64_t y_stride, x_stride;
@@ -856,15 +857,18 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
-    const int64_t lin = xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg);
-    const int sg = (int)(lin % a.nseg), rg = (int)(lin / a.nseg);
+    const int64_t lin = xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks);
+    const int kch = (int)(lin % a.kchunks);
+    const int64_t l2 = lin / a.kchunks;
+    const int sg = (int)(l2 % a.nseg), rg = (int)(l2 / a.nseg);
     const int ci = rg * T_WAVES + wave;
     if (ci >= a.n_r) return;
     const int64_t task = (int64_t)ci * a.nseg + sg;
     const int64_t vbeg = a.vtask[task], vend = a.vtask[task + 1];
-    const int jlo = sg * VISIT_SEG;
-    const int jhi = min(jlo + VISIT_SEG, a.n_phi);
+    const int jlo = sg * a.vseg;
+    const int jhi = min(jlo + a.vseg, a.n_phi);
     const int ncol = jhi - jlo + 1;
+    const int kc = kch * WAVE * V;       // first hat of this wave's chunk
     const float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
     float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
     const int rowbytes = a.F * 4;
@@ -879,7 +883,7 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
             float* xr = x + (int64_t)(ci * a.n_phi + (jlo - 1 + col)) * a.K;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int k = lane + WAVE * v;
+                const int k = kc + lane + WAVE * v;
                 if (k < a.K) xr[k] = acc_a[v];
             }
         }
@@ -891,12 +895,21 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
         ++col;
     };
 
+    // visit records of the first batch; each iteration prefetches the next batch's records
+    int4 n0 = make_int4(0, 0, 0, 0), n1 = make_int4(0, 0, 0, 0);
+    if (lane < NB && vbeg + lane < vend) {
+        const int4* vp = (const int4*)(a.visits + vbeg + lane);
+        n0 = vp[0];
+        n1 = vp[1];
+    }
     for (int64_t e0 = vbeg; e0 < vend; e0 += NB) {
-        int4 r0 = make_int4(0, 0, 0, 0), r1 = make_int4(0, 0, 0, 0);
-        if (lane < NB && e0 + lane < vend) {
-            const int4* vp = (const int4*)(a.visits + e0 + lane);
-            r0 = vp[0];
-            r1 = vp[1];
+        const int4 r0 = n0, r1 = n1;
+        n0 = make_int4(0, 0, 0, 0);
+        n1 = make_int4(0, 0, 0, 0);
+        if (lane < NB && e0 + NB + lane < vend) {
+            const int4* vp = (const int4*)(a.visits + e0 + NB + lane);
+            n0 = vp[0];
+            n1 = vp[1];
         }
         float yv[NB][V][T], tw[NB][T], wa[NB], wb[NB];
         int vcol[NB];
@@ -911,14 +924,19 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
             vcol[j] = valid ? __builtin_amdgcn_readlane(r1.y, j) : ncol;
             const int order = __builtin_amdgcn_readlane(r1.z, j);
             const bool on = valid && ((a.mask >> order) & 1u);
-            // zero-sized range for skipped visits: their loads return 0 without touching memory
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc((void*)(y + (int64_t)row * a.F), (short)0, on ? rowbytes : 0,
-                                                  0x00020000);
+            // zero-sized range for skipped visits: their loads return 0 without touching memory.
+            // The descriptor fields are made provably uniform (scalar registers), otherwise every
+            // buffer load would be wrapped in a per-lane waterfall loop.
+            const uint64_t base = (uint64_t)(y + (int64_t)row * a.F);
+            const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+            const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+            const int nrec = __builtin_amdgcn_readfirstlane(on ? rowbytes : 0);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(((uint64_t)bhi << 32) | blo), (short)0, nrec, 0x00020000);
             TP_::weights(th0, tw[j]);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int ub = (Q * (WAVE * v - k0) + TP_::MLO) * 4;   // uniform part of the offset
+                const int ub = (Q * (kc + WAVE * v - k0) + TP_::MLO) * 4;   // uniform part of the offset
                 if (PAIR) {
 #pragma unroll
                     for (int t = 0; t < T; t += 2) {
@@ -1237,7 +1255,7 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_sweep(AdjArgs a)
 // launchers
 // --------------------------------------------------------------------------------------------
 // Adjoint variants: 0-2 LDS tile kernels, 3-6 sweep kernels (TC column segment, V hats per lane),
-// 7-10 batched LDS tile kernels, 11 visit-list kernel (dt_obs/dt_src = 1 or 1/2, n_hat <= 512).
+// 7-10 batched LDS tile kernels, 11 visit-list kernel (dt_obs/dt_src = 1 or 1/2).
 struct AdjVariant {
     const char* name;
     int kind;   // 0 tile, 1 sweep, 2 batched tile
@@ -1263,7 +1281,7 @@ bool lean_supported(const Member& m)
     return m.P == 1 && (m.Q == 1 || m.Q == 2) && (int64_t)m.grid.n_r * m.grid.n_phi * m.grid.n_hat < (1ll << 29);
 }
 
-bool visit_supported(const Member& m) { return m.P == 1 && (m.Q == 1 || m.Q == 2) && m.grid.n_hat <= 512; }
+bool visit_supported(const Member& m) { return m.P == 1 && (m.Q == 1 || m.Q == 2); }
 
 int default_adjoint_variant(const Member& m)
 {
@@ -1443,9 +1461,10 @@ static void adjoint_dispatch_sweep(const AdjArgs& a, int P, int Q, int nvec, hip
 }
 
 template <int Q, int V, int NB, bool PAIR>
-static void visit_launch(const VisitArgs& a, int nvec, hipStream_t s)
+static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
-    const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg;
+    a.kchunks = (a.K + WAVE * V - 1) / (WAVE * V);
+    const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
     hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR>), dim3((unsigned)blocks, (unsigned)nvec),
                        dim3(T_WAVES * WAVE), 0, s, a);
 }
@@ -1454,7 +1473,10 @@ template <int Q, bool PAIR>
 static void visit_dispatch(const VisitArgs& a, int nvec, hipStream_t s)
 {
     constexpr int NB1 = Q == 1 ? 8 : 4;
-    if (a.K <= 64) visit_launch<Q, 1, NB1, PAIR>(a, nvec, s);
+    // enough waves to fill the chip with one wave per (row, segment): cover all hats per wave;
+    // otherwise split the hats into 64-hat chunks, one per wave
+    const int64_t waves = (int64_t)a.n_r * a.nseg * nvec;
+    if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 8, PAIR>(a, nvec, s);
     else if (a.K <= 128) visit_launch<Q, 2, NB1, PAIR>(a, nvec, s);
     else if (a.K <= 256) visit_launch<Q, 4, Q == 1 ? 4 : 2, PAIR>(a, nvec, s);
     else visit_launch<Q, 8, 2, PAIR>(a, nvec, s);
@@ -1482,14 +1504,17 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
     if (variant < 0 || variant >= n_adjoint_variants()) variant = m.adj_variant;
     if (variant == 11 && !visit_supported(m)) variant = 2;
     if (variant == 11) {
+        // the wide segment set when the vectors alone give enough waves, else the narrow one
+        const int set = ((int64_t)m.grid.n_r * m.nseg[0] * nvec >= 16384) ? 0 : 1;
         VisitArgs va;
-        va.visits = g->d_visits + m.visit_begin;
-        va.vtask = g->d_vtask + m.vtask_begin;
+        va.visits = g->d_visits + m.visit_begin[set];
+        va.vtask = g->d_vtask + m.vtask_begin[set];
         va.n_r = m.grid.n_r;
         va.n_phi = m.grid.n_phi;
         va.K = m.grid.n_hat;
         va.F = m.grid.n_frames;
-        va.nseg = m.nseg;
+        va.nseg = m.nseg[set];
+        va.vseg = m.vseg[set];
         va.y = y;
         va.x = x;
         va.y_stride = y_stride;

@@ -41,7 +41,7 @@ struct alignas(16) Visit {
     int32_t pad;
 };
 static_assert(sizeof(Visit) == 32, "Visit must be 32 bytes");
-constexpr int VISIT_SEG = 16;   // columns per sweep segment
+constexpr int VISIT_SEG_MAX = 16;   // widest sweep segment (columns)
 
 // Forward record of one ray (48 bytes): corner offsets and weights precomputed so
 // the forward kernel does no integer division and no weight arithmetic.
@@ -70,9 +70,12 @@ struct Member {
     int32_t adj_variant;   // adjoint kernel variant (default heuristic or autotuner)
     int32_t apply_variant; // forward kernel variant
     uint64_t digest;       // FNV-1a of the grid and this member's device records
-    int64_t visit_begin;   // first visit record of this member
-    int64_t vtask_begin;   // first entry of the task offsets (n_r * nseg + 1 entries)
-    int32_t nseg;          // sweep segments per cell row
+    // two visit-list sets: [0] 16-column segments (many vectors per call), [1] narrower
+    // segments chosen so one vector alone gives enough (row, segment) tasks
+    int64_t visit_begin[2];  // first visit record of each set
+    int64_t vtask_begin[2];  // first entry of each set's task offsets (n_r * nseg + 1 entries)
+    int32_t nseg[2];         // sweep segments per cell row
+    int32_t vseg[2];         // columns per sweep segment
 };
 
 }  // namespace rtt

@@ -196,40 +196,48 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
         // visit lists: for cell row ci and segment sg (columns [jlo, jhi)), sweep the base
         // columns u = jlo-1 .. jhi-1; rays with base row ci-1 feed row ci with radial weight fr,
         // rays with base row ci with 1 - fr; azimuthal weights (1-fphi) -> column u, fphi -> u+1.
-        const int nseg = (g.n_phi + VISIT_SEG - 1) / VISIT_SEG;
-        m.nseg = nseg;
-        m.visit_begin = (int64_t)visits.size();
-        m.vtask_begin = (int64_t)vtask.size();
-        for (int ci = 0; ci < g.n_r; ++ci) {
-            for (int sg = 0; sg < nseg; ++sg) {
-                vtask.push_back((int64_t)visits.size() - m.visit_begin);
-                const int jlo = sg * VISIT_SEG, jhi = std::min(jlo + VISIT_SEG, g.n_phi);
-                for (int c = 0; c <= jhi - jlo; ++c) {
-                    const int u = jlo - 1 + c;
-                    const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
-                    for (int part = 0; part < 2; ++part) {
-                        const int ib = part == 0 ? ci - 1 : ci;
-                        if (ib < 0 || ib > g.n_r - 2) continue;
-                        const int64_t cell = (int64_t)ib * g.n_phi + ub;
-                        for (int32_t q = cs[cell]; q < cs[cell + 1]; ++q) {
-                            const RayRec& rr = gr[q];
-                            const double wr = part == 0 ? (double)rr.fr : 1.0 - (double)rr.fr;
-                            Visit v;
-                            v.row = rr.row;
-                            v.k0 = rr.k0;
-                            v.th0 = rr.th0;
-                            v.wa = (float)((double)rr.w * wr * (1.0 - (double)rr.fphi));
-                            v.wb = (float)((double)rr.w * wr * (double)rr.fphi);
-                            v.col = c;
-                            v.order = rr.order;
-                            v.pad = 0;
-                            visits.push_back(v);
+        // segment widths: set 0 uses 16 columns; set 1 the widest of 16/8/4 columns that still
+        // gives >= 2048 (row, segment) tasks for a single vector
+        int narrow = VISIT_SEG_MAX;
+        while (narrow > 4 && (int64_t)g.n_r * ((g.n_phi + narrow - 1) / narrow) < 2048) narrow /= 2;
+        for (int set = 0; set < 2; ++set) {
+            const int vseg = set == 0 ? VISIT_SEG_MAX : narrow;
+            const int nseg = (g.n_phi + vseg - 1) / vseg;
+            m.nseg[set] = nseg;
+            m.vseg[set] = vseg;
+            m.visit_begin[set] = (int64_t)visits.size();
+            m.vtask_begin[set] = (int64_t)vtask.size();
+            for (int ci = 0; ci < g.n_r; ++ci) {
+                for (int sg = 0; sg < nseg; ++sg) {
+                    vtask.push_back((int64_t)visits.size() - m.visit_begin[set]);
+                    const int jlo = sg * vseg, jhi = std::min(jlo + vseg, g.n_phi);
+                    for (int c = 0; c <= jhi - jlo; ++c) {
+                        const int u = jlo - 1 + c;
+                        const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
+                        for (int part = 0; part < 2; ++part) {
+                            const int ib = part == 0 ? ci - 1 : ci;
+                            if (ib < 0 || ib > g.n_r - 2) continue;
+                            const int64_t cell = (int64_t)ib * g.n_phi + ub;
+                            for (int32_t q = cs[cell]; q < cs[cell + 1]; ++q) {
+                                const RayRec& rr = gr[q];
+                                const double wr = part == 0 ? (double)rr.fr : 1.0 - (double)rr.fr;
+                                Visit v;
+                                v.row = rr.row;
+                                v.k0 = rr.k0;
+                                v.th0 = rr.th0;
+                                v.wa = (float)((double)rr.w * wr * (1.0 - (double)rr.fphi));
+                                v.wb = (float)((double)rr.w * wr * (double)rr.fphi);
+                                v.col = c;
+                                v.order = rr.order;
+                                v.pad = 0;
+                                visits.push_back(v);
+                            }
                         }
                     }
                 }
             }
+            vtask.push_back((int64_t)visits.size() - m.visit_begin[set]);
         }
-        vtask.push_back((int64_t)visits.size() - m.visit_begin);
         for (const RayRec& rr : gr) {
             const int i = rr.cell / g.n_phi, j0 = rr.cell % g.n_phi;
             const int j1 = (j0 + 1 == g.n_phi) ? 0 : j0 + 1;
@@ -358,7 +366,7 @@ extern "C" int geometry_set_variant(rtt_geometry* g, int32_t idx, int32_t apply_
             return fail(RTT_EINVAL, "lean forward variants need dt_obs/dt_src = 1 or 1/2");
         if (apply_variant >= 0) m.apply_variant = apply_variant;
         if (adjoint_variant == 11 && !visit_supported(m))
-            return fail(RTT_EINVAL, "visit adjoint variant needs dt_obs/dt_src = 1 or 1/2 and n_hat <= 512");
+            return fail(RTT_EINVAL, "visit adjoint variant needs dt_obs/dt_src = 1 or 1/2");
         if (adjoint_variant >= 0) m.adj_variant = adjoint_variant;
     }
     return RTT_OK;
