@@ -28,6 +28,14 @@ sys.path.insert(0, ROOT)
 METRIC = "A+A^T applies/sec and HBM GB/s; batched vs plain at 1e-5 rel err"
 HBM_PEAK_GBPS = 8000.0
 RAY_RECORD_BYTES = 32
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip")
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on this workload
+# (FETCH_SIZE scaled by 2.0, the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only
+# for the kernel source digest they were taken on (see profiles/).
+MEASURED_TRAFFIC = {
+    "op_apply_adjoint": {"bytes": 2553542083, "digest": "9c26ad0db9fe5f6f", "nvec": 264},
+    "op_apply": {"bytes": 2104417208, "digest": "9c26ad0db9fe5f6f", "nvec": 264},
+}
 
 
 def log(*a):
@@ -40,6 +48,30 @@ def algorithmic_bytes(n_rows, n_cols, n_rays, n_cells, n_orders, nvec, adjoint):
     if adjoint:
         b += 4 * (n_cells + 1)
     return b
+
+
+def source_digest():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def time_pair(torch, rtt, G, X, Y, XT, reps=10):
+    """Average kernel time (ms) of op_apply and of op_apply_adjoint, each over `reps`
+    back-to-back launches bracketed by HIP events on the current stream."""
+    rtt.op_apply(G, X, Y)
+    rtt.op_apply_adjoint(G, Y, XT)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        rtt.op_apply(G, X, Y)
+    e[1].record()
+    for _ in range(reps):
+        rtt.op_apply_adjoint(G, Y, XT)
+    e[2].record()
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
 
 
 def calibrate(torch, dev, gib=2):
@@ -78,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-rsvd", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -190,6 +224,50 @@ def main():
                "sample": "one full step: %d A + %d A^T FP64 applies (plain C, single thread), %.1f s"
                          % (n_s, n_s, tc)}
 
+    # the large single geometry (512^2 x 512 frames, orders 0-2): one vector per launch
+    large = None
+    if not args.no_large:
+        del X, Y, XT
+        torch.cuda.empty_cache()
+        geo5 = synth.geometry_for("cfg5")
+        G5 = rtt.Geometry(geo5)
+        G5.tune(nvec=1, reps=3)
+        x5 = torch.from_numpy(synth.uniform_emissivity(geo5.grid, seed=5000).astype(np.float32)).to(dev)
+        y5 = torch.empty(G5.n_rows, dtype=torch.float32, device=dev)
+        xt5 = torch.empty_like(x5)
+        ta5, tat5 = time_pair(torch, rtt, G5, x5, y5, xt5, reps=20)
+        g5 = geo5.grid
+        b5 = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, False)
+        b5t = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, True)
+        large = {"workload": "cfg5: " + synth.config("cfg5")["label"] + ", one vector per launch",
+                 "op_apply": {"ms": ta5, "GBps": b5 / (ta5 * 1e-3) / 1e9,
+                              "frac": b5 / (ta5 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                              "variant": rtt.variant_names(False)[G5.members[0]["apply_variant"]]},
+                 "op_apply_adjoint": {"ms": tat5, "GBps": b5t / (tat5 * 1e-3) / 1e9,
+                                      "frac": b5t / (tat5 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                      "variant": rtt.variant_names(True)[G5.members[0]["adjoint_variant"]]},
+                 "applies_per_s": 2.0 / ((ta5 + tat5) * 1e-3)}
+        log("large geometry: A %.3f ms (%.0f GB/s), A^T %.3f ms (%.0f GB/s)" % (
+            ta5, large["op_apply"]["GBps"], tat5, large["op_apply_adjoint"]["GBps"]))
+        del G5, x5, y5, xt5
+        torch.cuda.empty_cache()
+
+    # randomized SVD of the benchmark geometry (k = 256, p = 8, q = 2), wall time
+    rs = None
+    if not args.no_rsvd:
+        torch.cuda.synchronize()
+        t0r = time.perf_counter()
+        sv = rtt.rsvd(G, k=p.get("rsvd_k", 256), p=p.get("rsvd_p", 8), q=p.get("rsvd_q", 2), seed=2001)
+        torch.cuda.synchronize()
+        rs = {"seconds": time.perf_counter() - t0r, "k": sv.k, "sigma_1": float(sv.sigma[0]),
+              "sigma_k": float(sv.sigma[-1]), "block_applies": 6 * (p.get("rsvd_k", 256) + p.get("rsvd_p", 8))}
+        log("rsvd: %.2f s, sigma_1 %.4g sigma_k %.4g" % (rs["seconds"], rs["sigma_1"], rs["sigma_k"]))
+        del sv
+
+    digest = source_digest()
+    meas = MEASURED_TRAFFIC.get(dom)
+    traffic = meas["bytes"] if (meas and meas.get("digest") == digest and meas.get("nvec") == nvec) else None
+
     out = {
         "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
@@ -198,7 +276,8 @@ def main():
                                % (args.workload, p["label"], nvec),
                    "rays_per_order": geo.rays_per_order, "rows": G.n_rows, "cols": G.n_cols, "nvec": nvec},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": dom_gbps / HBM_PEAK_GBPS, "traffic": None, "bytes_per_launch": dom_bytes},
+                     "frac": dom_gbps / HBM_PEAK_GBPS, "traffic": traffic, "bytes_per_launch": dom_bytes,
+                     "kernel_source_digest": digest},
         "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a},
                     "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at}},
         "hbm_gbps": (b_a + b_at) / ((ms_a + ms_at) * 1e-3) / 1e9,
@@ -206,6 +285,8 @@ def main():
                      "op_apply_adjoint": rtt.variant_names(True)[G.members[0]["adjoint_variant"]]},
         "plain_value": plain,
         "calibration": calib,
+        "large_single_vector": large,
+        "rsvd": rs,
         "parity": parity,
         "cpu_baseline": cpu,
     }
