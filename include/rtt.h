@@ -91,6 +91,8 @@ typedef struct {
     int64_t n_cols;        /* total columns                                    */
     int64_t n_rays;        /* total retained rays                              */
     int64_t table_bytes;   /* device bytes held by the handle                  */
+    int32_t batch_apply_mode;   /* launch mode of whole-operator op_apply (below)  */
+    int32_t batch_adjoint_mode; /* launch mode of whole-operator op_apply_adjoint  */
 } rtt_geometry_info;
 
 /* Per-geometry layout inside a handle (geometry g of geometry_info). */
@@ -128,15 +130,30 @@ int geometry_member(const rtt_geometry* geom, int32_t g, rtt_member_info* info);
  * variant_name().  Errors: RTT_EINVAL for an unknown index.
  */
 int geometry_set_variant(rtt_geometry* geom, int32_t g, int32_t apply_variant, int32_t adjoint_variant);
+/*
+ * geometry_set_batch_mode -- how op_apply / op_apply_adjoint (and the drivers
+ * built on them) launch a handle with G > 1 geometries: 0 = one launch per
+ * geometry; 1 (default) = one launch for up to 16 geometries, their blocks
+ * numbered consecutively; 2 = the same launch made persistent (2048 blocks
+ * that stride over the work).  Modes 1 and 2 apply when every geometry of the
+ * group uses the lean forward / visit-list adjoint variant with one common
+ * dt_obs/dt_src; otherwise the call falls back to one launch per geometry.
+ * -1 leaves a mode unchanged.  geometry_tune picks the fastest.  All modes give
+ * bitwise identical results.  Errors: RTT_EINVAL for other values.
+ */
+int geometry_set_batch_mode(rtt_geometry* geom, int32_t apply_mode, int32_t adjoint_mode);
+
 /* Name of variant v of the forward (adjoint = 0) or adjoint (1) kernel, NULL if out of range. */
 const char* variant_name(int32_t adjoint, int32_t v);
 
 /*
  * geometry_tune -- autotuner: times every applicable variant of both kernels
  * on nvec random vectors (HIP events on `stream`, median of `reps`) for each
- * member, keeps the fastest, and records the choice in the text cache at
- * cache_path (nullable; one "digest nvec apply adjoint" line per entry).  A
- * cache hit skips the timing.  Blocking; allocates scratch vectors.
+ * member, keeps the fastest, then (G > 1) times the three launch modes of
+ * geometry_set_batch_mode on the whole operator, and records the choices in
+ * the text cache at cache_path (nullable; one "digest nvec apply adjoint" line
+ * per member, one "multi digest nvec apply_mode adjoint_mode" line per
+ * handle).  A cache hit skips the timing.  Blocking; allocates scratch vectors.
  */
 int geometry_tune(rtt_geometry* geom, int32_t nvec, int32_t reps, const char* cache_path, void* stream);
 

@@ -20,7 +20,7 @@ RTT_OK, RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE, RTT_ENOCONV, RTT_ESTATE = 0, -1, -2
 RTT_SVD_RSVD, RTT_SVD_BLOCK_LANCZOS = 0, 1
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
-            "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
+            "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
             "tsvd_solve", "ridge_solve", "last_error")
 
 
@@ -58,7 +58,8 @@ class rtt_load_opts(ctypes.Structure):
 
 class rtt_geometry_info(ctypes.Structure):
     _fields_ = [("n_geometries", ctypes.c_int32), ("n_rows", ctypes.c_int64),
-                ("n_cols", ctypes.c_int64), ("n_rays", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
+                ("n_cols", ctypes.c_int64), ("n_rays", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
+                ("batch_apply_mode", ctypes.c_int32), ("batch_adjoint_mode", ctypes.c_int32)]
 
 
 class rtt_member_info(ctypes.Structure):
@@ -110,6 +111,7 @@ def require_native():
         "geometry_info": [vp, ctypes.POINTER(rtt_geometry_info)],
         "geometry_member": [vp, i32, ctypes.POINTER(rtt_member_info)],
         "geometry_set_variant": [vp, i32, i32, i32],
+        "geometry_set_batch_mode": [vp, i32, i32],
         "geometry_tune": [vp, i32, i32, ctypes.c_char_p, vp],
         "op_apply": [vp, vp, vp, i32, u32, vp],
         "op_apply_adjoint": [vp, vp, vp, i32, u32, vp],
@@ -224,8 +226,18 @@ class Geometry:
         _check(require_native().geometry_set_variant(self.handle, member, apply, adjoint))
         self._read_members()
 
+    def set_batch_mode(self, apply=-1, adjoint=-1):
+        """Launch mode of whole-operator calls on several geometries (0, 1, 2; see include/rtt.h)."""
+        _check(require_native().geometry_set_batch_mode(self.handle, apply, adjoint))
+
+    @property
+    def batch_mode(self):
+        info = rtt_geometry_info()
+        _check(require_native().geometry_info(self.handle, ctypes.byref(info)))
+        return info.batch_apply_mode, info.batch_adjoint_mode
+
     def tune(self, nvec=1, reps=5, cache_path=None, stream=None):
-        """Autotune the kernel variants of every member (see include/rtt.h)."""
+        """Autotune the kernel variants of every member and the batch launch mode (see include/rtt.h)."""
         cp = None if cache_path is None else str(cache_path).encode()
         _check(require_native().geometry_tune(self.handle, nvec, reps, cp, _stream(stream)))
         self._read_members()

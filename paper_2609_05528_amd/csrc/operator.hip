@@ -66,6 +66,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb)
     int64_t per = nb >> 3, rem = nb & 7;
     return x * per + (x < rem ? x : rem) + i;
 }
+__device__ __forceinline__ uint32_t xcd_remap32(uint32_t b, uint32_t nb)
+{
+    uint32_t x = b & 7, i = b >> 3;
+    uint32_t per = nb >> 3, rem = nb & 7;
+    return x * per + (x < rem ? x : rem) + i;
+}
 
 // --------------------------------------------------------------------------------------------
 // A: y = A x
@@ -659,8 +665,29 @@ struct LeanArgs {
     uint32_t mask;
 };
 
+// A forward record read through the constant address space (the tables never change while a
+// kernel runs), so uniform reads stay scalar loads.
+typedef int i4v __attribute__((ext_vector_type(4)));
+struct RecWords {
+    i4v w0, w1, w2;
+};
+static_assert(sizeof(RecWords) == sizeof(FwdRec), "FwdRec is three 16-byte words");
+__device__ __forceinline__ FwdRec load_const_rec(const FwdRec* p)
+{
+    typedef const __attribute__((address_space(4))) i4v* cptr;
+    const cptr q = (cptr)p;
+    RecWords r;
+    r.w0 = q[0];
+    r.w1 = q[1];
+    r.w2 = q[2];
+    return __builtin_bit_cast(FwdRec, r);
+}
+
+// One block of the lean forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, frame chunk
+// `chunk`, one vector (x, y already offset to the member's blocks).
 template <int Q, int NB, bool VEC4>
-__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
+__device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __restrict__ x, float* __restrict__ y,
+                                          int64_t blk, int chunk)
 {
     constexpr int FC = 128 * Q;          // frames per chunk
     constexpr int W = FC / Q + 4;        // hats staged per ray
@@ -669,14 +696,15 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
     __shared__ __attribute__((aligned(16))) float zs_all[A_WAVES][NB][ZS];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r0 = (blk * A_WAVES + wave) * NB;
     if (r0 >= a.n_rays) return;
-    const float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
-    float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
-    const int f0 = blockIdx.z * FC;
+    const int f0 = chunk * FC;
     const int fend = min(a.F, f0 + FC);
     float(*zs)[ZS] = zs_all[wave];
+    // the previous task of a persistent block may still be reading this wave's LDS rows
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
 
     // phase 1: every record of the batch (independent scalar loads)
@@ -685,7 +713,8 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int64_t ri = r0 + j;
-        rc[j] = a.rec[__builtin_amdgcn_readfirstlane((int)(ri < a.n_rays ? ri : r0))];
+        // scalar loads even after the stores of an earlier task of a persistent block
+        rc[j] = load_const_rec(a.rec + __builtin_amdgcn_readfirstlane((int)(ri < a.n_rays ? ri : r0)));
     }
     // phase 2: every gather of the batch
     float xv[NB][ZI][4];
@@ -797,6 +826,62 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
     }
 }
 
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
+{
+    lean_body<Q, NB, VEC4>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
+                           xcd_remap(blockIdx.x, gridDim.x), blockIdx.z);
+}
+
+// Every member of a handle (up to MULTI_MAX) in one launch.  Tasks are (vector, member, frame
+// chunk, ray block), numbered with the ray block fastest; a member's tasks start at blk_begin
+// inside each vector.  With gridDim.x < total the launch is persistent: block b takes tasks
+// b, b + gridDim.x, ... (gridDim.x is a multiple of 8, so every task of a block stays on the
+// block's XCD and the XCD-contiguous numbering of xcd_remap still holds).
+constexpr int MULTI_MAX = 16;
+struct LeanMember {
+    const FwdRec* rec;
+    int64_t n_rays;
+    int64_t x_off, y_off;
+    uint32_t blk_begin;  // first task of this member inside one vector
+    uint32_t nrb;        // ray blocks per frame chunk
+    int K, F, nk, x_bytes;
+    uint32_t mask;
+};
+struct LeanMulti {
+    LeanMember m[MULTI_MAX];
+    int G;
+    uint32_t per_vec, total;   // tasks per vector and in all (below 2^31, checked by the host)
+    const float* x;
+    float* y;
+    int64_t x_stride, y_stride;
+};
+
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean_multi(LeanMulti a)
+{
+    for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
+        const uint32_t lt = xcd_remap32(t, a.total);
+        const uint32_t v = lt / a.per_vec;
+        uint32_t b = lt - v * a.per_vec;
+        int g = 0;
+        while (g + 1 < a.G && b >= a.m[g + 1].blk_begin) ++g;
+        const LeanMember& mm = a.m[g];
+        b -= mm.blk_begin;
+        LeanArgs la;
+        la.rec = mm.rec;
+        la.n_rays = mm.n_rays;
+        la.K = mm.K;
+        la.F = mm.F;
+        la.nk = mm.nk;
+        la.x_bytes = mm.x_bytes;
+        la.mask = mm.mask;
+        const uint32_t chunk = b / mm.nrb;
+        lean_body<Q, NB, VEC4>(la, a.x + (int64_t)v * a.x_stride + mm.x_off, a.y + (int64_t)v * a.y_stride + mm.y_off,
+                               (int64_t)(b - chunk * mm.nrb), (int)chunk);
+    }
+}
+
 // --------------------------------------------------------------------------------------------
 // A^T, visit-list form (dt_obs/dt_src = 1/Q).  A wave owns cell row ci, a segment of vseg
 // columns and a chunk of 64 V hats (V per lane).  Its visit list (built at load time) holds, in
@@ -848,16 +933,17 @@ struct Taps {
     }
 };
 
+// One block of the visit-list adjoint: task `lin` = (row group, segment, hat chunk) of one member
+// and one vector (y, x already offset to the member's blocks).
 template <int Q, int V, int NB, bool PAIR>
-__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
+__device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y, float* __restrict__ x,
+                                           int64_t lin)
 {
     typedef Taps<Q> TP_;
     constexpr int T = TP_::T;
     typedef float f2 __attribute__((ext_vector_type(2)));
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
-    const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
-    const int64_t lin = xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks);
     const int kch = (int)(lin % a.kchunks);
     const int64_t l2 = lin / a.kchunks;
     const int sg = (int)(l2 % a.nseg), rg = (int)(l2 / a.nseg);
@@ -869,8 +955,6 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
     const int jhi = min(jlo + a.vseg, a.n_phi);
     const int ncol = jhi - jlo + 1;
     const int kc = kch * WAVE * V;       // first hat of this wave's chunk
-    const float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
-    float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
     const int rowbytes = a.F * 4;
     const int lane_off = Q * lane * 4;   // per-lane part of every frame offset
 
@@ -970,6 +1054,59 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
         }
     }
     while (col < ncol) emit();
+}
+
+template <int Q, int V, int NB, bool PAIR>
+__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
+{
+    const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
+    visit_body<Q, V, NB, PAIR>(a, a.y + (int64_t)blockIdx.y * a.y_stride, a.x + (int64_t)blockIdx.y * a.x_stride,
+                               xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
+}
+
+// Every member of a handle (up to MULTI_MAX) in one launch; tasks numbered as in
+// k_apply_lean_multi (vector, member, then the member's own task order).
+struct VisitMember {
+    const Visit* visits;
+    const int64_t* vtask;
+    int64_t y_off, x_off;
+    uint32_t blk_begin;
+    int n_r, n_phi, K, F, nseg, vseg, kchunks;
+    uint32_t mask;
+};
+struct VisitMulti {
+    VisitMember m[MULTI_MAX];
+    int G;
+    uint32_t per_vec, total;
+    const float* y;
+    float* x;
+    int64_t y_stride, x_stride;
+};
+
+template <int Q, int V, int NB, bool PAIR>
+__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMulti a)
+{
+    for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
+        const uint32_t lt = xcd_remap32(t, a.total);
+        const uint32_t v = lt / a.per_vec;
+        const uint32_t b = lt - v * a.per_vec;
+        int g = 0;
+        while (g + 1 < a.G && b >= a.m[g + 1].blk_begin) ++g;
+        const VisitMember& mm = a.m[g];
+        VisitArgs va;
+        va.visits = mm.visits;
+        va.vtask = mm.vtask;
+        va.n_r = mm.n_r;
+        va.n_phi = mm.n_phi;
+        va.K = mm.K;
+        va.F = mm.F;
+        va.nseg = mm.nseg;
+        va.vseg = mm.vseg;
+        va.kchunks = mm.kchunks;
+        va.mask = mm.mask;
+        visit_body<Q, V, NB, PAIR>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
+                                   a.x + (int64_t)v * a.x_stride + mm.x_off, (int64_t)(b - mm.blk_begin));
+    }
 }
 
 // --------------------------------------------------------------------------------------------
@@ -1321,8 +1458,8 @@ static void apply_stream_launch(const ApplyArgs& a, int nvec, hipStream_t s)
     const int64_t nbatch = (a.n_rays + NB - 1) / NB;
     const int64_t total = nbatch * nch * nvec;
     int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t blocks = std::min<int64_t>((int64_t)cus * 8, (total + A_WAVES - 1) / A_WAVES);
     blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
     hipLaunchKernelGGL((k_apply_stream<TP, TQ, NB, ZI>), dim3((unsigned)blocks), dim3(A_WAVES * WAVE), 0, s, a, fc,
@@ -1482,6 +1619,166 @@ static void visit_dispatch(const VisitArgs& a, int nvec, hipStream_t s)
     else visit_launch<Q, 8, 2, PAIR>(a, nvec, s);
 }
 
+// ------------------------------------------------------------------ one launch for many members
+// Resident blocks of a persistent launch: 256 CUs x 8 (a multiple of 8, see k_apply_lean_multi).
+constexpr int64_t PERSIST_BLOCKS = 2048;
+
+static unsigned multi_grid(int64_t total, bool persist)
+{
+    return (unsigned)(persist ? std::min<int64_t>(total, PERSIST_BLOCKS) : total);
+}
+
+// Forward of members [b, e) in one launch; false if they do not fit the lean multi kernel.
+static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
+                        hipStream_t s, bool persist, int* rc)
+{
+    const Member& m0 = g->members[b];
+    bool vec4 = (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (g->n_rows % 4) == 0);
+    bool all8 = true;
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        if (!lean_supported(m) || m.Q != m0.Q || (m.apply_variant != 4 && m.apply_variant != 5)) return false;
+        all8 = all8 && m.apply_variant == 5;
+        vec4 = vec4 && (m.grid.n_frames % 4) == 0 && (m.row_offset % 4) == 0;
+    }
+    const int NB = all8 ? 8 : 4;
+    LeanMulti a;
+    a.G = e - b;
+    int64_t nb = 0;
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        LeanMember& d = a.m[i - b];
+        d.rec = g->d_fwd + m.ray_begin;
+        d.n_rays = m.n_rays;
+        d.blk_begin = (uint32_t)nb;
+        d.x_off = m.col_offset;
+        d.y_off = m.row_offset;
+        d.K = m.grid.n_hat;
+        d.F = m.grid.n_frames;
+        d.nk = m.grid.n_phi * m.grid.n_hat;
+        d.x_bytes = (int)(m.n_cols * 4);
+        d.nrb = (uint32_t)((m.n_rays + (int64_t)A_WAVES * NB - 1) / ((int64_t)A_WAVES * NB));
+        d.mask = effective_mask(m, mask);
+        const int nch = (m.grid.n_frames + 128 * m.Q - 1) / (128 * m.Q);
+        nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
+    }
+    if (nb * nvec >= (1ll << 31)) return false;
+    a.per_vec = (uint32_t)nb;
+    a.total = (uint32_t)(nb * nvec);
+    a.x = x;
+    a.y = y;
+    a.x_stride = g->n_cols;
+    a.y_stride = g->n_rows;
+    *rc = RTT_OK;
+    if (a.total == 0) return true;
+    const dim3 grid(multi_grid(a.total, persist)), blk(A_WAVES * WAVE);
+    if (m0.Q == 1) {
+        if (NB == 4) {
+            if (vec4) hipLaunchKernelGGL((k_apply_lean_multi<1, 4, true>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_apply_lean_multi<1, 4, false>), grid, blk, 0, s, a);
+        } else {
+            if (vec4) hipLaunchKernelGGL((k_apply_lean_multi<1, 8, true>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_apply_lean_multi<1, 8, false>), grid, blk, 0, s, a);
+        }
+    } else {
+        if (NB == 4) {
+            if (vec4) hipLaunchKernelGGL((k_apply_lean_multi<2, 4, true>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_apply_lean_multi<2, 4, false>), grid, blk, 0, s, a);
+        } else {
+            if (vec4) hipLaunchKernelGGL((k_apply_lean_multi<2, 8, true>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_apply_lean_multi<2, 8, false>), grid, blk, 0, s, a);
+        }
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) *rc = hip_fail(err, "k_apply_lean_multi");
+    return true;
+}
+
+template <int Q, int V, int NB, bool PAIR>
+static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec, bool persist,
+                               hipStream_t s)
+{
+    int64_t nb = 0;
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        VisitMember& d = a.m[i - b];
+        d.kchunks = (m.grid.n_hat + WAVE * V - 1) / (WAVE * V);
+        d.blk_begin = (uint32_t)nb;
+        nb += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * d.nseg * d.kchunks;
+    }
+    a.per_vec = (uint32_t)nb;
+    a.total = (uint32_t)(nb * nvec);   // below 2^31: checked by adjoint_multi
+    if (a.total == 0) return;
+    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR>), dim3(multi_grid(a.total, persist)),
+                       dim3(T_WAVES * WAVE), 0, s, a);
+}
+
+template <int Q, bool PAIR>
+static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec,
+                                 bool persist, hipStream_t s)
+{
+    constexpr int NB1 = Q == 1 ? 8 : 4;
+    int64_t waves = 0;
+    int K = 0;
+    for (int i = b; i < e; ++i) {
+        waves += (int64_t)g->members[i].grid.n_r * g->members[i].nseg[set] * nvec;
+        K = std::max(K, g->members[i].grid.n_hat);
+    }
+    if (K <= 64 || waves < 16384) visit_multi_launch<Q, 1, 8, PAIR>(a, g, b, e, set, nvec, persist, s);
+    else if (K <= 128) visit_multi_launch<Q, 2, NB1, PAIR>(a, g, b, e, set, nvec, persist, s);
+    else if (K <= 256) visit_multi_launch<Q, 4, Q == 1 ? 4 : 2, PAIR>(a, g, b, e, set, nvec, persist, s);
+    else visit_multi_launch<Q, 8, 2, PAIR>(a, g, b, e, set, nvec, persist, s);
+}
+
+// Adjoint of members [b, e) in one launch; false if they do not fit the visit multi kernel.
+static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, float* x, int nvec, uint32_t mask,
+                          hipStream_t s, bool persist, int* rc)
+{
+    const Member& m0 = g->members[b];
+    bool pair = (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (g->n_rows % 2) == 0);
+    int64_t wide = 0;
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        if (!visit_supported(m) || m.Q != m0.Q || m.adj_variant != 11) return false;
+        pair = pair && (m.grid.n_frames % 2) == 0 && (m.row_offset % 2) == 0;
+        wide += (int64_t)m.grid.n_r * m.nseg[0] * nvec;
+    }
+    const int set = wide >= 16384 ? 0 : 1;
+    int64_t most = 0;   // task count with one hat chunk of 64 per wave (the largest any V gives)
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        most += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * m.nseg[set] * ((m.grid.n_hat + WAVE - 1) / WAVE);
+    }
+    if (most * nvec >= (1ll << 31)) return false;
+    VisitMulti a;
+    a.G = e - b;
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        VisitMember& d = a.m[i - b];
+        d.visits = g->d_visits + m.visit_begin[set];
+        d.vtask = g->d_vtask + m.vtask_begin[set];
+        d.y_off = m.row_offset;
+        d.x_off = m.col_offset;
+        d.n_r = m.grid.n_r;
+        d.n_phi = m.grid.n_phi;
+        d.K = m.grid.n_hat;
+        d.F = m.grid.n_frames;
+        d.nseg = m.nseg[set];
+        d.vseg = m.vseg[set];
+        d.mask = effective_mask(m, mask);
+    }
+    a.y = y;
+    a.x = x;
+    a.y_stride = g->n_rows;
+    a.x_stride = g->n_cols;
+    if (m0.Q == 1) visit_multi_dispatch<1, false>(a, g, b, e, set, nvec, persist, s);
+    else if (pair) visit_multi_dispatch<2, true>(a, g, b, e, set, nvec, persist, s);
+    else visit_multi_dispatch<2, false>(a, g, b, e, set, nvec, persist, s);
+    hipError_t err = hipGetLastError();
+    *rc = err == hipSuccess ? RTT_OK : hip_fail(err, "k_adjoint_visit_multi");
+    return true;
+}
+
 int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float* x, int nvec,
                    int64_t y_stride, int64_t x_stride, uint32_t mask, hipStream_t s, int variant)
 {
@@ -1558,13 +1855,27 @@ int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, f
         return adjoint ? launch_adjoint(g, m, in, out, nvec, m.n_rows, m.n_cols, em, s, -1)
                        : launch_apply(g, m, in, out, nvec, m.n_cols, m.n_rows, em, s, -1);
     }
-    for (const Member& m : g->members) {
-        const uint32_t em = effective_mask(m, mask);
-        int rc = adjoint ? launch_adjoint(g, m, in + m.row_offset, out + m.col_offset, nvec, g->n_rows, g->n_cols,
-                                          em, s, -1)
-                         : launch_apply(g, m, in + m.col_offset, out + m.row_offset, nvec, g->n_cols, g->n_rows,
-                                        em, s, -1);
-        if (rc) return rc;
+    if (nvec == 0) return RTT_OK;
+    const int G = (int)g->members.size();
+    const int mode = adjoint ? g->batch_adjoint_mode : g->batch_apply_mode;
+    for (int b = 0; b < G; b += MULTI_MAX) {
+        const int e = std::min(G, b + MULTI_MAX);
+        if (G > 1 && mode != 0) {
+            int rc = RTT_OK;
+            const bool done = adjoint ? adjoint_multi(g, b, e, in, out, nvec, mask, s, mode == 2, &rc)
+                                      : apply_multi(g, b, e, in, out, nvec, mask, s, mode == 2, &rc);
+            if (rc) return rc;
+            if (done) continue;
+        }
+        for (int i = b; i < e; ++i) {
+            const Member& m = g->members[i];
+            const uint32_t em = effective_mask(m, mask);
+            int rc = adjoint ? launch_adjoint(g, m, in + m.row_offset, out + m.col_offset, nvec, g->n_rows,
+                                              g->n_cols, em, s, -1)
+                             : launch_apply(g, m, in + m.col_offset, out + m.row_offset, nvec, g->n_cols,
+                                            g->n_rows, em, s, -1);
+            if (rc) return rc;
+        }
     }
     return RTT_OK;
 }

@@ -89,6 +89,9 @@ struct rtt_geometry {
     int64_t* d_vtask = nullptr;         // per member task offsets into the visit lists
     int64_t n_rows = 0, n_cols = 0, n_rays = 0;
     int64_t table_bytes = 0;
+    // whole-operator calls on G > 1 members: 0 = one launch per member, 1 = one launch for
+    // up to 16 members, 2 = the same as a persistent launch (one block per resident slot)
+    int32_t batch_apply_mode = 1, batch_adjoint_mode = 1;
     int device = 0;
     uint32_t magic = 0x52545447u;
 };

@@ -330,6 +330,18 @@ extern "C" int geometry_info(const rtt_geometry* g, rtt_geometry_info* info)
     info->n_cols = g->n_cols;
     info->n_rays = g->n_rays;
     info->table_bytes = g->table_bytes;
+    info->batch_apply_mode = g->batch_apply_mode;
+    info->batch_adjoint_mode = g->batch_adjoint_mode;
+    return RTT_OK;
+}
+
+extern "C" int geometry_set_batch_mode(rtt_geometry* g, int32_t apply_mode, int32_t adjoint_mode)
+{
+    if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
+    if (apply_mode < -1 || apply_mode > 2 || adjoint_mode < -1 || adjoint_mode > 2)
+        return fail(RTT_EINVAL, "launch mode must be -1 (unchanged), 0, 1 or 2");
+    if (apply_mode >= 0) g->batch_apply_mode = apply_mode;
+    if (adjoint_mode >= 0) g->batch_adjoint_mode = adjoint_mode;
     return RTT_OK;
 }
 

@@ -1,4 +1,6 @@
-// Autotuner: pick the fastest kernel variant of A and A^T for each member geometry.
+// Autotuner: pick the fastest kernel variant of A and A^T for each member geometry and, for a
+// handle with several members, the fastest launch mode of the whole operator (one launch per
+// member, one launch for all members, or one persistent launch).
 //
 // Every applicable variant is timed with HIP events on the caller's stream
 // over `reps` launches on `nvec` random vectors (median).  Choices are cached
@@ -20,7 +22,10 @@ struct CacheEntry {
     int nvec, apply, adjoint;
 };
 
-std::vector<CacheEntry> read_cache(const char* path)
+// Member lines are "digest nvec apply adjoint"; whole-handle lines (launch mode of a handle with
+// several members) are "multi digest nvec apply_mode adjoint_mode" and are kept with apply
+// and adjoint holding the modes and multi set.
+std::vector<CacheEntry> read_cache(const char* path, std::vector<CacheEntry>* multi)
 {
     std::vector<CacheEntry> out;
     if (!path) return out;
@@ -29,9 +34,45 @@ std::vector<CacheEntry> read_cache(const char* path)
     while (std::getline(f, line)) {
         std::istringstream is(line);
         CacheEntry e;
+        if (line.compare(0, 6, "multi ") == 0) {
+            std::string tag;
+            if (is >> tag >> std::hex >> e.digest >> std::dec >> e.nvec >> e.apply >> e.adjoint) multi->push_back(e);
+            continue;
+        }
         if (is >> std::hex >> e.digest >> std::dec >> e.nvec >> e.apply >> e.adjoint) out.push_back(e);
     }
     return out;
+}
+
+// Median time of the whole-operator call under launch mode `mode` (see rtt_geometry).
+int time_mode(rtt_geometry* g, bool adjoint, int mode, const float* in, float* out, int nvec, int reps,
+              hipStream_t s, float* ms_out)
+{
+    int32_t& slot = adjoint ? g->batch_adjoint_mode : g->batch_apply_mode;
+    const int32_t keep = slot;
+    slot = mode;
+    hipEvent_t e0, e1;
+    RTT_HIP(hipEventCreate(&e0));
+    RTT_HIP(hipEventCreate(&e1));
+    std::vector<float> t;
+    int rc = RTT_OK;
+    for (int r = 0; r <= reps && !rc; ++r) {
+        RTT_HIP(hipEventRecord(e0, s));
+        rc = apply_op(g, -1, adjoint, in, out, nvec, 0u, s);
+        if (rc) break;
+        RTT_HIP(hipEventRecord(e1, s));
+        RTT_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        RTT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0) t.push_back(ms);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    slot = keep;
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    return RTT_OK;
 }
 
 int time_variant(const rtt_geometry* g, const Member& m, bool adjoint, int variant, const float* in, float* out,
@@ -67,7 +108,8 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
     if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
     if (nvec < 1 || nvec > 4096 || reps < 1 || reps > 1000) return fail(RTT_EINVAL, "need 1 <= nvec <= 4096, 1 <= reps <= 1000");
     hipStream_t s = (hipStream_t)stream;
-    std::vector<CacheEntry> cache = read_cache(cache_path);
+    std::vector<CacheEntry> multi_cache;
+    std::vector<CacheEntry> cache = read_cache(cache_path, &multi_cache);
     int64_t max_rows = 0, max_cols = 0;
     for (const Member& m : g->members) {
         max_rows = std::max(max_rows, m.n_rows);
@@ -121,10 +163,53 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         m.adj_variant = best_v;
         added.push_back({m.digest, nvec, m.apply_variant, m.adj_variant});
     }
-    if (cache_path && !added.empty()) {
+    // several members: one launch per member, one launch for all, or one persistent launch
+    bool multi_added = false;
+    uint64_t hd = 1469598103934665603ull;
+    if (g->members.size() > 1) {
+        for (const Member& m : g->members) {
+            const int32_t v[2] = {m.apply_variant, m.adj_variant};
+            hd = fnv1a(&m.digest, sizeof(m.digest), hd);
+            hd = fnv1a(v, sizeof(v), hd);
+        }
+        bool hit = false;
+        for (const CacheEntry& e : multi_cache)
+            if (e.digest == hd && e.nvec == nvec && e.apply >= 0 && e.apply <= 2 && e.adjoint >= 0 && e.adjoint <= 2) {
+                g->batch_apply_mode = e.apply;
+                g->batch_adjoint_mode = e.adjoint;
+                hit = true;
+            }
+        if (!hit) {
+            float* xa = (float*)ws.get("tune_xa", sizeof(float) * (size_t)nvec * g->n_cols);
+            float* ya = (float*)ws.get("tune_ya", sizeof(float) * (size_t)nvec * g->n_rows);
+            if (!xa || !ya) return fail(RTT_ENOMEM, "tune buffers");
+            int rc = normal_fill(xa, (int64_t)nvec * g->n_cols, 12345, s);
+            if (!rc) rc = normal_fill(ya, (int64_t)nvec * g->n_rows, 54321, s);
+            if (rc) return rc;
+            for (int adj = 0; adj < 2; ++adj) {
+                float best = 1e30f;
+                int best_m = 1;
+                for (int mode = 0; mode <= 2; ++mode) {
+                    float ms;
+                    rc = adj ? time_mode(g, true, mode, ya, xa, nvec, reps, s, &ms)
+                             : time_mode(g, false, mode, xa, ya, nvec, reps, s, &ms);
+                    if (rc) return rc;
+                    if (std::getenv("RTT_LOG"))
+                        std::fprintf(stderr, "[rtt] tune %s launch mode %d: %.4f ms\n", adj ? "adjoint" : "apply", mode, ms);
+                    if (ms < best) { best = ms; best_m = mode; }
+                }
+                (adj ? g->batch_adjoint_mode : g->batch_apply_mode) = best_m;
+            }
+            multi_added = true;
+        }
+    }
+    if (cache_path && (!added.empty() || multi_added)) {
         std::ofstream f(cache_path, std::ios::app);
         for (const CacheEntry& e : added)
             f << std::hex << e.digest << std::dec << " " << e.nvec << " " << e.apply << " " << e.adjoint << "\n";
+        if (multi_added)
+            f << "multi " << std::hex << hd << std::dec << " " << nvec << " " << g->batch_apply_mode << " "
+              << g->batch_adjoint_mode << "\n";
     }
     RTT_HIP(hipStreamSynchronize(s));
     return RTT_OK;

@@ -256,6 +256,45 @@ def test_batched_handle_is_block_diagonal(gpu_lib):
         assert rel(xa[m["col_offset"]:m["col_offset"] + m["n_cols"]], oracle.adjoint(geo, ys)) <= TOL
 
 
+BATCH_CASES = {
+    "ragged_frames": dict(n=3, frames=lambda i: 5 + 3 * i, dt_obs=4.0),
+    "aligned_frames": dict(n=4, frames=lambda i: 8 * (i + 1), dt_obs=4.0),
+    "half_ratio": dict(n=3, frames=lambda i: 10 + 6 * i, dt_obs=2.0),
+    "seventeen_members": dict(n=17, frames=lambda i: 4 + (i % 5), dt_obs=4.0),
+}
+
+
+@pytest.mark.parametrize("name", list(BATCH_CASES))
+def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name):
+    """One launch for all geometries (plain and persistent) equals one launch per geometry."""
+    rtt = gpu_lib
+    c = BATCH_CASES[name]
+    say("case batch modes", name)
+    geos = [tiny_geometry(seed=60 + i, rays=(30 + 11 * i, 7, 3), n_frames=c["frames"](i), dt_obs=c["dt_obs"],
+                          n_r=4 + i % 3, n_phi=6 + 2 * (i % 4)) for i in range(c["n"])]
+    G = rtt.Geometry(geos)
+    rng = np.random.default_rng(19)
+    X = rng.random((3, G.n_cols)).astype(np.float32)
+    Y = rng.standard_normal((3, G.n_rows)).astype(np.float32)
+    outs = {}
+    for mode in (0, 1, 2):
+        G.set_batch_mode(apply=mode, adjoint=mode)
+        assert G.batch_mode == (mode, mode)
+        outs[mode] = (rtt.op_apply(G, to_dev(X)).cpu().numpy(), rtt.op_apply_adjoint(G, to_dev(Y)).cpu().numpy())
+    for mode in (1, 2):
+        assert np.array_equal(outs[mode][0], outs[0][0]), mode
+        assert np.array_equal(outs[mode][1], outs[0][1]), mode
+    ya, xa = outs[1]
+    for geo, m in zip(geos, G.members):
+        cs = slice(m["col_offset"], m["col_offset"] + m["n_cols"])
+        rs = slice(m["row_offset"], m["row_offset"] + m["n_rows"])
+        yr = oracle.forward(geo, X[:, cs].astype(np.float64))
+        xr = oracle.adjoint(geo, Y[:, rs].astype(np.float64))
+        for b in range(3):
+            assert rel(ya[b, rs], yr[b]) <= TOL
+            assert rel(xa[b, cs], xr[b]) <= TOL
+
+
 VARIANT_CASES = {
     "many_tiles": dict(seed=23, rays=(900, 200, 150), n_r=19, n_phi=21, n_frames=70),
     "ratio_half": dict(seed=12, rays=(300, 50, 40), dt_obs=2.0, n_frames=90, n_r=7, n_phi=66),
