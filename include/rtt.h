@@ -177,6 +177,8 @@ int op_apply_adjoint(const rtt_geometry* geom, const float* y, float* x, int32_t
 
 /* ------------------------------------------------------------------ spectra */
 enum { RTT_SVD_RSVD = 0, RTT_SVD_BLOCK_LANCZOS = 1 };
+/* rtt_svd_opts.geometry: factorise every geometry of the handle on its own (rSVD only). */
+enum { RTT_EACH_GEOMETRY = -2 };
 
 typedef struct {
     int32_t method;     /* RTT_SVD_RSVD or RTT_SVD_BLOCK_LANCZOS                 */
@@ -186,7 +188,9 @@ typedef struct {
     int32_t block;      /* Lanczos block size b                                   */
     int32_t steps;      /* Lanczos steps (b*steps right vectors)                  */
     uint32_t order_mask;/* rows used (0 = all)                                    */
-    int32_t geometry;   /* member geometry for G > 1 handles (-1 = whole operator) */
+    int32_t geometry;   /* member geometry g (vectors of that geometry alone), -1 =
+                           the whole operator, RTT_EACH_GEOMETRY = every geometry
+                           separately in one call (full-length vectors)           */
     uint64_t seed;      /* used when omega == NULL (counter-based normal draws)   */
     int32_t keep_u;     /* 1: also store left vectors (rSVD)                       */
     int32_t reserved[3];
@@ -200,30 +204,50 @@ typedef struct {
  * FP64 SVD of the projected l x l factor.  Block Lanczos: block Golub-Kahan
  * with one-sided FP64 reorthogonalisation.  omega: device FP32 [l][n_cols]
  * start block (NULL: drawn from seed).  Blocking (returns after the small SVD).
+ * With geometry = RTT_EACH_GEOMETRY the G geometries of the handle are
+ * factorised independently in one run: every application of A or A^T is one
+ * batched call on the whole handle, every orthonormalisation and small SVD is
+ * done per geometry block; row i of V then holds the i-th right singular
+ * vector of every geometry in that geometry's column block.
  */
 int rsvd(const rtt_geometry* geom, const rtt_svd_opts* opts, const float* omega,
          rtt_svd** out, void* stream);
 int svd_free(rtt_svd* s);
 /* sigma_host[k] (FP64 host, descending), *V_dev = device [k][n_cols] FP32
- * right vectors, *U_dev = device [k][n_rows] left vectors or NULL. Any output
- * pointer may be NULL.  *k_out receives k.  Pointers stay owned by s. */
+ * right vectors, *U_dev = device [k][n_rows] left vectors or NULL,
+ * resid_host[k] = ||A v_i - sigma_i u_i|| (rSVD with keep_u) or the Ritz
+ * residual estimate (Lanczos).  For RTT_EACH_GEOMETRY factors sigma_host and
+ * resid_host receive [G][k] values.  Any output pointer may be NULL.  *k_out
+ * receives k.  Pointers stay owned by s. */
 int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, const float** V_dev,
             const float** U_dev, double* resid_host);
 
 /*
  * tsvd_solve -- TSVD estimate of Sec. 9: x = V_t diag(sigma_t^-2) V_t^T A^T y
  * (= sum_{i<t} v_i (u_i . y)/sigma_i for an exact factorisation).
- * y: device [nrhs][n_rows]; x: device [nrhs][n_cols].  t <= k; t <= 0 means
- * t = #{sigma_i >= sigma_min} with sigma_min given.
+ * y: device [nrhs][n_rows]; x: device [nrhs][n_cols], with the lengths of the
+ * factorised operator (one geometry's for factors of a member g, the handle's
+ * otherwise; RTT_EACH_GEOMETRY factors solve every geometry with its own
+ * factors).  t <= k keeps the t leading components; t <= 0 keeps those with
+ * sigma_i >= sigma_min (per geometry).  Zero singular values are never kept.
+ * Stream-ordered (no host synchronisation).  Scratch memory is kept by s and
+ * only grows, so a call with no more right-hand sides than an earlier one
+ * allocates nothing and may be captured into a hipGraph; calls on one s must
+ * not overlap in time.
  */
 int tsvd_solve(const rtt_geometry* geom, const rtt_svd* s, const float* y, int32_t nrhs,
                int32_t t, double sigma_min, float* x, void* stream);
 
+enum { RTT_SOLVE_ASYNC = 1 };
+
 typedef struct {
-    float tol;          /* stop when ||r|| <= tol ||A^T y|| (per right-hand side) */
-    int32_t maxit;      /* iteration cap                                           */
+    float tol;          /* stop when ||r|| <= tol ||A^T y|| (per right-hand side
+                           and geometry)                                         */
+    int32_t maxit;      /* iteration cap (RTT_SOLVE_ASYNC: iteration count)      */
     uint32_t order_mask;
-    int32_t reserved[5];
+    int32_t flags;      /* RTT_SOLVE_ASYNC: stream-ordered, see ridge_solve      */
+    float* resid_dev;   /* nullable device FP32 [nrhs][G]: final ||r||/||A^T y||  */
+    int32_t reserved[2];
 } rtt_cg_opts;
 
 typedef struct {
@@ -236,10 +260,20 @@ typedef struct {
 /*
  * ridge_solve -- ridge (Tikhonov) estimate of Sec. 9:
  * argmin 1/2||A x - y||^2 + lambda/2 ||x||^2, by conjugate gradients on
- * (A^T A + lambda I) x = A^T y with independent scalars per right-hand side.
- * y: device [nrhs][n_rows]; x: device [nrhs][n_cols] (overwritten; the
- * start is x = 0).  info may be NULL.  Blocking.  Returns RTT_ENOCONV if some
- * right-hand side did not reach tol within maxit (x still holds the iterate).
+ * (A^T A + lambda I) x = A^T y.  Every (right-hand side, geometry) pair of
+ * the block-diagonal operator runs its own CG (own step lengths, own stop
+ * test), so a handle of G geometries solves G x nrhs independent problems in
+ * one call.  y: device [nrhs][n_rows]; x: device [nrhs][n_cols] (overwritten;
+ * the start is x = 0).  info may be NULL.
+ * Default mode: blocking; returns RTT_ENOCONV if some pair did not reach tol
+ * within maxit (x still holds the iterate; info counts pairs).
+ * flags & RTT_SOLVE_ASYNC: stream-ordered, no host synchronisation: exactly
+ * maxit iterations are enqueued (a pair that meets tol stops changing), the
+ * final relative residuals go to opts->resid_dev when given, info (if any)
+ * gets iterations = maxit and converged = -1.  Scratch memory is kept by the
+ * handle and only grows, so a call that needs no more than an earlier one
+ * allocates nothing and may be captured into a hipGraph.  Asynchronous solves
+ * on one handle must not overlap in time (they share that scratch).
  */
 int ridge_solve(const rtt_geometry* geom, const float* y, int32_t nrhs, float lambda,
                 const rtt_cg_opts* opts, float* x, rtt_solve_info* info, void* stream);

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "librtt.so")
 
 RTT_OK, RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE, RTT_ENOCONV, RTT_ESTATE = 0, -1, -2, -3, -4, -5
 RTT_SVD_RSVD, RTT_SVD_BLOCK_LANCZOS = 0, 1
+RTT_SOLVE_ASYNC = 1
+RTT_EACH_GEOMETRY = -2
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
@@ -78,7 +80,7 @@ class rtt_svd_opts(ctypes.Structure):
 
 class rtt_cg_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_float), ("maxit", ctypes.c_int32), ("order_mask", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("flags", ctypes.c_int32), ("resid_dev", ctypes.c_void_p), ("reserved", ctypes.c_int32 * 2)]
 
 
 class rtt_solve_info(ctypes.Structure):

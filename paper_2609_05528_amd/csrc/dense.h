@@ -28,6 +28,15 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
 // out[v] = <a_v, b_v> in FP64 for nvec vectors of length n.
 int dots(Workspace& ws, const float* a, int64_t lda, const float* b, int64_t ldb, int64_t n, int nvec,
          double* out_dev, hipStream_t s);
+// out[v*G + g] = <a_v, b_v> over segment g (device table seg[2g] = offset, seg[2g+1] = length,
+// max_len >= every length), FP64, deterministic.
+int dots_seg(Workspace& ws, const float* a, int64_t lda, const float* b, int64_t ldb, const int64_t* seg_dev,
+             int G, int64_t max_len, int nvec, double* out_dev, hipStream_t s);
+// p[0..n) = v with a kernel (safe inside captured graphs, unlike memset nodes).
+int fill(float* p, int64_t n, float v, hipStream_t s);
+// C[set][i][r] = Cd[set][i][r] / sigma[set*k + i]^2 if sigma >= sigma_min and > 0, else 0 (FP64 in, FP32 out).
+int scale_inv_sq(const double* Cd, const double* sigma_dev, int sets, int t, int k, int nrhs, double sigma_min,
+                 float* C, hipStream_t s);
 // N(0,1) FP32 draws from Philox-4x32-10 counters (seeded).
 int normal_fill(float* out, int64_t n, uint64_t seed, hipStream_t s);
 

@@ -192,6 +192,48 @@ __global__ void k_dot_final(const double* __restrict__ part, int nsplit, int nve
     out[v] = s;
 }
 
+// Segmented variant: segment g of vector v is [seg[2g], seg[2g] + seg[2g+1]) and its dot product
+// goes to out[v * G + g]; slices of one segment are summed in a fixed order as above.
+__global__ void k_dot_partial_seg(const float* __restrict__ a, int64_t lda, const float* __restrict__ b,
+                                  int64_t ldb, const int64_t* __restrict__ seg, int G, double* __restrict__ part)
+{
+    __shared__ double red[256];
+    const int s = blockIdx.x, v = blockIdx.y, g = blockIdx.z;
+    const int nsplit = gridDim.x;
+    const int64_t off = seg[2 * g], len = seg[2 * g + 1];
+    const int64_t slice = (len + nsplit - 1) / nsplit;
+    const float* av = a + (int64_t)v * lda + off;
+    const float* bv = b + (int64_t)v * ldb + off;
+    const int64_t l0 = (int64_t)s * slice, l1 = min(len, l0 + slice);
+    double acc = 0.0;
+    for (int64_t l = l0 + threadIdx.x; l < l1; l += blockDim.x) acc += (double)av[l] * (double)bv[l];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((int64_t)v * G + g) * nsplit + s] = red[0];
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// C[set][i][r] = Cd[set][i][r] / sigma[set][i]^2 when sigma[set][i] >= sigma_min and > 0, else 0
+__global__ void k_scale_inv_sq(const double* __restrict__ Cd, const double* __restrict__ sigma, int sets, int t,
+                               int k, int nrhs, double sigma_min, float* __restrict__ C)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)sets * t * nrhs) return;
+    const int set = (int)(e / ((int64_t)t * nrhs));
+    const int i = (int)((e / nrhs) % t);
+    const double sg = sigma[(int64_t)set * k + i];
+    C[e] = (sg >= sigma_min && sg > 0.0) ? (float)(Cd[e] / (sg * sg)) : 0.f;
+}
+
 // --------------------------------------------------------------------------------- host side
 Workspace::~Workspace() { release(); }
 void Workspace::release()
@@ -271,6 +313,40 @@ int normal_fill(float* out, int64_t n, uint64_t seed, hipStream_t s)
 {
     const int64_t q = (n + 3) / 4;
     hipLaunchKernelGGL(k_normal, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, out, n, seed, (uint64_t)0);
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+int dots_seg(Workspace& ws, const float* a, int64_t lda, const float* b, int64_t ldb, const int64_t* seg_dev,
+             int G, int64_t max_len, int nvec, double* out_dev, hipStream_t s)
+{
+    if (nvec <= 0 || G <= 0) return RTT_OK;
+    const int nsplit = (int)std::min<int64_t>(std::max<int64_t>(1, max_len / 4096), 256);
+    double* part = (double*)ws.get("dotseg_part", sizeof(double) * (size_t)nsplit * nvec * G);
+    if (!part) return fail(RTT_ENOMEM, "dot workspace");
+    hipLaunchKernelGGL(k_dot_partial_seg, dim3((unsigned)nsplit, (unsigned)nvec, (unsigned)G), dim3(256), 0, s, a,
+                       lda, b, ldb, seg_dev, G, part);
+    const int tot = nvec * G;
+    hipLaunchKernelGGL(k_dot_final, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, s, part, nsplit, tot, out_dev);
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+int fill(float* p, int64_t n, float v, hipStream_t s)
+{
+    if (n <= 0) return RTT_OK;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+int scale_inv_sq(const double* Cd, const double* sigma_dev, int sets, int t, int k, int nrhs, double sigma_min,
+                 float* C, hipStream_t s)
+{
+    const int64_t n = (int64_t)sets * t * nrhs;
+    if (n <= 0) return RTT_OK;
+    hipLaunchKernelGGL(k_scale_inv_sq, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Cd, sigma_dev, sets, t, k,
+                       nrhs, sigma_min, C);
     RTT_HIP(hipGetLastError());
     return RTT_OK;
 }

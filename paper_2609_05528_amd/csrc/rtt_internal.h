@@ -78,6 +78,8 @@ struct Member {
     int32_t vseg[2];         // columns per sweep segment
 };
 
+struct Workspace;
+
 }  // namespace rtt
 
 struct rtt_geometry {
@@ -87,6 +89,9 @@ struct rtt_geometry {
     rtt::Visit* d_visits = nullptr;     // per member visit lists (cell row x segment tasks)
     rtt::FwdRec* d_fwd = nullptr;       // forward records, same order as d_rays
     int64_t* d_vtask = nullptr;         // per member task offsets into the visit lists
+    int64_t* d_seg = nullptr;           // [G] (col_offset, n_cols) then [G] (row_offset, n_rows)
+    // grow-only scratch of the stream-ordered (graph-capturable) solver mode, kept across calls
+    mutable rtt::Workspace* solve_ws = nullptr;
     int64_t n_rows = 0, n_cols = 0, n_rays = 0;
     int64_t table_bytes = 0;
     // whole-operator calls on G > 1 members: 0 = one launch per member, 1 = one launch for

@@ -28,25 +28,37 @@ using namespace rtt;
 struct rtt_svd {
     uint32_t magic = 0x53564431u;
     int k = 0;
-    int member = -1;
+    int member = -1;      // -1 whole operator, g >= 0 one member, RTT_EACH_GEOMETRY every member
+    int sets = 1;         // independent factorisations held (G for RTT_EACH_GEOMETRY)
     int64_t n_rows = 0, n_cols = 0;
-    std::vector<double> sigma, resid;
+    std::vector<double> sigma, resid;   // [sets][k]
     float* V = nullptr;
     float* U = nullptr;
+    double* d_sigma = nullptr;          // device copy of sigma
+    rtt::Workspace* ws = nullptr;       // grow-only scratch of tsvd_solve
     ~rtt_svd()
     {
         if (V) hipFree(V);
         if (U) hipFree(U);
+        if (d_sigma) hipFree(d_sigma);
+        delete ws;
     }
 };
 
 namespace {
 
+// A block of rows (or columns) processed as one independent problem: [off, off + len) of
+// vectors whose stride is the full length.
+struct Seg {
+    int64_t off, len;
+};
+
 struct Ctx {
     const rtt_geometry* g;
     int member;
     uint32_t mask;
-    int64_t n_rows, n_cols;
+    int64_t n_rows, n_cols;          // vector lengths (strides)
+    std::vector<Seg> rseg, cseg;     // one problem: {0, n}; every member: the member blocks
     hipStream_t s;
     Workspace ws;
 };
@@ -76,47 +88,60 @@ int upload_f32(Ctx& c, const char* name, const std::vector<double>& h, size_t n,
     return RTT_OK;
 }
 
-// Orthonormalise the l (padded to lp) vectors of length n stored in *Y (row
-// stride n), using *T as ping-pong storage; on return *Y holds Q.  R_total
-// (lp x lp, row-major, upper) receives the accumulated triangular factor with
-// Y = Q R_total on the retained columns.
-int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, std::vector<double>& R_total, int* n_dead)
+// Orthonormalise, independently on every segment, the l (padded to lp) vectors stored in *Y
+// (row stride n), using *T as ping-pong storage; on return *Y holds Q.  R_total[seg] (lp x lp,
+// row-major, upper) receives the accumulated triangular factor with Y = Q R_total on the
+// retained columns of that segment.
+int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>& segs,
+         std::vector<std::vector<double>>& R_total)
 {
     double* Gd = (double*)c.ws.get("orth_gram", sizeof(double) * lp * lp);
     if (!Gd) return fail(RTT_ENOMEM, "orth gram");
-    R_total.assign((size_t)lp * lp, 0.0);
-    for (int i = 0; i < lp; ++i) R_total[(size_t)i * lp + i] = 1.0;
-    int passes = 2;
+    const size_t ns = segs.size();
+    R_total.assign(ns, std::vector<double>((size_t)lp * lp, 0.0));
+    std::vector<int> passes(ns, 2);
+    for (size_t q = 0; q < ns; ++q)
+        for (int i = 0; i < lp; ++i) R_total[q][(size_t)i * lp + i] = 1.0;
     std::vector<double> G, R, Ri, Rt;
     std::vector<char> dead;
-    for (int pass = 0; pass < passes; ++pass) {
-        int rc = gram(c.ws, *Y, n, *Y, n, lp, lp, n, Gd, c.s);
-        if (rc) return rc;
-        if ((rc = download(c, Gd, G, (size_t)lp * lp))) return rc;
-        double maxdiag = 0.0;
-        for (int i = 0; i < lp; ++i) maxdiag = std::max(maxdiag, G[(size_t)i * lp + i]);
-        double shift = 0.0;
-        const double dead_tol = pass == 0 ? 1e-12 : 1e-8;
-        int nd = cholesky_upper(G, lp, 0.0, dead_tol, R, dead);
-        if (pass == 0) {
-            // a pivot below the FP32 Gram accuracy: shift the first pass and add a third one
-            double minpiv = INFINITY;
-            for (int i = 0; i < lp; ++i)
-                if (!dead[i]) minpiv = std::min(minpiv, R[(size_t)i * lp + i] * R[(size_t)i * lp + i]);
-            if (minpiv < 1e-5 * maxdiag) {
-                shift = 1e-6 * maxdiag;
-                nd = cholesky_upper(G, lp, shift, dead_tol, R, dead);
-                passes = 3;
+    for (int pass = 0; pass < 3; ++pass) {
+        if (pass == 2 && std::none_of(passes.begin(), passes.end(), [](int p) { return p > 2; })) break;
+        for (size_t q = 0; q < ns; ++q) {
+            const Seg sg = segs[q];
+            float* Ys = *Y + sg.off;
+            float* Ts = *T + sg.off;
+            if (pass >= passes[q]) {
+                // this segment is finished: carry it over to the buffer that becomes *Y
+                if (sg.len > 0)
+                    RTT_HIP(hipMemcpy2DAsync(Ts, n * sizeof(float), Ys, n * sizeof(float), sg.len * sizeof(float),
+                                             lp, hipMemcpyDeviceToDevice, c.s));
+                continue;
             }
+            int rc = gram(c.ws, Ys, n, Ys, n, lp, lp, sg.len, Gd, c.s);
+            if (rc) return rc;
+            if ((rc = download(c, Gd, G, (size_t)lp * lp))) return rc;
+            double maxdiag = 0.0;
+            for (int i = 0; i < lp; ++i) maxdiag = std::max(maxdiag, G[(size_t)i * lp + i]);
+            const double dead_tol = pass == 0 ? 1e-12 : 1e-8;
+            cholesky_upper(G, lp, 0.0, dead_tol, R, dead);
+            if (pass == 0) {
+                // a pivot below the FP32 Gram accuracy: shift the first pass and add a third one
+                double minpiv = INFINITY;
+                for (int i = 0; i < lp; ++i)
+                    if (!dead[i]) minpiv = std::min(minpiv, R[(size_t)i * lp + i] * R[(size_t)i * lp + i]);
+                if (minpiv < 1e-5 * maxdiag) {
+                    cholesky_upper(G, lp, 1e-6 * maxdiag, dead_tol, R, dead);
+                    passes[q] = 3;
+                }
+            }
+            upper_inverse(R, lp, dead, Ri);
+            float* Cd = nullptr;
+            if ((rc = upload_f32(c, "orth_rinv", Ri, (size_t)lp * lp, &Cd))) return rc;
+            if ((rc = combine(Cd, lp, lp, Ys, n, Ts, n, sg.len, 0.f, c.s))) return rc;
+            matmul(R, R_total[q], lp, Rt);
+            R_total[q].swap(Rt);
         }
-        if (n_dead) *n_dead = nd;
-        upper_inverse(R, lp, dead, Ri);
-        float* Cd = nullptr;
-        if ((rc = upload_f32(c, "orth_rinv", Ri, (size_t)lp * lp, &Cd))) return rc;
-        if ((rc = combine(Cd, lp, lp, *Y, n, *T, n, n, 0.f, c.s))) return rc;
         std::swap(*Y, *T);
-        matmul(R, R_total, lp, Rt);
-        R_total.swap(Rt);
     }
     return RTT_OK;
 }
@@ -128,80 +153,97 @@ float* dev_alloc(Ctx& c, const char* name, size_t n)
 
 int apply(Ctx& c, bool adjoint, const float* in, float* out, int nvec)
 {
-    return apply_op(c.g, c.member, adjoint, in, out, nvec, c.mask, c.s);
+    return apply_op(c.g, c.member >= 0 ? c.member : -1, adjoint, in, out, nvec, c.mask, c.s);
 }
 
 int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
 {
     const int l = o.k + o.p, lp = pad32(l);
     const int64_t n = c.n_cols, m = c.n_rows;
+    const int sets = (int)c.cseg.size();
     float* X = dev_alloc(c, "rs_x", (size_t)lp * n);
     float* X2 = dev_alloc(c, "rs_x2", (size_t)lp * n);
     float* Y = dev_alloc(c, "rs_y", (size_t)lp * m);
     float* Y2 = dev_alloc(c, "rs_y2", (size_t)lp * m);
     if (!X || !X2 || !Y || !Y2) return fail(RTT_ENOMEM, "rsvd block buffers");
-    RTT_HIP(hipMemsetAsync(X, 0, sizeof(float) * lp * n, c.s));
-    RTT_HIP(hipMemsetAsync(Y, 0, sizeof(float) * lp * m, c.s));
-    RTT_HIP(hipMemsetAsync(X2, 0, sizeof(float) * lp * n, c.s));
-    RTT_HIP(hipMemsetAsync(Y2, 0, sizeof(float) * lp * m, c.s));
-    if (omega) RTT_HIP(hipMemcpyAsync(X, omega, sizeof(float) * l * n, hipMemcpyDeviceToDevice, c.s));
-    else {
-        int rc = normal_fill(X, (int64_t)l * n, o.seed, c.s);
-        if (rc) return rc;
-    }
-    std::vector<double> R;
     int rc;
+    if ((rc = fill(X, (int64_t)lp * n, 0.f, c.s)) || (rc = fill(Y, (int64_t)lp * m, 0.f, c.s)) ||
+        (rc = fill(X2, (int64_t)lp * n, 0.f, c.s)) || (rc = fill(Y2, (int64_t)lp * m, 0.f, c.s)))
+        return rc;
+    if (omega) RTT_HIP(hipMemcpyAsync(X, omega, sizeof(float) * l * n, hipMemcpyDeviceToDevice, c.s));
+    else if ((rc = normal_fill(X, (int64_t)l * n, o.seed, c.s))) return rc;
+    std::vector<std::vector<double>> R;
     // Y = A Omega; Q = orth(Y)
     if ((rc = apply(c, false, X, Y, l))) return rc;
-    if ((rc = orth(c, &Y, &Y2, lp, m, R, nullptr))) return rc;
+    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R))) return rc;
     for (int it = 0; it < o.q; ++it) {
         if ((rc = apply(c, true, Y, X, l))) return rc;
-        if ((rc = orth(c, &X, &X2, lp, n, R, nullptr))) return rc;
+        if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R))) return rc;
         if ((rc = apply(c, false, X, Y, l))) return rc;
-        if ((rc = orth(c, &Y, &Y2, lp, m, R, nullptr))) return rc;
+        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R))) return rc;
     }
     // B^T = A^T Q = Qb R
     if ((rc = apply(c, true, Y, X, l))) return rc;
-    if ((rc = orth(c, &X, &X2, lp, n, R, nullptr))) return rc;
-    // SVD of R^T (l x l leading block)
-    std::vector<double> Mt((size_t)l * l), Ur, s, W;
-    for (int i = 0; i < l; ++i)
-        for (int j = 0; j < l; ++j) Mt[(size_t)i * l + j] = R[(size_t)j * lp + i];
-    jacobi_svd(Mt, l, Ur, s, W);
+    if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R))) return rc;
     const int k = o.k;
     res->k = k;
-    res->sigma.assign(s.begin(), s.begin() + k);
-    res->resid.assign(k, 0.0);
-    // V = Qb W[:, :k] ; U = Q Ur[:, :k]
-    std::vector<double> Wk((size_t)l * k), Uk((size_t)l * k);
-    for (int i = 0; i < l; ++i)
-        for (int j = 0; j < k; ++j) {
-            Wk[(size_t)i * k + j] = W[(size_t)i * l + j];
-            Uk[(size_t)i * k + j] = Ur[(size_t)i * l + j];
-        }
-    float* Cw = nullptr;
-    if ((rc = upload_f32(c, "rs_w", Wk, Wk.size(), &Cw))) return rc;
+    res->sets = sets;
+    res->sigma.assign((size_t)sets * k, 0.0);
+    res->resid.assign((size_t)sets * k, 0.0);
     RTT_HIP(hipMalloc((void**)&res->V, sizeof(float) * (size_t)k * n));
-    if ((rc = combine(Cw, l, k, X, n, res->V, n, n, 0.f, c.s))) return rc;
+    if (o.keep_u) RTT_HIP(hipMalloc((void**)&res->U, sizeof(float) * (size_t)k * m));
+    for (int q = 0; q < sets; ++q) {
+        // SVD of R^T (l x l leading block) of this set
+        std::vector<double> Mt((size_t)l * l), Ur, sv, W;
+        for (int i = 0; i < l; ++i)
+            for (int j = 0; j < l; ++j) Mt[(size_t)i * l + j] = R[q][(size_t)j * lp + i];
+        jacobi_svd(Mt, l, Ur, sv, W);
+        std::copy(sv.begin(), sv.begin() + k, res->sigma.begin() + (size_t)q * k);
+        // V = Qb W[:, :k] ; U = Q Ur[:, :k]
+        std::vector<double> Wk((size_t)l * k), Uk((size_t)l * k);
+        for (int i = 0; i < l; ++i)
+            for (int j = 0; j < k; ++j) {
+                Wk[(size_t)i * k + j] = W[(size_t)i * l + j];
+                Uk[(size_t)i * k + j] = Ur[(size_t)i * l + j];
+            }
+        float* Cw = nullptr;
+        if ((rc = upload_f32(c, "rs_w", Wk, Wk.size(), &Cw))) return rc;
+        const Seg cs = c.cseg[q], rs = c.rseg[q];
+        if ((rc = combine(Cw, l, k, X + cs.off, n, res->V + cs.off, n, cs.len, 0.f, c.s))) return rc;
+        if (o.keep_u) {
+            float* Cu = nullptr;
+            if ((rc = upload_f32(c, "rs_u", Uk, Uk.size(), &Cu))) return rc;
+            if ((rc = combine(Cu, l, k, Y + rs.off, m, res->U + rs.off, m, rs.len, 0.f, c.s))) return rc;
+        }
+    }
     if (o.keep_u) {
-        float* Cu = nullptr;
-        if ((rc = upload_f32(c, "rs_u", Uk, Uk.size(), &Cu))) return rc;
-        RTT_HIP(hipMalloc((void**)&res->U, sizeof(float) * (size_t)k * m));
-        if ((rc = combine(Cu, l, k, Y, m, res->U, m, m, 0.f, c.s))) return rc;
-        // residuals || A v_i - sigma_i u_i ||
+        // residuals || A v_i - sigma_i u_i || per set
         float* AV = Y2;
         if ((rc = apply(c, false, res->V, AV, k))) return rc;
-        double* d = (double*)c.ws.get("rs_dots", sizeof(double) * 3 * k);
-        if (!d) return fail(RTT_ENOMEM, "dots");
-        if ((rc = dots(c.ws, AV, m, AV, m, m, k, d, c.s))) return rc;
-        if ((rc = dots(c.ws, AV, m, res->U, m, m, k, d + k, c.s))) return rc;
-        if ((rc = dots(c.ws, res->U, m, res->U, m, m, k, d + 2 * k, c.s))) return rc;
-        std::vector<double> h;
-        if ((rc = download(c, d, h, 3 * (size_t)k))) return rc;
-        for (int i = 0; i < k; ++i) {
-            const double si = res->sigma[i];
-            res->resid[i] = std::sqrt(std::max(0.0, h[i] - 2 * si * h[k + i] + si * si * h[2 * k + i]));
+        const size_t nd = (size_t)k * sets;
+        double* d = (double*)c.ws.get("rs_dots", sizeof(double) * 3 * nd);
+        int64_t* segd = (int64_t*)c.ws.get("rs_seg", sizeof(int64_t) * 2 * sets);
+        if (!d || !segd) return fail(RTT_ENOMEM, "dots");
+        std::vector<int64_t> hs;
+        int64_t maxlen = 0;
+        for (const Seg& sg : c.rseg) {
+            hs.insert(hs.end(), {sg.off, sg.len});
+            maxlen = std::max(maxlen, sg.len);
         }
+        RTT_HIP(hipMemcpyAsync(segd, hs.data(), hs.size() * sizeof(int64_t), hipMemcpyHostToDevice, c.s));
+        if ((rc = dots_seg(c.ws, AV, m, AV, m, segd, sets, maxlen, k, d, c.s))) return rc;
+        if ((rc = dots_seg(c.ws, AV, m, res->U, m, segd, sets, maxlen, k, d + nd, c.s))) return rc;
+        if ((rc = dots_seg(c.ws, res->U, m, res->U, m, segd, sets, maxlen, k, d + 2 * nd, c.s))) return rc;
+        std::vector<double> h;
+        if ((rc = download(c, d, h, 3 * nd))) return rc;
+        // dots_seg output index: vector i, set q -> i * sets + q
+        for (int q = 0; q < sets; ++q)
+            for (int i = 0; i < k; ++i) {
+                const size_t e = (size_t)i * sets + q;
+                const double si = res->sigma[(size_t)q * k + i];
+                res->resid[(size_t)q * k + i] =
+                    std::sqrt(std::max(0.0, h[e] - 2 * si * h[nd + e] + si * si * h[2 * nd + e]));
+            }
     }
     RTT_HIP(hipStreamSynchronize(c.s));
     return RTT_OK;
@@ -225,7 +267,10 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
     if (start) RTT_HIP(hipMemcpyAsync(Z, start, sizeof(float) * b * n, hipMemcpyDeviceToDevice, c.s));
     else if ((rc = normal_fill(Z, (int64_t)b * n, o.seed, c.s))) return rc;
     std::vector<double> R, L, Rprev, T((size_t)mdim * mdim, 0.0), coef;
-    if ((rc = orth(c, &Z, &Z2, b, n, R, nullptr))) return rc;
+    std::vector<std::vector<double>> Rs;
+    const std::vector<Seg> cwhole{{0, n}}, rwhole{{0, m}};
+    if ((rc = orth(c, &Z, &Z2, b, n, cwhole, Rs))) return rc;
+    R = Rs[0];
     RTT_HIP(hipMemcpyAsync(Vall, Z, sizeof(float) * b * n, hipMemcpyDeviceToDevice, c.s));
     bool have_prev = false;
     for (int j = 0; j < steps; ++j) {
@@ -240,7 +285,8 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
             if ((rc = upload_f32(c, "lz_c1", C, C.size(), &Cf))) return rc;
             if ((rc = combine(Cf, b, b, Up, m, W, m, m, 1.f, c.s))) return rc;
         }
-        if ((rc = orth(c, &W, &W2, b, m, L, nullptr))) return rc;   // W now holds U_j
+        if ((rc = orth(c, &W, &W2, b, m, rwhole, Rs))) return rc;   // W now holds U_j
+        L = Rs[0];
         for (int i = 0; i < b; ++i)
             for (int jj = 0; jj < b; ++jj) T[(size_t)(j * b + i) * mdim + j * b + jj] = L[(size_t)i * b + jj];
         // Z = A^T U_j - V_j L_j^T
@@ -263,7 +309,8 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
             if ((rc = upload_f32(c, "lz_c3", coef, coef.size(), &Cf))) return rc;
             if ((rc = combine(Cf, nv, b, Vall, n, Z, n, n, 1.f, c.s))) return rc;
         }
-        if ((rc = orth(c, &Z, &Z2, b, n, R, nullptr))) return rc;   // Z = V_{j+1}, R_j
+        if ((rc = orth(c, &Z, &Z2, b, n, cwhole, Rs))) return rc;   // Z = V_{j+1}, R_j
+        R = Rs[0];
         if (j + 1 < steps) {
             for (int i = 0; i < b; ++i)
                 for (int jj = 0; jj < b; ++jj)
@@ -308,13 +355,25 @@ extern "C" int rsvd(const rtt_geometry* g, const rtt_svd_opts* o, const float* o
     if (out) *out = nullptr;
     if (!out || !o) return fail(RTT_EINVAL, "rsvd: NULL opts or out");
     if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
-    if (o->geometry < -1 || o->geometry >= (int)g->members.size()) return fail(RTT_EINVAL, "rsvd: bad member index");
+    if (o->geometry < RTT_EACH_GEOMETRY || o->geometry >= (int)g->members.size())
+        return fail(RTT_EINVAL, "rsvd: bad member index");
     Ctx c;
     c.g = g;
     c.member = o->geometry;
     c.mask = o->order_mask;
     c.n_rows = c.member < 0 ? g->n_rows : g->members[c.member].n_rows;
     c.n_cols = c.member < 0 ? g->n_cols : g->members[c.member].n_cols;
+    if (c.member == RTT_EACH_GEOMETRY) {
+        for (const Member& m : g->members) {
+            c.rseg.push_back({m.row_offset, m.n_rows});
+            c.cseg.push_back({m.col_offset, m.n_cols});
+        }
+    } else {
+        c.rseg.push_back({0, c.n_rows});
+        c.cseg.push_back({0, c.n_cols});
+    }
+    int64_t min_dim = INT64_MAX;
+    for (size_t q = 0; q < c.rseg.size(); ++q) min_dim = std::min({min_dim, c.rseg[q].len, c.cseg[q].len});
     c.s = (hipStream_t)stream;
     std::unique_ptr<rtt_svd> res(new rtt_svd());
     res->member = c.member;
@@ -324,10 +383,11 @@ extern "C" int rsvd(const rtt_geometry* g, const rtt_svd_opts* o, const float* o
     if (o->method == RTT_SVD_RSVD) {
         if (o->k < 1 || o->p < 0 || o->q < 0 || o->q > 64) return fail(RTT_EINVAL, "rsvd: need k >= 1, p >= 0, 0 <= q <= 64");
         if (o->k + o->p > 512) return fail(RTT_EINVAL, "rsvd: k + p must be <= 512");
-        if ((int64_t)(o->k + o->p) > std::min(c.n_rows, c.n_cols))
+        if ((int64_t)(o->k + o->p) > min_dim)
             return fail(RTT_EINVAL, "rsvd: k + p exceeds the matrix dimensions");
         rc = run_rsvd(c, *o, omega, res.get());
     } else if (o->method == RTT_SVD_BLOCK_LANCZOS) {
+        if (c.member == RTT_EACH_GEOMETRY) return fail(RTT_EINVAL, "lanczos: one geometry (or the whole operator) per call");
         if (o->block < 32 || o->steps < 1 || (int64_t)o->block * o->steps > 1024 || o->k < 1)
             return fail(RTT_EINVAL, "lanczos: need block >= 32 (multiple of 32), steps >= 1, block*steps <= 1024");
         if ((int64_t)o->block * o->steps > std::min(c.n_rows, c.n_cols))
@@ -337,6 +397,8 @@ extern "C" int rsvd(const rtt_geometry* g, const rtt_svd_opts* o, const float* o
         return fail(RTT_EINVAL, "rsvd: unknown method");
     }
     if (rc) return rc;
+    RTT_HIP(hipMalloc((void**)&res->d_sigma, sizeof(double) * res->sigma.size()));
+    RTT_HIP(hipMemcpy(res->d_sigma, res->sigma.data(), sizeof(double) * res->sigma.size(), hipMemcpyHostToDevice));
     *out = res.release();
     return RTT_OK;
 }
@@ -355,8 +417,8 @@ extern "C" int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, con
 {
     if (!s || s->magic != 0x53564431u) return fail(RTT_EINVAL, "invalid svd handle");
     if (k_out) *k_out = s->k;
-    if (sigma_host) std::memcpy(sigma_host, s->sigma.data(), sizeof(double) * s->k);
-    if (resid_host) std::memcpy(resid_host, s->resid.data(), sizeof(double) * s->k);
+    if (sigma_host) std::memcpy(sigma_host, s->sigma.data(), sizeof(double) * s->sigma.size());
+    if (resid_host) std::memcpy(resid_host, s->resid.data(), sizeof(double) * s->resid.size());
     if (V_dev) *V_dev = s->V;
     if (U_dev) *U_dev = s->U;
     return RTT_OK;
@@ -369,38 +431,46 @@ extern "C" int tsvd_solve(const rtt_geometry* g, const rtt_svd* sv, const float*
     if (!sv || sv->magic != 0x53564431u) return fail(RTT_EINVAL, "invalid svd handle");
     if (nrhs < 0 || nrhs > 4096) return fail(RTT_EINVAL, "nrhs must be 0..4096");
     if (nrhs > 0 && (!y || !x)) return fail(RTT_EINVAL, "NULL data pointer");
+    if (sv->member >= (int)g->members.size() || (sv->member == RTT_EACH_GEOMETRY && sv->sets != (int)g->members.size()) ||
+        sv->n_cols != (sv->member >= 0 ? g->members[sv->member].n_cols : g->n_cols))
+        return fail(RTT_EINVAL, "tsvd_solve: the factors belong to another geometry");
+    if (t > sv->k) return fail(RTT_EINVAL, "tsvd_solve: t exceeds the number of singular triplets");
     if (nrhs == 0) return RTT_OK;
+    // kept components: i < t (t > 0), or sigma_i >= sigma_min (t <= 0); zero singular values never
     int tt = t;
-    if (tt <= 0) {
+    double smin = t > 0 ? 0.0 : sigma_min;
+    if (t <= 0) {
         tt = 0;
-        while (tt < sv->k && sv->sigma[tt] >= sigma_min && sv->sigma[tt] > 0.0) ++tt;
+        for (int q = 0; q < sv->sets; ++q) {
+            int c = 0;
+            while (c < sv->k && sv->sigma[(size_t)q * sv->k + c] >= sigma_min && sv->sigma[(size_t)q * sv->k + c] > 0.0)
+                ++c;
+            tt = std::max(tt, c);
+        }
     }
-    if (tt > sv->k) return fail(RTT_EINVAL, "tsvd_solve: t exceeds the number of singular triplets");
-    Ctx c;
-    c.g = g;
-    c.member = sv->member;
-    c.mask = 0;
-    c.n_rows = sv->n_rows;
-    c.n_cols = sv->n_cols;
-    c.s = (hipStream_t)stream;
-    const int64_t n = c.n_cols;
-    if (tt == 0) {
-        RTT_HIP(hipMemsetAsync(x, 0, sizeof(float) * (size_t)nrhs * n, c.s));
-        return RTT_OK;
-    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = sv->n_cols;
     int rc;
-    // g = A^T y (into x), c = V_t g, c_i /= sigma_i^2, x = V_t^T c
-    if ((rc = apply_op(g, c.member, true, y, x, nrhs, 0, c.s))) return rc;
-    double* Cd = (double*)c.ws.get("ts_c", sizeof(double) * (size_t)tt * nrhs);
-    if (!Cd) return fail(RTT_ENOMEM, "tsvd workspace");
-    if ((rc = gram(c.ws, sv->V, n, x, n, tt, nrhs, n, Cd, c.s))) return rc;
-    std::vector<double> coef;
-    if ((rc = download(c, Cd, coef, (size_t)tt * nrhs))) return rc;
-    for (int i = 0; i < tt; ++i)
-        for (int r = 0; r < nrhs; ++r) coef[(size_t)i * nrhs + r] /= sv->sigma[i] * sv->sigma[i];
-    float* Cf = nullptr;
-    if ((rc = upload_f32(c, "ts_cf", coef, coef.size(), &Cf))) return rc;
-    if ((rc = combine(Cf, tt, nrhs, sv->V, n, x, n, n, 0.f, c.s))) return rc;
-    RTT_HIP(hipStreamSynchronize(c.s));
+    if (tt == 0) return fill(x, (int64_t)nrhs * n, 0.f, s);
+    if (!sv->ws) const_cast<rtt_svd*>(sv)->ws = new (std::nothrow) Workspace();
+    if (!sv->ws) return fail(RTT_ENOMEM, "tsvd workspace");
+    Workspace& ws = *sv->ws;
+    const int sets = sv->sets;
+    double* Cd = (double*)ws.get("ts_c", sizeof(double) * (size_t)sets * tt * nrhs);
+    float* Cf = (float*)ws.get("ts_cf", sizeof(float) * (size_t)sets * tt * nrhs);
+    if (!Cd || !Cf) return fail(RTT_ENOMEM, "tsvd workspace");
+    // x = A^T y, then per set c = V_t x (coefficients), c_i /= sigma_i^2, x = V_t^T c
+    if ((rc = apply_op(g, sv->member >= 0 ? sv->member : -1, true, y, x, nrhs, 0, s))) return rc;
+    for (int q = 0; q < sets; ++q) {
+        const int64_t off = sets > 1 ? g->members[q].col_offset : 0;
+        const int64_t len = sets > 1 ? g->members[q].n_cols : n;
+        if ((rc = gram(ws, sv->V + off, n, x + off, n, tt, nrhs, len, Cd + (size_t)q * tt * nrhs, s))) return rc;
+    }
+    if ((rc = scale_inv_sq(Cd, sv->d_sigma, sets, tt, sv->k, nrhs, smin, Cf, s))) return rc;
+    for (int q = 0; q < sets; ++q) {
+        const int64_t off = sets > 1 ? g->members[q].col_offset : 0;
+        const int64_t len = sets > 1 ? g->members[q].n_cols : n;
+        if ((rc = combine(Cf + (size_t)q * tt * nrhs, tt, nrhs, sv->V + off, n, x + off, n, len, 0.f, s))) return rc;
+    }
     return RTT_OK;
 }

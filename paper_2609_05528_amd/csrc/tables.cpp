@@ -10,7 +10,7 @@
 #include <numeric>
 #include <sstream>
 
-#include "rtt_internal.h"
+#include "dense.h"
 
 namespace rtt {
 
@@ -95,6 +95,20 @@ static int check_grid(const rtt_grid& g, int idx)
 }  // namespace rtt
 
 using namespace rtt;
+
+// device memory of a handle (tables and the solver workspace)
+static void release_tables(rtt_geometry* h)
+{
+    if (h->d_rays) hipFree(h->d_rays);
+    if (h->d_cell_start) hipFree(h->d_cell_start);
+    if (h->d_visits) hipFree(h->d_visits);
+    if (h->d_vtask) hipFree(h->d_vtask);
+    if (h->d_fwd) hipFree(h->d_fwd);
+    if (h->d_seg) hipFree(h->d_seg);
+    delete h->solve_ws;
+    h->d_rays = nullptr;
+    h->solve_ws = nullptr;
+}
 
 extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int32_t n_geometries,
                              const rtt_load_opts* opts, rtt_geometry** out)
@@ -293,17 +307,20 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     if (e == hipSuccess && !visits.empty())
         e = hipMemcpy(h->d_visits, visits.data(), visits.size() * sizeof(Visit), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_vtask, vtask.data(), tb, hipMemcpyHostToDevice);
+    // (offset, length) of every member's column and row block, for per-member reductions
+    std::vector<int64_t> seg;
+    for (const Member& m : h->members) seg.insert(seg.end(), {m.col_offset, m.n_cols});
+    for (const Member& m : h->members) seg.insert(seg.end(), {m.row_offset, m.n_rows});
+    const size_t sb = seg.size() * sizeof(int64_t);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->d_seg, sb);
+    if (e == hipSuccess) e = hipMemcpy(h->d_seg, seg.data(), sb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "geometry_load upload");
-        if (h->d_rays) hipFree(h->d_rays);
-        if (h->d_cell_start) hipFree(h->d_cell_start);
-        if (h->d_visits) hipFree(h->d_visits);
-        if (h->d_vtask) hipFree(h->d_vtask);
-        if (h->d_fwd) hipFree(h->d_fwd);
+        release_tables(h);
         delete h;
         return rc;
     }
-    h->table_bytes = (int64_t)(rb + cb + vb + tb + fb);
+    h->table_bytes = (int64_t)(rb + cb + vb + tb + fb + sb);
     *out = h;
     return RTT_OK;
 }
@@ -312,11 +329,7 @@ extern "C" int geometry_free(rtt_geometry* g)
 {
     if (!g) return RTT_OK;
     if (g->magic != 0x52545447u) return fail(RTT_ESTATE, "not a geometry handle");
-    if (g->d_rays) hipFree(g->d_rays);
-    if (g->d_cell_start) hipFree(g->d_cell_start);
-    if (g->d_visits) hipFree(g->d_visits);
-    if (g->d_vtask) hipFree(g->d_vtask);
-    if (g->d_fwd) hipFree(g->d_fwd);
+    release_tables(g);
     g->magic = 0;
     delete g;
     return RTT_OK;

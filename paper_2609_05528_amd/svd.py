@@ -5,26 +5,28 @@ import ctypes
 
 import numpy as np
 
-from . import (RTT_SVD_BLOCK_LANCZOS, RTT_SVD_RSVD, _check, _dev_ptr, _nvec, _stream, require_native,
-               rtt_cg_opts, rtt_solve_info, rtt_svd_opts)
+from . import (RTT_EACH_GEOMETRY, RTT_SOLVE_ASYNC, RTT_SVD_BLOCK_LANCZOS, RTT_SVD_RSVD, _check, _dev_ptr, _nvec,
+               _stream, require_native, rtt_cg_opts, rtt_solve_info, rtt_svd_opts)
 
 
 class SVD:
     """Singular factors held in device memory by the library (rtt_svd)."""
 
-    def __init__(self, handle, geom):
+    def __init__(self, handle, geom, sets=1):
         self._h = handle
         self.geom = geom
         lib = require_native()
         k = ctypes.c_int32()
         _check(lib.svd_get(handle, ctypes.byref(k), None, None, None, None))
         self.k = k.value
-        sig = np.zeros(self.k)
-        res = np.zeros(self.k)
+        self.sets = sets
+        sig = np.zeros(self.k * sets)
+        res = np.zeros(self.k * sets)
         _check(lib.svd_get(handle, None, sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None,
                            res.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        self.sigma = sig
-        self.residual = res
+        # [k] for one operator, [G][k] for factors of every geometry
+        self.sigma = sig if sets == 1 else sig.reshape(sets, self.k)
+        self.residual = res if sets == 1 else res.reshape(sets, self.k)
 
     def _ptr(self, which):
         lib = require_native()
@@ -42,6 +44,11 @@ class SVD:
     @property
     def geom_rows(self):
         return self.geom.n_rows if self._member is None else self.geom.members[self._member]["n_rows"]
+
+    def block(self, V, g):
+        """Geometry g's part of a [k][n_cols] factor of RTT_EACH_GEOMETRY factors."""
+        m = self.geom.members[g]
+        return V[:, m["col_offset"]:m["col_offset"] + m["n_cols"]]
 
     _member = None
 
@@ -111,7 +118,7 @@ def rsvd(geom, k=256, p=8, q=2, omega=None, method="rsvd", block=32, steps=16, o
         om = _dev_ptr(omega, nv * n_cols, "omega")
     h = ctypes.c_void_p()
     _check(lib.rsvd(geom.handle, ctypes.byref(opts), om, ctypes.byref(h), _stream(stream)))
-    s = SVD(h, geom)
+    s = SVD(h, geom, sets=geom.n_geometries if geometry == RTT_EACH_GEOMETRY else 1)
     s._member = None if geometry < 0 else int(geometry)
     return s
 
@@ -129,13 +136,21 @@ def tsvd_solve(geom, svd: SVD, y, t=0, sigma_min=0.0, x=None, stream=None):
     return x
 
 
-def ridge_solve(geom, y, lam, tol=1e-6, maxit=1000, order_mask=0, x=None, stream=None, raise_on_noconv=True):
-    """Ridge estimate by CG on (A^T A + lam I) x = A^T y; returns (x, info dict)."""
+def ridge_solve(geom, y, lam, tol=1e-6, maxit=1000, order_mask=0, x=None, stream=None, raise_on_noconv=True,
+                async_mode=False, resid=None):
+    """Ridge estimate by CG on (A^T A + lam I) x = A^T y, one CG per (right-hand side, geometry);
+    returns (x, info dict).
+
+    async_mode: stream-ordered solve of exactly ``maxit`` iterations with no host
+    synchronisation (capturable into a graph once its scratch exists); ``resid``
+    (float32 CUDA [nrhs * n_geometries]) then receives the final relative residuals.
+    """
     import torch
     nrhs = _nvec(y, geom.n_rows)
     if x is None:
         x = torch.empty(y.shape[:-1] + (geom.n_cols,), dtype=torch.float32, device=y.device)
-    opts = rtt_cg_opts(float(tol), int(maxit), int(order_mask))
+    rp = None if resid is None else _dev_ptr(resid, nrhs * geom.n_geometries, "resid").value
+    opts = rtt_cg_opts(float(tol), int(maxit), int(order_mask), RTT_SOLVE_ASYNC if async_mode else 0, rp)
     info = rtt_solve_info()
     rc = require_native().ridge_solve(geom.handle, _dev_ptr(y, nrhs * geom.n_rows, "y"), nrhs, float(lam),
                                       ctypes.byref(opts), _dev_ptr(x, nrhs * geom.n_cols, "x"),
