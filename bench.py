@@ -12,7 +12,11 @@ Printed: one JSON line with the throughput (applies/s), the roofline of the
 dominant kernel (algorithmic bytes / measured kernel time vs the 8 TB/s HBM
 peak), the plain per-vector throughput beside the batched one, parity against
 the FP64 oracle on sampled vectors, and the oracle's own CPU throughput on
-one full step of the same work.
+one full step of the same work.  Extra sections: the 512^2 x 512-frame
+geometry one vector at a time, the rSVD wall time, and the batch of 12
+geometries x 60 histories (batched vs per-instance A/A^T and autograd, the
+rSVD of every geometry in one call, and one captured graph of A, A^T, TSVD
+and a fixed-count ridge solve of every (geometry, history) pair).
 """
 import argparse
 import json
@@ -100,6 +104,170 @@ def calibrate(torch, dev, gib=2):
     return out
 
 
+def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=2):
+    """The 12-geometry x 60-history batch: batched vs per-instance A/A^T and autograd, and one
+    captured graph of A, A^T, TSVD and a fixed-count ridge solve of every (geometry, history)."""
+    from paper_2609_05528_amd.autograd import ridge_loss
+    geos = synth.batch_geometries()
+    ng, nh = len(geos), synth.BATCH_HISTORIES
+    G = rtt.Geometry(geos)
+    lam = 1e-3
+    t0 = time.perf_counter()
+    G.tune(nvec=nh, reps=3)
+    t_tune = time.perf_counter() - t0
+    H = torch.from_numpy(synth.blob_histories(geos[0].grid, nh, dtype=np.float32)).to(dev)   # [60][S*K]
+    X = H.repeat(1, ng).contiguous()          # history h in every geometry's column block
+    Y = torch.empty((nh, G.n_rows), dtype=torch.float32, device=dev)
+    XT = torch.empty_like(X)
+    pairs = ng * nh
+    log("batch: %d geometries, %d histories, rows %d, cols %d, launch modes %s" % (
+        ng, nh, G.n_rows, G.n_cols, G.batch_mode))
+
+    # batched A + A^T over every (geometry, history) pair
+    rtt.op_apply(G, X, Y)
+    rtt.op_apply_adjoint(G, Y, XT)
+    torch.cuda.synchronize()
+    reps = 5
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        rtt.op_apply(G, X, Y)
+    ev[1].record()
+    for _ in range(reps):
+        rtt.op_apply_adjoint(G, Y, XT)
+    ev[2].record()
+    torch.cuda.synchronize()
+    ms_a, ms_at = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    ncell = sum(g.grid.n_cells for g in geos)
+    b_a = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, ncell, 3, nh, False)
+    b_at = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, ncell, 3, nh, True)
+    batched = 2 * pairs / ((ms_a + ms_at) * 1e-3)
+
+    # parity of sampled (geometry, history) pairs against the FP64 oracle
+    par = []
+    for gi, hi in ((0, 0), (ng - 1, nh - 1), (5, 31)):
+        m = G.members[gi]
+        yr = oracle.forward(geos[gi], H[hi].double().cpu().numpy())
+        ya = Y[hi, m["row_offset"]:m["row_offset"] + m["n_rows"]].double().cpu().numpy()
+        par.append(float(np.linalg.norm(ya - yr) / np.linalg.norm(yr)))
+        xr = oracle.adjoint(geos[gi], Y[hi, m["row_offset"]:m["row_offset"] + m["n_rows"]].double().cpu().numpy())
+        xa = XT[hi, m["col_offset"]:m["col_offset"] + m["n_cols"]].double().cpu().numpy()
+        par.append(float(np.linalg.norm(xa - xr) / np.linalg.norm(xr)))
+
+    # the same work as a plain loop: one handle per geometry, one history per call
+    singles = [rtt.Geometry(g) for g in geos]
+    for Gs in singles:
+        Gs.tune(nvec=1, reps=3)
+    yb = [torch.empty(Gs.n_rows, dtype=torch.float32, device=dev) for Gs in singles]
+    xb = [torch.empty(Gs.n_cols, dtype=torch.float32, device=dev) for Gs in singles]
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for h in range(nh):
+        for gi, Gs in enumerate(singles):
+            rtt.op_apply(Gs, H[h], yb[gi])
+            rtt.op_apply_adjoint(Gs, yb[gi], xb[gi])
+    torch.cuda.synchronize()
+    plain = 2 * pairs / (time.perf_counter() - tp0)
+
+    # autograd: ridge loss of every pair and its gradient in one call, vs one pair per call
+    Yobs = Y.clone()
+    Yobs.add_(0.01)
+    Xg = X.clone().requires_grad_(True)
+
+    def grad_step():
+        Xg.grad = None
+        ridge_loss(Xg, Yobs, G, lam).backward()
+
+    grad_step()
+    torch.cuda.synchronize()
+    ta0 = time.perf_counter()
+    for _ in range(3):
+        grad_step()
+    torch.cuda.synchronize()
+    ag_batched = 3 * pairs / (time.perf_counter() - ta0)
+    xs = [H[h].clone().requires_grad_(True) for h in range(nh)]
+    ys = [[Yobs[h, m["row_offset"]:m["row_offset"] + m["n_rows"]].contiguous() for m in G.members] for h in range(nh)]
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    for h in range(nh):
+        for gi, Gs in enumerate(singles):
+            xs[h].grad = None
+            ridge_loss(xs[h], ys[h][gi], Gs, lam).backward()
+    torch.cuda.synchronize()
+    ag_plain = pairs / (time.perf_counter() - tb0)
+    g_rel = float((xs[nh - 1].grad - Xg.grad[nh - 1, G.members[ng - 1]["col_offset"]:
+                                               G.members[ng - 1]["col_offset"] + G.members[ng - 1]["n_cols"]]).norm()
+                  / xs[nh - 1].grad.norm())
+    del xs, ys, singles, yb, xb, Xg
+    torch.cuda.empty_cache()
+
+    # rSVD of every geometry in one call, then the captured step
+    torch.cuda.synchronize()
+    tr0 = time.perf_counter()
+    sv = rtt.rsvd(G, k=k, p=p, q=q, seed=4001, geometry=rtt.RTT_EACH_GEOMETRY)
+    torch.cuda.synchronize()
+    t_rsvd = time.perf_counter() - tr0
+    Xts = torch.empty_like(X)
+    Xrg = torch.empty_like(X)
+    resid = torch.empty(pairs, dtype=torch.float32, device=dev)
+
+    def step():
+        rtt.op_apply(G, X, Y)
+        rtt.op_apply_adjoint(G, Yobs, XT)
+        rtt.tsvd_solve(G, sv, Yobs, t=k, x=Xts)
+        rtt.ridge_solve(G, Yobs, lam, maxit=ridge_iters, x=Xrg, async_mode=True, resid=resid)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - te0
+    ref = [t.clone() for t in (Y, XT, Xts, Xrg)]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    same = all(bool(torch.equal(a, b)) for a, b in zip(ref, (Y, XT, Xts, Xrg)))
+    gev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    greps = 3
+    gev[0].record()
+    for _ in range(greps):
+        graph.replay()
+    gev[1].record()
+    torch.cuda.synchronize()
+    ms_graph = gev[0].elapsed_time(gev[1]) / greps
+    del graph, sv
+    torch.cuda.empty_cache()
+    out = {
+        "workload": "12 geometries (spins 0/0.3/0.6/0.94 x incl 20/50/75, 96^2-256^2, 64-160 frames, "
+                    "orders 0-2) x 60 Gaussian-blob histories on a shared 64x64x96 basis",
+        "pairs": pairs, "rows": G.n_rows, "cols": G.n_cols, "rays": G.n_rays,
+        "launch_modes": list(G.batch_mode), "tune_seconds": t_tune,
+        "op_apply": {"ms": ms_a, "GBps": b_a / (ms_a * 1e-3) / 1e9},
+        "op_apply_adjoint": {"ms": ms_at, "GBps": b_at / (ms_at * 1e-3) / 1e9},
+        "batched_applies_per_s": batched, "plain_applies_per_s": plain,
+        "autograd_pairs_per_s": {"batched": ag_batched, "plain": ag_plain, "grad_rel_diff": g_rel},
+        "parity_max_rel_err": max(par),
+        "rsvd_each_geometry": {"seconds": t_rsvd, "k": k, "p": p, "q": q},
+        "graph_step": {"ms_replay": ms_graph, "s_eager": t_eager, "replay_equals_eager": same,
+                       "ridge_iterations": ridge_iters, "tsvd_t": k,
+                       "contents": "A + A^T + TSVD + ridge CG on every (geometry, history) pair"},
+    }
+    log("batch: A %.2f ms A^T %.2f ms (%.0f / %.0f GB/s); batched %.0f vs plain %.0f applies/s; "
+        "autograd %.0f vs %.0f pairs/s; graph %.1f ms" % (ms_a, ms_at, out["op_apply"]["GBps"],
+                                                          out["op_apply_adjoint"]["GBps"], batched, plain,
+                                                          ag_batched, ag_plain, ms_graph))
+    del X, Y, XT, Xts, Xrg, Yobs, H, G
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +280,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-rsvd", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -180,6 +349,9 @@ def main():
     dom = "op_apply_adjoint" if ms_at >= ms_a else "op_apply"
     dom_gbps = gbps_at if ms_at >= ms_a else gbps_a
     dom_bytes = b_at if ms_at >= ms_a else b_a
+
+    variants = {"op_apply": rtt.variant_names(False)[G.members[0]["apply_variant"]],
+                "op_apply_adjoint": rtt.variant_names(True)[G.members[0]["adjoint_variant"]]}
 
     # parity of two vectors of the block against the FP64 oracle
     import oracle
@@ -264,6 +436,13 @@ def main():
         log("rsvd: %.2f s, sigma_1 %.4g sigma_k %.4g" % (rs["seconds"], rs["sigma_1"], rs["sigma_k"]))
         del sv
 
+    n_rows, n_cols = G.n_rows, G.n_cols
+    batch = None
+    if not args.no_batch:
+        del G
+        torch.cuda.empty_cache()
+        batch = batch_section(torch, rtt, synth, oracle, dev)
+
     digest = source_digest()
     meas = MEASURED_TRAFFIC.get(dom)
     traffic = meas["bytes"] if (meas and meas.get("digest") == digest and meas.get("nvec") == nvec) else None
@@ -274,19 +453,19 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "%s: %s; block of %d vectors (rSVD l=k+p); step = A + A^T on the block"
                                % (args.workload, p["label"], nvec),
-                   "rays_per_order": geo.rays_per_order, "rows": G.n_rows, "cols": G.n_cols, "nvec": nvec},
+                   "rays_per_order": geo.rays_per_order, "rows": n_rows, "cols": n_cols, "nvec": nvec},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": dom_gbps / HBM_PEAK_GBPS, "traffic": traffic, "bytes_per_launch": dom_bytes,
                      "kernel_source_digest": digest},
         "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a},
                     "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at}},
         "hbm_gbps": (b_a + b_at) / ((ms_a + ms_at) * 1e-3) / 1e9,
-        "variants": {"op_apply": rtt.variant_names(False)[G.members[0]["apply_variant"]],
-                     "op_apply_adjoint": rtt.variant_names(True)[G.members[0]["adjoint_variant"]]},
+        "variants": variants,
         "plain_value": plain,
         "calibration": calib,
         "large_single_vector": large,
         "rsvd": rs,
+        "batch": batch,
         "parity": parity,
         "cpu_baseline": cpu,
     }
