@@ -28,6 +28,7 @@
 // and the hat fraction th = th0 + (fP mod Q)/Q - carry.  Both kernels use the
 // same function, so A^T is the exact transpose of A.
 #include <algorithm>
+#include <cstdlib>
 
 #include "rtt_internal.h"
 
@@ -683,6 +684,86 @@ __device__ __forceinline__ FwdRec load_const_rec(const FwdRec* p)
     return __builtin_bit_cast(FwdRec, r);
 }
 
+// Output phase shared by the staged forward kernels: the wave's NB combined series z (LDS rows
+// of ZS floats starting at zs0, hat h of ray j at zs0[j*ZS + h]) are interpolated to the frames
+// [f0, fend) of each ray and written to its data row (four frames per lane, 16-byte stores
+// when VEC4).
+template <int Q, int NB, bool VEC4>
+__device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, const int* row, const bool* on,
+                                          int f0, int fend, int F, float* __restrict__ y)
+{
+    constexpr int FC = 128 * Q;
+    constexpr int W = FC / Q + 4;
+    constexpr int ZI = (W + WAVE - 1) / WAVE;
+    constexpr int ZS = ZI * WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const float(*zs)[ZS] = (const float(*)[ZS])zs0;
+    if (VEC4) {
+        constexpr int NG = FC / 4;               // frame groups per ray chunk: 32 (Q=1) or 64 (Q=2)
+        constexpr int RPP = WAVE / NG;           // rays per pass: 2 or 1
+#pragma unroll
+        for (int p = 0; p < NB / RPP; ++p) {
+            const int sub = (RPP == 2) ? (lane >> 5) : 0;
+            const int g = lane & (NG - 1);
+            const int jA = p * RPP, jB = p * RPP + RPP - 1;
+            const bool pickB = sub != 0;
+            const float th = pickB ? th0[jB] : th0[jA];
+            const int rw = pickB ? row[jB] : row[jA];
+            const bool active = pickB ? on[jB] : on[jA];
+            const int f = f0 + 4 * g;
+            const float* zr = &zs[0][0] + (pickB ? jB : jA) * ZS;
+            f4 v;
+            if (Q == 1) {
+                const f4 z4 = *(const f4*)(zr + 4 * g);
+                const float z5 = zr[4 * g + 4];
+                v[0] = z4[0] + th * (z4[1] - z4[0]);
+                v[1] = z4[1] + th * (z4[2] - z4[1]);
+                v[2] = z4[2] + th * (z4[3] - z4[2]);
+                v[3] = z4[3] + th * (z5 - z4[3]);
+            } else {
+                typedef float f2 __attribute__((ext_vector_type(2)));
+                const f2 za = *(const f2*)(zr + 2 * g);
+                const f2 zb = *(const f2*)(zr + 2 * g + 2);
+                const float z0 = za[0], z1 = za[1], z2 = zb[0], z3 = zb[1];
+                const bool c1 = th >= 0.5f;
+                const float th1 = c1 ? th - 0.5f : th + 0.5f;
+                const float a1 = c1 ? z1 : z0, b1 = c1 ? z2 : z1;
+                const float a3 = c1 ? z2 : z1, b3 = c1 ? z3 : z2;
+                v[0] = z0 + th * (z1 - z0);
+                v[1] = a1 + th1 * (b1 - a1);
+                v[2] = z1 + th * (z2 - z1);
+                v[3] = a3 + th1 * (b3 - a3);
+            }
+            if (active && f < fend) __builtin_nontemporal_store(v, (f4*)(y + (int64_t)rw * F + f));
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (!on[j]) continue;
+            float* yr = y + (int64_t)row[j] * F;
+#pragma unroll
+            for (int t = 0; t < FC / WAVE; ++t) {
+                const int q = lane + t * WAVE;
+                const int f = f0 + q;
+                if (f >= fend) continue;
+                int jz;
+                float th;
+                if (Q == 1) {
+                    jz = q;
+                    th = th0[j];
+                } else {
+                    const bool odd = q & 1;
+                    const bool c1 = th0[j] >= 0.5f;
+                    jz = (q >> 1) + ((odd && c1) ? 1 : 0);
+                    th = odd ? (c1 ? th0[j] - 0.5f : th0[j] + 0.5f) : th0[j];
+                }
+                const float za = zs[j][jz], zb = zs[j][jz + 1];
+                __builtin_nontemporal_store(za + th * (zb - za), yr + f);
+            }
+        }
+    }
+}
+
 // One block of the lean forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, frame chunk
 // `chunk`, one vector (x, y already offset to the member's blocks).
 template <int Q, int NB, bool VEC4>
@@ -760,70 +841,7 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    if (VEC4) {
-        constexpr int NG = FC / 4;               // frame groups per ray chunk: 32 (Q=1) or 64 (Q=2)
-        constexpr int RPP = WAVE / NG;           // rays per pass: 2 or 1
-#pragma unroll
-        for (int p = 0; p < NB / RPP; ++p) {
-            const int sub = (RPP == 2) ? (lane >> 5) : 0;
-            const int g = lane & (NG - 1);
-            const int jA = p * RPP, jB = p * RPP + RPP - 1;
-            const bool pickB = sub != 0;
-            const float th = pickB ? th0[jB] : th0[jA];
-            const int rw = pickB ? row[jB] : row[jA];
-            const bool active = pickB ? on[jB] : on[jA];
-            const int f = f0 + 4 * g;
-            const float* zr = &zs[0][0] + (pickB ? jB : jA) * ZS;
-            f4 v;
-            if (Q == 1) {
-                const f4 z4 = *(const f4*)(zr + 4 * g);
-                const float z5 = zr[4 * g + 4];
-                v[0] = z4[0] + th * (z4[1] - z4[0]);
-                v[1] = z4[1] + th * (z4[2] - z4[1]);
-                v[2] = z4[2] + th * (z4[3] - z4[2]);
-                v[3] = z4[3] + th * (z5 - z4[3]);
-            } else {
-                typedef float f2 __attribute__((ext_vector_type(2)));
-                const f2 za = *(const f2*)(zr + 2 * g);
-                const f2 zb = *(const f2*)(zr + 2 * g + 2);
-                const float z0 = za[0], z1 = za[1], z2 = zb[0], z3 = zb[1];
-                const bool c1 = th >= 0.5f;
-                const float th1 = c1 ? th - 0.5f : th + 0.5f;
-                const float a1 = c1 ? z1 : z0, b1 = c1 ? z2 : z1;
-                const float a3 = c1 ? z2 : z1, b3 = c1 ? z3 : z2;
-                v[0] = z0 + th * (z1 - z0);
-                v[1] = a1 + th1 * (b1 - a1);
-                v[2] = z1 + th * (z2 - z1);
-                v[3] = a3 + th1 * (b3 - a3);
-            }
-            if (active && f < fend) __builtin_nontemporal_store(v, (f4*)(y + (int64_t)rw * a.F + f));
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            if (!on[j]) continue;
-            float* yr = y + (int64_t)row[j] * a.F;
-#pragma unroll
-            for (int t = 0; t < FC / WAVE; ++t) {
-                const int q = lane + t * WAVE;
-                const int f = f0 + q;
-                if (f >= fend) continue;
-                int jz;
-                float th;
-                if (Q == 1) {
-                    jz = q;
-                    th = th0[j];
-                } else {
-                    const bool odd = q & 1;
-                    const bool c1 = th0[j] >= 0.5f;
-                    jz = (q >> 1) + ((odd && c1) ? 1 : 0);
-                    th = odd ? (c1 ? th0[j] - 0.5f : th0[j] + 0.5f) : th0[j];
-                }
-                const float za = zs[j][jz], zb = zs[j][jz + 1];
-                __builtin_nontemporal_store(za + th * (zb - za), yr + f);
-            }
-        }
-    }
+    lean_emit<Q, NB, VEC4>(&zs[0][0], th0, row, on, f0, fend, a.F, y);
 }
 
 template <int Q, int NB, bool VEC4>
@@ -879,6 +897,294 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean_multi(LeanMulti a
         const uint32_t chunk = b / mm.nrb;
         lean_body<Q, NB, VEC4>(la, a.x + (int64_t)v * a.x_stride + mm.x_off, a.y + (int64_t)v * a.y_stride + mm.y_off,
                                (int64_t)(b - chunk * mm.nrb), (int)chunk);
+    }
+}
+
+// --------------------------------------------------------------------------------------------
+// A, strip form for dt_obs/dt_src = 1/Q (Q = 1, 2).  A workgroup owns a strip of SC base cells
+// of one cell row i (rays are sorted by base cell, so the strip's rays are one contiguous run)
+// and one frame chunk.  It first copies the x rows of every corner cell the strip can touch --
+// cells (i, j) and (i+1, j) for the SC + 1 columns j of the strip, over the hats the chunk can
+// reach -- into LDS with coalesced loads, then each wave forms the combined series z of its
+// rays from LDS and writes the rows as the lean form does.  Every x value is fetched through
+// L1 once per strip instead of once per ray and corner, which is what limits the lean form.
+// --------------------------------------------------------------------------------------------
+struct StripArgs {
+    const FwdRec* rec;       // the member's records, sorted by base cell
+    const int32_t* cstart;   // the member's CSR over base cells (n_cells + 1 entries)
+    int n_r, n_phi, K, F;
+    int SC, nstrip;          // strip width in base cells, strips per cell row
+    int w_alloc;             // hats per staged row (LDS row length)
+    int k0min, k0max;        // range of the records' k0
+    const float* x;
+    float* y;
+    int64_t x_stride, y_stride;
+    uint32_t mask;
+};
+
+template <int Q, int NB, bool VEC4>
+__device__ __forceinline__ void strip_body(const StripArgs& a, const float* __restrict__ x, float* __restrict__ y,
+                                           int64_t blk, int chunk)
+{
+    constexpr int FC = 128 * Q;
+    constexpr int W = FC / Q + 4;
+    constexpr int ZI = (W + WAVE - 1) / WAVE;
+    constexpr int ZS = ZI * WAVE;
+    extern __shared__ __attribute__((aligned(16))) float lds_dyn[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i = (int)(blk / a.nstrip), sg = (int)(blk % a.nstrip);
+    const int j0 = sg * a.SC;
+    const int ncs = min(a.SC, a.n_phi - j0);           // base columns of this strip
+    const int cbase = i * a.n_phi + j0;
+    const int r_begin = a.cstart[cbase], r_end = a.cstart[cbase + ncs];
+    if (r_begin >= r_end) return;                       // uniform over the workgroup
+    const int f0 = chunk * FC;
+    const int fend = min(a.F, f0 + FC);
+    const int hlo = max(0, a.k0min + f0 / Q);
+    const int hhi = min(a.K, a.k0max + f0 / Q + FC / Q + 2);
+    const int wst = hhi - hlo;                          // staged hats (may be <= 0: all zero)
+    const int ws = a.w_alloc;
+    float* st = lds_dyn;                                // [2][SC + 1][w_alloc]
+    // stage the corner rows: rr = 0 (row i), 1 (row i+1); cc = 0 .. ncs (periodic column)
+    for (int r = wave; r < 2 * (a.SC + 1); r += A_WAVES) {
+        const int rr = r / (a.SC + 1), cc = r % (a.SC + 1);
+        if (cc > ncs) continue;
+        int jc = j0 + cc;
+        if (jc >= a.n_phi) jc -= a.n_phi;
+        const float* xr = x + ((int64_t)(i + rr) * a.n_phi + jc) * a.K + hlo;
+        for (int h = lane; h < wst; h += WAVE) st[r * ws + h] = xr[h];
+    }
+    __syncthreads();
+    float* zs = lds_dyn + 2 * (a.SC + 1) * ws + wave * NB * ZS;
+    for (int rb = r_begin + wave * NB; rb < r_end; rb += A_WAVES * NB) {
+        // the previous round's output phase may still be reading this wave's z rows
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float th0[NB];
+        int row[NB];
+        bool on[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int ri = rb + j;
+            const FwdRec rc = load_const_rec(a.rec + (ri < r_end ? ri : r_end - 1));
+            on[j] = ri < r_end && ((a.mask >> rc.order) & 1u);
+            th0[j] = rc.th0;
+            row[j] = rc.row;
+            const int jc = rc.cell - cbase;             // local base column, 0 .. ncs-1
+            const float* r00 = st + jc * ws - hlo;      // corner rows indexed by hat k
+            const float* r01 = r00 + ws;
+            const float* r10 = r00 + (a.SC + 1) * ws;
+            const float* r11 = r10 + ws;
+            const int klo = rc.k0 + f0 / Q;
+#pragma unroll
+            for (int it = 0; it < ZI; ++it) {
+                const int h = lane + it * WAVE;
+                const int k = klo + h;
+                const bool ok = on[j] && k >= hlo && k < hhi;
+                const int kk = ok ? k : hlo;
+                const float z = rc.b00 * r00[kk] + rc.b10 * r10[kk] + rc.b01 * r01[kk] + rc.b11 * r11[kk];
+                if (h < W) zs[j * ZS + h] = ok ? z : 0.f;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        lean_emit<Q, NB, VEC4>(zs, th0, row, on, f0, fend, a.F, y);
+    }
+}
+
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_strip(StripArgs a)
+{
+    strip_body<Q, NB, VEC4>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
+                            xcd_remap(blockIdx.x, gridDim.x), blockIdx.z);
+}
+
+// --------------------------------------------------------------------------------------------
+// A, register form for dt_obs/dt_src = 1/Q (Q = 1, 2).  Lanes run over frames, four consecutive
+// frames per lane: a ray's frame chunk of 4 LPR frames is covered by LPR lanes and 64/LPR rays
+// share a wave pass.  Each lane reads the hats its four frames need straight into registers,
+// one 16-byte load per stencil corner (plus one 4-byte load for the fifth hat when Q = 1),
+// combines the corners, interpolates and writes its frames with one 16-byte store: no LDS, and
+// about a third of the memory instructions of the staged form.  A lane whose window would leave
+// the x vector (corners in the first or last cells only) reads its hats one by one with offsets
+// clamped into the vector.  Hats outside [0, K) contribute zero.  Records are scalar loads of
+// the pass's rays, picked per lane.
+// --------------------------------------------------------------------------------------------
+struct RegArgs {
+    const FwdRec* rec;
+    int64_t n_rays;
+    int K, F, nk, x_bytes;   // nk = n_phi * K: element step to the radial neighbour corner
+    const float* x;
+    float* y;
+    int64_t x_stride, y_stride;
+    uint32_t mask;
+};
+
+template <int Q, int LPR, int NI, bool VEC4>
+__device__ __forceinline__ void reg_body(const RegArgs& a, const float* __restrict__ x, float* __restrict__ y,
+                                         int64_t blk, int chunk)
+{
+    constexpr int R = WAVE / LPR;           // rays side by side in a pass
+    constexpr int FC = 4 * LPR;             // frames per chunk
+    constexpr int NH = Q == 1 ? 5 : 4;      // hats per lane
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar record loads
+    const int sub = lane / LPR;             // ray of this lane inside a pass
+    const int li = lane % LPR;              // lane inside the ray
+    const int64_t rb = (blk * A_WAVES + wave) * (int64_t)(R * NI);
+    if (rb >= a.n_rays) return;
+    const int f = chunk * FC + 4 * li;      // first frame of this lane (a multiple of 4)
+    const int hoff = f / Q;                 // its hat offset from k0 (exact: Q divides 4)
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
+    const int lim = a.x_bytes - 4 * NH;     // largest start (bytes) of a window inside x
+    const int last = a.x_bytes / 4 - 1;     // last element of x
+
+    int o[NI][4], kb[NI], row[NI];
+    float bw[NI][4], th[NI];
+    bool on[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        FwdRec rj[R];
+#pragma unroll
+        for (int s2 = 0; s2 < R; ++s2) {
+            const int64_t ri = rb + (int64_t)j * R + s2;
+            rj[s2] = load_const_rec(a.rec + (ri < a.n_rays ? ri : a.n_rays - 1));
+        }
+        FwdRec mine = rj[0];
+#pragma unroll
+        for (int s2 = 1; s2 < R; ++s2)
+            if (sub == s2) mine = rj[s2];
+        const int64_t ri = rb + (int64_t)j * R + sub;
+        on[j] = ri < a.n_rays && ((a.mask >> mine.order) & 1u) && f < a.F;
+        kb[j] = mine.k0 + hoff;
+        o[j][0] = mine.c00k + kb[j];          // corner (i, j0)
+        o[j][1] = o[j][0] + a.nk;             // corner (i+1, j0)
+        o[j][2] = o[j][0] + mine.d01k;        // corner (i, j0+1), periodic
+        o[j][3] = o[j][2] + a.nk;             // corner (i+1, j0+1)
+        bw[j][0] = mine.b00;
+        bw[j][1] = mine.b10;
+        bw[j][2] = mine.b01;
+        bw[j][3] = mine.b11;
+        th[j] = mine.th0;
+        row[j] = mine.row;
+    }
+    float xv[NI][4][NH];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        bool fast = lim >= 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fast = fast && (unsigned)(o[j][c] * 4) <= (unsigned)lim;
+        if (fast) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const f4 w = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, o[j][c] * 4, 0, 0));
+                xv[j][c][0] = w[0];
+                xv[j][c][1] = w[1];
+                xv[j][c][2] = w[2];
+                xv[j][c][3] = w[3];
+                if (Q == 1)
+                    xv[j][c][4] = __builtin_bit_cast(float,
+                                                     __builtin_amdgcn_raw_buffer_load_b32(xr, o[j][c] * 4 + 16, 0, 0));
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int h = 0; h < NH; ++h) {
+                    const int e = min(max(o[j][c] + h, 0), last);
+                    xv[j][c][h] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, e * 4, 0, 0));
+                }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+        if (!on[j]) continue;
+        float z[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const float zz = bw[j][0] * xv[j][0][h] + bw[j][1] * xv[j][1][h] + bw[j][2] * xv[j][2][h] +
+                             bw[j][3] * xv[j][3][h];
+            z[h] = (unsigned)(kb[j] + h) < (unsigned)a.K ? zz : 0.f;
+        }
+        const float t = th[j];
+        f4 v;
+        if (Q == 1) {
+            v[0] = z[0] + t * (z[1] - z[0]);
+            v[1] = z[1] + t * (z[2] - z[1]);
+            v[2] = z[2] + t * (z[3] - z[2]);
+            v[3] = z[3] + t * (z[4] - z[3]);
+        } else {
+            const bool c1 = t >= 0.5f;
+            const float t1 = c1 ? t - 0.5f : t + 0.5f;
+            const float a1 = c1 ? z[1] : z[0], b1 = c1 ? z[2] : z[1];
+            const float a3 = c1 ? z[2] : z[1], b3 = c1 ? z[3] : z[2];
+            v[0] = z[0] + t * (z[1] - z[0]);
+            v[1] = a1 + t1 * (b1 - a1);
+            v[2] = z[1] + t * (z[2] - z[1]);
+            v[3] = a3 + t1 * (b3 - a3);
+        }
+        float* yr = y + (int64_t)row[j] * a.F + f;
+        if (VEC4) {
+            __builtin_nontemporal_store(v, (f4*)yr);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (f + m < a.F) __builtin_nontemporal_store(v[m], yr + m);
+        }
+    }
+}
+
+template <int Q, int LPR, int NI, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_reg(RegArgs a)
+{
+    reg_body<Q, LPR, NI, VEC4>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
+                               xcd_remap(blockIdx.x, gridDim.x), blockIdx.z);
+}
+
+// Every member in one launch (tasks numbered as in k_apply_lean_multi).
+struct RegMember {
+    const FwdRec* rec;
+    int64_t n_rays;
+    int64_t x_off, y_off;
+    uint32_t blk_begin, nrb;
+    int K, F, nk, x_bytes;
+    uint32_t mask;
+};
+struct RegMulti {
+    RegMember m[MULTI_MAX];
+    int G;
+    uint32_t per_vec, total;
+    const float* x;
+    float* y;
+    int64_t x_stride, y_stride;
+};
+
+template <int Q, int LPR, int NI, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_reg_multi(RegMulti a)
+{
+    for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
+        const uint32_t lt = xcd_remap32(t, a.total);
+        const uint32_t v = lt / a.per_vec;
+        uint32_t b = lt - v * a.per_vec;
+        int g = 0;
+        while (g + 1 < a.G && b >= a.m[g + 1].blk_begin) ++g;
+        const RegMember& mm = a.m[g];
+        b -= mm.blk_begin;
+        RegArgs ra;
+        ra.rec = mm.rec;
+        ra.n_rays = mm.n_rays;
+        ra.K = mm.K;
+        ra.F = mm.F;
+        ra.nk = mm.nk;
+        ra.x_bytes = mm.x_bytes;
+        ra.mask = mm.mask;
+        const uint32_t chunk = b / mm.nrb;
+        reg_body<Q, LPR, NI, VEC4>(ra, a.x + (int64_t)v * a.x_stride + mm.x_off,
+                                   a.y + (int64_t)v * a.y_stride + mm.y_off, (int64_t)(b - chunk * mm.nrb),
+                                   (int)chunk);
     }
 }
 
@@ -1107,6 +1413,153 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMul
         visit_body<Q, V, NB, PAIR>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
                                    a.x + (int64_t)v * a.x_stride + mm.x_off, (int64_t)(b - mm.blk_begin));
     }
+}
+
+// --------------------------------------------------------------------------------------------
+// A^T, row-sweep form (dt_obs/dt_src = 1/Q) for launches over many vectors.  A wave owns a group
+// of CW output cell columns and a band of output cell rows of one vector, lanes running over
+// the hats (V per lane).  It sweeps the band's base rows in order; for every ray of base row i
+// whose stencil reaches its columns (base columns cw0-1 .. cw0+CW-1: one contiguous run of the
+// sorted rays, two at the periodic seam) it reads the ray's data row once, applies the ray's
+// fixed 2Q-tap hat filter and adds the four bilinear shares into two wave-private LDS rows:
+// output row i (top corners) and row i+1 (bottom corners).  Output row i is complete once base
+// rows i-1 and i are done: it is written with coalesced stores and its LDS row is cleared for
+// row i+2.  The rows are private to the wave and every lane owns its own hats, so plain
+// read-add-write updates in program order give bitwise reproducible sums (LDS float atomics
+// measured an order of magnitude slower).  A ray next to a column group or band edge is read by
+// both neighbours (once per 1/CW and 1/band of the rays).
+// --------------------------------------------------------------------------------------------
+struct RowsArgs {
+    const FwdRec* rec;       // the member's records, sorted by base cell
+    const int32_t* cstart;   // the member's CSR over base cells
+    int n_r, n_phi, K, F;
+    int ngroups, nbands, rb; // column groups, row bands, output rows per band
+    const float* y;
+    float* x;
+    int64_t y_stride, x_stride;
+    uint32_t mask;
+};
+
+template <int Q, int V, int CW, int NB, bool PAIR>
+__device__ __forceinline__ void rows_body(const RowsArgs& a, const float* __restrict__ y, float* __restrict__ x,
+                                          int grp, int band)
+{
+    typedef Taps<Q> TP_;
+    constexpr int T = TP_::T;
+    constexpr int KP = V * WAVE;
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    __shared__ float acc_all[T_WAVES][2][CW][KP];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float(*acc)[CW][KP] = acc_all[wave];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl)
+#pragma unroll
+        for (int c = 0; c < CW; ++c)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[sl][c][lane + WAVE * v] = 0.f;
+    if (grp >= a.ngroups || band >= a.nbands) return;
+    const int n_phi = a.n_phi;
+    const int cw0 = grp * CW;
+    const int cwe = min(CW, n_phi - cw0);            // columns owned
+    const int o0 = band * a.rb, o1 = min(a.n_r, o0 + a.rb);
+    const int ib = max(o0 - 1, 0), ie = min(o1, a.n_r - 1);
+    const int rowbytes = a.F * 4;
+    const int lane_off = Q * lane * 4;
+    const int cleft = cw0 == 0 ? n_phi - 1 : cw0 - 1; // base column feeding column cw0 from the left
+
+    // one run of rays [rb0, re0) of base row i; lfix >= -1: the run is base column cw0 + lfix
+    // (only for the left neighbour run, lfix = -1), else the local column comes from the record
+    auto run = [&](int i, int rb0, int re0, bool left) {
+        const int slot = i & 1;
+        const bool top = i >= o0, bot = i + 1 < o1;
+        for (int e0 = rb0; e0 < re0; e0 += NB) {
+            float yv[NB][V][T], tw[NB][T];
+            FwdRec rc[NB];
+            bool on[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int ri = e0 + j;
+                rc[j] = load_const_rec(a.rec + (ri < re0 ? ri : re0 - 1));
+                on[j] = ri < re0 && ((a.mask >> rc[j].order) & 1u);
+                const uint64_t base = (uint64_t)(y + (int64_t)rc[j].row * a.F);
+                const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+                const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+                const int nrec = __builtin_amdgcn_readfirstlane(on[j] ? rowbytes : 0);
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(((uint64_t)bhi << 32) | blo), (short)0, nrec, 0x00020000);
+                TP_::weights(rc[j].th0, tw[j]);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int ub = (Q * (WAVE * v - rc[j].k0) + TP_::MLO) * 4;
+                    if (PAIR) {
+#pragma unroll
+                        for (int t = 0; t < T; t += 2) {
+                            const unsigned off = min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u);
+                            const f2 p2 = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+                            yv[j][v][t] = p2[0];
+                            yv[j][v][t + 1] = p2[1];
+                        }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < T; ++t) {
+                            const unsigned off = min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u);
+                            yv[j][v][t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (!on[j]) continue;
+                // local column of the ray's j0 corner; its j1 corner is column lc + 1
+                const int lc = left ? -1 : rc[j].cell - (i * n_phi + cw0);
+                const bool c0 = lc >= 0, c1 = lc + 1 < cwe;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    float g = 0.f;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) g += tw[j][t] * yv[j][v][t];
+                    const int k = lane + WAVE * v;
+                    if (top && c0) acc[slot][lc][k] += rc[j].b00 * g;
+                    if (bot && c0) acc[slot ^ 1][lc][k] += rc[j].b10 * g;
+                    if (top && c1) acc[slot][lc + 1][k] += rc[j].b01 * g;
+                    if (bot && c1) acc[slot ^ 1][lc + 1][k] += rc[j].b11 * g;
+                }
+            }
+        }
+    };
+    auto emit_row = [&](int o) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int sl = o & 1;
+        for (int c = 0; c < cwe; ++c) {
+            float* xr = x + ((int64_t)o * n_phi + cw0 + c) * a.K;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k = lane + WAVE * v;
+                if (k < a.K) xr[k] = acc[sl][c][k];
+                acc[sl][c][k] = 0.f;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    for (int i = ib; i < ie; ++i) {
+        const int cb = i * n_phi;
+        run(i, a.cstart[cb + cleft], a.cstart[cb + cleft + 1], true);
+        run(i, a.cstart[cb + cw0], a.cstart[cb + cw0 + cwe], false);
+        if (i >= o0) emit_row(i);
+    }
+    if (o1 == a.n_r) emit_row(a.n_r - 1);
+}
+
+template <int Q, int V, int CW, int NB, bool PAIR>
+__global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_rows(RowsArgs a)
+{
+    // waves of a workgroup: consecutive column groups of one band (neighbours share rays)
+    const int64_t lin = xcd_remap(blockIdx.x, gridDim.x) * T_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = (int)(lin % a.ngroups), band = (int)(lin / a.ngroups);
+    rows_body<Q, V, CW, NB, PAIR>(a, a.y + (int64_t)blockIdx.y * a.y_stride, a.x + (int64_t)blockIdx.y * a.x_stride,
+                                  grp, band);
 }
 
 // --------------------------------------------------------------------------------------------
@@ -1402,15 +1855,17 @@ static const AdjVariant kAdjVariants[] = {
     {"tile8x8", 0, 8, 8},    {"tile4x8", 0, 4, 8},    {"tile4x4", 0, 4, 4},    {"sweep32v1", 1, 32, 1},
     {"sweep32v2", 1, 32, 2}, {"sweep16v1", 1, 16, 1}, {"sweep16v2", 1, 16, 2}, {"tb8x8", 2, 8, 8},
     {"tb4x8", 2, 4, 8},      {"tb4x4", 2, 4, 4},      {"tb2x4", 2, 2, 4},      {"visit", 3, 0, 0},
+    {"rows4", 4, 4, 0},      {"rows8", 4, 8, 0},
 };
 constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 6; }
+int n_apply_variants() { return 10; }
 const char* apply_variant_name(int v)
 {
-    static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8"};
+    static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8", "reg1", "reg2", "strip16",
+                                  "strip8"};
     return names[v];
 }
 bool lean_supported(const Member& m)
@@ -1419,6 +1874,48 @@ bool lean_supported(const Member& m)
 }
 
 bool visit_supported(const Member& m) { return m.P == 1 && (m.Q == 1 || m.Q == 2); }
+
+bool adjoint_variant_ok(const Member& m, int v)
+{
+    if (v < 0 || v >= n_adjoint_variants()) return false;
+    if (v == 11 && !visit_supported(m)) return false;
+    if (v >= 12 && !(visit_supported(m) && m.grid.n_hat <= 4 * WAVE)) return false;   // rows: K <= 256
+    return true;
+}
+
+// LDS bytes of the strip forward with strips of sc base cells (staged corner rows + z rows)
+static int64_t strip_lds_bytes(const Member& m, int sc)
+{
+    const int fcq = 128;   // hats per frame chunk (128 Q frames at ratio 1/Q)
+    const int64_t w = std::min<int64_t>(m.grid.n_hat, (int64_t)m.k0_max - m.k0_min + fcq + 2);
+    const int64_t zs = (int64_t)A_WAVES * 4 * (((fcq + 4) + WAVE - 1) / WAVE * WAVE);
+    return 4 * (2 * (int64_t)(sc + 1) * std::max<int64_t>(w, 1) + zs);
+}
+
+bool apply_variant_ok(const Member& m, int v)
+{
+    if (v < 0 || v >= n_apply_variants()) return false;
+    if ((v == 2 || v == 3) && m.P > m.Q) return false;   // batch / stream need dt_obs <= dt_src
+    if (v >= 4 && !lean_supported(m)) return false;      // lean / reg / strip need dt_obs/dt_src = 1 or 1/2
+    if (v >= 8 && strip_lds_bytes(m, v == 8 ? 16 : 8) > 65536) return false;
+    return true;
+}
+
+// Lanes per ray of the register forward (frames per chunk = 4 * LPR) for rows of F frames: the
+// chunk that wastes the fewest lanes, the longer one on ties.
+static int reg_lpr(int64_t F)
+{
+    int best = 64;
+    int64_t waste = INT64_MAX;
+    for (int lpr : {64, 32, 16}) {
+        const int64_t fc = 4 * lpr, w = (F + fc - 1) / fc * fc - F;
+        if (w < waste) {
+            waste = w;
+            best = lpr;
+        }
+    }
+    return best;
+}
 
 int default_adjoint_variant(const Member& m)
 {
@@ -1502,12 +1999,88 @@ static void lean_launch(const LeanArgs& a, int nvec, bool vec4, hipStream_t s)
     else hipLaunchKernelGGL((k_apply_lean<Q, NB, false>), grid, dim3(A_WAVES * WAVE), 0, s, a);
 }
 
+template <int Q, int LPR, int NI>
+static void reg_launch(const RegArgs& a, int nvec, bool vec4, hipStream_t s)
+{
+    constexpr int64_t rays_per_block = (int64_t)A_WAVES * (WAVE / LPR) * NI;
+    const int nch = (a.F + 4 * LPR - 1) / (4 * LPR);
+    dim3 grid((unsigned)((a.n_rays + rays_per_block - 1) / rays_per_block), (unsigned)nvec, (unsigned)nch);
+    if (vec4) hipLaunchKernelGGL((k_apply_reg<Q, LPR, NI, true>), grid, dim3(A_WAVES * WAVE), 0, s, a);
+    else hipLaunchKernelGGL((k_apply_reg<Q, LPR, NI, false>), grid, dim3(A_WAVES * WAVE), 0, s, a);
+}
+
+template <int Q, int NI>
+static void reg_dispatch(const RegArgs& a, int nvec, bool vec4, hipStream_t s)
+{
+    switch (reg_lpr(a.F)) {
+    case 16: reg_launch<Q, 16, NI>(a, nvec, vec4, s); break;
+    case 32: reg_launch<Q, 32, NI>(a, nvec, vec4, s); break;
+    default: reg_launch<Q, 64, NI>(a, nvec, vec4, s); break;
+    }
+}
+
 int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* y, int nvec,
                  int64_t x_stride, int64_t y_stride, uint32_t mask, hipStream_t s, int variant)
 {
     if (m.n_rays == 0 || nvec == 0) return RTT_OK;
     if (variant < 0 || variant >= n_apply_variants()) variant = m.apply_variant;
-    if ((variant == 4 || variant == 5) && !lean_supported(m)) variant = m.P <= m.Q ? 2 : 1;
+    if (!apply_variant_ok(m, variant)) variant = m.P <= m.Q ? 2 : 1;
+    if (variant == 8 || variant == 9) {
+        StripArgs sa;
+        sa.rec = g->d_fwd + m.ray_begin;
+        sa.cstart = g->d_cell_start + m.cell_begin;
+        sa.n_r = m.grid.n_r;
+        sa.n_phi = m.grid.n_phi;
+        sa.K = m.grid.n_hat;
+        sa.F = m.grid.n_frames;
+        sa.SC = variant == 8 ? 16 : 8;
+        sa.nstrip = (sa.n_phi + sa.SC - 1) / sa.SC;
+        sa.w_alloc = (int)std::max<int64_t>(1, std::min<int64_t>(sa.K, (int64_t)m.k0_max - m.k0_min + 130));
+        sa.k0min = m.k0_min;
+        sa.k0max = m.k0_max;
+        sa.x = x;
+        sa.y = y;
+        sa.x_stride = x_stride;
+        sa.y_stride = y_stride;
+        sa.mask = mask;
+        const bool vec4 = (sa.F % 4) == 0 && (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (y_stride % 4) == 0);
+        const int nch = (sa.F + 128 * m.Q - 1) / (128 * m.Q);
+        const dim3 grid((unsigned)((int64_t)(sa.n_r - 1) * sa.nstrip), (unsigned)nvec, (unsigned)nch);
+        const size_t lds = (size_t)strip_lds_bytes(m, sa.SC);
+        if (m.Q == 1) {
+            if (vec4) hipLaunchKernelGGL((k_apply_strip<1, 4, true>), grid, dim3(A_WAVES * WAVE), lds, s, sa);
+            else hipLaunchKernelGGL((k_apply_strip<1, 4, false>), grid, dim3(A_WAVES * WAVE), lds, s, sa);
+        } else {
+            if (vec4) hipLaunchKernelGGL((k_apply_strip<2, 4, true>), grid, dim3(A_WAVES * WAVE), lds, s, sa);
+            else hipLaunchKernelGGL((k_apply_strip<2, 4, false>), grid, dim3(A_WAVES * WAVE), lds, s, sa);
+        }
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
+    if (variant == 6 || variant == 7) {
+        RegArgs ra;
+        ra.rec = g->d_fwd + m.ray_begin;
+        ra.n_rays = m.n_rays;
+        ra.K = m.grid.n_hat;
+        ra.F = m.grid.n_frames;
+        ra.nk = m.grid.n_phi * m.grid.n_hat;
+        ra.x_bytes = (int)(m.n_cols * 4);
+        ra.x = x;
+        ra.y = y;
+        ra.x_stride = x_stride;
+        ra.y_stride = y_stride;
+        ra.mask = mask;
+        const bool vec4 = (ra.F % 4) == 0 && (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (y_stride % 4) == 0);
+        if (m.Q == 1) {
+            if (variant == 6) reg_dispatch<1, 1>(ra, nvec, vec4, s);
+            else reg_dispatch<1, 2>(ra, nvec, vec4, s);
+        } else {
+            if (variant == 6) reg_dispatch<2, 1>(ra, nvec, vec4, s);
+            else reg_dispatch<2, 2>(ra, nvec, vec4, s);
+        }
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     if (variant == 4 || variant == 5) {
         LeanArgs la;
         la.rec = g->d_fwd + m.ray_begin;
@@ -1629,10 +2202,98 @@ static unsigned multi_grid(int64_t total, bool persist)
 }
 
 // Forward of members [b, e) in one launch; false if they do not fit the lean multi kernel.
+template <int Q, int LPR, int NI>
+static void reg_multi_launch(RegMulti& a, bool vec4, bool persist, hipStream_t s)
+{
+    const dim3 grid(multi_grid(a.total, persist)), blk(A_WAVES * WAVE);
+    if (vec4) hipLaunchKernelGGL((k_apply_reg_multi<Q, LPR, NI, true>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((k_apply_reg_multi<Q, LPR, NI, false>), grid, blk, 0, s, a);
+}
+
+template <int Q, int NI>
+static void reg_multi_dispatch(RegMulti& a, int lpr, bool vec4, bool persist, hipStream_t s)
+{
+    switch (lpr) {
+    case 16: reg_multi_launch<Q, 16, NI>(a, vec4, persist, s); break;
+    case 32: reg_multi_launch<Q, 32, NI>(a, vec4, persist, s); break;
+    default: reg_multi_launch<Q, 64, NI>(a, vec4, persist, s); break;
+    }
+}
+
+// Register forward of members [b, e) in one launch (all members on reg1 or all on reg2).
+static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
+                            hipStream_t s, bool persist, int* rc)
+{
+    const Member& m0 = g->members[b];
+    const int v0 = m0.apply_variant;
+    bool vec4 = (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (g->n_rows % 4) == 0);
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        if (!lean_supported(m) || m.Q != m0.Q || m.apply_variant != v0) return false;
+        vec4 = vec4 && (m.grid.n_frames % 4) == 0 && (m.row_offset % 4) == 0;
+    }
+    const int NI = v0 == 6 ? 1 : 2;
+    // one chunk length for the launch: the fewest idle lanes over all rows
+    int lpr = 64;
+    int64_t best = INT64_MAX;
+    for (int c : {64, 32, 16}) {
+        int64_t w = 0;
+        for (int i = b; i < e; ++i) {
+            const int64_t F = g->members[i].grid.n_frames, fc = 4 * c;
+            w += g->members[i].n_rays * ((F + fc - 1) / fc * fc - F);
+        }
+        if (w < best) {
+            best = w;
+            lpr = c;
+        }
+    }
+    RegMulti a;
+    a.G = e - b;
+    int64_t nb = 0;
+    const int64_t rays_per_block = (int64_t)A_WAVES * (WAVE / lpr) * NI;
+    for (int i = b; i < e; ++i) {
+        const Member& m = g->members[i];
+        RegMember& d = a.m[i - b];
+        d.rec = g->d_fwd + m.ray_begin;
+        d.n_rays = m.n_rays;
+        d.x_off = m.col_offset;
+        d.y_off = m.row_offset;
+        d.K = m.grid.n_hat;
+        d.F = m.grid.n_frames;
+        d.nk = m.grid.n_phi * m.grid.n_hat;
+        d.x_bytes = (int)(m.n_cols * 4);
+        d.mask = effective_mask(m, mask);
+        d.blk_begin = (uint32_t)nb;
+        d.nrb = (uint32_t)((m.n_rays + rays_per_block - 1) / rays_per_block);
+        const int64_t nch = (m.grid.n_frames + 4 * lpr - 1) / (4 * lpr);
+        nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
+    }
+    if (nb * nvec >= (1ll << 31)) return false;
+    a.per_vec = (uint32_t)nb;
+    a.total = (uint32_t)(nb * nvec);
+    a.x = x;
+    a.y = y;
+    a.x_stride = g->n_cols;
+    a.y_stride = g->n_rows;
+    *rc = RTT_OK;
+    if (a.total == 0) return true;
+    if (m0.Q == 1) {
+        if (NI == 1) reg_multi_dispatch<1, 1>(a, lpr, vec4, persist, s);
+        else reg_multi_dispatch<1, 2>(a, lpr, vec4, persist, s);
+    } else {
+        if (NI == 1) reg_multi_dispatch<2, 1>(a, lpr, vec4, persist, s);
+        else reg_multi_dispatch<2, 2>(a, lpr, vec4, persist, s);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) *rc = hip_fail(err, "k_apply_reg_multi");
+    return true;
+}
+
 static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
                         hipStream_t s, bool persist, int* rc)
 {
     const Member& m0 = g->members[b];
+    if (m0.apply_variant == 6 || m0.apply_variant == 7) return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, rc);
     bool vec4 = (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (g->n_rows % 4) == 0);
     bool all8 = true;
     for (int i = b; i < e; ++i) {
@@ -1779,6 +2440,26 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     return true;
 }
 
+template <int Q, int V, int CW, bool PAIR>
+static void rows_launch(const RowsArgs& a, int nvec, hipStream_t s)
+{
+    constexpr int NB = Q == 1 ? (V <= 2 ? 8 : 4) : (V <= 2 ? 4 : 2);
+    const int64_t waves = (int64_t)a.ngroups * a.nbands;
+    const dim3 grid((unsigned)((waves + T_WAVES - 1) / T_WAVES), (unsigned)nvec);
+    hipLaunchKernelGGL((k_adjoint_rows<Q, V, CW, NB, PAIR>), grid, dim3(T_WAVES * WAVE), 0, s, a);
+}
+
+template <int Q, int CW, bool PAIR>
+static void rows_dispatch(const RowsArgs& a, int nvec, hipStream_t s)
+{
+    switch ((a.K + WAVE - 1) / WAVE) {
+    case 1: rows_launch<Q, 1, CW, PAIR>(a, nvec, s); break;
+    case 2: rows_launch<Q, 2, CW, PAIR>(a, nvec, s); break;
+    case 3: rows_launch<Q, 3, CW, PAIR>(a, nvec, s); break;
+    default: rows_launch<Q, 4, CW, PAIR>(a, nvec, s); break;
+    }
+}
+
 int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float* x, int nvec,
                    int64_t y_stride, int64_t x_stride, uint32_t mask, hipStream_t s, int variant)
 {
@@ -1799,7 +2480,43 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
     a.x_stride = x_stride;
     a.mask = mask;
     if (variant < 0 || variant >= n_adjoint_variants()) variant = m.adj_variant;
-    if (variant == 11 && !visit_supported(m)) variant = 2;
+    if (!adjoint_variant_ok(m, variant)) variant = 2;
+    if (variant == 12 || variant == 13) {
+        RowsArgs ra;
+        ra.rec = g->d_fwd + m.ray_begin;
+        ra.cstart = g->d_cell_start + m.cell_begin;
+        ra.n_r = m.grid.n_r;
+        ra.n_phi = m.grid.n_phi;
+        ra.K = m.grid.n_hat;
+        ra.F = m.grid.n_frames;
+        const int CW = variant == 12 ? 4 : 8;
+        ra.ngroups = (ra.n_phi + CW - 1) / CW;
+        // enough waves to hide memory latency: split the rows into bands when the groups and
+        // vectors alone give fewer than 65536 waves (bands of at least 4 rows)
+        const int64_t base = (int64_t)ra.ngroups * nvec;
+        const int64_t want = std::max<int64_t>(1, (65536 + base - 1) / base);
+        const int nb = (int)std::min<int64_t>(want, (ra.n_r + 3) / 4);
+        ra.rb = (ra.n_r + nb - 1) / nb;
+        ra.nbands = (ra.n_r + ra.rb - 1) / ra.rb;
+        ra.y = y;
+        ra.x = x;
+        ra.y_stride = y_stride;
+        ra.x_stride = x_stride;
+        ra.mask = mask;
+        const bool pair = (ra.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
+        if (m.Q == 1) {
+            if (CW == 4) rows_dispatch<1, 4, false>(ra, nvec, s);
+            else rows_dispatch<1, 8, false>(ra, nvec, s);
+        } else if (pair) {
+            if (CW == 4) rows_dispatch<2, 4, true>(ra, nvec, s);
+            else rows_dispatch<2, 8, true>(ra, nvec, s);
+        } else {
+            if (CW == 4) rows_dispatch<2, 4, false>(ra, nvec, s);
+            else rows_dispatch<2, 8, false>(ra, nvec, s);
+        }
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     if (variant == 11) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
         const int set = ((int64_t)m.grid.n_r * m.nseg[0] * nvec >= 16384) ? 0 : 1;

@@ -53,7 +53,8 @@ struct alignas(16) FwdRec {
     float th0;      // fraction of frame 0
     int32_t row;    // caller ray index
     int32_t order;  // image order
-    int32_t pad0, pad1;
+    int32_t cell;   // base cell s = i*n_phi + j0
+    int32_t pad1;
 };
 static_assert(sizeof(FwdRec) == 48, "FwdRec must be 48 bytes");
 
@@ -76,6 +77,7 @@ struct Member {
     int64_t vtask_begin[2];  // first entry of each set's task offsets (n_r * nseg + 1 entries)
     int32_t nseg[2];         // sweep segments per cell row
     int32_t vseg[2];         // columns per sweep segment
+    int32_t k0_min, k0_max;  // range of the hat origins k0 of the member's rays
 };
 
 struct Workspace;
@@ -130,6 +132,9 @@ int default_adjoint_variant(const Member& m);
 int default_apply_variant(const Member& m);
 bool visit_supported(const Member& m);
 bool lean_supported(const Member& m);
+// forward / adjoint variant v can run on member m (ratio and size limits)
+bool apply_variant_ok(const Member& m, int v);
+bool adjoint_variant_ok(const Member& m, int v);
 
 uint32_t effective_mask(const Member& m, uint32_t mask);
 

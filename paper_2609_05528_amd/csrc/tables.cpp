@@ -267,9 +267,15 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
             f.th0 = rr.th0;
             f.row = rr.row;
             f.order = rr.order;
-            f.pad0 = f.pad1 = 0;
+            f.cell = rr.cell;
+            f.pad1 = 0;
             fwd.push_back(f);
             (void)i;
+        }
+        m.k0_min = m.k0_max = 0;
+        for (size_t r = 0; r < gr.size(); ++r) {
+            m.k0_min = r ? std::min(m.k0_min, gr[r].k0) : gr[r].k0;
+            m.k0_max = r ? std::max(m.k0_max, gr[r].k0) : gr[r].k0;
         }
         cstart.insert(cstart.end(), cs.begin(), cs.end());
         recs.insert(recs.end(), gr.begin(), gr.end());
@@ -387,11 +393,11 @@ extern "C" int geometry_set_variant(rtt_geometry* g, int32_t idx, int32_t apply_
         Member& m = g->members[i];
         if ((apply_variant == 2 || apply_variant == 3) && m.P > m.Q)
             return fail(RTT_EINVAL, "batch/stream forward variants need dt_obs <= dt_src");
-        if ((apply_variant == 4 || apply_variant == 5) && !lean_supported(m))
-            return fail(RTT_EINVAL, "lean forward variants need dt_obs/dt_src = 1 or 1/2");
+        if (apply_variant >= 0 && !apply_variant_ok(m, apply_variant))
+            return fail(RTT_EINVAL, "lean/reg forward variants need dt_obs/dt_src = 1 or 1/2");
         if (apply_variant >= 0) m.apply_variant = apply_variant;
-        if (adjoint_variant == 11 && !visit_supported(m))
-            return fail(RTT_EINVAL, "visit adjoint variant needs dt_obs/dt_src = 1 or 1/2");
+        if (adjoint_variant >= 0 && !adjoint_variant_ok(m, adjoint_variant))
+            return fail(RTT_EINVAL, "visit/rows adjoint variants need dt_obs/dt_src = 1 or 1/2 (rows: n_hat <= 256)");
         if (adjoint_variant >= 0) m.adj_variant = adjoint_variant;
     }
     return RTT_OK;

@@ -122,9 +122,8 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
     for (Member& m : g->members) {
         bool hit = false;
         for (const CacheEntry& e : cache)
-            if (e.digest == m.digest && e.nvec == nvec && e.apply >= 0 && e.apply < n_apply_variants() &&
-                e.adjoint >= 0 && e.adjoint < n_adjoint_variants() && !((e.apply == 2 || e.apply == 3) && m.P > m.Q) &&
-                !((e.apply == 4 || e.apply == 5) && !lean_supported(m))) {
+            if (e.digest == m.digest && e.nvec == nvec && apply_variant_ok(m, e.apply) &&
+                adjoint_variant_ok(m, e.adjoint)) {
                 m.apply_variant = e.apply;
                 m.adj_variant = e.adjoint;
                 hit = true;
@@ -141,8 +140,7 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         float best = 1e30f;
         int best_v = m.apply_variant;
         for (int v = 0; v < n_apply_variants(); ++v) {
-            if ((v == 2 || v == 3) && m.P > m.Q) continue;
-            if ((v == 4 || v == 5) && !lean_supported(m)) continue;
+            if (!apply_variant_ok(m, v)) continue;
             float ms;
             int rc = time_variant(g, m, false, v, xb, yb, nvec, reps, s, &ms);
             if (rc) return rc;
@@ -153,7 +151,7 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         best = 1e30f;
         best_v = m.adj_variant;
         for (int v = 0; v < n_adjoint_variants(); ++v) {
-            if (v == 11 && !visit_supported(m)) continue;
+            if (!adjoint_variant_ok(m, v)) continue;
             float ms;
             int rc = time_variant(g, m, true, v, yb, xb, nvec, reps, s, &ms);
             if (rc) return rc;

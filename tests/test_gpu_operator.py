@@ -264,15 +264,17 @@ BATCH_CASES = {
 }
 
 
+@pytest.mark.parametrize("fwd", ["lean4", "reg1", "reg2", "strip16"])
 @pytest.mark.parametrize("name", list(BATCH_CASES))
-def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name):
+def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd):
     """One launch for all geometries (plain and persistent) equals one launch per geometry."""
     rtt = gpu_lib
     c = BATCH_CASES[name]
-    say("case batch modes", name)
+    say("case batch modes", name, fwd)
     geos = [tiny_geometry(seed=60 + i, rays=(30 + 11 * i, 7, 3), n_frames=c["frames"](i), dt_obs=c["dt_obs"],
                           n_r=4 + i % 3, n_phi=6 + 2 * (i % 4)) for i in range(c["n"])]
     G = rtt.Geometry(geos)
+    G.set_variant(apply=rtt.variant_names(False).index(fwd))
     rng = np.random.default_rng(19)
     X = rng.random((3, G.n_cols)).astype(np.float32)
     Y = rng.standard_normal((3, G.n_rows)).astype(np.float32)
@@ -300,6 +302,8 @@ VARIANT_CASES = {
     "ratio_half": dict(seed=12, rays=(300, 50, 40), dt_obs=2.0, n_frames=90, n_r=7, n_phi=66),
     "ratio3_4": dict(seed=22, rays=(300, 70), dt_obs=3.0, n_frames=41, n_r=5, n_phi=40),
     "long_rows": dict(seed=26, rays=(200, 30, 20), n_frames=700, n_r=4, n_phi=9),
+    "k_wide": dict(seed=27, rays=(300, 60, 40), n_frames=220, n_r=5, n_phi=10),
+    "k_mid_half": dict(seed=28, rays=(300, 60, 40), dt_obs=2.0, n_frames=300, n_r=6, n_phi=11),
     "ring1": dict(seed=24, rays=(40, 10), n_r=5, n_phi=1, n_frames=5),
 }
 
@@ -321,7 +325,7 @@ def test_every_kernel_variant_matches_oracle(gpu_lib, name):
     for v, vname in enumerate(rtt.variant_names(False)):
         if vname in ("batch", "stream") and not ratio_le1:
             continue
-        if vname.startswith("lean") and not unit_or_half:
+        if vname.startswith(("lean", "reg", "strip")) and not unit_or_half:
             continue
         G.set_variant(apply=v)
         ya = rtt.op_apply(G, to_dev(X)).cpu().numpy()
@@ -330,6 +334,8 @@ def test_every_kernel_variant_matches_oracle(gpu_lib, name):
     visit_ok = unit_or_half
     for v, vname in enumerate(rtt.variant_names(True)):
         if vname == "visit" and not visit_ok:
+            continue
+        if vname.startswith("rows") and not (visit_ok and geo.grid.n_hat <= 256):
             continue
         G.set_variant(adjoint=v)
         xa = rtt.op_apply_adjoint(G, to_dev(Yv)).cpu().numpy()

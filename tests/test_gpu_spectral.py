@@ -158,13 +158,15 @@ def test_ridge_matches_dense_solve_tiny(gpu_lib):
     assert rel(x.cpu().numpy(), xe) <= 1e-4
 
 
-def test_ridge_normal_equation_residual_workload(gpu_lib):
-    """64^2 workload, lambda = 1e-3 (absolute): FP64 residual of the normal equations."""
+@pytest.mark.parametrize("wl", ["cfg1", "cfg3"])
+def test_ridge_normal_equation_residual_workload(gpu_lib, wl):
+    """64^2 and 256^2 x 192-frame workloads, lambda = 1e-3 (absolute): FP64 residual of the
+    normal equations."""
     rtt = gpu_lib
-    geo = synth.geometry_for("cfg1")
-    say("case ridge cfg1")
+    geo = synth.geometry_for(wl)
+    say("case ridge", wl)
     G = rtt.Geometry(geo)
-    xt = synth.uniform_emissivity(geo.grid, seed=1000)
+    xt = synth.uniform_emissivity(geo.grid, seed=synth.config(wl)["seed"])
     y = oracle.forward(geo, xt).astype(np.float32)
     lam = 1e-3
     x, info = rtt.ridge_solve(G, to_dev(y), lam, tol=1e-6, maxit=20000, raise_on_noconv=False)
@@ -176,10 +178,13 @@ def test_ridge_normal_equation_residual_workload(gpu_lib):
 
 
 def test_autograd_gradient_matches_oracle_and_fd(gpu_lib):
+    """The differentiable ridge workload: 256^2 screen, 192 frames, lambda = 1e-3; gradient
+    against the FP64 oracle gradient and central differences (h = 1e-3) on 64 coordinates."""
     import torch
     rtt = gpu_lib
     from paper_2609_05528_amd.autograd import ridge_loss
-    geo = synth.geometry_for("cfg1")
+    geo = synth.geometry_for("cfg3")
+    say("case autograd cfg3")
     G = rtt.Geometry(geo)
     rng = np.random.default_rng(3001)
     xt = rng.random(geo.grid.n_cols).astype(np.float32)
@@ -226,3 +231,29 @@ def test_double_backward_is_linear(gpu_lib):
     (gw,) = torch.autograd.grad((gx * v).sum(), w)                     # d/dw <A^T w, v> = A v
     ref = oracle.forward(geo, v.double().cpu().numpy())
     assert rel(gw.cpu().numpy(), ref) <= 1e-5
+
+
+def test_block_lanczos_512_vectors_on_the_large_geometry(gpu_lib):
+    """512^2 x 512 frames, orders 0-2: block Lanczos with 512 right vectors (32 x 16 steps).
+    At this size the oracle checks the leading Ritz pair through its own A and A^T: the Ritz
+    value must match ||A v_1|| and the FP64 residual of A^T A v_1 = theta_1^2 v_1 must be within
+    the reported residual estimate."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg5")
+    say("case lanczos cfg5")
+    G = rtt.Geometry(geo)
+    sv = rtt.rsvd(G, method="lanczos", k=64, block=32, steps=16, seed=5001)
+    th = sv.sigma
+    assert np.all(np.diff(th) <= 1e-6 * th[0])
+    v1 = sv.V()[0].double().cpu().numpy()
+    v1 /= np.linalg.norm(v1)
+    av = oracle.forward(geo, v1)
+    nav = np.linalg.norm(av)
+    say("theta_1", th[0], "||A v1||", nav, "resid est", sv.residual[0])
+    assert abs(nav - th[0]) <= 1e-4 * th[0]
+    r = oracle.adjoint(geo, av) - th[0] ** 2 * v1
+    assert np.linalg.norm(r) / th[0] <= max(10 * sv.residual[0], 1e-4 * th[0])
+    # the second Ritz pair, checked the same way
+    v2 = sv.V()[1].double().cpu().numpy()
+    v2 /= np.linalg.norm(v2)
+    assert abs(np.linalg.norm(oracle.forward(geo, v2)) - th[1]) <= 1e-4 * th[0]
