@@ -149,11 +149,13 @@ const char* variant_name(int32_t adjoint, int32_t v);
 /*
  * geometry_tune -- autotuner: times every applicable variant of both kernels
  * on nvec random vectors (HIP events on `stream`, median of `reps`) for each
- * member, keeps the fastest, then (G > 1) times the three launch modes of
- * geometry_set_batch_mode on the whole operator, and records the choices in
- * the text cache at cache_path (nullable; one "digest nvec apply adjoint" line
- * per member, one "multi digest nvec apply_mode adjoint_mode" line per
- * handle).  A cache hit skips the timing.  Blocking; allocates scratch vectors.
+ * member, keeps the fastest, then (G > 1) times the whole operator with those
+ * choices launched per member against one variant shared by every member in
+ * one launch (launch modes of geometry_set_batch_mode), keeps the fastest, and
+ * records the choices in the text cache at cache_path (nullable; one "digest
+ * nvec apply adjoint" line per member, one "multi digest nvec apply_mode
+ * adjoint_mode apply_shared adjoint_shared" line per handle).  A cache hit
+ * skips the timing.  Blocking; allocates scratch vectors.
  */
 int geometry_tune(rtt_geometry* geom, int32_t nvec, int32_t reps, const char* cache_path, void* stream);
 

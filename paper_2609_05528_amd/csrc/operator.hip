@@ -810,9 +810,18 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
         const int s10 = a.nk * 4;
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
-            const int kc = min(max(klo + lane + it * WAVE, 0), a.K - 1);
-            const int off0 = (rc[j].c00k + kc) * 4;
-            const int off1 = off0 + rc[j].d01k * 4;
+            // hats outside [0, K) carry no basis function: a chunk with none inside is skipped
+            // (uniform branch), lanes outside get an offset past the end of x, which returns 0
+            // without a memory access
+            const int kb = klo + it * WAVE;
+            if (kb >= a.K || kb + WAVE <= 0) {
+                xv[j][it][0] = xv[j][it][1] = xv[j][it][2] = xv[j][it][3] = 0.f;
+                continue;
+            }
+            const int k = kb + lane;
+            const bool in = (unsigned)k < (unsigned)a.K;
+            const int off0 = in ? (rc[j].c00k + k) * 4 : 0x7FFFFFF0;
+            const int off1 = in ? off0 + rc[j].d01k * 4 : 0x7FFFFFF0;
             xv[j][it][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off0, 0, 0));
             xv[j][it][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off0, s10, 0));
             xv[j][it][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off1, 0, 0));
@@ -1085,7 +1094,7 @@ __device__ __forceinline__ void reg_body(const RegArgs& a, const float* __restri
                 xv[j][c][1] = w[1];
                 xv[j][c][2] = w[2];
                 xv[j][c][3] = w[3];
-                if (Q == 1)
+                if constexpr (Q == 1)
                     xv[j][c][4] = __builtin_bit_cast(float,
                                                      __builtin_amdgcn_raw_buffer_load_b32(xr, o[j][c] * 4 + 16, 0, 0));
             }
@@ -1111,7 +1120,7 @@ __device__ __forceinline__ void reg_body(const RegArgs& a, const float* __restri
         }
         const float t = th[j];
         f4 v;
-        if (Q == 1) {
+        if constexpr (Q == 1) {
             v[0] = z[0] + t * (z[1] - z[0]);
             v[1] = z[1] + t * (z[2] - z[1]);
             v[2] = z[2] + t * (z[3] - z[2]);
@@ -1204,6 +1213,7 @@ struct VisitArgs {
     const int64_t* vtask;
     int n_r, n_phi, K, F, nseg, vseg;
     int kchunks;        // hat chunks of 64*V hats (one per wave)
+    int nvec;           // vectors of the launch (a workgroup takes NVW of them)
     const float* y;
     float* x;
     int64_t y_stride, x_stride;
@@ -1240,10 +1250,13 @@ struct Taps {
 };
 
 // One block of the visit-list adjoint: task `lin` = (row group, segment, hat chunk) of one member
-// and one vector (y, x already offset to the member's blocks).
-template <int Q, int V, int NB, bool PAIR>
-__device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y, float* __restrict__ x,
-                                           int64_t lin)
+// for NVW consecutive vectors (y0, x0: the first of them, already offset to the member's blocks;
+// nv of them exist).  Everything that depends only on the visit -- record decode, tap weights,
+// frame offsets, the sweep position -- is shared by the vectors; only the data loads and the
+// accumulation are repeated per vector.
+template <int Q, int V, int NB, bool PAIR, int NVW>
+__device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y0, float* __restrict__ x0,
+                                           int nv, int64_t lin)
 {
     typedef Taps<Q> TP_;
     constexpr int T = TP_::T;
@@ -1264,24 +1277,33 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     const int rowbytes = a.F * 4;
     const int lane_off = Q * lane * 4;   // per-lane part of every frame offset
 
-    float acc_a[V], acc_b[V];
+    float acc_a[NVW][V], acc_b[NVW][V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc_a[v] = acc_b[v] = 0.f;
+    for (int u = 0; u < NVW; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc_a[u][v] = acc_b[u][v] = 0.f;
     int col = 0;
     auto emit = [&]() {
         if (col >= 1) {
-            float* xr = x + (int64_t)(ci * a.n_phi + (jlo - 1 + col)) * a.K;
+            const int64_t xo = (int64_t)(ci * a.n_phi + (jlo - 1 + col)) * a.K;
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int k = kc + lane + WAVE * v;
-                if (k < a.K) xr[k] = acc_a[v];
+            for (int u = 0; u < NVW; ++u) {
+                if (u >= nv) break;
+                float* xr = x0 + (int64_t)u * a.x_stride + xo;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int k = kc + lane + WAVE * v;
+                    if (k < a.K) xr[k] = acc_a[u][v];
+                }
             }
         }
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            acc_a[v] = acc_b[v];
-            acc_b[v] = 0.f;
-        }
+        for (int u = 0; u < NVW; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                acc_a[u][v] = acc_b[u][v];
+                acc_b[u][v] = 0.f;
+            }
         ++col;
     };
 
@@ -1301,7 +1323,7 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             n0 = vp[0];
             n1 = vp[1];
         }
-        float yv[NB][V][T], tw[NB][T], wa[NB], wb[NB];
+        float yv[NB][NVW][V][T], tw[NB][T], wa[NB], wb[NB];
         int vcol[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
@@ -1314,34 +1336,47 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             vcol[j] = valid ? __builtin_amdgcn_readlane(r1.y, j) : ncol;
             const int order = __builtin_amdgcn_readlane(r1.z, j);
             const bool on = valid && ((a.mask >> order) & 1u);
-            // zero-sized range for skipped visits: their loads return 0 without touching memory.
-            // The descriptor fields are made provably uniform (scalar registers), otherwise every
-            // buffer load would be wrapped in a per-lane waterfall loop.
-            const uint64_t base = (uint64_t)(y + (int64_t)row * a.F);
-            const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-            const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-            const int nrec = __builtin_amdgcn_readfirstlane(on ? rowbytes : 0);
-            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)(((uint64_t)bhi << 32) | blo), (short)0, nrec, 0x00020000);
             TP_::weights(th0, tw[j]);
+            // frame offsets (bytes) of this visit, identical for every vector.  Lanes whose hat
+            // lies outside [0, K) get an offset past the row: their frames are never fetched.
+            unsigned off[V][T];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int ub = (Q * (kc + WAVE * v - k0) + TP_::MLO) * 4;   // uniform part of the offset
-                if (PAIR) {
+                const bool in = kc + WAVE * v + lane < a.K;
 #pragma unroll
-                    for (int t = 0; t < T; t += 2) {
-                        // frames before the row: clamp the unsigned offset far below 2^32 so that
-                        // offset + 8 cannot wrap back into the row's range
-                        const unsigned off = min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u);
-                        const f2 p = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
-                        yv[j][v][t] = p[0];
-                        yv[j][v][t + 1] = p[1];
-                    }
-                } else {
+                for (int t = 0; t < T; ++t)
+                    // frames before the row: clamp the unsigned offset far below 2^32 so that
+                    // offset + 8 cannot wrap back into the row's range
+                    off[v][t] = in ? min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u) : 0x7FFFFFF0u;
+            }
 #pragma unroll
-                    for (int t = 0; t < T; ++t) {
-                        const unsigned off = min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u);
-                        yv[j][v][t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+            for (int u = 0; u < NVW; ++u) {
+                // zero-sized range for skipped visits and missing vectors: their loads return 0
+                // without touching memory.  The descriptor fields are made provably uniform
+                // (scalar registers), otherwise every buffer load would be wrapped in a per-lane
+                // waterfall loop.
+                const uint64_t base = (uint64_t)(y0 + (int64_t)u * a.y_stride + (int64_t)row * a.F);
+                const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+                const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+                const int nrec = __builtin_amdgcn_readfirstlane((on && u < nv) ? rowbytes : 0);
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(((uint64_t)bhi << 32) | blo), (short)0, nrec, 0x00020000);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (PAIR) {
+#pragma unroll
+                        for (int t = 0; t < T; t += 2) {
+                            const f2 p2 = __builtin_bit_cast(
+                                f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[v][t], 0, 0));
+                            yv[j][u][v][t] = p2[0];
+                            yv[j][u][v][t + 1] = p2[1];
+                        }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < T; ++t)
+                            yv[j][u][v][t] = __builtin_bit_cast(
+                                float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[v][t], 0, 0));
                     }
                 }
             }
@@ -1350,24 +1385,27 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
         for (int j = 0; j < NB; ++j) {
             while (col < vcol[j]) emit();
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                float h = 0.f;
+            for (int u = 0; u < NVW; ++u)
 #pragma unroll
-                for (int t = 0; t < T; ++t) h += tw[j][t] * yv[j][v][t];
-                acc_a[v] += wa[j] * h;
-                acc_b[v] += wb[j] * h;
-            }
+                for (int v = 0; v < V; ++v) {
+                    float h = 0.f;
+#pragma unroll
+                    for (int t = 0; t < T; ++t) h += tw[j][t] * yv[j][u][v][t];
+                    acc_a[u][v] += wa[j] * h;
+                    acc_b[u][v] += wb[j] * h;
+                }
         }
     }
     while (col < ncol) emit();
 }
 
-template <int Q, int V, int NB, bool PAIR>
+template <int Q, int V, int NB, bool PAIR, int NVW>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
     const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
-    visit_body<Q, V, NB, PAIR>(a, a.y + (int64_t)blockIdx.y * a.y_stride, a.x + (int64_t)blockIdx.y * a.x_stride,
-                               xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
+    const int v0 = blockIdx.y * NVW;
+    visit_body<Q, V, NB, PAIR, NVW>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
+                                    min(NVW, a.nvec - v0), xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
 }
 
 // Every member of a handle (up to MULTI_MAX) in one launch; tasks numbered as in
@@ -1410,8 +1448,10 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMul
         va.vseg = mm.vseg;
         va.kchunks = mm.kchunks;
         va.mask = mm.mask;
-        visit_body<Q, V, NB, PAIR>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
-                                   a.x + (int64_t)v * a.x_stride + mm.x_off, (int64_t)(b - mm.blk_begin));
+        va.y_stride = a.y_stride;
+        va.x_stride = a.x_stride;
+        visit_body<Q, V, NB, PAIR, 1>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
+                                      a.x + (int64_t)v * a.x_stride + mm.x_off, 1, (int64_t)(b - mm.blk_begin));
     }
 }
 
@@ -1848,14 +1888,14 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_sweep(AdjArgs a)
 // 7-10 batched LDS tile kernels, 11 visit-list kernel (dt_obs/dt_src = 1 or 1/2).
 struct AdjVariant {
     const char* name;
-    int kind;   // 0 tile, 1 sweep, 2 batched tile
-    int a, b;   // tile: TR, TC; sweep: TC, V
+    int kind;   // 0 tile, 1 sweep, 2 batched tile, 3 visit list, 4 row sweep
+    int a, b;   // tile: TR, TC; sweep: TC, V; visit list: vectors per wave; row sweep: CW
 };
 static const AdjVariant kAdjVariants[] = {
     {"tile8x8", 0, 8, 8},    {"tile4x8", 0, 4, 8},    {"tile4x4", 0, 4, 4},    {"sweep32v1", 1, 32, 1},
     {"sweep32v2", 1, 32, 2}, {"sweep16v1", 1, 16, 1}, {"sweep16v2", 1, 16, 2}, {"tb8x8", 2, 8, 8},
     {"tb4x8", 2, 4, 8},      {"tb4x4", 2, 4, 4},      {"tb2x4", 2, 2, 4},      {"visit", 3, 0, 0},
-    {"rows4", 4, 4, 0},      {"rows8", 4, 8, 0},
+    {"rows4", 4, 4, 0},      {"rows8", 4, 8, 0},      {"visit2v", 3, 2, 0},    {"visit4v", 3, 4, 0},
 };
 constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
@@ -1878,8 +1918,8 @@ bool visit_supported(const Member& m) { return m.P == 1 && (m.Q == 1 || m.Q == 2
 bool adjoint_variant_ok(const Member& m, int v)
 {
     if (v < 0 || v >= n_adjoint_variants()) return false;
-    if (v == 11 && !visit_supported(m)) return false;
-    if (v >= 12 && !(visit_supported(m) && m.grid.n_hat <= 4 * WAVE)) return false;   // rows: K <= 256
+    if ((v == 11 || v >= 14) && !visit_supported(m)) return false;
+    if ((v == 12 || v == 13) && !(visit_supported(m) && m.grid.n_hat <= 4 * WAVE)) return false;   // rows: K <= 256
     return true;
 }
 
@@ -2170,26 +2210,40 @@ static void adjoint_dispatch_sweep(const AdjArgs& a, int P, int Q, int nvec, hip
         hipLaunchKernelGGL((k_adjoint_sweep<0, 0, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, int V, int NB, bool PAIR>
+template <int Q, int V, int NB, bool PAIR, int NVW>
 static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
     a.kchunks = (a.K + WAVE * V - 1) / (WAVE * V);
+    a.nvec = nvec;
     const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR>), dim3((unsigned)blocks, (unsigned)nvec),
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW>), dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)),
                        dim3(T_WAVES * WAVE), 0, s, a);
 }
 
+// vpw: vectors per wave (1, 2 or 4).  Loads in flight per lane stay near NB * V * T / 8.
 template <int Q, bool PAIR>
-static void visit_dispatch(const VisitArgs& a, int nvec, hipStream_t s)
+static void visit_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s)
 {
     constexpr int NB1 = Q == 1 ? 8 : 4;
     // enough waves to fill the chip with one wave per (row, segment): cover all hats per wave;
     // otherwise split the hats into 64-hat chunks, one per wave
-    const int64_t waves = (int64_t)a.n_r * a.nseg * nvec;
-    if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 8, PAIR>(a, nvec, s);
-    else if (a.K <= 128) visit_launch<Q, 2, NB1, PAIR>(a, nvec, s);
-    else if (a.K <= 256) visit_launch<Q, 4, Q == 1 ? 4 : 2, PAIR>(a, nvec, s);
-    else visit_launch<Q, 8, 2, PAIR>(a, nvec, s);
+    const int64_t waves = (int64_t)a.n_r * a.nseg * ((nvec + vpw - 1) / vpw);
+    if (vpw == 4) {
+        if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 2, PAIR, 4>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, Q == 1 ? 2 : 1, PAIR, 4>(a, nvec, s);
+        else visit_launch<Q, 4, 1, PAIR, 4>(a, nvec, s);
+        return;
+    }
+    if (vpw == 2) {
+        if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 4, PAIR, 2>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, Q == 1 ? 4 : 2, PAIR, 2>(a, nvec, s);
+        else visit_launch<Q, 4, Q == 1 ? 2 : 1, PAIR, 2>(a, nvec, s);
+        return;
+    }
+    if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 8, PAIR, 1>(a, nvec, s);
+    else if (a.K <= 128) visit_launch<Q, 2, NB1, PAIR, 1>(a, nvec, s);
+    else if (a.K <= 256) visit_launch<Q, 4, Q == 1 ? 4 : 2, PAIR, 1>(a, nvec, s);
+    else visit_launch<Q, 8, 2, PAIR, 1>(a, nvec, s);
 }
 
 // ------------------------------------------------------------------ one launch for many members
@@ -2517,9 +2571,10 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
-    if (variant == 11) {
+    if (variant == 11 || variant == 14 || variant == 15) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
-        const int set = ((int64_t)m.grid.n_r * m.nseg[0] * nvec >= 16384) ? 0 : 1;
+        const int vpw = variant == 14 ? 2 : variant == 15 ? 4 : 1;
+        const int set = ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
         VisitArgs va;
         va.visits = g->d_visits + m.visit_begin[set];
         va.vtask = g->d_vtask + m.vtask_begin[set];
@@ -2536,9 +2591,9 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         va.mask = mask;
         // frame pairs need 8-byte aligned rows: even n_frames and aligned data vectors
         const bool pair = (va.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
-        if (m.Q == 1) visit_dispatch<1, false>(va, nvec, s);
-        else if (pair) visit_dispatch<2, true>(va, nvec, s);
-        else visit_dispatch<2, false>(va, nvec, s);
+        if (m.Q == 1) visit_dispatch<1, false>(va, nvec, vpw, s);
+        else if (pair) visit_dispatch<2, true>(va, nvec, vpw, s);
+        else visit_dispatch<2, false>(va, nvec, vpw, s);
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }

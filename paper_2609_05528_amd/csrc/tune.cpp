@@ -1,6 +1,7 @@
 // Autotuner: pick the fastest kernel variant of A and A^T for each member geometry and, for a
-// handle with several members, the fastest launch mode of the whole operator (one launch per
-// member, one launch for all members, or one persistent launch).
+// handle with several members, the fastest way to launch the whole operator: the per-member
+// choices one launch per member, or one variant shared by all members in one launch (plain or
+// persistent).
 //
 // Every applicable variant is timed with HIP events on the caller's stream
 // over `reps` launches on `nvec` random vectors (median).  Choices are cached
@@ -20,11 +21,12 @@ namespace {
 struct CacheEntry {
     uint64_t digest;
     int nvec, apply, adjoint;
+    int uni_apply = -1, uni_adjoint = -1;   // multi lines: variant shared by every member, or -1
 };
 
-// Member lines are "digest nvec apply adjoint"; whole-handle lines (launch mode of a handle with
-// several members) are "multi digest nvec apply_mode adjoint_mode" and are kept with apply
-// and adjoint holding the modes and multi set.
+// Member lines are "digest nvec apply adjoint"; whole-handle lines (handles with several
+// members) are "multi digest nvec apply_mode adjoint_mode apply_shared adjoint_shared", where a
+// shared variant (or -1) replaces every member's own choice.
 std::vector<CacheEntry> read_cache(const char* path, std::vector<CacheEntry>* multi)
 {
     std::vector<CacheEntry> out;
@@ -36,7 +38,10 @@ std::vector<CacheEntry> read_cache(const char* path, std::vector<CacheEntry>* mu
         CacheEntry e;
         if (line.compare(0, 6, "multi ") == 0) {
             std::string tag;
-            if (is >> tag >> std::hex >> e.digest >> std::dec >> e.nvec >> e.apply >> e.adjoint) multi->push_back(e);
+            if (is >> tag >> std::hex >> e.digest >> std::dec >> e.nvec >> e.apply >> e.adjoint) {
+                if (!(is >> e.uni_apply >> e.uni_adjoint)) e.uni_apply = e.uni_adjoint = -1;
+                multi->push_back(e);
+            }
             continue;
         }
         if (is >> std::hex >> e.digest >> std::dec >> e.nvec >> e.apply >> e.adjoint) out.push_back(e);
@@ -161,9 +166,11 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         m.adj_variant = best_v;
         added.push_back({m.digest, nvec, m.apply_variant, m.adj_variant});
     }
-    // several members: one launch per member, one launch for all, or one persistent launch
+    // several members: the per-member choices launched one by one, or one variant shared by every
+    // member (the ones with a single-launch form) launched as one launch or one persistent launch
     bool multi_added = false;
     uint64_t hd = 1469598103934665603ull;
+    int uni[2] = {-1, -1};   // variant given to every member (-1: keep the per-member choices)
     if (g->members.size() > 1) {
         for (const Member& m : g->members) {
             const int32_t v[2] = {m.apply_variant, m.adj_variant};
@@ -175,9 +182,16 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
             if (e.digest == hd && e.nvec == nvec && e.apply >= 0 && e.apply <= 2 && e.adjoint >= 0 && e.adjoint <= 2) {
                 g->batch_apply_mode = e.apply;
                 g->batch_adjoint_mode = e.adjoint;
+                uni[0] = e.uni_apply;
+                uni[1] = e.uni_adjoint;
                 hit = true;
             }
-        if (!hit) {
+        if (hit) {
+            for (Member& m : g->members) {
+                if (uni[0] >= 0 && apply_variant_ok(m, uni[0])) m.apply_variant = uni[0];
+                if (uni[1] >= 0 && adjoint_variant_ok(m, uni[1])) m.adj_variant = uni[1];
+            }
+        } else {
             float* xa = (float*)ws.get("tune_xa", sizeof(float) * (size_t)nvec * g->n_cols);
             float* ya = (float*)ws.get("tune_ya", sizeof(float) * (size_t)nvec * g->n_rows);
             if (!xa || !ya) return fail(RTT_ENOMEM, "tune buffers");
@@ -185,18 +199,44 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
             if (!rc) rc = normal_fill(ya, (int64_t)nvec * g->n_rows, 54321, s);
             if (rc) return rc;
             for (int adj = 0; adj < 2; ++adj) {
+                std::vector<int32_t> tuned;
+                for (const Member& m : g->members) tuned.push_back(adj ? m.adj_variant : m.apply_variant);
+                // candidates: -1 = the per-member choices; then the single-launch variants
+                std::vector<int> cands = {-1};
+                for (int v : adj ? std::vector<int>{11} : std::vector<int>{4, 6, 7}) {
+                    bool ok = true;
+                    for (const Member& m : g->members) ok = ok && (adj ? adjoint_variant_ok(m, v) : apply_variant_ok(m, v));
+                    if (ok) cands.push_back(v);
+                }
                 float best = 1e30f;
-                int best_m = 1;
-                for (int mode = 0; mode <= 2; ++mode) {
-                    float ms;
-                    rc = adj ? time_mode(g, true, mode, ya, xa, nvec, reps, s, &ms)
-                             : time_mode(g, false, mode, xa, ya, nvec, reps, s, &ms);
-                    if (rc) return rc;
-                    if (std::getenv("RTT_LOG"))
-                        std::fprintf(stderr, "[rtt] tune %s launch mode %d: %.4f ms\n", adj ? "adjoint" : "apply", mode, ms);
-                    if (ms < best) { best = ms; best_m = mode; }
+                int best_m = 0, best_u = -1;
+                for (int u : cands) {
+                    for (size_t i = 0; i < g->members.size(); ++i) {
+                        int32_t& slot = adj ? g->members[i].adj_variant : g->members[i].apply_variant;
+                        slot = u >= 0 ? u : tuned[i];
+                    }
+                    for (int mode = 0; mode <= 2; ++mode) {
+                        if (u >= 0 && mode == 0) continue;   // the per-member launches are covered by u = -1
+                        float ms;
+                        rc = adj ? time_mode(g, true, mode, ya, xa, nvec, reps, s, &ms)
+                                 : time_mode(g, false, mode, xa, ya, nvec, reps, s, &ms);
+                        if (rc) return rc;
+                        if (std::getenv("RTT_LOG"))
+                            std::fprintf(stderr, "[rtt] tune %s shared variant %d launch mode %d: %.4f ms\n",
+                                         adj ? "adjoint" : "apply", u, mode, ms);
+                        if (ms < best) {
+                            best = ms;
+                            best_m = mode;
+                            best_u = u;
+                        }
+                    }
+                }
+                for (size_t i = 0; i < g->members.size(); ++i) {
+                    int32_t& slot = adj ? g->members[i].adj_variant : g->members[i].apply_variant;
+                    slot = best_u >= 0 ? best_u : tuned[i];
                 }
                 (adj ? g->batch_adjoint_mode : g->batch_apply_mode) = best_m;
+                uni[adj] = best_u;
             }
             multi_added = true;
         }
@@ -207,7 +247,7 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
             f << std::hex << e.digest << std::dec << " " << e.nvec << " " << e.apply << " " << e.adjoint << "\n";
         if (multi_added)
             f << "multi " << std::hex << hd << std::dec << " " << nvec << " " << g->batch_apply_mode << " "
-              << g->batch_adjoint_mode << "\n";
+              << g->batch_adjoint_mode << " " << uni[0] << " " << uni[1] << "\n";
     }
     RTT_HIP(hipStreamSynchronize(s));
     return RTT_OK;

@@ -333,7 +333,7 @@ def test_every_kernel_variant_matches_oracle(gpu_lib, name):
             assert max(block_rel(geo, ya[b], yr[b])) <= TOL, (vname, b)
     visit_ok = unit_or_half
     for v, vname in enumerate(rtt.variant_names(True)):
-        if vname == "visit" and not visit_ok:
+        if vname.startswith("visit") and not visit_ok:
             continue
         if vname.startswith("rows") and not (visit_ok and geo.grid.n_hat <= 256):
             continue
@@ -358,3 +358,28 @@ def test_autotuner_picks_a_valid_variant_and_caches(gpu_lib, tmp_path):
     assert G2.tune(nvec=2, reps=3, cache_path=cache) == choice      # cache hit
     y = rtt.op_apply(G2, to_dev(x)).cpu().numpy()
     assert rel(y, oracle.forward(geo, x.astype(np.float64))) <= TOL
+
+
+def test_autotuner_on_several_geometries_caches_the_launch_choice(gpu_lib, tmp_path):
+    rtt = gpu_lib
+    geos = [tiny_geometry(seed=130 + i, rays=(60 + 9 * i, 10, 5), n_frames=12 + 4 * i, n_r=5, n_phi=8)
+            for i in range(3)]
+    G = rtt.Geometry(geos)
+    cache = tmp_path / "tune.txt"
+    G.tune(nvec=3, reps=2, cache_path=cache)
+    lines = cache.read_text().splitlines()
+    assert sum(1 for ln in lines if ln.startswith("multi ")) == 1
+    choice = ([(m["apply_variant"], m["adjoint_variant"]) for m in G.members], G.batch_mode)
+    G2 = rtt.Geometry(geos)
+    G2.tune(nvec=3, reps=2, cache_path=cache)                       # cache hit: same choices
+    assert ([(m["apply_variant"], m["adjoint_variant"]) for m in G2.members], G2.batch_mode) == choice
+    rng = np.random.default_rng(5)
+    X = rng.random((3, G2.n_cols)).astype(np.float32)
+    Y = rng.standard_normal((3, G2.n_rows)).astype(np.float32)
+    ya = rtt.op_apply(G2, to_dev(X)).cpu().numpy()
+    xa = rtt.op_apply_adjoint(G2, to_dev(Y)).cpu().numpy()
+    for geo, m in zip(geos, G2.members):
+        cs = slice(m["col_offset"], m["col_offset"] + m["n_cols"])
+        rs = slice(m["row_offset"], m["row_offset"] + m["n_rows"])
+        assert rel(ya[:, rs], oracle.forward(geo, X[:, cs].astype(np.float64))) <= TOL
+        assert rel(xa[:, cs], oracle.adjoint(geo, Y[:, rs].astype(np.float64))) <= TOL
