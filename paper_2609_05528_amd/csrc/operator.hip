@@ -799,14 +799,15 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
     }
     // phase 2: every gather of the batch
     float xv[NB][ZI][4];
+    bool live[NB][ZI];
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         on[j] = (r0 + j < a.n_rays) && ((a.mask >> rc[j].order) & 1u);
         const int klo = rc[j].k0 + f0 / Q;
         // The scalar offset is unsigned and not range checked: it only carries the
         // non-negative row step n_phi*K.  The column step to the periodic neighbour can be
-        // negative (wrap at 2 pi), so it goes into the vector offset, which is an in-range
-        // element index of the x vector for every lane (hat clamped into [0, K)).
+        // negative (wrap at 2 pi), so it goes into the vector offset, which is either an
+        // element offset inside the x vector or, for a hat outside [0, K), a value past its end.
         const int s10 = a.nk * 4;
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
@@ -814,10 +815,8 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
             // (uniform branch), lanes outside get an offset past the end of x, which returns 0
             // without a memory access
             const int kb = klo + it * WAVE;
-            if (kb >= a.K || kb + WAVE <= 0) {
-                xv[j][it][0] = xv[j][it][1] = xv[j][it][2] = xv[j][it][3] = 0.f;
-                continue;
-            }
+            live[j][it] = kb < a.K && kb + WAVE > 0;
+            if (!live[j][it]) continue;
             const int k = kb + lane;
             const bool in = (unsigned)k < (unsigned)a.K;
             const int off0 = in ? (rc[j].c00k + k) * 4 : 0x7FFFFFF0;
@@ -835,15 +834,14 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
     for (int j = 0; j < NB; ++j) {
         th0[j] = rc[j].th0;
         row[j] = rc[j].row;
-        const int klo = rc[j].k0 + f0 / Q;
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
+            // lanes of hats outside [0, K) loaded zeros; rays that are off are not written
             const int h = lane + it * WAVE;
-            const int k = klo + h;
-            const float z = rc[j].b00 * xv[j][it][0] + rc[j].b10 * xv[j][it][1] + rc[j].b01 * xv[j][it][2] +
-                            rc[j].b11 * xv[j][it][3];
-            const bool ok = on[j] && (unsigned)k < (unsigned)a.K;
-            if (h < W) zs[j][h] = ok ? z : 0.f;
+            const float z = live[j][it] ? rc[j].b00 * xv[j][it][0] + rc[j].b10 * xv[j][it][1] +
+                                              rc[j].b01 * xv[j][it][2] + rc[j].b11 * xv[j][it][3]
+                                        : 0.f;
+            if (h < W) zs[j][h] = z;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
