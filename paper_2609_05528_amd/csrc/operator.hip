@@ -1252,10 +1252,11 @@ struct Taps {
 // nv of them exist).  Everything that depends only on the visit -- record decode, tap weights,
 // frame offsets, the sweep position -- is shared by the vectors; only the data loads and the
 // accumulation are repeated per vector.
-template <int Q, int V, int NB, bool PAIR, int NVW>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false>
 __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y0, float* __restrict__ x0,
                                            int nv, int64_t lin)
 {
+    static_assert(!DPP || (Q == 1 && !PAIR) || (Q == 2 && PAIR), "lane-shifted taps: Q = 1, or Q = 2 with frame pairs");
     typedef Taps<Q> TP_;
     constexpr int T = TP_::T;
     typedef float f2 __attribute__((ext_vector_type(2)));
@@ -1362,7 +1363,37 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
                     (void*)(((uint64_t)bhi << 32) | blo), (short)0, nrec, 0x00020000);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    if (PAIR) {
+                    if constexpr (DPP && Q == 1) {
+                        // tap m = 0 (frame k - k0) loaded once per lane; tap m = -1 is formed from it in
+                        // the accumulation (previous lane's value); lane 0 of the first chunk needs one
+                        // extra load
+                        yv[j][u][v][1] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[v][1], 0, 0));
+                        if (v == 0) {
+                            yv[j][u][0][0] = 0.f;
+                            if (lane == 0)
+                                yv[j][u][0][0] = __builtin_bit_cast(
+                                    float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[0][0], 0, 0));
+                        }
+                    } else if constexpr (DPP && Q == 2) {
+                        // frame pair m = (0, 1) loaded once per lane; pairs (-2, -1) and (-4, -3) are the
+                        // pairs (0, 1) of the previous two lanes, formed in the accumulation; lane 0 of the
+                        // first chunk loads its two earlier pairs itself
+                        const f2 p2 = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[v][4], 0, 0));
+                        yv[j][u][v][4] = p2[0];
+                        yv[j][u][v][5] = p2[1];
+                        if (v == 0) {
+                            yv[j][u][0][0] = yv[j][u][0][1] = yv[j][u][0][2] = yv[j][u][0][3] = 0.f;
+                            if (lane == 0) {
+                                const f2 pa = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[0][2], 0, 0));
+                                const f2 pb = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[0][0], 0, 0));
+                                yv[j][u][0][2] = pa[0];
+                                yv[j][u][0][3] = pa[1];
+                                yv[j][u][0][0] = pb[0];
+                                yv[j][u][0][1] = pb[1];
+                            }
+                        }
+                    } else if (PAIR) {
 #pragma unroll
                         for (int t = 0; t < T; t += 2) {
                             const f2 p2 = __builtin_bit_cast(
@@ -1382,6 +1413,35 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             while (col < vcol[j]) emit();
+            if constexpr (DPP) {
+                // earlier taps of lane i are later taps of lanes i - 1 (and i - 2): wave shifts right by
+                // one lane; lane 0 takes the previous chunk's last lane, or its own extra loads in the
+                // first chunk
+                auto shr1 = [](int old, float src) {
+                    return __builtin_bit_cast(
+                        float, __builtin_amdgcn_update_dpp(old, __builtin_bit_cast(int, src), 0x138 /* wave_shr:1 */,
+                                                           0xf, 0xf, false));
+                };
+                auto last = [](float v) { return __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63); };
+#pragma unroll
+                for (int u = 0; u < NVW; ++u)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        if constexpr (Q == 1) {
+                            const int o0 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][0]) : last(yv[j][u][v - 1][1]);
+                            yv[j][u][v][0] = shr1(o0, yv[j][u][v][1]);
+                        } else {
+                            const int o2 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][2]) : last(yv[j][u][v - 1][4]);
+                            const int o3 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][3]) : last(yv[j][u][v - 1][5]);
+                            const int o0 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][0]) : last(yv[j][u][v - 1][2]);
+                            const int o1 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][1]) : last(yv[j][u][v - 1][3]);
+                            yv[j][u][v][2] = shr1(o2, yv[j][u][v][4]);
+                            yv[j][u][v][3] = shr1(o3, yv[j][u][v][5]);
+                            yv[j][u][v][0] = shr1(o0, yv[j][u][v][2]);
+                            yv[j][u][v][1] = shr1(o1, yv[j][u][v][3]);
+                        }
+                    }
+            }
 #pragma unroll
             for (int u = 0; u < NVW; ++u)
 #pragma unroll
@@ -1397,12 +1457,12 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     while (col < ncol) emit();
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
     const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
     const int v0 = blockIdx.y * NVW;
-    visit_body<Q, V, NB, PAIR, NVW>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
+    visit_body<Q, V, NB, PAIR, NVW, DPP>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
                                     min(NVW, a.nvec - v0), xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
 }
 
@@ -1425,7 +1485,7 @@ struct VisitMulti {
     int64_t y_stride, x_stride;
 };
 
-template <int Q, int V, int NB, bool PAIR>
+template <int Q, int V, int NB, bool PAIR, bool DPP>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMulti a)
 {
     for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
@@ -1448,7 +1508,7 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMul
         va.mask = mm.mask;
         va.y_stride = a.y_stride;
         va.x_stride = a.x_stride;
-        visit_body<Q, V, NB, PAIR, 1>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
+        visit_body<Q, V, NB, PAIR, 1, DPP>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
                                       a.x + (int64_t)v * a.x_stride + mm.x_off, 1, (int64_t)(b - mm.blk_begin));
     }
 }
@@ -1887,13 +1947,14 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_sweep(AdjArgs a)
 struct AdjVariant {
     const char* name;
     int kind;   // 0 tile, 1 sweep, 2 batched tile, 3 visit list, 4 row sweep
-    int a, b;   // tile: TR, TC; sweep: TC, V; visit list: vectors per wave; row sweep: CW
+    int a, b;   // tile: TR, TC; sweep: TC, V; visit list: vectors per wave, lane-shifted taps; row sweep: CW
 };
 static const AdjVariant kAdjVariants[] = {
     {"tile8x8", 0, 8, 8},    {"tile4x8", 0, 4, 8},    {"tile4x4", 0, 4, 4},    {"sweep32v1", 1, 32, 1},
     {"sweep32v2", 1, 32, 2}, {"sweep16v1", 1, 16, 1}, {"sweep16v2", 1, 16, 2}, {"tb8x8", 2, 8, 8},
     {"tb4x8", 2, 4, 8},      {"tb4x4", 2, 4, 4},      {"tb2x4", 2, 2, 4},      {"visit", 3, 0, 0},
     {"rows4", 4, 4, 0},      {"rows8", 4, 8, 0},      {"visit2v", 3, 2, 0},    {"visit4v", 3, 4, 0},
+    {"visitd", 3, 1, 1},     {"visitd2v", 3, 2, 1},   {"visitd4v", 3, 4, 1},
 };
 constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
@@ -2208,14 +2269,38 @@ static void adjoint_dispatch_sweep(const AdjArgs& a, int P, int Q, int nvec, hip
         hipLaunchKernelGGL((k_adjoint_sweep<0, 0, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false>
 static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
     a.kchunks = (a.K + WAVE * V - 1) / (WAVE * V);
     a.nvec = nvec;
     const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW>), dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)),
-                       dim3(T_WAVES * WAVE), 0, s, a);
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP>),
+                       dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)), dim3(T_WAVES * WAVE), 0, s, a);
+}
+
+// lane-shifted taps (Q = 1, or Q = 2 with frame pairs); vpw vectors per wave
+template <int Q>
+static void visitd_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s)
+{
+    constexpr bool P = Q == 2;
+    const int64_t waves = (int64_t)a.n_r * a.nseg * ((nvec + vpw - 1) / vpw);
+    if (vpw == 4) {
+        if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 2, P, 4, true>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, 2, P, 4, true>(a, nvec, s);
+        else visit_launch<Q, 4, 1, P, 4, true>(a, nvec, s);
+        return;
+    }
+    if (vpw == 2) {
+        if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 4, P, 2, true>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, 4, P, 2, true>(a, nvec, s);
+        else visit_launch<Q, 4, 2, P, 2, true>(a, nvec, s);
+        return;
+    }
+    if (a.K <= 64 || waves < 16384) visit_launch<Q, 1, 8, P, 1, true>(a, nvec, s);
+    else if (a.K <= 128) visit_launch<Q, 2, 8, P, 1, true>(a, nvec, s);
+    else if (a.K <= 256) visit_launch<Q, 4, 4, P, 1, true>(a, nvec, s);
+    else visit_launch<Q, 8, 2, P, 1, true>(a, nvec, s);
 }
 
 // vpw: vectors per wave (1, 2 or 4).  Loads in flight per lane stay near NB * V * T / 8.
@@ -2407,7 +2492,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     return true;
 }
 
-template <int Q, int V, int NB, bool PAIR>
+template <int Q, int V, int NB, bool PAIR, bool DPP>
 static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec, bool persist,
                                hipStream_t s)
 {
@@ -2422,11 +2507,11 @@ static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int 
     a.per_vec = (uint32_t)nb;
     a.total = (uint32_t)(nb * nvec);   // below 2^31: checked by adjoint_multi
     if (a.total == 0) return;
-    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR>), dim3(multi_grid(a.total, persist)),
+    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP>), dim3(multi_grid(a.total, persist)),
                        dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, bool PAIR>
+template <int Q, bool PAIR, bool DPP = false>
 static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec,
                                  bool persist, hipStream_t s)
 {
@@ -2437,10 +2522,10 @@ static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, in
         waves += (int64_t)g->members[i].grid.n_r * g->members[i].nseg[set] * nvec;
         K = std::max(K, g->members[i].grid.n_hat);
     }
-    if (K <= 64 || waves < 16384) visit_multi_launch<Q, 1, 8, PAIR>(a, g, b, e, set, nvec, persist, s);
-    else if (K <= 128) visit_multi_launch<Q, 2, NB1, PAIR>(a, g, b, e, set, nvec, persist, s);
-    else if (K <= 256) visit_multi_launch<Q, 4, Q == 1 ? 4 : 2, PAIR>(a, g, b, e, set, nvec, persist, s);
-    else visit_multi_launch<Q, 8, 2, PAIR>(a, g, b, e, set, nvec, persist, s);
+    if (K <= 64 || waves < 16384) visit_multi_launch<Q, 1, 8, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
+    else if (K <= 128) visit_multi_launch<Q, 2, NB1, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
+    else if (K <= 256) visit_multi_launch<Q, 4, Q == 1 ? 4 : 2, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
+    else visit_multi_launch<Q, 8, 2, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
 }
 
 // Adjoint of members [b, e) in one launch; false if they do not fit the visit multi kernel.
@@ -2452,7 +2537,9 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     int64_t wide = 0;
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
-        if (!visit_supported(m) || m.Q != m0.Q || m.adj_variant != 11) return false;
+        if (!visit_supported(m) || m.Q != m0.Q || m.adj_variant != m0.adj_variant ||
+            (m0.adj_variant != 11 && m0.adj_variant != 16))
+            return false;
         pair = pair && (m.grid.n_frames % 2) == 0 && (m.row_offset % 2) == 0;
         wide += (int64_t)m.grid.n_r * m.nseg[0] * nvec;
     }
@@ -2484,7 +2571,9 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     a.x = x;
     a.y_stride = g->n_rows;
     a.x_stride = g->n_cols;
-    if (m0.Q == 1) visit_multi_dispatch<1, false>(a, g, b, e, set, nvec, persist, s);
+    if (m0.Q == 1 && m0.adj_variant == 16) visit_multi_dispatch<1, false, true>(a, g, b, e, set, nvec, persist, s);
+    else if (m0.Q == 1) visit_multi_dispatch<1, false>(a, g, b, e, set, nvec, persist, s);
+    else if (pair && m0.adj_variant == 16) visit_multi_dispatch<2, true, true>(a, g, b, e, set, nvec, persist, s);
     else if (pair) visit_multi_dispatch<2, true>(a, g, b, e, set, nvec, persist, s);
     else visit_multi_dispatch<2, false>(a, g, b, e, set, nvec, persist, s);
     hipError_t err = hipGetLastError();
@@ -2569,9 +2658,9 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
-    if (variant == 11 || variant == 14 || variant == 15) {
+    if (variant == 11 || variant >= 14) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
-        const int vpw = variant == 14 ? 2 : variant == 15 ? 4 : 1;
+        const int vpw = (variant == 14 || variant == 17) ? 2 : (variant == 15 || variant == 18) ? 4 : 1;
         const int set = ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
         VisitArgs va;
         va.visits = g->d_visits + m.visit_begin[set];
@@ -2589,7 +2678,9 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         va.mask = mask;
         // frame pairs need 8-byte aligned rows: even n_frames and aligned data vectors
         const bool pair = (va.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
-        if (m.Q == 1) visit_dispatch<1, false>(va, nvec, vpw, s);
+        if (variant >= 16 && m.Q == 1) visitd_dispatch<1>(va, nvec, vpw, s);
+        else if (variant >= 16 && pair) visitd_dispatch<2>(va, nvec, vpw, s);
+        else if (m.Q == 1) visit_dispatch<1, false>(va, nvec, vpw, s);
         else if (pair) visit_dispatch<2, true>(va, nvec, vpw, s);
         else visit_dispatch<2, false>(va, nvec, vpw, s);
         RTT_HIP(hipGetLastError());

@@ -264,17 +264,17 @@ BATCH_CASES = {
 }
 
 
-@pytest.mark.parametrize("fwd", ["lean4", "reg1", "reg2", "strip16"])
+@pytest.mark.parametrize("fwd,adj", [("lean4", "visit"), ("reg1", "visitd"), ("reg2", "visit"), ("strip16", "visitd")])
 @pytest.mark.parametrize("name", list(BATCH_CASES))
-def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd):
+def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd, adj):
     """One launch for all geometries (plain and persistent) equals one launch per geometry."""
     rtt = gpu_lib
     c = BATCH_CASES[name]
-    say("case batch modes", name, fwd)
+    say("case batch modes", name, fwd, adj)
     geos = [tiny_geometry(seed=60 + i, rays=(30 + 11 * i, 7, 3), n_frames=c["frames"](i), dt_obs=c["dt_obs"],
                           n_r=4 + i % 3, n_phi=6 + 2 * (i % 4)) for i in range(c["n"])]
     G = rtt.Geometry(geos)
-    G.set_variant(apply=rtt.variant_names(False).index(fwd))
+    G.set_variant(apply=rtt.variant_names(False).index(fwd), adjoint=rtt.variant_names(True).index(adj))
     rng = np.random.default_rng(19)
     X = rng.random((3, G.n_cols)).astype(np.float32)
     Y = rng.standard_normal((3, G.n_rows)).astype(np.float32)
