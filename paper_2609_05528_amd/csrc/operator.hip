@@ -851,6 +851,87 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
     lean_emit<Q, NB, VEC4>(&zs[0][0], th0, row, on, f0, fend, a.F, y);
 }
 
+// Quad-gather form of the lean forward, for K % 4 == 0: every x row then starts 16-byte aligned,
+// so the hats a chunk needs are read as aligned quads, one 16-byte load per stencil corner on
+// at most 35 lanes instead of one 4-byte load per hat; a quad lies wholly inside or wholly
+// outside [0, K) and is fetched or skipped as a whole.  The combined series is written to LDS
+// shifted to the ray's first hat, and the output phase is the lean one.
+template <int Q, int NB, bool VEC4>
+__device__ __forceinline__ void leanq_body(const LeanArgs& a, const float* __restrict__ x, float* __restrict__ y,
+                                           int64_t blk, int chunk)
+{
+    constexpr int FC = 128 * Q;
+    constexpr int W = FC / Q + 4;
+    constexpr int ZI = (W + WAVE - 1) / WAVE;
+    constexpr int ZS = ZI * WAVE;
+    constexpr int NQ = (W + 3) / 4 + 1;   // quads covering W hats from any start (35)
+    __shared__ __attribute__((aligned(16))) float zs_all[A_WAVES][NB][ZS];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t r0 = (blk * A_WAVES + wave) * NB;
+    if (r0 >= a.n_rays) return;
+    const int f0 = chunk * FC;
+    const int fend = min(a.F, f0 + FC);
+    float(*zs)[ZS] = zs_all[wave];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
+    const int s10 = a.nk * 4;
+
+    FwdRec rc[NB];
+    bool on[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int64_t ri = r0 + j;
+        rc[j] = load_const_rec(a.rec + __builtin_amdgcn_readfirstlane((int)(ri < a.n_rays ? ri : r0)));
+    }
+    f4 xq[NB][4];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        on[j] = (r0 + j < a.n_rays) && ((a.mask >> rc[j].order) & 1u);
+        const int klo = rc[j].k0 + f0 / Q;
+        const int ka = klo & ~3;                      // aligned start (floor, also for klo < 0)
+        const int kq = ka + 4 * lane;                 // this lane's quad
+        const bool in = lane < NQ && kq >= 0 && kq < a.K;
+        const int off0 = in ? (rc[j].c00k + kq) * 4 : 0x7FFFFFF0;
+        const int off1 = in ? off0 + rc[j].d01k * 4 : 0x7FFFFFF0;
+        xq[j][0] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, off0, 0, 0));
+        xq[j][1] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, off0, s10, 0));
+        xq[j][2] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, off1, 0, 0));
+        xq[j][3] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(xr, off1, s10, 0));
+    }
+    float th0[NB];
+    int row[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        th0[j] = rc[j].th0;
+        row[j] = rc[j].row;
+        const int klo = rc[j].k0 + f0 / Q;
+        const int base = 4 * lane - (klo - (klo & ~3));   // LDS position of the quad's first hat
+        const f4 z = rc[j].b00 * xq[j][0] + rc[j].b10 * xq[j][1] + rc[j].b01 * xq[j][2] + rc[j].b11 * xq[j][3];
+        // every position of z[j][0 .. W) is written by exactly one lane
+        if (lane < NQ) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int h = base + t;
+                if (h >= 0 && h < W) zs[j][h] = z[t];
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    lean_emit<Q, NB, VEC4>(&zs[0][0], th0, row, on, f0, fend, a.F, y);
+}
+
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_leanq(LeanArgs a)
+{
+    leanq_body<Q, NB, VEC4>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
+                            xcd_remap(blockIdx.x, gridDim.x), blockIdx.z);
+}
+
 template <int Q, int NB, bool VEC4>
 __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
 {
@@ -1960,11 +2041,11 @@ constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 10; }
+int n_apply_variants() { return 11; }
 const char* apply_variant_name(int v)
 {
     static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8", "reg1", "reg2", "strip16",
-                                  "strip8"};
+                                  "strip8", "lean4q"};
     return names[v];
 }
 bool lean_supported(const Member& m)
@@ -1996,7 +2077,8 @@ bool apply_variant_ok(const Member& m, int v)
     if (v < 0 || v >= n_apply_variants()) return false;
     if ((v == 2 || v == 3) && m.P > m.Q) return false;   // batch / stream need dt_obs <= dt_src
     if (v >= 4 && !lean_supported(m)) return false;      // lean / reg / strip need dt_obs/dt_src = 1 or 1/2
-    if (v >= 8 && strip_lds_bytes(m, v == 8 ? 16 : 8) > 65536) return false;
+    if ((v == 8 || v == 9) && strip_lds_bytes(m, v == 8 ? 16 : 8) > 65536) return false;
+    if (v == 10 && m.grid.n_hat % 4 != 0) return false;   // quad gathers need 16-byte aligned x rows
     return true;
 }
 
@@ -2088,12 +2170,17 @@ static void apply_dispatch(const ApplyArgs& a, int nvec, int variant, hipStream_
         hipLaunchKernelGGL((k_apply<TP, TQ, 1>), grid, dim3(A_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, int NB>
+template <int Q, int NB, bool QUAD = false>
 static void lean_launch(const LeanArgs& a, int nvec, bool vec4, hipStream_t s)
 {
     const int64_t rays_per_block = (int64_t)A_WAVES * NB;
     const int nch = (a.F + 128 * Q - 1) / (128 * Q);
     dim3 grid((unsigned)((a.n_rays + rays_per_block - 1) / rays_per_block), (unsigned)nvec, (unsigned)nch);
+    if (QUAD) {
+        if (vec4) hipLaunchKernelGGL((k_apply_leanq<Q, NB, true>), grid, dim3(A_WAVES * WAVE), 0, s, a);
+        else hipLaunchKernelGGL((k_apply_leanq<Q, NB, false>), grid, dim3(A_WAVES * WAVE), 0, s, a);
+        return;
+    }
     if (vec4) hipLaunchKernelGGL((k_apply_lean<Q, NB, true>), grid, dim3(A_WAVES * WAVE), 0, s, a);
     else hipLaunchKernelGGL((k_apply_lean<Q, NB, false>), grid, dim3(A_WAVES * WAVE), 0, s, a);
 }
@@ -2180,7 +2267,9 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
-    if (variant == 4 || variant == 5) {
+    // quad gathers read 16-byte words: they need 16-byte aligned coefficient vectors
+    if (variant == 10 && ((((uintptr_t)x) & 15) != 0 || (nvec > 1 && (x_stride % 4) != 0))) variant = 4;
+    if (variant == 4 || variant == 5 || variant == 10) {
         LeanArgs la;
         la.rec = g->d_fwd + m.ray_begin;
         la.n_rays = m.n_rays;
@@ -2196,10 +2285,12 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         // float4 rows need F % 4 == 0 and 16-byte aligned vectors
         const bool vec4 = (la.F % 4) == 0 && (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (y_stride % 4) == 0);
         if (m.Q == 1) {
-            if (variant == 4) lean_launch<1, 4>(la, nvec, vec4, s);
+            if (variant == 10) lean_launch<1, 4, true>(la, nvec, vec4, s);
+            else if (variant == 4) lean_launch<1, 4>(la, nvec, vec4, s);
             else lean_launch<1, 8>(la, nvec, vec4, s);
         } else {
-            if (variant == 4) lean_launch<2, 4>(la, nvec, vec4, s);
+            if (variant == 10) lean_launch<2, 4, true>(la, nvec, vec4, s);
+            else if (variant == 4) lean_launch<2, 4>(la, nvec, vec4, s);
             else lean_launch<2, 8>(la, nvec, vec4, s);
         }
         RTT_HIP(hipGetLastError());

@@ -304,6 +304,7 @@ VARIANT_CASES = {
     "long_rows": dict(seed=26, rays=(200, 30, 20), n_frames=700, n_r=4, n_phi=9),
     "k_wide": dict(seed=27, rays=(300, 60, 40), n_frames=220, n_r=5, n_phi=10),
     "k_mid_half": dict(seed=28, rays=(300, 60, 40), dt_obs=2.0, n_frames=300, n_r=6, n_phi=11),
+    "k_quad": dict(seed=29, rays=(500, 90, 60), n_frames=67, n_r=9, n_phi=14),
     "ring1": dict(seed=24, rays=(40, 10), n_r=5, n_phi=1, n_frames=5),
 }
 
@@ -326,6 +327,8 @@ def test_every_kernel_variant_matches_oracle(gpu_lib, name):
         if vname in ("batch", "stream") and not ratio_le1:
             continue
         if vname.startswith(("lean", "reg", "strip")) and not unit_or_half:
+            continue
+        if vname == "lean4q" and geo.grid.n_hat % 4:
             continue
         G.set_variant(apply=v)
         ya = rtt.op_apply(G, to_dev(X)).cpu().numpy()
