@@ -35,10 +35,10 @@ RAY_RECORD_BYTES = 32
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip")
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on this workload
 # (FETCH_SIZE scaled by 2.0, the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only
-# for the kernel source digest they were taken on (see profiles/).
+# for the kernel source digest and variant they were taken on (see profiles/).
 MEASURED_TRAFFIC = {
-    "op_apply_adjoint": {"bytes": 2553542083, "digest": "9c26ad0db9fe5f6f", "nvec": 264},
-    "op_apply": {"bytes": 2104417208, "digest": "9c26ad0db9fe5f6f", "nvec": 264},
+    "op_apply_adjoint": {"bytes": 2217375744, "digest": "9fae70cc970287ce", "nvec": 264, "variant": "visitd2v"},
+    "op_apply": {"bytes": 2104403968, "digest": "9fae70cc970287ce", "nvec": 264, "variant": "lean4"},
 }
 
 
@@ -445,7 +445,8 @@ def main():
 
     digest = source_digest()
     meas = MEASURED_TRAFFIC.get(dom)
-    traffic = meas["bytes"] if (meas and meas.get("digest") == digest and meas.get("nvec") == nvec) else None
+    traffic = meas["bytes"] if (meas and meas.get("digest") == digest and meas.get("nvec") == nvec
+                                and meas.get("variant") == variants[dom]) else None
 
     out = {
         "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": args.steps,
