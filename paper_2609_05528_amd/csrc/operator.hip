@@ -809,6 +809,17 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
         // negative (wrap at 2 pi), so it goes into the vector offset, which is either an
         // element offset inside the x vector or, for a hat outside [0, K), a value past its end.
         const int s10 = a.nk * 4;
+        // rays sorted by base cell: a ray with the same cell and hat origin as the previous one
+        // needs exactly the same x values (uniform branch)
+        if (j > 0 && rc[j].c00k == rc[j - 1].c00k && rc[j].d01k == rc[j - 1].d01k && rc[j].k0 == rc[j - 1].k0) {
+#pragma unroll
+            for (int it = 0; it < ZI; ++it) {
+                live[j][it] = live[j - 1][it];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xv[j][it][c] = xv[j - 1][it][c];
+            }
+            continue;
+        }
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
             // hats outside [0, K) carry no basis function: a chunk with none inside is skipped
@@ -890,6 +901,12 @@ __device__ __forceinline__ void leanq_body(const LeanArgs& a, const float* __res
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         on[j] = (r0 + j < a.n_rays) && ((a.mask >> rc[j].order) & 1u);
+        // same base cell and hat origin as the previous ray: the same x values (uniform branch)
+        if (j > 0 && rc[j].c00k == rc[j - 1].c00k && rc[j].d01k == rc[j - 1].d01k && rc[j].k0 == rc[j - 1].k0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) xq[j][c] = xq[j - 1][c];
+            continue;
+        }
         const int klo = rc[j].k0 + f0 / Q;
         const int ka = klo & ~3;                      // aligned start (floor, also for klo < 0)
         const int kq = ka + 4 * lane;                 // this lane's quad
