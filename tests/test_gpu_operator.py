@@ -305,6 +305,7 @@ VARIANT_CASES = {
     "k_wide": dict(seed=27, rays=(300, 60, 40), n_frames=220, n_r=5, n_phi=10),
     "k_mid_half": dict(seed=28, rays=(300, 60, 40), dt_obs=2.0, n_frames=300, n_r=6, n_phi=11),
     "k_quad": dict(seed=29, rays=(500, 90, 60), n_frames=67, n_r=9, n_phi=14),
+    "k_even_f_even": dict(seed=31, rays=(500, 90, 60), n_frames=70, n_r=9, n_phi=14, extra_hats=2),
     "ring1": dict(seed=24, rays=(40, 10), n_r=5, n_phi=1, n_frames=5),
 }
 
