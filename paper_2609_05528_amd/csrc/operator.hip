@@ -1295,31 +1295,43 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_reg_multi(RegMulti a)
 
 // --------------------------------------------------------------------------------------------
 // A^T, visit-list form (dt_obs/dt_src = 1/Q).  A wave owns cell row ci, a segment of vseg
-// columns and a chunk of 64 V hats (V per lane).  Its visit list (built at load time) holds, in
+// columns and a chunk of hats (V per lane).  Its visit list (built at load time) holds, in
 // sweep order, every ray that touches the row inside the segment with the row's weights
-// already folded in.  The wave fetches NB visit records with one vector load, reads each ray's
-// data row through a buffer descriptor whose range is exactly the row (out-of-range frames read
-// as 0; negative offsets are clamped to a large positive value first, so no offset can wrap
-// into range), applies the ray's fixed 2Q-tap hat filter
-// (frame f = Q (k - k0) + m, weight 1 - |th0 + m/Q|), and accumulates into two sliding
-// register accumulators (target columns u and u+1).  A finished column is written once.
+// already folded in.  The wave reads NB visit records with scalar loads, applies each ray's
+// fixed 2Q-tap hat filter (frame f = Q (k - k0) + m, weight 1 - |th0 + m/Q|) to its data row
+// and accumulates into two sliding register accumulators (target columns u and u+1).  A
+// finished column is written once.
+//
+// Memory access: one buffer descriptor spans the wave's data vectors and one its output
+// vectors.  The uniform part of an address (row or column start, vector) goes into the scalar
+// offset; the per-lane part is checked against the row (frames outside [0, F), hats outside
+// [0, K), switched-off visits) and replaced by an offset past every range when it fails, so
+// such lanes read 0 or drop their store without touching memory.
 // --------------------------------------------------------------------------------------------
 struct VisitArgs {
     const Visit* visits;
     const int64_t* vtask;
     int n_r, n_phi, K, F, nseg, vseg;
-    int kchunks;        // hat chunks of 64*V hats (one per wave)
+    int kchunks;        // hat chunks per cell row (visit_chunk hats each, one per wave)
     int nvec;           // vectors of the launch (a workgroup takes NVW of them)
     const float* y;
     float* x;
     int64_t y_stride, x_stride;
     uint32_t mask;
+    uint32_t y_bytes, x_bytes;   // the member's data and output block of one vector (bytes)
 };
 
-__device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, int byte_off)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
-}
+// Offset past every buffer range used here (ranges stay below 2^31 - 256, so adding a scalar
+// offset below that cannot wrap).
+constexpr unsigned VISIT_SENT = 0x7FFFFFF0u;
+// Lane-shifted taps with halo lanes: the first H lanes of a chunk load the frames of the H hats
+// before it and only feed their neighbours (no extra loads for lane 0).
+template <int Q, bool DPP, bool HALO>
+struct VisitHalo {
+    static constexpr int H = (DPP && HALO) ? (Q == 1 ? 1 : 2) : 0;
+};
+template <int Q, int V, bool DPP, bool HALO>
+constexpr int visit_chunk() { return WAVE * V - VisitHalo<Q, DPP, HALO>::H; }
 
 // Tap weights of one visit: frame f = Q (k - k0) + MLO + t feeds hat k with weight
 // 1 - |th0 + (MLO + t)/Q| (zero outside the hat).  Q = 1: taps m = -1, 0.  Q = 2: taps
@@ -1347,32 +1359,66 @@ struct Taps {
 
 // One block of the visit-list adjoint: task `lin` = (row group, segment, hat chunk) of one member
 // for NVW consecutive vectors (y0, x0: the first of them, already offset to the member's blocks;
-// nv of them exist).  Everything that depends only on the visit -- record decode, tap weights,
-// frame offsets, the sweep position -- is shared by the vectors; only the data loads and the
-// accumulation are repeated per vector.
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false>
+// nv of them exist).
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO>
 __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y0, float* __restrict__ x0,
                                            int nv, int64_t lin)
 {
     static_assert(!DPP || (Q == 1 && !PAIR) || (Q == 2 && PAIR), "lane-shifted taps: Q = 1, or Q = 2 with frame pairs");
+    static_assert(DPP || !HALO, "halo lanes serve the lane-shifted taps");
     typedef Taps<Q> TP_;
     constexpr int T = TP_::T;
+    constexpr int H = VisitHalo<Q, DPP, HALO>::H;
+    constexpr int C = visit_chunk<Q, V, DPP, HALO>();
     typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(4))) int64_t* ci64p;
+    typedef const __attribute__((address_space(4))) i4v* cvisp;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x >> 6;
+    // wave index in a scalar register: everything a wave reads from the task and visit
+    // tables then comes through scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int kch = (int)(lin % a.kchunks);
     const int64_t l2 = lin / a.kchunks;
     const int sg = (int)(l2 % a.nseg), rg = (int)(l2 / a.nseg);
     const int ci = rg * T_WAVES + wave;
     if (ci >= a.n_r) return;
     const int64_t task = (int64_t)ci * a.nseg + sg;
-    const int64_t vbeg = a.vtask[task], vend = a.vtask[task + 1];
+    const int64_t vbeg = ((ci64p)a.vtask)[task], vend = ((ci64p)a.vtask)[task + 1];
     const int jlo = sg * a.vseg;
     const int jhi = min(jlo + a.vseg, a.n_phi);
     const int ncol = jhi - jlo + 1;
-    const int kc = kch * WAVE * V;       // first hat of this wave's chunk
-    const int rowbytes = a.F * 4;
+    const int kc = kch * C;              // first output hat of this wave's chunk
+    const unsigned rowbytes = (unsigned)a.F * 4u;
     const int lane_off = Q * lane * 4;   // per-lane part of every frame offset
+
+    // descriptors over the wave's vectors: the range ends with the last vector that exists
+    auto span = [](const float* p, int64_t stride, uint32_t bytes, int n) {
+        const uint64_t base = (uint64_t)p;
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+        const int nrec = __builtin_amdgcn_readfirstlane((int)((uint32_t)(n - 1) * (uint32_t)stride * 4u + bytes));
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0, nrec, 0x00020000);
+    };
+    const __amdgpu_buffer_rsrc_t ry = span(y0, a.y_stride, a.y_bytes, nv);
+    const __amdgpu_buffer_rsrc_t rx = span(x0, a.x_stride, a.x_bytes, nv);
+    // scalar offsets of the vectors; missing vectors re-read the first one (their sums are
+    // never stored)
+    int soy[NVW], sox[NVW];
+#pragma unroll
+    for (int u = 0; u < NVW; ++u) {
+        soy[u] = u < nv ? (int)((uint32_t)u * (uint32_t)a.y_stride * 4u) : 0;
+        sox[u] = (int)((uint32_t)u * (uint32_t)a.x_stride * 4u);
+    }
+    // hats of this lane: kc - H + lane + 64 v.  Frames are fetched for hats below K (halo lanes
+    // included); sums are stored for the chunk's own hats below K.
+    bool hat_in[V];
+    unsigned st_off[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int k = kc - H + lane + WAVE * v;
+        hat_in[v] = k < a.K;
+        st_off[v] = (k >= kc && k < a.K) ? (unsigned)k * 4u : VISIT_SENT;
+    }
 
     float acc_a[NVW][V], acc_b[NVW][V];
 #pragma unroll
@@ -1382,16 +1428,14 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     int col = 0;
     auto emit = [&]() {
         if (col >= 1) {
-            const int64_t xo = (int64_t)(ci * a.n_phi + (jlo - 1 + col)) * a.K;
+            const int xo = (ci * a.n_phi + (jlo - 1 + col)) * a.K * 4;   // column start (bytes)
 #pragma unroll
             for (int u = 0; u < NVW; ++u) {
                 if (u >= nv) break;
-                float* xr = x0 + (int64_t)u * a.x_stride + xo;
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const int k = kc + lane + WAVE * v;
-                    if (k < a.K) xr[k] = acc_a[u][v];
-                }
+                for (int v = 0; v < V; ++v)
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_a[u][v]), rx, (int)st_off[v],
+                                                          sox[u] + xo, 0);
             }
         }
 #pragma unroll
@@ -1403,88 +1447,78 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             }
         ++col;
     };
+    // byte offset of a frame of the row, or the sentinel when the frame or hat is out of range
+    auto frame_off = [&](int fb, bool ok) -> int {
+        return (ok && (unsigned)fb < rowbytes) ? fb : (int)VISIT_SENT;
+    };
 
-    // visit records of the first batch; each iteration prefetches the next batch's records
-    int4 n0 = make_int4(0, 0, 0, 0), n1 = make_int4(0, 0, 0, 0);
-    if (lane < NB && vbeg + lane < vend) {
-        const int4* vp = (const int4*)(a.visits + vbeg + lane);
-        n0 = vp[0];
-        n1 = vp[1];
-    }
     for (int64_t e0 = vbeg; e0 < vend; e0 += NB) {
-        const int4 r0 = n0, r1 = n1;
-        n0 = make_int4(0, 0, 0, 0);
-        n1 = make_int4(0, 0, 0, 0);
-        if (lane < NB && e0 + NB + lane < vend) {
-            const int4* vp = (const int4*)(a.visits + e0 + NB + lane);
-            n0 = vp[0];
-            n1 = vp[1];
+        // the batch's visit records, scalar loads (the last batch re-reads its last record for
+        // the missing ones, which are then switched off)
+        i4v r0[NB], r1[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const cvisp q = (cvisp)(a.visits + min(e0 + j, vend - 1));
+            r0[j] = q[0];
+            r1[j] = q[1];
         }
         float yv[NB][NVW][V][T], tw[NB][T], wa[NB], wb[NB];
         int vcol[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const bool valid = e0 + j < vend;
-            const int row = __builtin_amdgcn_readlane(r0.x, j);
-            const int k0 = __builtin_amdgcn_readlane(r0.y, j);
-            const float th0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(r0.z, j));
-            wa[j] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(r0.w, j));
-            wb[j] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(r1.x, j));
-            vcol[j] = valid ? __builtin_amdgcn_readlane(r1.y, j) : ncol;
-            const int order = __builtin_amdgcn_readlane(r1.z, j);
+            // a vector element is copied to a plain int before its bits are reinterpreted
+            // (bit_cast applied to the element expression itself reads element 0)
+            const int row = r0[j].x, k0 = r0[j].y, th0_b = r0[j].z, wa_b = r0[j].w;
+            const int wb_b = r1[j].x, col_j = r1[j].y, order = r1[j].z;
+            wa[j] = __builtin_bit_cast(float, wa_b);
+            wb[j] = __builtin_bit_cast(float, wb_b);
+            vcol[j] = valid ? col_j : ncol;
             const bool on = valid && ((a.mask >> order) & 1u);
-            TP_::weights(th0, tw[j]);
-            // frame offsets (bytes) of this visit, identical for every vector.  Lanes whose hat
-            // lies outside [0, K) get an offset past the row: their frames are never fetched.
-            unsigned off[V][T];
+            TP_::weights(__builtin_bit_cast(float, th0_b), tw[j]);
+            const int rowoff = row * a.F * 4;   // start of the data row in the vector (bytes)
+            // frame offsets of this visit within the row, identical for every vector
+            int off[V][T];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int ub = (Q * (kc + WAVE * v - k0) + TP_::MLO) * 4;   // uniform part of the offset
-                const bool in = kc + WAVE * v + lane < a.K;
+                const int ub = (Q * (kc - H + WAVE * v - k0) + TP_::MLO) * 4;   // uniform part
 #pragma unroll
-                for (int t = 0; t < T; ++t)
-                    // frames before the row: clamp the unsigned offset far below 2^32 so that
-                    // offset + 8 cannot wrap back into the row's range
-                    off[v][t] = in ? min((unsigned)(lane_off + ub + 4 * t), 0x7FFFFFF0u) : 0x7FFFFFF0u;
+                for (int t = 0; t < T; ++t) off[v][t] = frame_off(lane_off + ub + 4 * t, on && hat_in[v]);
+            }
+            // lane 0 of a chunk without halo lanes loads the earlier taps of its hat itself
+            int off0[T];
+            if constexpr (DPP && !HALO) {
+                const int ub0 = (Q * (kc - k0) + TP_::MLO) * 4;
+#pragma unroll
+                for (int t = 0; t < T; ++t) off0[t] = frame_off(ub0 + 4 * t, on);
             }
 #pragma unroll
             for (int u = 0; u < NVW; ++u) {
-                // zero-sized range for skipped visits and missing vectors: their loads return 0
-                // without touching memory.  The descriptor fields are made provably uniform
-                // (scalar registers), otherwise every buffer load would be wrapped in a per-lane
-                // waterfall loop.
-                const uint64_t base = (uint64_t)(y0 + (int64_t)u * a.y_stride + (int64_t)row * a.F);
-                const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-                const uint32_t bhi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-                const int nrec = __builtin_amdgcn_readfirstlane((on && u < nv) ? rowbytes : 0);
-                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(((uint64_t)bhi << 32) | blo), (short)0, nrec, 0x00020000);
+                const int so = soy[u] + rowoff;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     if constexpr (DPP && Q == 1) {
-                        // tap m = 0 (frame k - k0) loaded once per lane; tap m = -1 is formed from it in
-                        // the accumulation (previous lane's value); lane 0 of the first chunk needs one
-                        // extra load
+                        // tap m = 0 (frame k - k0) loaded once per lane; tap m = -1 is the previous
+                        // lane's, formed in the accumulation
                         yv[j][u][v][1] = __builtin_bit_cast(
-                            float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[v][1], 0, 0));
-                        if (v == 0) {
+                            float, __builtin_amdgcn_raw_buffer_load_b32(ry, off[v][1], so, 0));
+                        if (!HALO && v == 0) {
                             yv[j][u][0][0] = 0.f;
                             if (lane == 0)
                                 yv[j][u][0][0] = __builtin_bit_cast(
-                                    float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[0][0], 0, 0));
+                                    float, __builtin_amdgcn_raw_buffer_load_b32(ry, off0[0], so, 0));
                         }
                     } else if constexpr (DPP && Q == 2) {
                         // frame pair m = (0, 1) loaded once per lane; pairs (-2, -1) and (-4, -3) are the
-                        // pairs (0, 1) of the previous two lanes, formed in the accumulation; lane 0 of the
-                        // first chunk loads its two earlier pairs itself
-                        const f2 p2 = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[v][4], 0, 0));
+                        // pairs (0, 1) of the previous two lanes, formed in the accumulation
+                        const f2 p2 = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ry, off[v][4], so, 0));
                         yv[j][u][v][4] = p2[0];
                         yv[j][u][v][5] = p2[1];
-                        if (v == 0) {
+                        if (!HALO && v == 0) {
                             yv[j][u][0][0] = yv[j][u][0][1] = yv[j][u][0][2] = yv[j][u][0][3] = 0.f;
                             if (lane == 0) {
-                                const f2 pa = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[0][2], 0, 0));
-                                const f2 pb = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[0][0], 0, 0));
+                                const f2 pa = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ry, off0[2], so, 0));
+                                const f2 pb = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(ry, off0[0], so, 0));
                                 yv[j][u][0][2] = pa[0];
                                 yv[j][u][0][3] = pa[1];
                                 yv[j][u][0][0] = pb[0];
@@ -1492,10 +1526,11 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
                             }
                         }
                     } else if (PAIR) {
+                        // aligned frame pairs (even F): a pair is inside the row or outside it
 #pragma unroll
                         for (int t = 0; t < T; t += 2) {
                             const f2 p2 = __builtin_bit_cast(
-                                f2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off[v][t], 0, 0));
+                                f2, __builtin_amdgcn_raw_buffer_load_b64(ry, off[v][t], so, 0));
                             yv[j][u][v][t] = p2[0];
                             yv[j][u][v][t + 1] = p2[1];
                         }
@@ -1503,7 +1538,7 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
 #pragma unroll
                         for (int t = 0; t < T; ++t)
                             yv[j][u][v][t] = __builtin_bit_cast(
-                                float, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off[v][t], 0, 0));
+                                float, __builtin_amdgcn_raw_buffer_load_b32(ry, off[v][t], so, 0));
                     }
                 }
             }
@@ -1513,8 +1548,8 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             while (col < vcol[j]) emit();
             if constexpr (DPP) {
                 // earlier taps of lane i are later taps of lanes i - 1 (and i - 2): wave shifts right by
-                // one lane; lane 0 takes the previous chunk's last lane, or its own extra loads in the
-                // first chunk
+                // one lane; lane 0 takes the previous slot's last lane, or in the first slot its own
+                // extra loads (halo lanes: anything, their sums are not stored)
                 auto shr1 = [](int old, float src) {
                     return __builtin_bit_cast(
                         float, __builtin_amdgcn_update_dpp(old, __builtin_bit_cast(int, src), 0x138 /* wave_shr:1 */,
@@ -1526,13 +1561,14 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
                         if constexpr (Q == 1) {
-                            const int o0 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][0]) : last(yv[j][u][v - 1][1]);
+                            const int o0 = v > 0 ? last(yv[j][u][v - 1][1])
+                                                 : __builtin_bit_cast(int, yv[j][u][0][HALO ? 1 : 0]);
                             yv[j][u][v][0] = shr1(o0, yv[j][u][v][1]);
                         } else {
-                            const int o2 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][2]) : last(yv[j][u][v - 1][4]);
-                            const int o3 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][3]) : last(yv[j][u][v - 1][5]);
-                            const int o0 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][0]) : last(yv[j][u][v - 1][2]);
-                            const int o1 = v == 0 ? __builtin_bit_cast(int, yv[j][u][0][1]) : last(yv[j][u][v - 1][3]);
+                            const int o2 = v > 0 ? last(yv[j][u][v - 1][4]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 4 : 2]);
+                            const int o3 = v > 0 ? last(yv[j][u][v - 1][5]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 5 : 3]);
+                            const int o0 = v > 0 ? last(yv[j][u][v - 1][2]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 4 : 0]);
+                            const int o1 = v > 0 ? last(yv[j][u][v - 1][3]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 5 : 1]);
                             yv[j][u][v][2] = shr1(o2, yv[j][u][v][4]);
                             yv[j][u][v][3] = shr1(o3, yv[j][u][v][5]);
                             yv[j][u][v][0] = shr1(o0, yv[j][u][v][2]);
@@ -1555,13 +1591,14 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     while (col < ncol) emit();
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
     const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
     const int v0 = blockIdx.y * NVW;
-    visit_body<Q, V, NB, PAIR, NVW, DPP>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
-                                    min(NVW, a.nvec - v0), xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
+    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
+                                               min(NVW, a.nvec - v0),
+                                               xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
 }
 
 // Every member of a handle (up to MULTI_MAX) in one launch; tasks numbered as in
@@ -1573,6 +1610,7 @@ struct VisitMember {
     uint32_t blk_begin;
     int n_r, n_phi, K, F, nseg, vseg, kchunks;
     uint32_t mask;
+    uint32_t y_bytes, x_bytes;
 };
 struct VisitMulti {
     VisitMember m[MULTI_MAX];
@@ -1583,7 +1621,7 @@ struct VisitMulti {
     int64_t y_stride, x_stride;
 };
 
-template <int Q, int V, int NB, bool PAIR, bool DPP>
+template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMulti a)
 {
     for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
@@ -1606,8 +1644,10 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMul
         va.mask = mm.mask;
         va.y_stride = a.y_stride;
         va.x_stride = a.x_stride;
-        visit_body<Q, V, NB, PAIR, 1, DPP>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
-                                      a.x + (int64_t)v * a.x_stride + mm.x_off, 1, (int64_t)(b - mm.blk_begin));
+        va.y_bytes = mm.y_bytes;
+        va.x_bytes = mm.x_bytes;
+        visit_body<Q, V, NB, PAIR, 1, DPP, HALO>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
+                                                 a.x + (int64_t)v * a.x_stride + mm.x_off, 1, (int64_t)(b - mm.blk_begin));
     }
 }
 
@@ -2377,13 +2417,38 @@ static void adjoint_dispatch_sweep(const AdjArgs& a, int P, int Q, int nvec, hip
         hipLaunchKernelGGL((k_adjoint_sweep<0, 0, TC, V, NB>), grid, dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false>
+// The visit kernel addresses the data and output vectors of a wave through one buffer range
+// each: nvw vectors (stride in floats) of a member's n_rows data and n_cols output floats must
+// span less than 2^31 - 256 bytes.
+static bool visit_fits(int64_t n_rows, int64_t n_cols, int64_t y_stride, int64_t x_stride, int nvw)
+{
+    const int64_t lim = (int64_t)VISIT_SENT - 240;
+    return (int64_t)(nvw - 1) * y_stride * 4 + n_rows * 4 <= lim && (int64_t)(nvw - 1) * x_stride * 4 + n_cols * 4 <= lim;
+}
+
+// Halo lanes (lane-shifted taps) when they cost no extra hat chunk: K hats in as many chunks of
+// 64 V - H hats as of 64 V.
+template <int Q, int V>
+static bool visit_halo_fits(int K)
+{
+    constexpr int C = visit_chunk<Q, V, true, true>();
+    return (K + C - 1) / C == (K + WAVE * V - 1) / (WAVE * V);
+}
+
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false>
 static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
-    a.kchunks = (a.K + WAVE * V - 1) / (WAVE * V);
+    if constexpr (DPP && !HALO) {
+        if (visit_halo_fits<Q, V>(a.K)) {
+            visit_launch<Q, V, NB, PAIR, NVW, true, true>(a, nvec, s);
+            return;
+        }
+    }
+    constexpr int C = visit_chunk<Q, V, DPP, HALO>();
+    a.kchunks = (a.K + C - 1) / C;
     a.nvec = nvec;
     const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP>),
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO>),
                        dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)), dim3(T_WAVES * WAVE), 0, s, a);
 }
 
@@ -2600,22 +2665,31 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     return true;
 }
 
-template <int Q, int V, int NB, bool PAIR, bool DPP>
+template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO = false>
 static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec, bool persist,
                                hipStream_t s)
 {
+    if constexpr (DPP && !HALO) {
+        bool fits = true;
+        for (int i = b; i < e; ++i) fits = fits && visit_halo_fits<Q, V>(g->members[i].grid.n_hat);
+        if (fits) {
+            visit_multi_launch<Q, V, NB, PAIR, true, true>(a, g, b, e, set, nvec, persist, s);
+            return;
+        }
+    }
+    constexpr int C = visit_chunk<Q, V, DPP, HALO>();
     int64_t nb = 0;
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
         VisitMember& d = a.m[i - b];
-        d.kchunks = (m.grid.n_hat + WAVE * V - 1) / (WAVE * V);
+        d.kchunks = (m.grid.n_hat + C - 1) / C;
         d.blk_begin = (uint32_t)nb;
         nb += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * d.nseg * d.kchunks;
     }
     a.per_vec = (uint32_t)nb;
     a.total = (uint32_t)(nb * nvec);   // below 2^31: checked by adjoint_multi
     if (a.total == 0) return;
-    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP>), dim3(multi_grid(a.total, persist)),
+    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP, HALO>), dim3(multi_grid(a.total, persist)),
                        dim3(T_WAVES * WAVE), 0, s, a);
 }
 
@@ -2652,10 +2726,13 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
         wide += (int64_t)m.grid.n_r * m.nseg[0] * nvec;
     }
     const int set = wide >= 16384 ? 0 : 1;
-    int64_t most = 0;   // task count with one hat chunk of 64 per wave (the largest any V gives)
+    // task count with the narrowest hat chunk (62 hats, the largest count any V gives); every
+    // member's blocks must fit the visit kernel's 31-bit buffer ranges
+    int64_t most = 0;
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
-        most += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * m.nseg[set] * ((m.grid.n_hat + WAVE - 1) / WAVE);
+        if (!visit_fits(m.n_rows, m.n_cols, 0, 0, 1)) return false;
+        most += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * m.nseg[set] * ((m.grid.n_hat + WAVE - 3) / (WAVE - 2));
     }
     if (most * nvec >= (1ll << 31)) return false;
     VisitMulti a;
@@ -2674,6 +2751,8 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
         d.nseg = m.nseg[set];
         d.vseg = m.vseg[set];
         d.mask = effective_mask(m, mask);
+        d.y_bytes = (uint32_t)(m.n_rows * 4);
+        d.x_bytes = (uint32_t)(m.n_cols * 4);
     }
     a.y = y;
     a.x = x;
@@ -2766,9 +2845,11 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
+    if ((variant == 11 || variant >= 14) && !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 1)) variant = 2;
     if (variant == 11 || variant >= 14) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
-        const int vpw = (variant == 14 || variant == 17) ? 2 : (variant == 15 || variant == 18) ? 4 : 1;
+        int vpw = (variant == 14 || variant == 17) ? 2 : (variant == 15 || variant == 18) ? 4 : 1;
+        if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = 1;
         const int set = ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
         VisitArgs va;
         va.visits = g->d_visits + m.visit_begin[set];
@@ -2784,6 +2865,8 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         va.y_stride = y_stride;
         va.x_stride = x_stride;
         va.mask = mask;
+        va.y_bytes = (uint32_t)(m.n_rows * 4);
+        va.x_bytes = (uint32_t)(m.n_cols * 4);
         // frame pairs need 8-byte aligned rows: even n_frames and aligned data vectors
         const bool pair = (va.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
         if (variant >= 16 && m.Q == 1) visitd_dispatch<1>(va, nvec, vpw, s);
