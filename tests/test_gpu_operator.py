@@ -229,6 +229,40 @@ def test_multi_vector_and_order_mask(gpu_lib):
     assert rel(ys[P[0]:P[0] + P[1]].cpu().numpy(), ref[P[0]:P[0] + P[1]]) <= TOL
 
 
+@pytest.mark.parametrize("dt_obs", [4.0, 2.0])
+def test_every_variant_on_a_ragged_block_matches_single_vectors(gpu_lib, dt_obs):
+    """7 vectors: the multi-vector forms (2 or 4 vectors per wave) meet a partial last group;
+    every vector of the block must equal the same variant applied to that vector alone, bitwise,
+    and the oracle to 1e-5."""
+    import torch
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=33, rays=(400, 80, 60), n_r=8, n_phi=13, n_frames=72, dt_obs=dt_obs)
+    say("case ragged block", dt_obs, geo.grid.n_hat)
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(9)
+    nb = 7
+    X = to_dev(rng.random((nb, geo.grid.n_cols)))
+    Yt = to_dev(rng.standard_normal((nb, geo.n_rows)))
+    yr = oracle.forward(geo, X.double().cpu().numpy())
+    xr = oracle.adjoint(geo, Yt.double().cpu().numpy())
+    for v, vname in enumerate(rtt.variant_names(False)):
+        if vname == "lean4q" and geo.grid.n_hat % 4:
+            continue
+        if vname in ("batch", "stream") and dt_obs > geo.grid.dt_src:
+            continue
+        G.set_variant(apply=v)
+        Y = rtt.op_apply(G, X)
+        for b in range(nb):
+            assert torch.equal(Y[b], rtt.op_apply(G, X[b].contiguous())), (vname, b)
+            assert max(block_rel(geo, Y[b].cpu().numpy(), yr[b])) <= TOL, (vname, b)
+    for v, vname in enumerate(rtt.variant_names(True)):
+        G.set_variant(adjoint=v)
+        XT = rtt.op_apply_adjoint(G, Yt)
+        for b in range(nb):
+            assert torch.equal(XT[b], rtt.op_apply_adjoint(G, Yt[b].contiguous())), (vname, b)
+            assert rel(XT[b].cpu().numpy(), xr[b]) <= TOL, (vname, b)
+
+
 def test_drop_invalid_rays_write_zero_rows(gpu_lib):
     rtt = gpu_lib
     geo = tiny_geometry(seed=32, rays=(20, 5))
