@@ -1548,33 +1548,63 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             while (col < vcol[j]) emit();
             if constexpr (DPP) {
                 // earlier taps of lane i are later taps of lanes i - 1 (and i - 2): wave shifts right by
-                // one lane; lane 0 takes the previous slot's last lane, or in the first slot its own
-                // extra loads (halo lanes: anything, their sums are not stored)
-                auto shr1 = [](int old, float src) {
+                // one lane.  Lane 0 of a slot takes the previous slot's last lane through a rotation of
+                // that slot (the shift's fill value); in the first slot it takes its own extra loads,
+                // or, with halo lanes, the rotation itself (halo sums are not stored).
+                auto shr1 = [](float old, float src) {
                     return __builtin_bit_cast(
-                        float, __builtin_amdgcn_update_dpp(old, __builtin_bit_cast(int, src), 0x138 /* wave_shr:1 */,
-                                                           0xf, 0xf, false));
+                        float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, src),
+                                                           0x138 /* wave_shr:1 */, 0xf, 0xf, false));
                 };
-                auto last = [](float v) { return __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63); };
+                auto ror1 = [](float src) {
+                    return __builtin_bit_cast(
+                        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, src), 0x13C /* wave_ror:1 */, 0xf, 0xf, false));
+                };
 #pragma unroll
-                for (int u = 0; u < NVW; ++u)
+                for (int u = 0; u < NVW; ++u) {
+                    if constexpr (Q == 1) {
+                        float o = 0.f;   // fill of the next slot: this slot rotated by one lane
 #pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        if constexpr (Q == 1) {
-                            const int o0 = v > 0 ? last(yv[j][u][v - 1][1])
-                                                 : __builtin_bit_cast(int, yv[j][u][0][HALO ? 1 : 0]);
-                            yv[j][u][v][0] = shr1(o0, yv[j][u][v][1]);
-                        } else {
-                            const int o2 = v > 0 ? last(yv[j][u][v - 1][4]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 4 : 2]);
-                            const int o3 = v > 0 ? last(yv[j][u][v - 1][5]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 5 : 3]);
-                            const int o0 = v > 0 ? last(yv[j][u][v - 1][2]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 4 : 0]);
-                            const int o1 = v > 0 ? last(yv[j][u][v - 1][3]) : __builtin_bit_cast(int, yv[j][u][0][HALO ? 5 : 1]);
-                            yv[j][u][v][2] = shr1(o2, yv[j][u][v][4]);
-                            yv[j][u][v][3] = shr1(o3, yv[j][u][v][5]);
-                            yv[j][u][v][0] = shr1(o0, yv[j][u][v][2]);
-                            yv[j][u][v][1] = shr1(o1, yv[j][u][v][3]);
+                        for (int v = 0; v < V; ++v) {
+                            float* t = yv[j][u][v];
+                            if (v == 0 && HALO) {
+                                t[0] = ror1(t[1]);
+                                o = t[0];
+                            } else {
+                                t[0] = shr1(v == 0 ? t[0] : o, t[1]);
+                                if (v + 1 < V) o = ror1(t[1]);
+                            }
+                        }
+                    } else {
+                        float o4 = 0.f, o5 = 0.f, o2 = 0.f, o3 = 0.f;
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            float* t = yv[j][u][v];
+                            if (v == 0 && HALO) {
+                                t[2] = ror1(t[4]);
+                                t[3] = ror1(t[5]);
+                                t[0] = ror1(t[2]);
+                                t[1] = ror1(t[3]);
+                                o4 = t[2];
+                                o5 = t[3];
+                                o2 = t[0];
+                                o3 = t[1];
+                            } else {
+                                // slot 0 without halo lanes: fill values are lane 0's own extra loads
+                                t[2] = shr1(v == 0 ? t[2] : o4, t[4]);
+                                t[3] = shr1(v == 0 ? t[3] : o5, t[5]);
+                                t[0] = shr1(v == 0 ? t[0] : o2, t[2]);
+                                t[1] = shr1(v == 0 ? t[1] : o3, t[3]);
+                                if (v + 1 < V) {
+                                    o4 = ror1(t[4]);
+                                    o5 = ror1(t[5]);
+                                    o2 = ror1(t[2]);
+                                    o3 = ror1(t[3]);
+                                }
+                            }
                         }
                     }
+                }
             }
 #pragma unroll
             for (int u = 0; u < NVW; ++u)
