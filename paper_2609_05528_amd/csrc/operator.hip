@@ -686,8 +686,9 @@ __device__ __forceinline__ FwdRec load_const_rec(const FwdRec* p)
 
 // Output phase shared by the staged forward kernels: the wave's NB combined series z (LDS rows
 // of ZS floats starting at zs0, hat h of ray j at zs0[j*ZS + h]) are interpolated to the frames
-// [f0, fend) of each ray and written to its data row (four frames per lane, 16-byte stores
-// when VEC4).
+// [f0, fend) of each ray and written to its data row.  With aligned rows (VEC4): Q = 1 takes one
+// ray per pass with two frames per lane (8-byte stores), Q = 2 four frames per lane (16-byte
+// stores); otherwise one frame per lane.
 template <int Q, int NB, bool VEC4>
 __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, const int* row, const bool* on,
                                           int f0, int fend, int F, float* __restrict__ y)
@@ -698,7 +699,23 @@ __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, co
     constexpr int ZS = ZI * WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
     const float(*zs)[ZS] = (const float(*)[ZS])zs0;
-    if (VEC4) {
+    if (VEC4 && Q == 1) {
+        // one ray per pass, two frames per lane (8-byte stores): ray values stay uniform
+        typedef float f2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (!on[j]) continue;
+            const float* zr = &zs[0][0] + j * ZS;
+            const f2 za = *(const f2*)(zr + 2 * lane);
+            const float zc = zr[2 * lane + 2];
+            const float th = th0[j];
+            f2 v;
+            v[0] = za[0] + th * (za[1] - za[0]);
+            v[1] = za[1] + th * (zc - za[1]);
+            const int f = f0 + 2 * lane;
+            if (f < fend) __builtin_nontemporal_store(v, (f2*)(y + (int64_t)row[j] * F + f));
+        }
+    } else if (VEC4) {
         constexpr int NG = FC / 4;               // frame groups per ray chunk: 32 (Q=1) or 64 (Q=2)
         constexpr int RPP = WAVE / NG;           // rays per pass: 2 or 1
 #pragma unroll
