@@ -664,6 +664,7 @@ struct LeanArgs {
     int64_t x_stride, y_stride;
     int x_bytes;        // bytes of one coefficient vector
     uint32_t mask;
+    int fc;             // frames per chunk (multiple of 4, at most lean_fcmax(Q))
 };
 
 // A forward record read through the constant address space (the tables never change while a
@@ -689,69 +690,68 @@ __device__ __forceinline__ FwdRec load_const_rec(const FwdRec* p)
 // [f0, fend) of each ray and written to its data row.  With aligned rows (VEC4): Q = 1 takes one
 // ray per pass with two frames per lane (8-byte stores), Q = 2 four frames per lane (16-byte
 // stores); otherwise one frame per lane.
+// Hats staged per ray chunk (LDS row length) and the longest frame chunk they serve: a chunk
+// of fc frames starting at hat klo reads hats klo .. klo + fc/Q + 1.
+constexpr int LEAN_ZI = 3;
+constexpr int LEAN_ZS = LEAN_ZI * WAVE;
+constexpr int lean_fcmax(int Q) { return Q * (LEAN_ZS - 4); }
+
 template <int Q, int NB, bool VEC4>
 __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, const int* row, const bool* on,
                                           int f0, int fend, int F, float* __restrict__ y)
 {
-    constexpr int FC = 128 * Q;
-    constexpr int W = FC / Q + 4;
-    constexpr int ZI = (W + WAVE - 1) / WAVE;
-    constexpr int ZS = ZI * WAVE;
+    constexpr int ZS = LEAN_ZS;
     const int lane = threadIdx.x & (WAVE - 1);
     const float(*zs)[ZS] = (const float(*)[ZS])zs0;
+    const int nf = fend - f0;   // frames of this chunk (at most lean_fcmax(Q))
     if (VEC4 && Q == 1) {
-        // one ray per pass, two frames per lane (8-byte stores): ray values stay uniform
+        // one ray per pass of 128 frames, two frames per lane (8-byte stores): ray values stay uniform
         typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (!on[j]) continue;
-            const float* zr = &zs[0][0] + j * ZS;
-            const f2 za = *(const f2*)(zr + 2 * lane);
-            const float zc = zr[2 * lane + 2];
             const float th = th0[j];
-            f2 v;
-            v[0] = za[0] + th * (za[1] - za[0]);
-            v[1] = za[1] + th * (zc - za[1]);
-            const int f = f0 + 2 * lane;
-            if (f < fend) __builtin_nontemporal_store(v, (f2*)(y + (int64_t)row[j] * F + f));
+            float* yr = y + (int64_t)row[j] * F;
+#pragma unroll
+            for (int p = 0; p < (lean_fcmax(1) + 127) / 128; ++p) {
+                if (p * 128 >= nf) break;
+                const int q = p * 128 + 2 * lane;
+                const float* zr = &zs[0][0] + j * ZS + q;
+                const f2 za = *(const f2*)zr;
+                const float zc = zr[2];
+                f2 v;
+                v[0] = za[0] + th * (za[1] - za[0]);
+                v[1] = za[1] + th * (zc - za[1]);
+                if (q < nf) __builtin_nontemporal_store(v, (f2*)(yr + f0 + q));
+            }
         }
     } else if (VEC4) {
-        constexpr int NG = FC / 4;               // frame groups per ray chunk: 32 (Q=1) or 64 (Q=2)
-        constexpr int RPP = WAVE / NG;           // rays per pass: 2 or 1
+        // Q = 2: one ray per pass of 256 frames, four frames per lane (16-byte stores)
+        typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int p = 0; p < NB / RPP; ++p) {
-            const int sub = (RPP == 2) ? (lane >> 5) : 0;
-            const int g = lane & (NG - 1);
-            const int jA = p * RPP, jB = p * RPP + RPP - 1;
-            const bool pickB = sub != 0;
-            const float th = pickB ? th0[jB] : th0[jA];
-            const int rw = pickB ? row[jB] : row[jA];
-            const bool active = pickB ? on[jB] : on[jA];
-            const int f = f0 + 4 * g;
-            const float* zr = &zs[0][0] + (pickB ? jB : jA) * ZS;
-            f4 v;
-            if (Q == 1) {
-                const f4 z4 = *(const f4*)(zr + 4 * g);
-                const float z5 = zr[4 * g + 4];
-                v[0] = z4[0] + th * (z4[1] - z4[0]);
-                v[1] = z4[1] + th * (z4[2] - z4[1]);
-                v[2] = z4[2] + th * (z4[3] - z4[2]);
-                v[3] = z4[3] + th * (z5 - z4[3]);
-            } else {
-                typedef float f2 __attribute__((ext_vector_type(2)));
-                const f2 za = *(const f2*)(zr + 2 * g);
-                const f2 zb = *(const f2*)(zr + 2 * g + 2);
+        for (int j = 0; j < NB; ++j) {
+            if (!on[j]) continue;
+            const float th = th0[j];
+            const bool c1 = th >= 0.5f;
+            const float th1 = c1 ? th - 0.5f : th + 0.5f;
+            float* yr = y + (int64_t)row[j] * F;
+#pragma unroll
+            for (int p = 0; p < (lean_fcmax(2) + 255) / 256; ++p) {
+                if (p * 256 >= nf) break;
+                const int g = p * 64 + lane;
+                const float* zr = &zs[0][0] + j * ZS + 2 * g;
+                const f2 za = *(const f2*)zr;
+                const f2 zb = *(const f2*)(zr + 2);
                 const float z0 = za[0], z1 = za[1], z2 = zb[0], z3 = zb[1];
-                const bool c1 = th >= 0.5f;
-                const float th1 = c1 ? th - 0.5f : th + 0.5f;
                 const float a1 = c1 ? z1 : z0, b1 = c1 ? z2 : z1;
                 const float a3 = c1 ? z2 : z1, b3 = c1 ? z3 : z2;
+                f4 v;
                 v[0] = z0 + th * (z1 - z0);
                 v[1] = a1 + th1 * (b1 - a1);
                 v[2] = z1 + th * (z2 - z1);
                 v[3] = a3 + th1 * (b3 - a3);
+                if (4 * g < nf) __builtin_nontemporal_store(v, (f4*)(yr + f0 + 4 * g));
             }
-            if (active && f < fend) __builtin_nontemporal_store(v, (f4*)(y + (int64_t)rw * F + f));
         }
     } else {
 #pragma unroll
@@ -759,10 +759,10 @@ __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, co
             if (!on[j]) continue;
             float* yr = y + (int64_t)row[j] * F;
 #pragma unroll
-            for (int t = 0; t < FC / WAVE; ++t) {
+            for (int t = 0; t < (lean_fcmax(Q) + WAVE - 1) / WAVE; ++t) {
+                if (t * WAVE >= nf) break;
                 const int q = lane + t * WAVE;
-                const int f = f0 + q;
-                if (f >= fend) continue;
+                if (q >= nf) continue;
                 int jz;
                 float th;
                 if (Q == 1) {
@@ -775,7 +775,7 @@ __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, co
                     th = odd ? (c1 ? th0[j] - 0.5f : th0[j] + 0.5f) : th0[j];
                 }
                 const float za = zs[j][jz], zb = zs[j][jz + 1];
-                __builtin_nontemporal_store(za + th * (zb - za), yr + f);
+                __builtin_nontemporal_store(za + th * (zb - za), yr + f0 + q);
             }
         }
     }
@@ -787,17 +787,15 @@ template <int Q, int NB, bool VEC4>
 __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __restrict__ x, float* __restrict__ y,
                                           int64_t blk, int chunk)
 {
-    constexpr int FC = 128 * Q;          // frames per chunk
-    constexpr int W = FC / Q + 4;        // hats staged per ray
-    constexpr int ZI = (W + WAVE - 1) / WAVE;
-    constexpr int ZS = ZI * WAVE;        // LDS row length (multiple of 4)
+    constexpr int ZI = LEAN_ZI;
+    constexpr int ZS = LEAN_ZS;          // LDS row length: hats staged per ray
     __shared__ __attribute__((aligned(16))) float zs_all[A_WAVES][NB][ZS];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t r0 = (blk * A_WAVES + wave) * NB;
     if (r0 >= a.n_rays) return;
-    const int f0 = chunk * FC;
-    const int fend = min(a.F, f0 + FC);
+    const int f0 = chunk * a.fc;
+    const int fend = min(a.F, f0 + a.fc);
     float(*zs)[ZS] = zs_all[wave];
     // the previous task of a persistent block may still be reading this wave's LDS rows
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -865,11 +863,10 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
             // lanes of hats outside [0, K) loaded zeros; rays that are off are not written
-            const int h = lane + it * WAVE;
             const float z = live[j][it] ? rc[j].b00 * xv[j][it][0] + rc[j].b10 * xv[j][it][1] +
                                               rc[j].b01 * xv[j][it][2] + rc[j].b11 * xv[j][it][3]
                                         : 0.f;
-            if (h < W) zs[j][h] = z;
+            zs[j][lane + it * WAVE] = z;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -987,6 +984,7 @@ struct LeanMember {
     uint32_t nrb;        // ray blocks per frame chunk
     int K, F, nk, x_bytes;
     uint32_t mask;
+    int fc;              // frames per chunk
 };
 struct LeanMulti {
     LeanMember m[MULTI_MAX];
@@ -1016,6 +1014,7 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean_multi(LeanMulti a
         la.nk = mm.nk;
         la.x_bytes = mm.x_bytes;
         la.mask = mm.mask;
+        la.fc = mm.fc;
         const uint32_t chunk = b / mm.nrb;
         lean_body<Q, NB, VEC4>(la, a.x + (int64_t)v * a.x_stride + mm.x_off, a.y + (int64_t)v * a.y_stride + mm.y_off,
                                (int64_t)(b - chunk * mm.nrb), (int)chunk);
@@ -2274,11 +2273,21 @@ static void apply_dispatch(const ApplyArgs& a, int nvec, int variant, hipStream_
         hipLaunchKernelGGL((k_apply<TP, TQ, 1>), grid, dim3(A_WAVES * WAVE), 0, s, a);
 }
 
+// Frame chunks of the lean forward: the fewest chunks of at most lean_fcmax(Q) frames, of equal
+// length rounded up to a multiple of 4 (chunk starts stay 16-byte aligned within a row).
+static void lean_chunks(int F, int Q, int* nch, int* fc)
+{
+    const int mx = Q == 1 ? lean_fcmax(1) : lean_fcmax(2);
+    *nch = std::max(1, (F + mx - 1) / mx);
+    *fc = ((F + *nch - 1) / *nch + 3) / 4 * 4;
+}
+
 template <int Q, int NB, bool QUAD = false>
-static void lean_launch(const LeanArgs& a, int nvec, bool vec4, hipStream_t s)
+static void lean_launch(LeanArgs a, int nvec, bool vec4, hipStream_t s)
 {
     const int64_t rays_per_block = (int64_t)A_WAVES * NB;
-    const int nch = (a.F + 128 * Q - 1) / (128 * Q);
+    int nch = (a.F + 128 * Q - 1) / (128 * Q);   // the quad-gather form keeps chunks of 128 Q frames
+    if (!QUAD) lean_chunks(a.F, Q, &nch, &a.fc);
     dim3 grid((unsigned)((a.n_rays + rays_per_block - 1) / rays_per_block), (unsigned)nvec, (unsigned)nch);
     if (QUAD) {
         if (vec4) hipLaunchKernelGGL((k_apply_leanq<Q, NB, true>), grid, dim3(A_WAVES * WAVE), 0, s, a);
@@ -2386,8 +2395,10 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         la.y_stride = y_stride;
         la.x_bytes = (int)(m.n_cols * 4);
         la.mask = mask;
-        // float4 rows need F % 4 == 0 and 16-byte aligned vectors
-        const bool vec4 = (la.F % 4) == 0 && (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (y_stride % 4) == 0);
+        la.fc = 128 * m.Q;
+        // wide output stores: 8-byte aligned rows at Q = 1 (F even), 16-byte at Q = 2 (F % 4 == 0)
+        const int wa = m.Q == 1 ? 2 : 4;
+        const bool vec4 = (la.F % wa) == 0 && (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (y_stride % wa) == 0);
         if (m.Q == 1) {
             if (variant == 10) lean_launch<1, 4, true>(la, nvec, vec4, s);
             else if (variant == 4) lean_launch<1, 4>(la, nvec, vec4, s);
@@ -2651,13 +2662,15 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
 {
     const Member& m0 = g->members[b];
     if (m0.apply_variant == 6 || m0.apply_variant == 7) return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, rc);
-    bool vec4 = (((uintptr_t)y) & 15) == 0 && (nvec == 1 || (g->n_rows % 4) == 0);
+    // wide output stores: 8-byte aligned rows at Q = 1, 16-byte at Q = 2
+    const int wa = m0.Q == 1 ? 2 : 4;
+    bool vec4 = (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (g->n_rows % wa) == 0);
     bool all8 = true;
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
         if (!lean_supported(m) || m.Q != m0.Q || (m.apply_variant != 4 && m.apply_variant != 5)) return false;
         all8 = all8 && m.apply_variant == 5;
-        vec4 = vec4 && (m.grid.n_frames % 4) == 0 && (m.row_offset % 4) == 0;
+        vec4 = vec4 && (m.grid.n_frames % wa) == 0 && (m.row_offset % wa) == 0;
     }
     const int NB = all8 ? 8 : 4;
     LeanMulti a;
@@ -2677,7 +2690,8 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
         d.x_bytes = (int)(m.n_cols * 4);
         d.nrb = (uint32_t)((m.n_rays + (int64_t)A_WAVES * NB - 1) / ((int64_t)A_WAVES * NB));
         d.mask = effective_mask(m, mask);
-        const int nch = (m.grid.n_frames + 128 * m.Q - 1) / (128 * m.Q);
+        int nch = 1;
+        lean_chunks(m.grid.n_frames, m.Q, &nch, &d.fc);
         nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
     }
     if (nb * nvec >= (1ll << 31)) return false;
