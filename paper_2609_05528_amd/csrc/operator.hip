@@ -781,6 +781,15 @@ __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, co
     }
 }
 
+// The staged forward's LDS rows, one array per batch size shared by every form of the body a
+// kernel inlines (so a kernel that branches between output forms allocates it once).
+template <int NB>
+__device__ __forceinline__ float (*lean_lds())[NB][LEAN_ZS]
+{
+    __shared__ __attribute__((aligned(16))) float zs_all[A_WAVES][NB][LEAN_ZS];
+    return zs_all;
+}
+
 // One block of the lean forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, frame chunk
 // `chunk`, one vector (x, y already offset to the member's blocks).
 template <int Q, int NB, bool VEC4>
@@ -789,7 +798,7 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
 {
     constexpr int ZI = LEAN_ZI;
     constexpr int ZS = LEAN_ZS;          // LDS row length: hats staged per ray
-    __shared__ __attribute__((aligned(16))) float zs_all[A_WAVES][NB][ZS];
+    float(*zs_all)[NB][ZS] = lean_lds<NB>();
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t r0 = (blk * A_WAVES + wave) * NB;
@@ -985,6 +994,7 @@ struct LeanMember {
     int K, F, nk, x_bytes;
     uint32_t mask;
     int fc;              // frames per chunk
+    int wide;            // rows aligned for the wide output stores
 };
 struct LeanMulti {
     LeanMember m[MULTI_MAX];
@@ -1016,8 +1026,12 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean_multi(LeanMulti a
         la.mask = mm.mask;
         la.fc = mm.fc;
         const uint32_t chunk = b / mm.nrb;
-        lean_body<Q, NB, VEC4>(la, a.x + (int64_t)v * a.x_stride + mm.x_off, a.y + (int64_t)v * a.y_stride + mm.y_off,
-                               (int64_t)(b - chunk * mm.nrb), (int)chunk);
+        const float* xv = a.x + (int64_t)v * a.x_stride + mm.x_off;
+        float* yv = a.y + (int64_t)v * a.y_stride + mm.y_off;
+        if (VEC4 && mm.wide)
+            lean_body<Q, NB, true>(la, xv, yv, (int64_t)(b - chunk * mm.nrb), (int)chunk);
+        else
+            lean_body<Q, NB, false>(la, xv, yv, (int64_t)(b - chunk * mm.nrb), (int)chunk);
     }
 }
 
@@ -2662,15 +2676,14 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
 {
     const Member& m0 = g->members[b];
     if (m0.apply_variant == 6 || m0.apply_variant == 7) return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, rc);
-    // wide output stores: 8-byte aligned rows at Q = 1, 16-byte at Q = 2
+    // wide output stores (8-byte aligned rows at Q = 1, 16-byte at Q = 2), decided per member
     const int wa = m0.Q == 1 ? 2 : 4;
-    bool vec4 = (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (g->n_rows % wa) == 0);
+    const bool vec4 = (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (g->n_rows % wa) == 0);
     bool all8 = true;
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
         if (!lean_supported(m) || m.Q != m0.Q || (m.apply_variant != 4 && m.apply_variant != 5)) return false;
         all8 = all8 && m.apply_variant == 5;
-        vec4 = vec4 && (m.grid.n_frames % wa) == 0 && (m.row_offset % wa) == 0;
     }
     const int NB = all8 ? 8 : 4;
     LeanMulti a;
@@ -2692,6 +2705,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
         d.mask = effective_mask(m, mask);
         int nch = 1;
         lean_chunks(m.grid.n_frames, m.Q, &nch, &d.fc);
+        d.wide = (m.grid.n_frames % wa) == 0 && (m.row_offset % wa) == 0;
         nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
     }
     if (nb * nvec >= (1ll << 31)) return false;
