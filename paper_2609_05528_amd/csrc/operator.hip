@@ -1390,7 +1390,7 @@ struct Taps {
 // One block of the visit-list adjoint: task `lin` = (row group, segment, hat chunk) of one member
 // for NVW consecutive vectors (y0, x0: the first of them, already offset to the member's blocks;
 // nv of them exist).
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, bool RP = false>
 __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y0, float* __restrict__ x0,
                                            int nv, int64_t lin)
 {
@@ -1410,9 +1410,12 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     const int kch = (int)(lin % a.kchunks);
     const int64_t l2 = lin / a.kchunks;
     const int sg = (int)(l2 % a.nseg), rg = (int)(l2 / a.nseg);
-    const int ci = rg * T_WAVES + wave;
-    if (ci >= a.n_r) return;
-    const int64_t task = (int64_t)ci * a.nseg + sg;
+    // a row, or with RP a pair of rows (2p, 2p+1) whose visits carry weights for both
+    const int ti = rg * T_WAVES + wave;
+    if (ti >= (RP ? (a.n_r + 1) / 2 : a.n_r)) return;
+    const int ci = RP ? 2 * ti : ti;
+    const bool row2 = RP && ci + 1 < a.n_r;
+    const int64_t task = (int64_t)ti * a.nseg + sg;
     const int64_t vbeg = ((ci64p)a.vtask)[task], vend = ((ci64p)a.vtask)[task + 1];
     const int jlo = sg * a.vseg;
     const int jhi = min(jlo + a.vseg, a.n_phi);
@@ -1450,11 +1453,12 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
         st_off[v] = (k >= kc && k < a.K) ? (unsigned)k * 4u : VISIT_SENT;
     }
 
-    float acc_a[NVW][V], acc_b[NVW][V];
+    float acc_a[NVW][V], acc_b[NVW][V];     // row ci: columns u, u+1 of the sweep
+    float acc_c[NVW][V], acc_d[NVW][V];     // row ci+1 (RP)
 #pragma unroll
     for (int u = 0; u < NVW; ++u)
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc_a[u][v] = acc_b[u][v] = 0.f;
+        for (int v = 0; v < V; ++v) acc_a[u][v] = acc_b[u][v] = acc_c[u][v] = acc_d[u][v] = 0.f;
     int col = 0;
     auto emit = [&]() {
         if (col >= 1) {
@@ -1466,6 +1470,13 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
                 for (int v = 0; v < V; ++v)
                     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_a[u][v]), rx, (int)st_off[v],
                                                           sox[u] + xo, 0);
+                if (row2) {
+                    const int xo1 = xo + a.n_phi * a.K * 4;
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_c[u][v]), rx,
+                                                              (int)st_off[v], sox[u] + xo1, 0);
+                }
             }
         }
 #pragma unroll
@@ -1474,6 +1485,10 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             for (int v = 0; v < V; ++v) {
                 acc_a[u][v] = acc_b[u][v];
                 acc_b[u][v] = 0.f;
+                if (RP) {
+                    acc_c[u][v] = acc_d[u][v];
+                    acc_d[u][v] = 0.f;
+                }
             }
         ++col;
     };
@@ -1492,7 +1507,7 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             r0[j] = q[0];
             r1[j] = q[1];
         }
-        float yv[NB][NVW][V][T], tw[NB][T], wa[NB], wb[NB];
+        float yv[NB][NVW][V][T], tw[NB][T], wa[NB], wb[NB], wc[NB], wd[NB];
         int vcol[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
@@ -1500,7 +1515,19 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             // a vector element is copied to a plain int before its bits are reinterpreted
             // (bit_cast applied to the element expression itself reads element 0)
             const int row = r0[j].x, k0 = r0[j].y, th0_b = r0[j].z, wa_b = r0[j].w;
-            const int wb_b = r1[j].x, col_j = r1[j].y, order = r1[j].z;
+            const int wb_b = r1[j].x;
+            int col_j, order;
+            if constexpr (RP) {
+                // row pair record: (wb0, wa1, wb1, col | order << 16) in the second word
+                const int wc_b = r1[j].y, wd_b = r1[j].z, co = r1[j].w;
+                wc[j] = __builtin_bit_cast(float, wc_b);
+                wd[j] = __builtin_bit_cast(float, wd_b);
+                col_j = co & 0xFFFF;
+                order = co >> 16;
+            } else {
+                col_j = r1[j].y;
+                order = r1[j].z;
+            }
             wa[j] = __builtin_bit_cast(float, wa_b);
             wb[j] = __builtin_bit_cast(float, wb_b);
             vcol[j] = valid ? col_j : ncol;
@@ -1645,20 +1672,24 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
                     for (int t = 0; t < T; ++t) h += tw[j][t] * yv[j][u][v][t];
                     acc_a[u][v] += wa[j] * h;
                     acc_b[u][v] += wb[j] * h;
+                    if (RP) {
+                        acc_c[u][v] += wc[j] * h;
+                        acc_d[u][v] += wd[j] * h;
+                    }
                 }
         }
     }
     while (col < ncol) emit();
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, bool RP>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
-    const int rgroups = (a.n_r + T_WAVES - 1) / T_WAVES;
+    const int rgroups = ((RP ? (a.n_r + 1) / 2 : a.n_r) + T_WAVES - 1) / T_WAVES;
     const int v0 = blockIdx.y * NVW;
-    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
-                                               min(NVW, a.nvec - v0),
-                                               xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
+    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO, RP>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
+                                                   min(NVW, a.nvec - v0),
+                                                   xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
 }
 
 // Every member of a handle (up to MULTI_MAX) in one launch; tasks numbered as in
@@ -2152,7 +2183,8 @@ static const AdjVariant kAdjVariants[] = {
     {"sweep32v2", 1, 32, 2}, {"sweep16v1", 1, 16, 1}, {"sweep16v2", 1, 16, 2}, {"tb8x8", 2, 8, 8},
     {"tb4x8", 2, 4, 8},      {"tb4x4", 2, 4, 4},      {"tb2x4", 2, 2, 4},      {"visit", 3, 0, 0},
     {"rows4", 4, 4, 0},      {"rows8", 4, 8, 0},      {"visit2v", 3, 2, 0},    {"visit4v", 3, 4, 0},
-    {"visitd", 3, 1, 1},     {"visitd2v", 3, 2, 1},   {"visitd4v", 3, 4, 1},
+    {"visitd", 3, 1, 1},     {"visitd2v", 3, 2, 1},   {"visitd4v", 3, 4, 1},   {"visitp2v", 3, 2, 2},
+    {"visitp4v", 3, 4, 2},
 };
 constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
@@ -2507,20 +2539,21 @@ static bool visit_halo_fits(int K)
     return (K + C - 1) / C == (K + WAVE * V - 1) / (WAVE * V);
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false, bool RP = false>
 static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
     if constexpr (DPP && !HALO) {
         if (visit_halo_fits<Q, V>(a.K)) {
-            visit_launch<Q, V, NB, PAIR, NVW, true, true>(a, nvec, s);
+            visit_launch<Q, V, NB, PAIR, NVW, true, true, RP>(a, nvec, s);
             return;
         }
     }
     constexpr int C = visit_chunk<Q, V, DPP, HALO>();
     a.kchunks = (a.K + C - 1) / C;
     a.nvec = nvec;
-    const int64_t blocks = (int64_t)((a.n_r + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO>),
+    const int rows = RP ? (a.n_r + 1) / 2 : a.n_r;
+    const int64_t blocks = (int64_t)((rows + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO, RP>),
                        dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)), dim3(T_WAVES * WAVE), 0, s, a);
 }
 
@@ -2546,6 +2579,22 @@ static void visitd_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s
     else if (a.K <= 128) visit_launch<Q, 2, 8, P, 1, true>(a, nvec, s);
     else if (a.K <= 256) visit_launch<Q, 4, 4, P, 1, true>(a, nvec, s);
     else visit_launch<Q, 8, 2, P, 1, true>(a, nvec, s);
+}
+
+// lane-shifted taps over row pairs (visit set 2); vpw vectors per wave (2 or 4)
+template <int Q>
+static void visitp_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s)
+{
+    constexpr bool P = Q == 2;
+    if (vpw == 4) {
+        if (a.K <= 64) visit_launch<Q, 1, 2, P, 4, true, false, true>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, 2, P, 4, true, false, true>(a, nvec, s);
+        else visit_launch<Q, 4, 1, P, 4, true, false, true>(a, nvec, s);
+        return;
+    }
+    if (a.K <= 64) visit_launch<Q, 1, 4, P, 2, true, false, true>(a, nvec, s);
+    else if (a.K <= 128) visit_launch<Q, 2, 4, P, 2, true, false, true>(a, nvec, s);
+    else visit_launch<Q, 4, 2, P, 2, true, false, true>(a, nvec, s);
 }
 
 // vpw: vectors per wave (1, 2 or 4).  Loads in flight per lane stay near NB * V * T / 8.
@@ -2921,11 +2970,17 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         return RTT_OK;
     }
     if ((variant == 11 || variant >= 14) && !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 1)) variant = 2;
+    // row pairs: two vectors per wave at least, and frame pairs at Q = 2; else the single-row form
+    if (variant == 19 || variant == 20) {
+        const bool fpair = m.Q == 1 || ((m.grid.n_frames % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0));
+        if (!fpair || !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 2)) variant = variant == 19 ? 17 : 18;
+    }
     if (variant == 11 || variant >= 14) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
-        int vpw = (variant == 14 || variant == 17) ? 2 : (variant == 15 || variant == 18) ? 4 : 1;
-        if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = 1;
-        const int set = ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
+        const bool rp = variant == 19 || variant == 20;   // row pairs (2 or 4 vectors per wave)
+        int vpw = (variant == 14 || variant == 17 || variant == 19) ? 2 : (variant == 15 || variant == 18 || variant == 20) ? 4 : 1;
+        if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = rp ? 2 : 1;
+        const int set = rp ? 2 : ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
         VisitArgs va;
         va.visits = g->d_visits + m.visit_begin[set];
         va.vtask = g->d_vtask + m.vtask_begin[set];
@@ -2944,7 +2999,9 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         va.x_bytes = (uint32_t)(m.n_cols * 4);
         // frame pairs need 8-byte aligned rows: even n_frames and aligned data vectors
         const bool pair = (va.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
-        if (variant >= 16 && m.Q == 1) visitd_dispatch<1>(va, nvec, vpw, s);
+        if (rp && m.Q == 1) visitp_dispatch<1>(va, nvec, vpw, s);
+        else if (rp) visitp_dispatch<2>(va, nvec, vpw, s);
+        else if (variant >= 16 && m.Q == 1) visitd_dispatch<1>(va, nvec, vpw, s);
         else if (variant >= 16 && pair) visitd_dispatch<2>(va, nvec, vpw, s);
         else if (m.Q == 1) visit_dispatch<1, false>(va, nvec, vpw, s);
         else if (pair) visit_dispatch<2, true>(va, nvec, vpw, s);

@@ -252,6 +252,53 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
             }
             vtask.push_back((int64_t)visits.size() - m.visit_begin[set]);
         }
+        // set 2: the same sweep for a pair of rows (2p, 2p+1): rays with base row 2p-1 feed row
+        // 2p (weight fr), base row 2p feeds both (1 - fr and fr), base row 2p+1 feeds row 2p+1
+        // (1 - fr); within a column the order is by base row, so each row sums its rays in the
+        // order of the single-row lists
+        {
+            const int vseg = VISIT_SEG_MAX;
+            const int nseg = (g.n_phi + vseg - 1) / vseg;
+            const int npair = (g.n_r + 1) / 2;
+            m.nseg[2] = nseg;
+            m.vseg[2] = vseg;
+            m.visit_begin[2] = (int64_t)visits.size();
+            m.vtask_begin[2] = (int64_t)vtask.size();
+            for (int pi = 0; pi < npair; ++pi) {
+                for (int sg = 0; sg < nseg; ++sg) {
+                    vtask.push_back((int64_t)visits.size() - m.visit_begin[2]);
+                    const int jlo = sg * vseg, jhi = std::min(jlo + vseg, g.n_phi);
+                    for (int c = 0; c <= jhi - jlo; ++c) {
+                        const int u = jlo - 1 + c;
+                        const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
+                        for (int part = 0; part < 3; ++part) {
+                            const int ib = 2 * pi - 1 + part;
+                            if (ib < 0 || ib > g.n_r - 2) continue;
+                            const int64_t cell = (int64_t)ib * g.n_phi + ub;
+                            for (int32_t q = cs[cell]; q < cs[cell + 1]; ++q) {
+                                const RayRec& rr = gr[q];
+                                // radial weights into rows 2p and 2p+1
+                                const double w0 = part == 0 ? (double)rr.fr : part == 1 ? 1.0 - (double)rr.fr : 0.0;
+                                const double w1 = part == 1 ? (double)rr.fr : part == 2 ? 1.0 - (double)rr.fr : 0.0;
+                                VisitPair v;
+                                v.row = rr.row;
+                                v.k0 = rr.k0;
+                                v.th0 = rr.th0;
+                                v.wa0 = (float)((double)rr.w * w0 * (1.0 - (double)rr.fphi));
+                                v.wb0 = (float)((double)rr.w * w0 * (double)rr.fphi);
+                                v.wa1 = (float)((double)rr.w * w1 * (1.0 - (double)rr.fphi));
+                                v.wb1 = (float)((double)rr.w * w1 * (double)rr.fphi);
+                                v.col_order = c | (rr.order << 16);
+                                Visit raw;
+                                std::memcpy(&raw, &v, sizeof raw);
+                                visits.push_back(raw);
+                            }
+                        }
+                    }
+                }
+            }
+            vtask.push_back((int64_t)visits.size() - m.visit_begin[2]);
+        }
         for (const RayRec& rr : gr) {
             const int i = rr.cell / g.n_phi, j0 = rr.cell % g.n_phi;
             const int j1 = (j0 + 1 == g.n_phi) ? 0 : j0 + 1;
