@@ -1390,7 +1390,7 @@ struct Taps {
 // One block of the visit-list adjoint: task `lin` = (row group, segment, hat chunk) of one member
 // for NVW consecutive vectors (y0, x0: the first of them, already offset to the member's blocks;
 // nv of them exist).
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, bool RP = false>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, int RR = 1>
 __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y0, float* __restrict__ x0,
                                            int nv, int64_t lin)
 {
@@ -1410,11 +1410,11 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     const int kch = (int)(lin % a.kchunks);
     const int64_t l2 = lin / a.kchunks;
     const int sg = (int)(l2 % a.nseg), rg = (int)(l2 / a.nseg);
-    // a row, or with RP a pair of rows (2p, 2p+1) whose visits carry weights for both
+    // RR consecutive rows ci .. ci + RR - 1 whose visits carry weights for each of them
+    static_assert(RR == 1 || RR == 2, "rows per wave: 1 or 2");
     const int ti = rg * T_WAVES + wave;
-    if (ti >= (RP ? (a.n_r + 1) / 2 : a.n_r)) return;
-    const int ci = RP ? 2 * ti : ti;
-    const bool row2 = RP && ci + 1 < a.n_r;
+    if (ti >= (a.n_r + RR - 1) / RR) return;
+    const int ci = RR * ti;
     const int64_t task = (int64_t)ti * a.nseg + sg;
     const int64_t vbeg = ((ci64p)a.vtask)[task], vend = ((ci64p)a.vtask)[task + 1];
     const int jlo = sg * a.vseg;
@@ -1453,12 +1453,13 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
         st_off[v] = (k >= kc && k < a.K) ? (unsigned)k * 4u : VISIT_SENT;
     }
 
-    float acc_a[NVW][V], acc_b[NVW][V];     // row ci: columns u, u+1 of the sweep
-    float acc_c[NVW][V], acc_d[NVW][V];     // row ci+1 (RP)
+    float acc_a[RR][NVW][V], acc_b[RR][NVW][V];   // row ci + r: columns u, u+1 of the sweep
 #pragma unroll
-    for (int u = 0; u < NVW; ++u)
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc_a[u][v] = acc_b[u][v] = acc_c[u][v] = acc_d[u][v] = 0.f;
+        for (int u = 0; u < NVW; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc_a[r][u][v] = acc_b[r][u][v] = 0.f;
     int col = 0;
     auto emit = [&]() {
         if (col >= 1) {
@@ -1467,29 +1468,25 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             for (int u = 0; u < NVW; ++u) {
                 if (u >= nv) break;
 #pragma unroll
-                for (int v = 0; v < V; ++v)
-                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_a[u][v]), rx, (int)st_off[v],
-                                                          sox[u] + xo, 0);
-                if (row2) {
-                    const int xo1 = xo + a.n_phi * a.K * 4;
+                for (int r = 0; r < RR; ++r) {
+                    if (r > 0 && ci + r >= a.n_r) break;
+                    const int xr = xo + r * a.n_phi * a.K * 4;
 #pragma unroll
                     for (int v = 0; v < V; ++v)
-                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_c[u][v]), rx,
-                                                              (int)st_off[v], sox[u] + xo1, 0);
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_a[r][u][v]), rx,
+                                                              (int)st_off[v], sox[u] + xr, 0);
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < NVW; ++u)
+        for (int r = 0; r < RR; ++r)
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                acc_a[u][v] = acc_b[u][v];
-                acc_b[u][v] = 0.f;
-                if (RP) {
-                    acc_c[u][v] = acc_d[u][v];
-                    acc_d[u][v] = 0.f;
+            for (int u = 0; u < NVW; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    acc_a[r][u][v] = acc_b[r][u][v];
+                    acc_b[r][u][v] = 0.f;
                 }
-            }
         ++col;
     };
     // byte offset of a frame of the row, or the sentinel when the frame or hat is out of range
@@ -1500,6 +1497,8 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     for (int64_t e0 = vbeg; e0 < vend; e0 += NB) {
         // the batch's visit records, scalar loads (the last batch re-reads its last record for
         // the missing ones, which are then switched off)
+        // RR = 1: (row, k0, th0, wa | wb, col, order, -); RR = 2: (row, k0, th0,
+        // col | order << 16 | wa0, wb0, wa1, wb1)
         i4v r0[NB], r1[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
@@ -1507,29 +1506,31 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
             r0[j] = q[0];
             r1[j] = q[1];
         }
-        float yv[NB][NVW][V][T], tw[NB][T], wa[NB], wb[NB], wc[NB], wd[NB];
+        float yv[NB][NVW][V][T], tw[NB][T], wa[NB][RR], wb[NB][RR];
         int vcol[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const bool valid = e0 + j < vend;
             // a vector element is copied to a plain int before its bits are reinterpreted
             // (bit_cast applied to the element expression itself reads element 0)
-            const int row = r0[j].x, k0 = r0[j].y, th0_b = r0[j].z, wa_b = r0[j].w;
-            const int wb_b = r1[j].x;
+            const int row = r0[j].x, k0 = r0[j].y, th0_b = r0[j].z;
             int col_j, order;
-            if constexpr (RP) {
-                // row pair record: (wb0, wa1, wb1, col | order << 16) in the second word
-                const int wc_b = r1[j].y, wd_b = r1[j].z, co = r1[j].w;
-                wc[j] = __builtin_bit_cast(float, wc_b);
-                wd[j] = __builtin_bit_cast(float, wd_b);
-                col_j = co & 0xFFFF;
-                order = co >> 16;
-            } else {
+            if constexpr (RR == 1) {
+                const int wa_b = r0[j].w, wb_b = r1[j].x;
+                wa[j][0] = __builtin_bit_cast(float, wa_b);
+                wb[j][0] = __builtin_bit_cast(float, wb_b);
                 col_j = r1[j].y;
                 order = r1[j].z;
+            } else {
+                const int co = r0[j].w;
+                const int e0b = r1[j].x, e1b = r1[j].y, e2b = r1[j].z, e3b = r1[j].w;
+                col_j = co & 0xFFFF;
+                order = co >> 16;
+                wa[j][0] = __builtin_bit_cast(float, e0b);
+                wb[j][0] = __builtin_bit_cast(float, e1b);
+                wa[j][1] = __builtin_bit_cast(float, e2b);
+                wb[j][1] = __builtin_bit_cast(float, e3b);
             }
-            wa[j] = __builtin_bit_cast(float, wa_b);
-            wb[j] = __builtin_bit_cast(float, wb_b);
             vcol[j] = valid ? col_j : ncol;
             const bool on = valid && ((a.mask >> order) & 1u);
             TP_::weights(__builtin_bit_cast(float, th0_b), tw[j]);
@@ -1670,11 +1671,10 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
                     float h = 0.f;
 #pragma unroll
                     for (int t = 0; t < T; ++t) h += tw[j][t] * yv[j][u][v][t];
-                    acc_a[u][v] += wa[j] * h;
-                    acc_b[u][v] += wb[j] * h;
-                    if (RP) {
-                        acc_c[u][v] += wc[j] * h;
-                        acc_d[u][v] += wd[j] * h;
+#pragma unroll
+                    for (int r = 0; r < RR; ++r) {
+                        acc_a[r][u][v] += wa[j][r] * h;
+                        acc_b[r][u][v] += wb[j][r] * h;
                     }
                 }
         }
@@ -1682,12 +1682,12 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     while (col < ncol) emit();
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, bool RP>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, int RR>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
-    const int rgroups = ((RP ? (a.n_r + 1) / 2 : a.n_r) + T_WAVES - 1) / T_WAVES;
+    const int rgroups = ((a.n_r + RR - 1) / RR + T_WAVES - 1) / T_WAVES;
     const int v0 = blockIdx.y * NVW;
-    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO, RP>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
+    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO, RR>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
                                                    min(NVW, a.nvec - v0),
                                                    xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
 }
@@ -1712,7 +1712,7 @@ struct VisitMulti {
     int64_t y_stride, x_stride;
 };
 
-template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO>
+template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO, int RR>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMulti a)
 {
     for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
@@ -1737,7 +1737,7 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMul
         va.x_stride = a.x_stride;
         va.y_bytes = mm.y_bytes;
         va.x_bytes = mm.x_bytes;
-        visit_body<Q, V, NB, PAIR, 1, DPP, HALO>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
+        visit_body<Q, V, NB, PAIR, 1, DPP, HALO, RR>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
                                                  a.x + (int64_t)v * a.x_stride + mm.x_off, 1, (int64_t)(b - mm.blk_begin));
     }
 }
@@ -2539,21 +2539,21 @@ static bool visit_halo_fits(int K)
     return (K + C - 1) / C == (K + WAVE * V - 1) / (WAVE * V);
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false, bool RP = false>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false, int RR = 1>
 static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
     if constexpr (DPP && !HALO) {
         if (visit_halo_fits<Q, V>(a.K)) {
-            visit_launch<Q, V, NB, PAIR, NVW, true, true, RP>(a, nvec, s);
+            visit_launch<Q, V, NB, PAIR, NVW, true, true, RR>(a, nvec, s);
             return;
         }
     }
     constexpr int C = visit_chunk<Q, V, DPP, HALO>();
     a.kchunks = (a.K + C - 1) / C;
     a.nvec = nvec;
-    const int rows = RP ? (a.n_r + 1) / 2 : a.n_r;
+    const int rows = (a.n_r + RR - 1) / RR;
     const int64_t blocks = (int64_t)((rows + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO, RP>),
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO, RR>),
                        dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)), dim3(T_WAVES * WAVE), 0, s, a);
 }
 
@@ -2581,20 +2581,26 @@ static void visitd_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s
     else visit_launch<Q, 8, 2, P, 1, true>(a, nvec, s);
 }
 
-// lane-shifted taps over row pairs (visit set 2); vpw vectors per wave (2 or 4)
-template <int Q>
-static void visitp_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s)
+// lane-shifted taps over row pairs (visit set 2); vpw vectors per wave
+template <int Q, int RR>
+static void visitg_dispatch(const VisitArgs& a, int nvec, int vpw, hipStream_t s)
 {
     constexpr bool P = Q == 2;
     if (vpw == 4) {
-        if (a.K <= 64) visit_launch<Q, 1, 2, P, 4, true, false, true>(a, nvec, s);
-        else if (a.K <= 128) visit_launch<Q, 2, 2, P, 4, true, false, true>(a, nvec, s);
-        else visit_launch<Q, 4, 1, P, 4, true, false, true>(a, nvec, s);
+        if (a.K <= 64) visit_launch<Q, 1, 2, P, 4, true, false, RR>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, 2, P, 4, true, false, RR>(a, nvec, s);
+        else visit_launch<Q, 4, 1, P, 4, true, false, RR>(a, nvec, s);
         return;
     }
-    if (a.K <= 64) visit_launch<Q, 1, 4, P, 2, true, false, true>(a, nvec, s);
-    else if (a.K <= 128) visit_launch<Q, 2, 4, P, 2, true, false, true>(a, nvec, s);
-    else visit_launch<Q, 4, 2, P, 2, true, false, true>(a, nvec, s);
+    if (vpw == 2) {
+        if (a.K <= 64) visit_launch<Q, 1, 4, P, 2, true, false, RR>(a, nvec, s);
+        else if (a.K <= 128) visit_launch<Q, 2, 4, P, 2, true, false, RR>(a, nvec, s);
+        else visit_launch<Q, 4, 2, P, 2, true, false, RR>(a, nvec, s);
+        return;
+    }
+    if (a.K <= 64) visit_launch<Q, 1, 4, P, 1, true, false, RR>(a, nvec, s);
+    else if (a.K <= 128) visit_launch<Q, 2, 4, P, 1, true, false, RR>(a, nvec, s);
+    else visit_launch<Q, 4, 2, P, 1, true, false, RR>(a, nvec, s);
 }
 
 // vpw: vectors per wave (1, 2 or 4).  Loads in flight per lane stay near NB * V * T / 8.
@@ -2789,7 +2795,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     return true;
 }
 
-template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO = false>
+template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO = false, int RR = 1>
 static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec, bool persist,
                                hipStream_t s)
 {
@@ -2797,7 +2803,7 @@ static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int 
         bool fits = true;
         for (int i = b; i < e; ++i) fits = fits && visit_halo_fits<Q, V>(g->members[i].grid.n_hat);
         if (fits) {
-            visit_multi_launch<Q, V, NB, PAIR, true, true>(a, g, b, e, set, nvec, persist, s);
+            visit_multi_launch<Q, V, NB, PAIR, true, true, RR>(a, g, b, e, set, nvec, persist, s);
             return;
         }
     }
@@ -2808,16 +2814,16 @@ static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int 
         VisitMember& d = a.m[i - b];
         d.kchunks = (m.grid.n_hat + C - 1) / C;
         d.blk_begin = (uint32_t)nb;
-        nb += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * d.nseg * d.kchunks;
+        nb += (int64_t)(((m.grid.n_r + RR - 1) / RR + T_WAVES - 1) / T_WAVES) * d.nseg * d.kchunks;
     }
     a.per_vec = (uint32_t)nb;
     a.total = (uint32_t)(nb * nvec);   // below 2^31: checked by adjoint_multi
     if (a.total == 0) return;
-    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP, HALO>), dim3(multi_grid(a.total, persist)),
+    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP, HALO, RR>), dim3(multi_grid(a.total, persist)),
                        dim3(T_WAVES * WAVE), 0, s, a);
 }
 
-template <int Q, bool PAIR, bool DPP = false>
+template <int Q, bool PAIR, bool DPP = false, int RR = 1>
 static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec,
                                  bool persist, hipStream_t s)
 {
@@ -2828,10 +2834,17 @@ static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, in
         waves += (int64_t)g->members[i].grid.n_r * g->members[i].nseg[set] * nvec;
         K = std::max(K, g->members[i].grid.n_hat);
     }
-    if (K <= 64 || waves < 16384) visit_multi_launch<Q, 1, 8, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
-    else if (K <= 128) visit_multi_launch<Q, 2, NB1, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
-    else if (K <= 256) visit_multi_launch<Q, 4, Q == 1 ? 4 : 2, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
-    else visit_multi_launch<Q, 8, 2, PAIR, DPP>(a, g, b, e, set, nvec, persist, s);
+    if (RR == 2) {
+        // row pairs: half the (row, segment) tasks; batches as in the single-geometry pair form
+        if (K <= 64) visit_multi_launch<Q, 1, 4, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
+        else if (K <= 128) visit_multi_launch<Q, 2, 4, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
+        else visit_multi_launch<Q, 4, 2, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
+        return;
+    }
+    if (K <= 64 || waves < 16384) visit_multi_launch<Q, 1, 8, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
+    else if (K <= 128) visit_multi_launch<Q, 2, NB1, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
+    else if (K <= 256) visit_multi_launch<Q, 4, Q == 1 ? 4 : 2, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
+    else visit_multi_launch<Q, 8, 2, PAIR, DPP, false, RR>(a, g, b, e, set, nvec, persist, s);
 }
 
 // Adjoint of members [b, e) in one launch; false if they do not fit the visit multi kernel.
@@ -2844,12 +2857,14 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
         if (!visit_supported(m) || m.Q != m0.Q || m.adj_variant != m0.adj_variant ||
-            (m0.adj_variant != 11 && m0.adj_variant != 16))
+            (m0.adj_variant != 11 && m0.adj_variant != 16 && m0.adj_variant != 19))
             return false;
         pair = pair && (m.grid.n_frames % 2) == 0 && (m.row_offset % 2) == 0;
         wide += (int64_t)m.grid.n_r * m.nseg[0] * nvec;
     }
-    const int set = wide >= 16384 ? 0 : 1;
+    // row pairs (lane-shifted taps; frame pairs at Q = 2) read visit set 2
+    const bool rp = m0.adj_variant == 19 && (m0.Q == 1 || pair);
+    const int set = rp ? 2 : wide >= 16384 ? 0 : 1;
     // task count with the narrowest hat chunk (62 hats, the largest count any V gives); every
     // member's blocks must fit the visit kernel's 31-bit buffer ranges
     int64_t most = 0;
@@ -2882,9 +2897,13 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     a.x = x;
     a.y_stride = g->n_rows;
     a.x_stride = g->n_cols;
-    if (m0.Q == 1 && m0.adj_variant == 16) visit_multi_dispatch<1, false, true>(a, g, b, e, set, nvec, persist, s);
+    if (rp && m0.Q == 1) visit_multi_dispatch<1, false, true, 2>(a, g, b, e, set, nvec, persist, s);
+    else if (rp) visit_multi_dispatch<2, true, true, 2>(a, g, b, e, set, nvec, persist, s);
+    else if (m0.Q == 1 && (m0.adj_variant == 16 || m0.adj_variant == 19))
+        visit_multi_dispatch<1, false, true>(a, g, b, e, set, nvec, persist, s);
     else if (m0.Q == 1) visit_multi_dispatch<1, false>(a, g, b, e, set, nvec, persist, s);
-    else if (pair && m0.adj_variant == 16) visit_multi_dispatch<2, true, true>(a, g, b, e, set, nvec, persist, s);
+    else if (pair && (m0.adj_variant == 16 || m0.adj_variant == 19))
+        visit_multi_dispatch<2, true, true>(a, g, b, e, set, nvec, persist, s);
     else if (pair) visit_multi_dispatch<2, true>(a, g, b, e, set, nvec, persist, s);
     else visit_multi_dispatch<2, false>(a, g, b, e, set, nvec, persist, s);
     hipError_t err = hipGetLastError();
@@ -2970,17 +2989,18 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         return RTT_OK;
     }
     if ((variant == 11 || variant >= 14) && !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 1)) variant = 2;
-    // row pairs: two vectors per wave at least, and frame pairs at Q = 2; else the single-row form
+    // row pairs: frame pairs at Q = 2, else the single-row form
     if (variant == 19 || variant == 20) {
         const bool fpair = m.Q == 1 || ((m.grid.n_frames % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0));
-        if (!fpair || !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 2)) variant = variant == 19 ? 17 : 18;
+        if (!fpair) variant = 16;
     }
     if (variant == 11 || variant >= 14) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
-        const bool rp = variant == 19 || variant == 20;   // row pairs (2 or 4 vectors per wave)
+        // rows per wave: 2 for the row-pair forms (visit set 2)
+        const int rr = (variant == 19 || variant == 20) ? 2 : 1;
         int vpw = (variant == 14 || variant == 17 || variant == 19) ? 2 : (variant == 15 || variant == 18 || variant == 20) ? 4 : 1;
-        if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = rp ? 2 : 1;
-        const int set = rp ? 2 : ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
+        if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = 1;
+        const int set = rr == 2 ? 2 : ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
         VisitArgs va;
         va.visits = g->d_visits + m.visit_begin[set];
         va.vtask = g->d_vtask + m.vtask_begin[set];
@@ -2999,8 +3019,8 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         va.x_bytes = (uint32_t)(m.n_cols * 4);
         // frame pairs need 8-byte aligned rows: even n_frames and aligned data vectors
         const bool pair = (va.F % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0);
-        if (rp && m.Q == 1) visitp_dispatch<1>(va, nvec, vpw, s);
-        else if (rp) visitp_dispatch<2>(va, nvec, vpw, s);
+        if (rr == 2 && m.Q == 1) visitg_dispatch<1, 2>(va, nvec, vpw, s);
+        else if (rr == 2) visitg_dispatch<2, 2>(va, nvec, vpw, s);
         else if (variant >= 16 && m.Q == 1) visitd_dispatch<1>(va, nvec, vpw, s);
         else if (variant >= 16 && pair) visitd_dispatch<2>(va, nvec, vpw, s);
         else if (m.Q == 1) visit_dispatch<1, false>(va, nvec, vpw, s);

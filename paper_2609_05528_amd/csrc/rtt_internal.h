@@ -41,17 +41,16 @@ struct alignas(16) Visit {
     int32_t pad;
 };
 static_assert(sizeof(Visit) == 32, "Visit must be 32 bytes");
-// One visit of a ray by the wave that owns a pair of cell rows (2p, 2p+1): weights into the
-// target columns col-1 and col of both rows (zero for a row the ray does not touch).  32 bytes.
-struct alignas(16) VisitPair {
+// One visit of a ray by the wave that owns a pair of cell rows (2p, 2p+1): this header, then
+// the weights (wa0, wb0, wa1, wb1) into the target columns col-1 and col of both rows (zero for
+// a row the ray does not touch).  32 bytes.
+struct alignas(16) VisitHead {
     int32_t row;        // caller ray index
     int32_t k0;         // hat origin of frame 0
     float th0;          // fraction of frame 0
-    float wa0, wb0;     // row 2p: weights into columns col-1 and col
-    float wa1, wb1;     // row 2p+1
     int32_t col_order;  // sweep position (low 16 bits) | image order << 16
 };
-static_assert(sizeof(VisitPair) == 32, "VisitPair must be 32 bytes");
+static_assert(sizeof(VisitHead) == 16, "VisitHead must be 16 bytes");
 constexpr int VISIT_SEG_MAX = 16;   // widest sweep segment (columns)
 
 // Forward record of one ray (48 bytes): corner offsets and weights precomputed so
@@ -84,9 +83,9 @@ struct Member {
     uint64_t digest;       // FNV-1a of the grid and this member's device records
     // two visit-list sets: [0] 16-column segments (many vectors per call), [1] narrower
     // segments chosen so one vector alone gives enough (row, segment) tasks
-    // set [2]: row pairs (VisitPair records, 16-column segments, ceil(n_r/2) * nseg tasks)
+    // set [2]: row pairs (VisitHead + weights, 16-column segments, ceil(n_r / 2) * nseg tasks)
     int64_t visit_begin[3];  // first visit record of each set
-    int64_t vtask_begin[3];  // first entry of each set's task offsets (rows (or pairs) * nseg + 1 entries)
+    int64_t vtask_begin[3];  // first entry of each set's task offsets (rows or pairs * nseg + 1 entries)
     int32_t nseg[3];         // sweep segments per cell row
     int32_t vseg[3];         // columns per sweep segment
     int32_t k0_min, k0_max;  // range of the hat origins k0 of the member's rays

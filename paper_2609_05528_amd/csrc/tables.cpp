@@ -252,10 +252,9 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
             }
             vtask.push_back((int64_t)visits.size() - m.visit_begin[set]);
         }
-        // set 2: the same sweep for a pair of rows (2p, 2p+1): rays with base row 2p-1 feed row
-        // 2p (weight fr), base row 2p feeds both (1 - fr and fr), base row 2p+1 feeds row 2p+1
-        // (1 - fr); within a column the order is by base row, so each row sums its rays in the
-        // order of the single-row lists
+        // set 2: the same sweep for a pair of rows (2p, 2p+1): a ray with base row ib feeds rows ib
+        // (1 - fr) and ib + 1 (fr); within a column the order is by base row, so each row sums its
+        // rays in the order of the single-row lists
         {
             const int vseg = VISIT_SEG_MAX;
             const int nseg = (g.n_phi + vseg - 1) / vseg;
@@ -271,26 +270,26 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
                     for (int c = 0; c <= jhi - jlo; ++c) {
                         const int u = jlo - 1 + c;
                         const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
-                        for (int part = 0; part < 3; ++part) {
-                            const int ib = 2 * pi - 1 + part;
+                        for (int part = 0; part <= 2; ++part) {
+                            const int ib = 2 * pi - 1 + part;   // base row; local rows part-1, part
                             if (ib < 0 || ib > g.n_r - 2) continue;
                             const int64_t cell = (int64_t)ib * g.n_phi + ub;
                             for (int32_t q = cs[cell]; q < cs[cell + 1]; ++q) {
                                 const RayRec& rr = gr[q];
-                                // radial weights into rows 2p and 2p+1
-                                const double w0 = part == 0 ? (double)rr.fr : part == 1 ? 1.0 - (double)rr.fr : 0.0;
-                                const double w1 = part == 1 ? (double)rr.fr : part == 2 ? 1.0 - (double)rr.fr : 0.0;
-                                VisitPair v;
-                                v.row = rr.row;
-                                v.k0 = rr.k0;
-                                v.th0 = rr.th0;
-                                v.wa0 = (float)((double)rr.w * w0 * (1.0 - (double)rr.fphi));
-                                v.wb0 = (float)((double)rr.w * w0 * (double)rr.fphi);
-                                v.wa1 = (float)((double)rr.w * w1 * (1.0 - (double)rr.fphi));
-                                v.wb1 = (float)((double)rr.w * w1 * (double)rr.fphi);
-                                v.col_order = c | (rr.order << 16);
+                                float wts[4];
+                                for (int lr = 0; lr < 2; ++lr) {
+                                    const double wr = lr == part ? (double)rr.fr : lr == part - 1 ? 1.0 - (double)rr.fr : 0.0;
+                                    wts[2 * lr] = (float)((double)rr.w * wr * (1.0 - (double)rr.fphi));
+                                    wts[2 * lr + 1] = (float)((double)rr.w * wr * (double)rr.fphi);
+                                }
+                                VisitHead h;
+                                h.row = rr.row;
+                                h.k0 = rr.k0;
+                                h.th0 = rr.th0;
+                                h.col_order = c | (rr.order << 16);
                                 Visit raw;
-                                std::memcpy(&raw, &v, sizeof raw);
+                                std::memcpy(&raw, &h, sizeof h);
+                                std::memcpy((char*)&raw + sizeof h, wts, sizeof wts);
                                 visits.push_back(raw);
                             }
                         }
