@@ -2989,16 +2989,21 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         return RTT_OK;
     }
     if ((variant == 11 || variant >= 14) && !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 1)) variant = 2;
-    // row pairs: frame pairs at Q = 2, else the single-row form
+    // row pairs: frame pairs at Q = 2, and enough (pair, segment, vector group) tasks to fill the
+    // chip once; else the single-row form, which narrows its segments for small launches
     if (variant == 19 || variant == 20) {
         const bool fpair = m.Q == 1 || ((m.grid.n_frames % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0));
-        if (!fpair) variant = 16;
+        const int pvw = std::min(variant == 19 ? 2 : 4, nvec);
+        const int64_t waves = (int64_t)((m.grid.n_r + 1) / 2) * m.nseg[2] * ((nvec + pvw - 1) / pvw);
+        if (!fpair || waves < 8192) variant = nvec >= 2 ? 17 : 16;
     }
     if (variant == 11 || variant >= 14) {
         // the wide segment set when the vectors alone give enough waves, else the narrow one
         // rows per wave: 2 for the row-pair forms (visit set 2)
         const int rr = (variant == 19 || variant == 20) ? 2 : 1;
         int vpw = (variant == 14 || variant == 17 || variant == 19) ? 2 : (variant == 15 || variant == 18 || variant == 20) ? 4 : 1;
+        // no more vectors per wave than the launch has (a missing vector costs a full one)
+        while (vpw > 1 && vpw > nvec) vpw /= 2;
         if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = 1;
         const int set = rr == 2 ? 2 : ((int64_t)m.grid.n_r * m.nseg[0] * ((nvec + vpw - 1) / vpw) >= 16384) ? 0 : 1;
         VisitArgs va;

@@ -263,6 +263,30 @@ def test_every_variant_on_a_ragged_block_matches_single_vectors(gpu_lib, dt_obs)
             assert rel(XT[b].cpu().numpy(), xr[b]) <= TOL, (vname, b)
 
 
+@pytest.mark.parametrize("dt_obs", [4.0, 2.0])
+def test_row_pair_adjoint_on_a_large_block_equals_single_rows(gpu_lib, dt_obs):
+    """The row-pair adjoint (taken only when a launch has enough pair tasks) on 259 vectors of a
+    64 x 64-cell grid: bitwise equal to the single-row form, and the oracle on sampled vectors."""
+    import torch
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=35, rays=(3000, 400, 300), n_r=64, n_phi=64, n_frames=20, dt_obs=dt_obs)
+    say("case row pairs", dt_obs, geo.grid.n_hat)
+    G = rtt.Geometry(geo)
+    names = rtt.variant_names(True)
+    nb = 259
+    Yt = to_dev(np.random.default_rng(10).standard_normal((nb, geo.n_rows)))
+    G.set_variant(adjoint=names.index("visitd2v"))
+    ref = rtt.op_apply_adjoint(G, Yt)
+    for vname in ("visitp2v", "visitp4v"):
+        G.set_variant(adjoint=names.index(vname))
+        XT = rtt.op_apply_adjoint(G, Yt)
+        assert torch.equal(XT, ref), vname
+    pick = [0, 129, 258]
+    xr = oracle.adjoint(geo, Yt[pick].double().cpu().numpy())
+    for i, b in enumerate(pick):
+        assert rel(XT[b].cpu().numpy(), xr[i]) <= TOL, b
+
+
 def test_drop_invalid_rays_write_zero_rows(gpu_lib):
     rtt = gpu_lib
     geo = tiny_geometry(seed=32, rays=(20, 5))
