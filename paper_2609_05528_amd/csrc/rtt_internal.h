@@ -81,9 +81,9 @@ struct Member {
     int32_t adj_variant;   // adjoint kernel variant (default heuristic or autotuner)
     int32_t apply_variant; // forward kernel variant
     uint64_t digest;       // FNV-1a of the grid and this member's device records
-    // two visit-list sets: [0] 16-column segments (many vectors per call), [1] narrower
-    // segments chosen so one vector alone gives enough (row, segment) tasks
-    // set [2]: row pairs (VisitHead + weights, 16-column segments, ceil(n_r / 2) * nseg tasks)
+    // visit-list sets: [0] single rows, 16-column segments (many vectors per call); [1] single
+    // rows, narrower segments chosen so one vector alone gives enough (row, segment) tasks;
+    // [2] row pairs (VisitHead + weights, 16-column segments, ceil(n_r / 2) * nseg tasks)
     int64_t visit_begin[3];  // first visit record of each set
     int64_t vtask_begin[3];  // first entry of each set's task offsets (rows or pairs * nseg + 1 entries)
     int32_t nseg[3];         // sweep segments per cell row
