@@ -39,6 +39,7 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip
 MEASURED_TRAFFIC = {
     "op_apply_adjoint": {"bytes": 2052182016, "digest": "7c5f844901216e10", "nvec": 264, "variant": "visitp2v"},
     "op_apply": {"bytes": 2104919040, "digest": "7c5f844901216e10", "nvec": 264, "variant": "lean4"},
+}
 
 
 def log(*a):
