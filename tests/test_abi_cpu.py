@@ -87,3 +87,16 @@ def test_synthetic_workload_shapes():
     gs = synth.batch_geometries()
     assert len(gs) == 12 and sum(g.n_rays for g in gs) == 295508
     assert [g.grid.s0 for g in (synth.geometry_for(c) for c in ("cfg1", "cfg2", "cfg5"))] == [-32.0, -72.0, -76.0]
+
+
+def test_bench_script_parses_and_refuses_several_gpus():
+    """bench.py is a driver contract: it must at least compile, and a request for more than one
+    GPU ends with a message (before any device work)."""
+    import subprocess
+    import sys as _sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = open(os.path.join(root, "bench.py")).read()
+    compile(src, "bench.py", "exec")
+    r = subprocess.run([_sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
