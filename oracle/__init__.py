@@ -16,6 +16,9 @@ with the GPU library.
 * ``tsvd_solve``, ``ridge_solve``, ``ridge_gradient``: the TSVD and ridge
   estimators of Sec. 9 and the ridge objective gradient.
 * ``s_ref`` and ``operational_rank``: eq. (17)-(18) and eq. (31).
+* ``mixer_matrix``, ``mix``, ``mix_adjoint``, ``mix_covariance``: the order mixer
+  L of Sec. 2 eq. (4) (unresolved image and total flux) and the propagation of
+  the data covariance through it, written out as dense matrices.
 
 Every function here is pinned by the "not gpu" tests against facts that do
 not come from this module (see the tests' docstrings).
@@ -291,3 +294,52 @@ def operational_rank(sigma, s_reference, snr0=100.0, rho=1.0):
     """eq. (31) with C = sigma_Omega^2 I, sigma_Omega = s_ref/SNR0 (eq. (18))."""
     thr = rho * s_reference / snr0
     return int(np.count_nonzero(np.asarray(sigma) >= thr))
+
+
+# ------------------------------------------------------------------ order mixer (Sec. 2, eq. (4))
+MIX_KINDS = ("unresolved", "total_flux")
+
+
+def mixer_matrix(geom, kind):
+    """The order mixer L of eq. (4) for one geometry, written out as a dense 0/1 matrix.
+
+    Columns are the order-resolved rays in data-row order (order 0's rays first, eq. (3)).
+    'unresolved': one row per distinct image pixel (ascending pixel index) adding the rays of
+    every order that land on that pixel -- the unresolved spatial image; 'total_flux': a single
+    row adding every ray -- the total-flux readout.  Returns (L, pixels of the rows or None).
+    """
+    pix = np.concatenate([np.asarray(m.pixel, dtype=np.int64) for m in geom.maps])
+    if kind == "total_flux":
+        return np.ones((1, pix.size)), None
+    if kind != "unresolved":
+        raise ValueError("kind must be one of %s" % (MIX_KINDS,))
+    rows = np.unique(pix)
+    return (pix[None, :] == rows[:, None]).astype(np.float64), rows
+
+
+def mix(geom, y, kind):
+    """d_L = (L kron I) d_R of eq. (4): y holds order-resolved rows [..., n_rays * F]."""
+    L, _ = mixer_matrix(geom, kind)
+    F = geom.grid.n_frames
+    y = np.asarray(y, dtype=np.float64)
+    lead = y.shape[:-1]
+    Y = y.reshape(lead + (geom.n_rays, F))
+    return np.einsum("or,...rf->...of", L, Y).reshape(lead + (L.shape[0] * F,))
+
+
+def mix_adjoint(geom, d, kind):
+    """(L^T kron I) d: every ray row receives the mixed row it feeds."""
+    L, _ = mixer_matrix(geom, kind)
+    F = geom.grid.n_frames
+    d = np.asarray(d, dtype=np.float64)
+    lead = d.shape[:-1]
+    D = d.reshape(lead + (L.shape[0], F))
+    return np.einsum("or,...of->...rf", L, D).reshape(lead + (geom.n_rays * F,))
+
+
+def mix_covariance(geom, var, kind):
+    """C_L = (L kron I) C_R (L^T kron I) of eq. (4) for a diagonal C_R = diag(var), var being the
+    per-datum variances in data-row order.  Returns the full matrix (small cases only)."""
+    L, _ = mixer_matrix(geom, kind)
+    K = np.kron(L, np.eye(geom.grid.n_frames))
+    return K @ np.diag(np.asarray(var, dtype=np.float64)) @ K.T

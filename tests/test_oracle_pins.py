@@ -318,3 +318,107 @@ def test_oracle_rejects_bad_grid():
     bad = synth.Geometry(grid=synth.Grid(**{**geo.grid.as_dict(), "n_r": 1}), maps=geo.maps)
     with pytest.raises(ValueError):
         oracle.forward(bad, np.zeros(bad.grid.n_cols))
+
+
+# ------------------------------------------------------------------ order mixer, eq. (4)
+def _golden_mixer():
+    """The hand-worked fixture tests/golden/order_mixer_example.txt as a geometry-like object."""
+    import os
+    import types
+    rows, unres, tf, vu, vt = [], {}, None, {}, None
+    with open(os.path.join(os.path.dirname(__file__), "golden", "order_mixer_example.txt")) as f:
+        for line in f:
+            t = line.split()
+            if not t or t[0].startswith("#"):
+                continue
+            if t[0] == "ray":
+                rows.append(tuple(float(v) for v in t[1:]))
+            elif t[0] == "unresolved":
+                unres[int(t[1])] = [float(t[2]), float(t[3])]
+            elif t[0] == "total_flux":
+                tf = [float(t[1]), float(t[2])]
+            elif t[0] == "var_unresolved":
+                vu[int(t[1])] = float(t[2])
+            elif t[0] == "var_total_flux":
+                vt = float(t[1])
+    maps = []
+    for n in range(3):
+        pix = np.array([int(r[2]) for r in rows if int(r[1]) == n])
+        maps.append(types.SimpleNamespace(pixel=pix, n_rays=pix.size))
+    geo = types.SimpleNamespace(maps=maps, n_rays=len(rows), grid=types.SimpleNamespace(n_frames=2))
+    y = np.array([[r[3], r[4]] for r in rows]).ravel()
+    var = np.array([[r[5], r[5]] for r in rows]).ravel()
+    return geo, y, var, unres, tf, vu, vt
+
+
+def test_order_mixer_hand_worked_example():
+    """eq. (4) on a five-ray, three-order example summed by hand (golden fixture)."""
+    geo, y, var, unres, tf, vu, vt = _golden_mixer()
+    L, pix = oracle.mixer_matrix(geo, "unresolved")
+    assert list(pix) == sorted(unres)
+    d = oracle.mix(geo, y, "unresolved").reshape(-1, 2)
+    for i, p in enumerate(pix):
+        assert np.array_equal(d[i], unres[p])
+    assert np.array_equal(oracle.mix(geo, y, "total_flux"), tf)
+    C = oracle.mix_covariance(geo, var, "unresolved")
+    assert np.array_equal(C, np.diag(np.repeat([vu[p] for p in pix], 2)))
+    assert np.array_equal(oracle.mix_covariance(geo, var, "total_flux"), vt * np.eye(2))
+
+
+def test_order_mixer_adjoint_and_total_flux_invariants():
+    """<L y, d> = <y, L^T d>; the total flux is the sum of the unresolved image over pixels."""
+    geo = tiny_geometry(seed=41, rays=(30, 20, 10), n_frames=7)
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal((2, geo.n_rows))
+    for kind in oracle.MIX_KINDS:
+        d = rng.standard_normal((2, oracle.mixer_matrix(geo, kind)[0].shape[0] * geo.grid.n_frames))
+        lhs = np.sum(oracle.mix(geo, y, kind) * d)
+        rhs = np.sum(y * oracle.mix_adjoint(geo, d, kind))
+        assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs) + 1)
+    du = oracle.mix(geo, y, "unresolved").reshape(2, -1, geo.grid.n_frames)
+    assert np.allclose(du.sum(axis=1), oracle.mix(geo, y, "total_flux"), rtol=1e-13, atol=1e-12)
+
+
+def test_order_mixer_covariance_matches_monte_carlo():
+    """C_L of eq. (4) against the sample covariance of L applied to independent Gaussian noise
+    with the per-datum variances of the fixture (a check that does not use the formula)."""
+    geo, _, var, *_ = _golden_mixer()
+    rng = np.random.default_rng(11)
+    N = 40000
+    Z = rng.standard_normal((N, var.size)) * np.sqrt(var)
+    for kind in oracle.MIX_KINDS:
+        D = oracle.mix(geo, Z, kind)
+        emp = D.T @ D / N
+        C = oracle.mix_covariance(geo, var, kind)
+        scale = np.sqrt(np.outer(np.diag(C), np.diag(C)))
+        # sample (co)variances have relative standard deviation about sqrt(2 / N) = 0.7%
+        assert np.max(np.abs(emp - C) / scale) < 0.04, kind
+
+
+def test_unresolved_echo_train_inverts_with_the_echo_recursion():
+    """Sec. 4, the scalar echo train: when every pixel sees the same source point in orders
+    n = 0, 1, 2 with delays Delta + n tau and weights a^n, the unresolved series is
+    d(t) = sum_n a^n y0(t - n tau), so d(t) - a d(t - tau) = y0(t) - a^3 y0(t - 3 tau) for the
+    three retained orders (tau a whole number of frames and hats, y0 the direct series)."""
+    m, a = 3, 0.45
+    grid = synth.Grid(n_orders=3, n_frames=40, t0=0.0, dt_obs=4.0, n_r=5, n_phi=7, r_in=6.0, r_out=20.0,
+                      n_hat=80, s0=-150.0, dt_src=4.0)
+    tau = m * grid.dt_obs
+    rng = np.random.default_rng(5)
+    npix = 25
+    r = rng.uniform(grid.r_in, grid.r_out, npix)
+    phi = rng.uniform(0.0, 2 * np.pi, npix)
+    dl = rng.uniform(0.3, 9.7, npix)
+    maps = [synth.RayMap(r=r, phi=phi, delay=dl + n * tau, weight=np.full(npix, a ** n),
+                         pixel=np.arange(npix, dtype=np.int32)) for n in range(3)]
+    geo = synth.Geometry(grid=grid, maps=maps)
+    x = rng.random(grid.n_cols)
+    y = oracle.forward(geo, x)
+    F = grid.n_frames
+    y0 = y[: npix * F].reshape(npix, F)
+    d = oracle.mix(geo, y, "unresolved").reshape(npix, F)
+    f = np.arange(3 * m, F)
+    lhs = d[:, f] - a * d[:, f - m]
+    rhs = y0[:, f] - a ** 3 * y0[:, f - 3 * m]
+    assert np.max(np.abs(lhs - rhs)) <= 1e-11 * np.max(np.abs(y0))
+    assert np.max(np.abs(rhs)) > 0.1 * np.max(np.abs(y0))
