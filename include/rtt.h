@@ -280,6 +280,78 @@ typedef struct {
 int ridge_solve(const rtt_geometry* geom, const float* y, int32_t nrhs, float lambda,
                 const rtt_cg_opts* opts, float* x, rtt_solve_info* info, void* stream);
 
+/* -------------------------------------------------------------- order mixer */
+/*
+ * Order mixers L of Sec. 3.1 eq. (4): d_L = (L kron I) d_R collapses the
+ * order-resolved rows of a handle (eq. (3)) into a coarser observation, and
+ * its noise follows through C_L = (L kron I) C_R (L^T kron I).  Two kinds:
+ *  - RTT_MIX_UNRESOLVED: the unresolved spatial image.  Each ray carries the
+ *    index of the image pixel it lands on; the rays of every order that share
+ *    a pixel are added.  A geometry's mixed rows are its distinct pixels in
+ *    ascending index order, each a row of n_frames frames.
+ *  - RTT_MIX_TOTAL_FLUX: the total-flux readout, one row (n_frames frames)
+ *    per geometry adding every ray of every order.
+ * A mixed data block is [nvec][n_rows] (mixer_info), geometries concatenated
+ * in handle order (offsets from mixer_member).  Every sum runs in a fixed
+ * order (source rays in data-row order, in chunks of 64 whose partial rows are
+ * then added in chunk order), so results are bitwise reproducible.
+ */
+typedef struct rtt_mixer rtt_mixer; /* opaque; owns the device gather tables */
+enum { RTT_MIX_UNRESOLVED = 0, RTT_MIX_TOTAL_FLUX = 1 };
+
+typedef struct {
+    int32_t kind;          /* RTT_MIX_*                                          */
+    int32_t n_geometries;
+    int64_t n_rows;        /* rows of a mixed data vector (all geometries)       */
+    int64_t n_src_rows;    /* rows of the handle's order-resolved data vectors   */
+    int32_t reserved[4];
+} rtt_mixer_info;
+
+/*
+ * mixer_create -- build the mixer of kind `kind` for every geometry of geom.
+ * pixels (RTT_MIX_UNRESOLVED only, else may be NULL): host arrays in the
+ * order of geometry_load's ray maps (geometry 0's orders first), pixels[i]
+ * holding one int64 pixel index >= 0 per ray of ray map i (NULL allowed for
+ * an empty map); caller-owned, copied.  Pixel indices are local to a
+ * geometry.  Blocking; *out receives a handle to release with mixer_free.
+ * The mixer does not keep geom.  Errors: RTT_EINVAL (bad kind, handle, NULL
+ * or negative pixels), RTT_ENOMEM, RTT_EDEVICE.
+ */
+int mixer_create(const rtt_geometry* geom, int32_t kind, const int64_t* const* pixels, rtt_mixer** out);
+int mixer_free(rtt_mixer* mixer);
+int mixer_info(const rtt_mixer* mixer, rtt_mixer_info* info);
+/* Mixed rows of geometry g: offset and length inside a mixed data vector, and
+ * the number of mixed rows (pixels, or 1 for the total flux).  Any output
+ * pointer may be NULL.  Errors: RTT_EINVAL for a bad handle or index. */
+int mixer_member(const rtt_mixer* mixer, int32_t g, int64_t* row_offset, int64_t* n_rows, int64_t* n_out);
+
+/*
+ * mix_apply -- d = (L kron I) y (eq. (4)).  y: device [nvec][n_src_rows]
+ * order-resolved data; d: device [nvec][n_rows], overwritten.  A mixer with
+ * rows of more than 64 rays keeps a partial-row scratch buffer of
+ * (number of chunks) x (largest n_frames) x nvec floats, allocated on the
+ * first call that needs more and reused after; calls on one mixer must not
+ * overlap in time.  0 <= nvec <= 65535.  Errors: RTT_EINVAL, RTT_ENOMEM,
+ * RTT_EDEVICE.
+ */
+int mix_apply(const rtt_mixer* mixer, const float* y, float* d, int32_t nvec, void* stream);
+
+/*
+ * mix_adjoint -- y = (L^T kron I) d: every order-resolved row receives the
+ * mixed row its ray feeds.  d: device [nvec][n_rows]; y: device
+ * [nvec][n_src_rows], every row overwritten.  Allocates nothing.
+ */
+int mix_adjoint(const rtt_mixer* mixer, const float* d, float* y, int32_t nvec, void* stream);
+
+/*
+ * mix_covariance -- C_L of eq. (4) for a diagonal C_R = diag(var).  Each
+ * order-resolved row feeds exactly one mixed row, so C_L is diagonal too and
+ * its diagonal is the mixed sum of the variances: var: device [n_src_rows];
+ * var_out: device [n_rows] (the diagonal of C_L).  Same scratch rule as
+ * mix_apply.
+ */
+int mix_covariance(const rtt_mixer* mixer, const float* var, float* var_out, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);
 

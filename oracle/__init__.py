@@ -17,7 +17,7 @@ with the GPU library.
   estimators of Sec. 9 and the ridge objective gradient.
 * ``s_ref`` and ``operational_rank``: eq. (17)-(18) and eq. (31).
 * ``mixer_matrix``, ``mix``, ``mix_adjoint``, ``mix_covariance``: the order mixer
-  L of Sec. 2 eq. (4) (unresolved image and total flux) and the propagation of
+  L of Sec. 3.1 eq. (4) (unresolved image and total flux) and the propagation of
   the data covariance through it, written out as dense matrices.
 
 Every function here is pinned by the "not gpu" tests against facts that do
@@ -296,7 +296,7 @@ def operational_rank(sigma, s_reference, snr0=100.0, rho=1.0):
     return int(np.count_nonzero(np.asarray(sigma) >= thr))
 
 
-# ------------------------------------------------------------------ order mixer (Sec. 2, eq. (4))
+# ------------------------------------------------------------------ order mixer (Sec. 3.1, eq. (4))
 MIX_KINDS = ("unresolved", "total_flux")
 
 

@@ -23,7 +23,8 @@ RTT_EACH_GEOMETRY = -2
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
-            "tsvd_solve", "ridge_solve", "last_error")
+            "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member",
+            "mix_apply", "mix_adjoint", "mix_covariance", "last_error")
 
 
 class RttError(RuntimeError):
@@ -123,6 +124,13 @@ def require_native():
         "tsvd_solve": [vp, vp, vp, i32, i32, ctypes.c_double, vp, vp],
         "ridge_solve": [vp, vp, i32, ctypes.c_float, ctypes.POINTER(rtt_cg_opts), vp,
                         ctypes.POINTER(rtt_solve_info), vp],
+        "mixer_create": [vp, i32, vp, ctypes.POINTER(vp)],
+        "mixer_free": [vp],
+        "mixer_info": [vp, vp],
+        "mixer_member": [vp, i32, vp, vp, vp],
+        "mix_apply": [vp, vp, vp, i32, vp],
+        "mix_adjoint": [vp, vp, vp, i32, vp],
+        "mix_covariance": [vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -308,3 +316,4 @@ def op_apply_adjoint(geom: Geometry, y, x=None, order_mask: int = 0, stream=None
 
 from .svd import SVD, rsvd, tsvd_solve, ridge_solve  # noqa: E402,F401
 from .autograd import RetardedTimeOp, retarded_time_apply  # noqa: E402,F401
+from .mixer import Mixer, mixer_create, mix_apply, mix_adjoint, mix_covariance  # noqa: E402,F401

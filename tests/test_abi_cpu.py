@@ -75,6 +75,15 @@ def test_null_arguments_are_errors():
     assert lib.geometry_free(None) == rtt.RTT_OK
     info = rtt.rtt_solve_info()
     assert lib.ridge_solve(None, None, 1, 1e-3, None, None, ctypes.byref(info), None) == rtt.RTT_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.mixer_create(None, 0, None, ctypes.byref(h)) == rtt.RTT_EINVAL and not h.value
+    assert b"invalid geometry handle" in lib.last_error()
+    assert lib.mixer_create(None, 0, None, None) == rtt.RTT_EINVAL
+    assert lib.mix_apply(None, None, None, 1, None) == rtt.RTT_EINVAL
+    assert lib.mix_adjoint(None, None, None, 1, None) == rtt.RTT_EINVAL
+    assert lib.mix_covariance(None, None, None, None) == rtt.RTT_EINVAL
+    assert b"invalid mixer handle" in lib.last_error()
+    assert lib.mixer_free(None) == rtt.RTT_OK
 
 
 def test_synthetic_workload_shapes():

@@ -1,0 +1,204 @@
+"""Order mixers of Sec. 3.1 eq. (4) on the GPU against the FP64 oracle.
+
+The unresolved image and the total-flux readout (mix_apply), their transpose
+(mix_adjoint) and the propagated diagonal covariance (mix_covariance), on a
+ragged batch of small geometries (frame counts 6, 7 and 8, so every vector
+width of the kernels runs; an empty order; rows of more than 64 rays, so the
+partial-row pass runs) and on the 128^2 x 128-frame Kerr workload (sampled
+pixels against the oracle run on just their rays, the total flux in full).
+Sums run in FP32 in a fixed order: 1e-5 relative against FP64 is the bar; the
+transpose only copies, so it is compared bit for bit.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tinygeo import tiny_geometry
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def with_pixels(geo, pixels):
+    maps = [dataclasses.replace(m, pixel=np.asarray(p, dtype=np.int32)) for m, p in zip(geo.maps, pixels)]
+    return synth.Geometry(grid=geo.grid, maps=maps, label=geo.label)
+
+
+def ragged_geometries():
+    """Three geometries: F = 6 (pixel ids shared across orders), F = 7 with an empty order,
+    F = 8 with 210 rays on three pixels (rows of ~70 rays: two chunks each)."""
+    g0 = tiny_geometry(seed=81, rays=(130, 40, 7), n_frames=6)
+    g1 = tiny_geometry(seed=82, rays=(20, 0, 9), n_frames=7)
+    g2 = tiny_geometry(seed=83, rays=(70, 70, 70), n_frames=8)
+    rng = np.random.default_rng(84)
+    g2 = with_pixels(g2, [rng.integers(0, 3, m.n_rays) for m in g2.maps])
+    return [g0, g1, g2]
+
+
+def pixel_arrays(geos):
+    return [np.asarray(m.pixel, dtype=np.int64) for g in geos for m in g.maps]
+
+
+@pytest.mark.parametrize("kind", ["unresolved", "total_flux"])
+def test_mixer_on_a_ragged_batch_matches_oracle(gpu_lib, kind):
+    rtt = gpu_lib
+    geos = ragged_geometries()
+    G = rtt.Geometry(geos)
+    say("case mixer ragged batch", kind)
+    M = rtt.Mixer(G, kind, pixel_arrays(geos) if kind == "unresolved" else None)
+    nvec = 5
+    rng = np.random.default_rng(85)
+    y = rng.standard_normal((nvec, G.n_rows)).astype(np.float32)
+    d_in = rng.standard_normal((nvec, M.n_rows)).astype(np.float32)
+    var = rng.uniform(0.5, 2.0, G.n_rows).astype(np.float32)
+    d = rtt.mix_apply(M, to_dev(y)).cpu().numpy()
+    yt = rtt.mix_adjoint(M, to_dev(d_in)).cpu().numpy()
+    cv = rtt.mix_covariance(M, to_dev(var)).cpu().numpy()
+    assert M.n_src_rows == G.n_rows
+    for g, geo in enumerate(geos):
+        mg, gm = M.members[g], G.members[g]
+        rs = slice(gm["row_offset"], gm["row_offset"] + gm["n_rows"])
+        ms = slice(mg["row_offset"], mg["row_offset"] + mg["n_rows"])
+        L, pix = oracle.mixer_matrix(geo, kind)
+        assert mg["n_out"] == L.shape[0] and mg["n_rows"] == L.shape[0] * geo.grid.n_frames
+        ref = oracle.mix(geo, y[:, rs].astype(np.float64), kind)
+        for v in range(nvec):
+            assert rel(d[v, ms], ref[v]) < TOL, (g, v, rel(d[v, ms], ref[v]))
+        # the transpose only copies mixed rows: exact
+        reft = oracle.mix_adjoint(geo, d_in[:, ms].astype(np.float64), kind)
+        np.testing.assert_array_equal(yt[:, rs], reft.astype(np.float32))
+        C = oracle.mix_covariance(geo, var[rs].astype(np.float64), kind)
+        assert np.count_nonzero(C - np.diag(np.diag(C))) == 0
+        assert rel(cv[ms], np.diag(C)) < TOL, (g, rel(cv[ms], np.diag(C)))
+
+
+def test_mixer_sums_are_bitwise_reproducible_and_width_independent(gpu_lib):
+    """Fixed summation order: repeated calls, one vector alone or inside a block, and inputs
+    that are only 4-byte aligned (the scalar path) all give the same bits."""
+    import torch
+    rtt = gpu_lib
+    geos = ragged_geometries()
+    G = rtt.Geometry(geos)
+    for kind in ("unresolved", "total_flux"):
+        say("case mixer bitwise", kind)
+        M = rtt.Mixer(G, kind, pixel_arrays(geos) if kind == "unresolved" else None)
+        y = to_dev(np.random.default_rng(86).standard_normal((3, G.n_rows)))
+        a = rtt.mix_apply(M, y)
+        b = rtt.mix_apply(M, y)
+        assert torch.equal(a, b)
+        assert torch.equal(rtt.mix_apply(M, y[1].contiguous()), a[1])
+        # storage offset of one float: 4-byte aligned only
+        buf = torch.empty(3 * G.n_rows + 1, device=y.device)
+        ys = buf[1:].view(3, G.n_rows)
+        ys.copy_(y)
+        out = torch.empty(3 * M.n_rows + 1, device=y.device)
+        rtt.mix_apply(M, ys, out[1:].view(3, M.n_rows))
+        torch.cuda.synchronize()
+        assert torch.equal(out[1:].view(3, M.n_rows), a)
+        dt = torch.randn(3, M.n_rows, device=y.device)
+        t = rtt.mix_adjoint(M, dt)
+        out2 = torch.empty(3 * G.n_rows + 1, device=y.device)
+        rtt.mix_adjoint(M, dt, out2[1:].view(3, G.n_rows))
+        assert torch.equal(out2[1:].view(3, G.n_rows), t)
+
+
+def test_mixer_rejects_bad_input(gpu_lib):
+    import ctypes
+    rtt = gpu_lib
+    geos = ragged_geometries()
+    G = rtt.Geometry(geos)
+    say("case mixer errors")
+    pix = pixel_arrays(geos)
+    pix[0] = pix[0].copy()
+    pix[0][3] = -1
+    with pytest.raises(rtt.RttError, match="pixel indices"):
+        rtt.Mixer(G, "unresolved", pix)
+    with pytest.raises(ValueError):
+        rtt.Mixer(G, "unresolved", pixel_arrays(geos)[:-1])
+    with pytest.raises(ValueError):
+        rtt.Mixer(G, "resolved")
+    lib = rtt.require_native()
+    h = ctypes.c_void_p()
+    assert lib.mixer_create(G.handle, 7, None, ctypes.byref(h)) == rtt.RTT_EINVAL
+    assert lib.mixer_create(G.handle, 0, None, ctypes.byref(h)) == rtt.RTT_EINVAL
+    M = rtt.Mixer(G, "total_flux")
+    assert lib.mix_apply(M.handle, None, None, 0, None) == rtt.RTT_OK   # nvec = 0: nothing to do
+    assert lib.mix_apply(M.handle, None, None, 1, None) == rtt.RTT_EINVAL
+
+
+def sub_geometry(geo, keep_pixels):
+    """The rays of geo whose pixel is in keep_pixels, and their data-row indices."""
+    keep = set(int(p) for p in keep_pixels)
+    maps, rows, base = [], [], 0
+    for m in geo.maps:
+        sel = np.array([int(p) in keep for p in m.pixel], dtype=bool)
+        idx = np.nonzero(sel)[0]
+        maps.append(synth.RayMap(r=m.r[idx], phi=m.phi[idx], delay=m.delay[idx], weight=m.weight[idx],
+                                 pixel=m.pixel[idx]))
+        rows.append(base + idx)
+        base += m.n_rays
+    return synth.Geometry(grid=geo.grid, maps=maps, label="sub"), np.concatenate(rows)
+
+
+def test_mixer_on_the_kerr_128_workload(gpu_lib):
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg2")
+    G = rtt.Geometry(geo)
+    F = geo.grid.n_frames
+    say("case mixer cfg2", G.n_rows)
+    rng = np.random.default_rng(87)
+    nvec = 2
+    y = rng.standard_normal((nvec, G.n_rows)).astype(np.float32)
+    yd = to_dev(y)
+    Y = y.reshape(nvec, geo.n_rays, F)
+    # unresolved: sampled pixels against the oracle run on their rays alone
+    Mu = rtt.Mixer(G, "unresolved", pixel_arrays([geo]))
+    du = rtt.mix_apply(Mu, yd).cpu().numpy().reshape(nvec, -1, F)
+    all_pix, counts = np.unique(np.concatenate([m.pixel for m in geo.maps]), return_counts=True)
+    assert du.shape[1] == all_pix.size
+    shared = all_pix[counts > 1]          # pixels that several orders land on
+    assert shared.size >= 32
+    sample = np.union1d(rng.choice(shared, 32, replace=False), rng.choice(all_pix[counts == 1], 32, replace=False))
+    sub, rows = sub_geometry(geo, sample)
+    ref = oracle.mix(sub, Y[:, rows, :].reshape(nvec, -1).astype(np.float64), "unresolved").reshape(nvec, -1, F)
+    got = du[:, np.searchsorted(all_pix, sample), :]
+    assert rel(got, ref) < TOL
+    # total flux in full
+    Mt = rtt.Mixer(G, "total_flux")
+    dt = rtt.mix_apply(Mt, yd).cpu().numpy()
+    reft = oracle.mix(geo, y.astype(np.float64), "total_flux")
+    for v in range(nvec):
+        assert rel(dt[v], reft[v]) < TOL, rel(dt[v], reft[v])
+    # adjoint identity <L y, d> = <y, L^T d> in FP64 on both mixers, and the covariance of a few pixels
+    for M, dm in ((Mu, du.reshape(nvec, -1)), (Mt, dt)):
+        dd = rng.standard_normal((nvec, M.n_rows)).astype(np.float32)
+        yt = rtt.mix_adjoint(M, to_dev(dd)).cpu().numpy().astype(np.float64)
+        lhs = np.sum(dm.astype(np.float64) * dd)
+        rhs = np.sum(y.astype(np.float64) * yt)
+        assert abs(lhs - rhs) <= TOL * np.linalg.norm(dm) * np.linalg.norm(dd)
+    var = rng.uniform(0.5, 2.0, G.n_rows).astype(np.float32)
+    cu = rtt.mix_covariance(Mu, to_dev(var)).cpu().numpy().reshape(-1, F)
+    few = sample[:6]
+    sub6, rows6 = sub_geometry(geo, few)
+    C = oracle.mix_covariance(sub6, var.reshape(-1, F)[rows6].reshape(-1).astype(np.float64), "unresolved")
+    assert rel(cu[np.searchsorted(all_pix, few)].reshape(-1), np.diag(C)) < TOL
