@@ -78,6 +78,45 @@ def time_pair(torch, rtt, G, X, Y, XT, reps=10):
     return e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
 
 
+def mixer_section(torch, rtt, oracle, geo, G, Y, reps=10):
+    """Order mixers of eq. (4) on the benchmark block Y = A X: the unresolved image (screen pixels)
+    and the total flux, forward and transpose, each timed over `reps` launches with HIP events.
+    Algorithmic bytes per launch: read the source rows and write the mixed rows (or the reverse),
+    4 * nvec * (n_src_rows + n_rows); the gather tables (8-32 B per ray) are left out."""
+    nvec = Y.shape[0]
+    pix = [np.asarray(m.pixel, dtype=np.int64) for m in geo.maps]
+    out = {}
+    for kind in ("unresolved", "total_flux"):
+        M = rtt.Mixer(G, kind, pix if kind == "unresolved" else None)
+        D = rtt.mix_apply(M, Y)
+        YT = rtt.mix_adjoint(M, D)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            rtt.mix_apply(M, Y, D)
+        e[1].record()
+        for _ in range(reps):
+            rtt.mix_adjoint(M, D, YT)
+        e[2].record()
+        torch.cuda.synchronize()
+        ms_f, ms_t = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+        b = 4 * nvec * (M.n_src_rows + M.n_rows)
+        out[kind] = {"mixed_rows": M.n_rows, "mix_apply": {"ms": ms_f, "GBps": b / (ms_f * 1e-3) / 1e9,
+                                                             "frac": b / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+                     "mix_adjoint": {"ms": ms_t, "GBps": b / (ms_t * 1e-3) / 1e9,
+                                     "frac": b / (ms_t * 1e-3) / 1e9 / HBM_PEAK_GBPS}, "bytes": b}
+        if kind == "total_flux":
+            ref = oracle.mix(geo, Y[0].double().cpu().numpy(), kind)
+            got = D[0].double().cpu().numpy()
+            out[kind]["parity_rel_err_vector0"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        log("mixer %s: apply %.3f ms (%.0f GB/s), adjoint %.3f ms (%.0f GB/s)" % (
+            kind, ms_f, out[kind]["mix_apply"]["GBps"], ms_t, out[kind]["mix_adjoint"]["GBps"]))
+        del D, YT, M
+        torch.cuda.empty_cache()
+    return out
+
+
 def calibrate(torch, dev, gib=2):
     """Streaming bandwidth of torch's plain copy and fill kernels on 2 GiB (HBM reference)."""
     n = gib * (1 << 30) // 4
@@ -281,6 +320,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-rsvd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-mixer", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -366,6 +406,8 @@ def main():
         par.setdefault("AT", []).append(float(np.linalg.norm(xa - xr) / np.linalg.norm(xr)))
     parity = {"A_max_rel_err": max(par["A"]), "AT_max_rel_err": max(par["AT"]), "vectors": [0, nvec - 1],
               "tol": 1e-5}
+
+    mixers = None if args.no_mixer else mixer_section(torch, rtt, oracle, geo, G, Y)
 
     # plain per-instance loop on the same GPU (one vector per call)
     plain = None
@@ -467,6 +509,7 @@ def main():
         "large_single_vector": large,
         "rsvd": rs,
         "batch": batch,
+        "mixers": mixers,
         "parity": parity,
         "cpu_baseline": cpu,
     }

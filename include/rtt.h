@@ -5,8 +5,9 @@
  * "Photon-Ring Retarded-Time Tomography" (Sec. 3.1, eq. (2)-(3); App. A.2,
  * eq. (47)) and its transpose on one GPU, and builds the spectral quantities
  * and estimators on top of it: randomized SVD / block Lanczos singular values
- * (Sec. 3.6 eq. (19), Sec. 4.4 eq. (31)) and the TSVD and ridge estimates of
- * Sec. 9.
+ * (Sec. 3.6 eq. (19), Sec. 4.4 eq. (31)), the TSVD and ridge estimates of
+ * Sec. 9, and the order mixers of Sec. 3.1 eq. (4) (unresolved image, total
+ * flux) with their covariance propagation.
  *
  * Discretisation.  A source history is a coefficient vector x[s][k] over
  * n_r x n_phi polar cells (s = i*n_phi + j; nodal bilinear basis on the cell
@@ -324,6 +325,17 @@ int mixer_info(const rtt_mixer* mixer, rtt_mixer_info* info);
  * the number of mixed rows (pixels, or 1 for the total flux).  Any output
  * pointer may be NULL.  Errors: RTT_EINVAL for a bad handle or index. */
 int mixer_member(const rtt_mixer* mixer, int32_t g, int64_t* row_offset, int64_t* n_rows, int64_t* n_out);
+
+/*
+ * mixer_set_variant -- pin how many vectors of a block one wave of mix_apply /
+ * mix_covariance (apply_vectors) or of mix_adjoint (adjoint_vectors) handles:
+ * 1, 2, 4 or 8; 0 = chosen per call (forward: 1 when mixed rows average 16 or
+ * more source rays, else 8; transpose: 4; either halved while the launch
+ * would have fewer than 32768 waves); -1 leaves a choice unchanged.  Every
+ * choice gives bitwise identical results.
+ * Errors: RTT_EINVAL for other values or a bad handle.
+ */
+int mixer_set_variant(rtt_mixer* mixer, int32_t apply_vectors, int32_t adjoint_vectors);
 
 /*
  * mix_apply -- d = (L kron I) y (eq. (4)).  y: device [nvec][n_src_rows]

@@ -23,7 +23,7 @@ RTT_EACH_GEOMETRY = -2
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
-            "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member",
+            "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
             "mix_apply", "mix_adjoint", "mix_covariance", "last_error")
 
 
@@ -128,6 +128,7 @@ def require_native():
         "mixer_free": [vp],
         "mixer_info": [vp, vp],
         "mixer_member": [vp, i32, vp, vp, vp],
+        "mixer_set_variant": [vp, i32, i32],
         "mix_apply": [vp, vp, vp, i32, vp],
         "mix_adjoint": [vp, vp, vp, i32, vp],
         "mix_covariance": [vp, vp, vp, vp],

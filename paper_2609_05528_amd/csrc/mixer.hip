@@ -27,6 +27,7 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int MIX_CHUNK = 64;     // source rays per chunk
 constexpr int MIX_WAVES = 4;      // waves per block
+constexpr int64_t MIX_MIN_WAVES = 32768;   // launch size below which fewer vectors go to a wave
 constexpr uint32_t MIX_MAGIC = 0x4D495852u;
 
 }  // namespace
@@ -47,6 +48,7 @@ struct rtt_mixer {
     int64_t* d_multi = nullptr;    // [n_multi][4]: mixed row offset, first entry of d_slots, slots, frames word
     int64_t* d_slots = nullptr;    // [n_slots]: element offset of each partial slot (slot * pitch)
     int64_t* d_src = nullptr;      // [n_src][4]: source row offset, mixed row offset, frames word, 0
+    int32_t vb_apply = 0, vb_adjoint = 0;   // pinned vectors per wave (0: chosen per call)
     int device = 0;
     mutable rtt::Workspace ws;
     uint32_t magic = rtt::MIX_MAGIC;
@@ -60,101 +62,192 @@ template <> struct Vec<1> { typedef float type; };
 template <> struct Vec<2> { typedef float type __attribute__((ext_vector_type(2))); };
 template <> struct Vec<4> { typedef float type __attribute__((ext_vector_type(4))); };
 
-// out[f] = sum over the cnt rows y + lst[i] (in list order) of row[f], f < F; lane l covers
-// frames l*VW .. l*VW+VW-1 of every 64*VW-frame pass (F and every offset multiples of VW)
-template <int VW>
-__device__ __forceinline__ void sum_rows(const float* __restrict__ y, const int64_t* __restrict__ lst, int64_t cnt,
-                                         int64_t F, float* __restrict__ out, int lane)
+// For nv <= VB vectors j (strides ys, os): out_j[f] = sum over the cnt rows y_j + lst[i], in list
+// order, of row[f], f < F.  Lane l covers frames l*VW .. l*VW+VW-1 of every 64*VW-frame pass (F
+// and every offset multiples of VW).  Rows are taken U at a time so that U * nv loads are in flight
+// before they are added (still in list order).  FULL: nv == VB, no per-vector tests.
+template <int VW, int VB, bool FULL>
+__device__ __forceinline__ void sum_rows(const float* __restrict__ y, int64_t ys, int nv,
+                                         const int64_t* __restrict__ lst, int64_t cnt, int64_t F,
+                                         float* __restrict__ out, int64_t os, int lane)
 {
     typedef typename Vec<VW>::type V;
+    constexpr int U = VB >= 16 ? 1 : 16 / VB;
     for (int64_t f = (int64_t)lane * VW; f < F; f += WAVE * VW) {
-        V acc = (V)(0.f);
-        for (int64_t i = 0; i < cnt; ++i) acc += *(const V*)(y + lst[i] + f);
-        *(V*)(out + f) = acc;
+        V acc[VB];
+#pragma unroll
+        for (int j = 0; j < VB; ++j) acc[j] = (V)(0.f);
+        int64_t i = 0;
+        for (; i + U <= cnt; i += U) {
+            V t[U][VB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float* row = y + lst[i + u] + f;
+#pragma unroll
+                for (int j = 0; j < VB; ++j)
+                    if (FULL || j < nv) t[u][j] = *(const V*)(row + j * ys);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < VB; ++j)
+                    if (FULL || j < nv) acc[j] += t[u][j];
+        }
+        for (; i < cnt; ++i) {
+            const float* row = y + lst[i] + f;
+#pragma unroll
+            for (int j = 0; j < VB; ++j)
+                if (FULL || j < nv) acc[j] += *(const V*)(row + j * ys);
+        }
+#pragma unroll
+        for (int j = 0; j < VB; ++j)
+            if (FULL || j < nv) *(V*)(out + j * os + f) = acc[j];
     }
 }
 
-// out[f] = in[f], f < F (VW as in sum_rows)
-template <int VW>
-__device__ __forceinline__ void copy_row(const float* __restrict__ in, int64_t F, float* __restrict__ out, int lane)
+// out_j[f] = in_j[f], f < F, for nv <= VB vectors (VW as in sum_rows)
+template <int VW, int VB, bool FULL>
+__device__ __forceinline__ void copy_row(const float* __restrict__ in, int64_t is, int nv, int64_t F,
+                                         float* __restrict__ out, int64_t os, int lane)
 {
     typedef typename Vec<VW>::type V;
-    for (int64_t f = (int64_t)lane * VW; f < F; f += WAVE * VW) *(V*)(out + f) = *(const V*)(in + f);
+    for (int64_t f = (int64_t)lane * VW; f < F; f += WAVE * VW) {
+        V t[VB];
+#pragma unroll
+        for (int j = 0; j < VB; ++j)
+            if (FULL || j < nv) t[j] = *(const V*)(in + j * is + f);
+#pragma unroll
+        for (int j = 0; j < VB; ++j)
+            if (FULL || j < nv) *(V*)(out + j * os + f) = t[j];
+    }
 }
 
-// one wave per (chunk, vector): the chunk's source rows added in list order, written to the
-// mixed row (single-chunk rows) or to the chunk's partial slot
+template <int VB>
+__device__ __forceinline__ void sum_rows_any(int vw, const float* y, int64_t ys, int nv, const int64_t* lst,
+                                             int64_t cnt, int64_t F, float* out, int64_t os, int lane)
+{
+    if (nv == VB) {
+        if (vw == 4)
+            sum_rows<4, VB, true>(y, ys, nv, lst, cnt, F, out, os, lane);
+        else if (vw == 2)
+            sum_rows<2, VB, true>(y, ys, nv, lst, cnt, F, out, os, lane);
+        else
+            sum_rows<1, VB, true>(y, ys, nv, lst, cnt, F, out, os, lane);
+    } else {
+        if (vw == 4)
+            sum_rows<4, VB, false>(y, ys, nv, lst, cnt, F, out, os, lane);
+        else if (vw == 2)
+            sum_rows<2, VB, false>(y, ys, nv, lst, cnt, F, out, os, lane);
+        else
+            sum_rows<1, VB, false>(y, ys, nv, lst, cnt, F, out, os, lane);
+    }
+}
+
+template <int VB>
+__device__ __forceinline__ void copy_row_any(int vw, const float* in, int64_t is, int nv, int64_t F, float* out,
+                                             int64_t os, int lane)
+{
+    if (nv == VB) {
+        if (vw == 4)
+            copy_row<4, VB, true>(in, is, nv, F, out, os, lane);
+        else if (vw == 2)
+            copy_row<2, VB, true>(in, is, nv, F, out, os, lane);
+        else
+            copy_row<1, VB, true>(in, is, nv, F, out, os, lane);
+    } else {
+        if (vw == 4)
+            copy_row<4, VB, false>(in, is, nv, F, out, os, lane);
+        else if (vw == 2)
+            copy_row<2, VB, false>(in, is, nv, F, out, os, lane);
+        else
+            copy_row<1, VB, false>(in, is, nv, F, out, os, lane);
+    }
+}
+
+// one wave per (chunk, group of VB vectors): the chunk's source rows added in list order, written
+// to the mixed row (single-chunk rows) or to the chunk's partial slot
+template <int VB>
 __global__ __launch_bounds__(MIX_WAVES * WAVE) void k_mix_chunks(const int64_t* __restrict__ chunk,
                                                                    const int64_t* __restrict__ list, int64_t n_chunks,
                                                                    const float* __restrict__ y, int64_t y_stride,
                                                                    float* __restrict__ d, int64_t d_stride,
                                                                    float* __restrict__ part, int64_t part_stride,
-                                                                   int64_t pitch, int vmax)
+                                                                   int64_t pitch, int nvec, int vmax)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t c = (int64_t)blockIdx.x * MIX_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (c >= n_chunks) return;
-    const int64_t v = blockIdx.y;
+    const int64_t v0 = (int64_t)blockIdx.y * VB;
+    const int nv = min(VB, nvec - (int)v0);
     const int64_t* ch = chunk + 4 * c;
     const int64_t first = ch[0], cnt = ch[1], target = ch[2];
     const int64_t F = ch[3] & 0xffffffffll;
     const int vw = min((int)(ch[3] >> 32), vmax);
-    const float* yv = y + v * y_stride;
-    float* out = target >= 0 ? d + v * d_stride + target : part + v * part_stride + (-1 - target) * pitch;
-    if (vw == 4)
-        sum_rows<4>(yv, list + first, cnt, F, out, lane);
-    else if (vw == 2)
-        sum_rows<2>(yv, list + first, cnt, F, out, lane);
-    else
-        sum_rows<1>(yv, list + first, cnt, F, out, lane);
+    const float* yv = y + v0 * y_stride;
+    float* out;
+    int64_t os;
+    if (target >= 0) {
+        out = d + v0 * d_stride + target;
+        os = d_stride;
+    } else {
+        out = part + v0 * part_stride + (-1 - target) * pitch;
+        os = part_stride;
+    }
+    sum_rows_any<VB>(vw, yv, y_stride, nv, list + first, cnt, F, out, os, lane);
 }
 
-// one wave per (multi-chunk row, vector): the row = its partial rows added in chunk order
+// one wave per (multi-chunk row, group of VB vectors): the row = its partial rows added in
+// chunk order
+template <int VB>
 __global__ __launch_bounds__(MIX_WAVES * WAVE) void k_mix_partials(const int64_t* __restrict__ multi,
                                                                      const int64_t* __restrict__ slots_off,
                                                                      int64_t n_multi, const float* __restrict__ part,
                                                                      int64_t part_stride, float* __restrict__ d,
-                                                                     int64_t d_stride, int vmax)
+                                                                     int64_t d_stride, int nvec, int vmax)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t r = (int64_t)blockIdx.x * MIX_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (r >= n_multi) return;
-    const int64_t v = blockIdx.y;
+    const int64_t v0 = (int64_t)blockIdx.y * VB;
+    const int nv = min(VB, nvec - (int)v0);
     const int64_t* m = multi + 4 * r;
     const int64_t off = m[0], first = m[1], slots = m[2];
     const int64_t F = m[3] & 0xffffffffll;
     const int vw = min((int)(m[3] >> 32), vmax);
-    const float* p = part + v * part_stride;
-    float* out = d + v * d_stride + off;
-    if (vw == 4)
-        sum_rows<4>(p, slots_off + first, slots, F, out, lane);
-    else if (vw == 2)
-        sum_rows<2>(p, slots_off + first, slots, F, out, lane);
-    else
-        sum_rows<1>(p, slots_off + first, slots, F, out, lane);
+    const float* p = part + v0 * part_stride;
+    float* out = d + v0 * d_stride + off;
+    sum_rows_any<VB>(vw, p, part_stride, nv, slots_off + first, slots, F, out, d_stride, lane);
 }
 
-// one wave per (source ray, vector): the ray's rows receive the mixed row it feeds
+// one wave per (source ray, group of VB vectors): the ray's rows receive the mixed row it feeds
+template <int VB>
 __global__ __launch_bounds__(MIX_WAVES * WAVE) void k_mix_transpose(const int64_t* __restrict__ src, int64_t n_src,
                                                                       const float* __restrict__ d, int64_t d_stride,
-                                                                      float* __restrict__ y, int64_t y_stride, int vmax)
+                                                                      float* __restrict__ y, int64_t y_stride,
+                                                                      int nvec, int vmax)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t r = (int64_t)blockIdx.x * MIX_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (r >= n_src) return;
-    const int64_t v = blockIdx.y;
+    const int64_t v0 = (int64_t)blockIdx.y * VB;
+    const int nv = min(VB, nvec - (int)v0);
     const int64_t* e = src + 4 * r;
     const int64_t so = e[0], mo = e[1];
     const int64_t F = e[2] & 0xffffffffll;
     const int vw = min((int)(e[2] >> 32), vmax);
-    const float* in = d + v * d_stride + mo;
-    float* out = y + v * y_stride + so;
-    if (vw == 4)
-        copy_row<4>(in, F, out, lane);
-    else if (vw == 2)
-        copy_row<2>(in, F, out, lane);
-    else
-        copy_row<1>(in, F, out, lane);
+    const float* in = d + v0 * d_stride + mo;
+    float* out = y + v0 * y_stride + so;
+    copy_row_any<VB>(vw, in, d_stride, nv, F, out, y_stride, lane);
+}
+
+// vectors per wave (1, 2, 4 or 8): the pinned choice, else `pref`, halved while the launch would
+// have fewer than MIX_MIN_WAVES waves for `tasks` tasks
+int pick_vb(int pinned, int pref, int64_t tasks, int nvec)
+{
+    if (pinned) return pinned;
+    int vb = pref;
+    while (vb > 1 && tasks * ((nvec + vb - 1) / vb) < MIX_MIN_WAVES) vb /= 2;
+    return vb;
 }
 
 // widest vector (4, 2 or 1 floats) that every address of a call keeps aligned
@@ -189,13 +282,28 @@ int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, 
     }
     const int vmax = call_vmax(y, d, y_stride, d_stride);
     const dim3 blk(MIX_WAVES * WAVE);
-    hipLaunchKernelGGL(k_mix_chunks, dim3((unsigned)((m->n_chunks + MIX_WAVES - 1) / MIX_WAVES), (unsigned)nvec), blk,
-                       0, s, m->d_chunk, m->d_list, m->n_chunks, y, y_stride, d, d_stride, part, part_stride, m->pitch,
-                       vmax);
-    if (m->n_multi > 0)
-        hipLaunchKernelGGL(k_mix_partials, dim3((unsigned)((m->n_multi + MIX_WAVES - 1) / MIX_WAVES), (unsigned)nvec),
-                           blk, 0, s, m->d_multi, m->d_slots, m->n_multi, part, part_stride, d, d_stride,
-                           std::min(vmax, call_vmax(part, d, part_stride, d_stride)));
+    // short source lists (the unresolved image: one to a few rays per pixel): 8 vectors a wave so
+    // that enough loads are in flight; long lists already keep 16 rows in flight with one vector
+    const int vb = pick_vb(m->vb_apply, m->n_src >= 16 * m->n_chunks ? 1 : 8, m->n_chunks, nvec);
+    const unsigned groups = (unsigned)((nvec + vb - 1) / vb);
+    const dim3 gc((unsigned)((m->n_chunks + MIX_WAVES - 1) / MIX_WAVES), groups);
+    const dim3 gp((unsigned)((m->n_multi + MIX_WAVES - 1) / MIX_WAVES), groups);
+    const int vmax_p = std::min(vmax, call_vmax(part, d, part_stride, d_stride));
+#define RTT_MIX_FWD(VB)                                                                                          \
+    do {                                                                                                         \
+        hipLaunchKernelGGL(k_mix_chunks<VB>, gc, blk, 0, s, m->d_chunk, m->d_list, m->n_chunks, y, y_stride, d,  \
+                           d_stride, part, part_stride, m->pitch, nvec, vmax);                                  \
+        if (m->n_multi > 0)                                                                                      \
+            hipLaunchKernelGGL(k_mix_partials<VB>, gp, blk, 0, s, m->d_multi, m->d_slots, m->n_multi, part,      \
+                               part_stride, d, d_stride, nvec, vmax_p);                                          \
+    } while (0)
+    switch (vb) {
+    case 8: RTT_MIX_FWD(8); break;
+    case 4: RTT_MIX_FWD(4); break;
+    case 2: RTT_MIX_FWD(2); break;
+    default: RTT_MIX_FWD(1); break;
+    }
+#undef RTT_MIX_FWD
     RTT_HIP(hipGetLastError());
     return RTT_OK;
 }
@@ -359,6 +467,16 @@ extern "C" int mixer_member(const rtt_mixer* m, int32_t gi, int64_t* row_offset,
     return RTT_OK;
 }
 
+extern "C" int mixer_set_variant(rtt_mixer* m, int32_t apply_vectors, int32_t adjoint_vectors)
+{
+    if (!valid_mixer(m)) return fail(RTT_EINVAL, "invalid mixer handle");
+    auto ok = [](int32_t v) { return v == -1 || v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
+    if (!ok(apply_vectors) || !ok(adjoint_vectors)) return fail(RTT_EINVAL, "vectors per wave must be 0, 1, 2, 4 or 8");
+    if (apply_vectors >= 0) m->vb_apply = apply_vectors;
+    if (adjoint_vectors >= 0) m->vb_adjoint = adjoint_vectors;
+    return RTT_OK;
+}
+
 extern "C" int mix_apply(const rtt_mixer* m, const float* y, float* d, int32_t nvec, void* stream)
 {
     int rc = check_mix_call(m, y, d, nvec);
@@ -372,9 +490,20 @@ extern "C" int mix_adjoint(const rtt_mixer* m, const float* d, float* y, int32_t
     if (rc) return rc;
     if (nvec == 0 || m->n_src == 0) return RTT_OK;
     RTT_HIP(hipSetDevice(m->device));
-    hipLaunchKernelGGL(k_mix_transpose, dim3((unsigned)((m->n_src + MIX_WAVES - 1) / MIX_WAVES), (unsigned)nvec),
-                       dim3(MIX_WAVES * WAVE), 0, (hipStream_t)stream, m->d_src, m->n_src, d, m->n_rows, y,
-                       m->n_src_rows, call_vmax(d, y, m->n_rows, m->n_src_rows));
+    const int vb = pick_vb(m->vb_adjoint, 4, m->n_src, nvec);
+    const dim3 grid((unsigned)((m->n_src + MIX_WAVES - 1) / MIX_WAVES), (unsigned)((nvec + vb - 1) / vb));
+    const int vmax = call_vmax(d, y, m->n_rows, m->n_src_rows);
+    hipStream_t s = (hipStream_t)stream;
+#define RTT_MIX_ADJ(VB)                                                                                         \
+    hipLaunchKernelGGL(k_mix_transpose<VB>, grid, dim3(MIX_WAVES * WAVE), 0, s, m->d_src, m->n_src, d, m->n_rows, y, \
+                       m->n_src_rows, nvec, vmax)
+    switch (vb) {
+    case 8: RTT_MIX_ADJ(8); break;
+    case 4: RTT_MIX_ADJ(4); break;
+    case 2: RTT_MIX_ADJ(2); break;
+    default: RTT_MIX_ADJ(1); break;
+    }
+#undef RTT_MIX_ADJ
     RTT_HIP(hipGetLastError());
     return RTT_OK;
 }

@@ -60,6 +60,10 @@ class Mixer:
             _check(lib.mixer_member(h, gi, ctypes.byref(off), ctypes.byref(n), ctypes.byref(n_out)))
             self.members.append(dict(row_offset=off.value, n_rows=n.value, n_out=n_out.value))
 
+    def set_variant(self, apply=-1, adjoint=-1):
+        """Pin vectors per wave (1, 2, 4, 8; 0 = automatic) of the forward and transposed kernels."""
+        _check(require_native().mixer_set_variant(self.handle, apply, adjoint))
+
     @property
     def handle(self):
         if self._h is None:

@@ -120,6 +120,17 @@ def test_mixer_sums_are_bitwise_reproducible_and_width_independent(gpu_lib):
         out2 = torch.empty(3 * G.n_rows + 1, device=y.device)
         rtt.mix_adjoint(M, dt, out2[1:].view(3, G.n_rows))
         assert torch.equal(out2[1:].view(3, G.n_rows), t)
+        # every vectors-per-wave choice, on a ragged block of 11 vectors
+        y11 = to_dev(np.random.default_rng(88).standard_normal((11, G.n_rows)))
+        d11 = torch.randn(11, M.n_rows, device=y.device)
+        M.set_variant(1, 1)
+        a1, t1 = rtt.mix_apply(M, y11), rtt.mix_adjoint(M, d11)
+        for vb in (2, 4, 8, 0):
+            M.set_variant(vb, vb)
+            assert torch.equal(rtt.mix_apply(M, y11), a1), vb
+            assert torch.equal(rtt.mix_adjoint(M, d11), t1), vb
+    with pytest.raises(rtt.RttError):
+        M.set_variant(3, 0)
 
 
 def test_mixer_rejects_bad_input(gpu_lib):
