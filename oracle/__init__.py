@@ -19,6 +19,10 @@ with the GPU library.
 * ``mixer_matrix``, ``mix``, ``mix_adjoint``, ``mix_covariance``: the order mixer
   L of Sec. 3.1 eq. (4) (unresolved image and total flux) and the propagation of
   the data covariance through it, written out as dense matrices.
+* ``probe_norm``, ``age_probes``, ``age_energy``, ``supported_ages``,
+  ``throughput_age_boundary``, ``reach``: the age-localised probes of Sec. 3.3
+  eq. (10)-(13), age information eq. (12)/(29) per observation arm, and the
+  threshold statistics T_reach, L_anchor (eq. (30)) and J_old (eq. (35)).
 
 Every function here is pinned by the "not gpu" tests against facts that do
 not come from this module (see the tests' docstrings).
@@ -343,3 +347,119 @@ def mix_covariance(geom, var, kind):
     L, _ = mixer_matrix(geom, kind)
     K = np.kron(L, np.eye(geom.grid.n_frames))
     return K @ np.diag(np.asarray(var, dtype=np.float64)) @ K.T
+
+
+# ------------------------------------------------------------------ age probes and reach (Sec. 3.3, Sec. 4.4, Sec. 6.5)
+def probe_norm(grid, h=3.0):
+    """N_h of eq. (11): the L2 norm of the unnormalised probe over the emission annulus
+    (area measure r dr dphi) and over all source times."""
+    return math.sqrt(math.pi * (grid.r_out ** 2 - grid.r_in ** 2) * h * math.sqrt(math.pi))
+
+
+def age_probes(grid, ages, h=3.0):
+    """The age-localised probes q_a of eq. (10) on the coefficient nodes: every cell node lies in the
+    annulus (indicator 1, no azimuthal modulation) and hat k takes the probe's value at its centre
+    s_k.  Returns [len(ages), n_cols] (hat index fastest)."""
+    ages = np.asarray(ages, dtype=np.float64)
+    s_k = grid.s0 + grid.dt_src * np.arange(grid.n_hat)
+    X = np.empty((ages.size, grid.n_cells, grid.n_hat))
+    for i, a in enumerate(ages):
+        X[i, :, :] = np.exp(-((s_k + a) ** 2) / (2.0 * h * h)) / probe_norm(grid, h)
+    return X.reshape(ages.size, grid.n_cols)
+
+
+def age_energy(geom, ages, h=3.0, arm="resolved", var=None):
+    """||C^{-1/2} A q_a||^2 of eq. (12)/(29) for every age, at sigma_Omega = 1.
+
+    arm: "direct" (order-0 rows, C = I), "resolved" (every order, C = I), or a mixer kind of eq. (4)
+    ("unresolved", "total_flux") whose covariance C_L = (L kron I) diag(var) (L^T kron I) is formed in
+    full and solved against (var: per-datum variances of the resolved rows, default 1)."""
+    X = age_probes(geom.grid, ages, h)
+    if arm in ("direct", "resolved"):
+        mask = 1 if arm == "direct" else None
+        Y = forward(geom, X, order_mask=mask)
+        return np.einsum("ar,ar->a", Y, Y)
+    Y = forward(geom, X)
+    v = np.ones(Y.shape[1]) if var is None else np.asarray(var, dtype=np.float64)
+    D = mix(geom, Y, arm)
+    C = mix_covariance(geom, v, arm)
+    return np.array([float(d @ np.linalg.solve(C, d)) for d in D])
+
+
+def supported_ages(geom, ages, h=3.0, order_mask=None):
+    """Centres whose operational support |t + a| <= 3h lies inside the source-time window that the
+    selected orders reach (eq. (13)), found by brute force over every datum's retarded time
+    t_f - Delta of the rays with chi = 1 (non-zero weight, radius inside the annulus)."""
+    g = geom.grid
+    t_f = g.t0 + g.dt_obs * np.arange(g.n_frames)
+    lo, hi = math.inf, -math.inf
+    for n, m in enumerate(geom.maps):
+        if order_mask is not None and not (int(order_mask) >> n) & 1:
+            continue
+        for p in range(m.n_rays):
+            if m.weight[p] == 0.0 or not (g.r_in <= m.r[p] <= g.r_out):
+                continue
+            t = t_f - m.delay[p]
+            lo, hi = min(lo, float(t.min())), max(hi, float(t.max()))
+    ages = np.asarray(ages, dtype=np.float64)
+    return np.array([lo <= -a - 3.0 * h and -a + 3.0 * h <= hi for a in ages], dtype=bool)
+
+
+def throughput_age_boundary(geom, q=0.999):
+    """A_{0,q} of eq. (35): the age below which the fraction q of the direct order's throughput lies,
+    every direct datum (ray p, frame f) carrying the age Delta_p - t_f and the weight |w_p|."""
+    g = geom.grid
+    m = geom.maps[0]
+    t_f = g.t0 + g.dt_obs * np.arange(g.n_frames)
+    age = (m.delay[:, None] - t_f[None, :]).ravel()
+    w = np.repeat(np.abs(m.weight), g.n_frames)
+    order = np.argsort(age, kind="stable")
+    cum = np.cumsum(w[order])
+    return float(age[order][np.searchsorted(cum, q * cum[-1])])
+
+
+def reach(ages, info, rho=1.0, supported=None, boundary=None):
+    """Threshold statistics of Sec. 4.4 on an age grid, from the physical information info(a)
+    (SNR0^2 times the normalised information).
+
+    mask: info >= rho^2 (eq. (30)); t_reach: the oldest passing centre (None if none passes);
+    anchor: the youngest supported centre; l_anchor: extent of the passing run that starts at the
+    anchor (None if the anchor fails); longest: extent of the longest passing run; j_old: eq. (35),
+    the sum of log(1 + info) over centres older than `boundary`, times the grid step."""
+    ages = [float(a) for a in ages]
+    info = [float(v) for v in info]
+    n = len(ages)
+    mask = [v >= rho * rho for v in info]
+    passing = [ages[i] for i in range(n) if mask[i]]
+    t_reach = max(passing) if passing else None
+    anchor = None
+    for i in range(n):
+        if supported is None or supported[i]:
+            anchor = i
+            break
+    l_anchor = None
+    if anchor is not None and mask[anchor]:
+        j = anchor
+        while j + 1 < n and mask[j + 1]:
+            j += 1
+        l_anchor = ages[j] - ages[anchor]
+    longest = None
+    i = 0
+    while i < n:
+        if mask[i]:
+            j = i
+            while j + 1 < n and mask[j + 1]:
+                j += 1
+            ext = ages[j] - ages[i]
+            longest = ext if longest is None or ext > longest else longest
+            i = j + 1
+        else:
+            i += 1
+    step = ages[1] - ages[0] if n > 1 else 0.0
+    j_old = None
+    if boundary is not None:
+        j_old = 0.0
+        for i in range(n):
+            if ages[i] > boundary:
+                j_old += math.log(1.0 + info[i]) * step
+    return dict(mask=mask, t_reach=t_reach, anchor=anchor, l_anchor=l_anchor, longest=longest, j_old=j_old)

@@ -14,7 +14,9 @@
   range, TSVD to the truncated pseudo-inverse, ridge CG to a dense solve;
 * the ridge gradient against central finite differences of the objective.
 """
+import dataclasses
 import math
+import os
 
 import numpy as np
 import pytest
@@ -422,3 +424,112 @@ def test_unresolved_echo_train_inverts_with_the_echo_recursion():
     rhs = y0[:, f] - a ** 3 * y0[:, f - 3 * m]
     assert np.max(np.abs(lhs - rhs)) <= 1e-11 * np.max(np.abs(y0))
     assert np.max(np.abs(rhs)) > 0.1 * np.max(np.abs(y0))
+
+
+# ----------------------------------------------------------------------------- age probes (Sec. 3.3, 4.4)
+def test_age_probe_has_unit_norm_over_the_annulus():
+    """eq. (10)-(11): the continuum probe has unit L2 norm under the area measure r dr dphi dt,
+    checked by numerical quadrature of the separable integrand (not by the closed form)."""
+    from scipy.integrate import quad
+    g = tiny_geometry(seed=1).grid
+    for h in (3.0, 1.7):
+        n2 = oracle.probe_norm(g, h) ** 2
+        radial = quad(lambda r: r, g.r_in, g.r_out)[0] * 2.0 * math.pi
+        for a in (0.0, 37.0):
+            temporal = quad(lambda t: math.exp(-((t + a) ** 2) / (h * h)), -a - 40 * h, -a + 40 * h)[0]
+            assert abs(radial * temporal / n2 - 1.0) < 1e-10
+
+
+def test_age_probe_response_is_the_linear_interpolant_of_the_gaussian():
+    """A flat probe on the nodes: the bilinear weights of a ray add to 1, so the datum is w times the
+    piecewise-linear interpolant (numpy.interp) of the probe's values at the hat centres."""
+    geo = tiny_geometry(seed=5, rays=(9, 4))
+    g = geo.grid
+    ages = np.array([0.0, 8.0, 20.0])
+    h = 3.0
+    Y = oracle.forward(geo, oracle.age_probes(g, ages, h))
+    s_k = g.s0 + g.dt_src * np.arange(g.n_hat)
+    t_f = g.t0 + g.dt_obs * np.arange(g.n_frames)
+    nh = oracle.probe_norm(g, h)
+    row = 0
+    for m in geo.maps:
+        for p in range(m.n_rays):
+            for i, a in enumerate(ages):
+                node = np.exp(-((s_k + a) ** 2) / (2 * h * h)) / nh
+                want = m.weight[p] * np.interp(t_f - m.delay[p], s_k, node, left=0.0, right=0.0)
+                assert np.allclose(Y[i, row * g.n_frames:(row + 1) * g.n_frames], want, rtol=1e-12, atol=1e-15)
+            row += 1
+
+
+def test_age_energy_orders_the_arms_and_a_one_ray_per_pixel_collapse_loses_nothing():
+    """Collapsing whitened data never adds information: total flux <= unresolved <= resolved and
+    direct <= resolved; a mixer that sends every ray to its own pixel is a permutation and keeps all."""
+    geo = tiny_geometry(seed=9, rays=(14, 8, 5), n_frames=5)
+    ages = np.arange(0.0, 40.0, 8.0)
+    res = oracle.age_energy(geo, ages, arm="resolved")
+    dire = oracle.age_energy(geo, ages, arm="direct")
+    unr = oracle.age_energy(geo, ages, arm="unresolved")
+    tot = oracle.age_energy(geo, ages, arm="total_flux")
+    assert np.all(res > 0)
+    assert np.all(dire <= res * (1 + 1e-12)) and np.all(unr <= res * (1 + 1e-12))
+    assert np.all(tot <= unr * (1 + 1e-12))
+    base = 0
+    pix = []
+    for m in geo.maps:
+        pix.append(np.arange(base, base + m.n_rays))
+        base += m.n_rays
+    own = synth.Geometry(grid=geo.grid, maps=[dataclasses.replace(m, pixel=p) for m, p in zip(geo.maps, pix)])
+    assert np.allclose(oracle.age_energy(own, ages, arm="unresolved"), res, rtol=1e-12)
+    # per-datum variances scale the information down: var = 4 everywhere quarters it
+    var = np.full(geo.n_rows, 4.0)
+    assert np.allclose(oracle.age_energy(geo, ages, arm="unresolved", var=var), unr / 4.0, rtol=1e-12)
+
+
+def test_supported_ages_match_the_footprint_of_eq_13():
+    """Brute force over every datum agrees with the footprint [t_min - Delta_max, t_max - Delta_min]."""
+    geo = tiny_geometry(seed=13, rays=(7, 5, 4), n_frames=20, delay_hi=30.0)
+    g = geo.grid
+    ages = np.arange(0.0, 120.0, 4.0)
+    t_lo, t_hi = g.t0, g.t0 + g.dt_obs * (g.n_frames - 1)
+    for mask in (1, 7):
+        d = np.concatenate([m.delay for n, m in enumerate(geo.maps) if (mask >> n) & 1])
+        lo, hi = t_lo - d.max(), t_hi - d.min()
+        want = (-ages - 9.0 >= lo) & (-ages + 9.0 <= hi)
+        assert np.array_equal(oracle.supported_ages(geo, ages, 3.0, order_mask=mask), want)
+        assert want.any() and not want.all()
+
+
+def test_throughput_age_boundary_hand_example():
+    """Two direct rays (weights 1 and -3, delays 10 and 20) seen at t = 0 and 4: ages 10, 6, 20, 16
+    with weights 1, 1, 3, 3; cumulative 1, 2, 5, 8 in age order."""
+    grid = synth.Grid(n_orders=1, n_frames=2, t0=0.0, dt_obs=4.0, n_r=2, n_phi=2, r_in=6.0, r_out=20.0,
+                      n_hat=4, s0=-30.0, dt_src=4.0)
+    m = synth.RayMap(r=np.array([8.0, 9.0]), phi=np.array([0.1, 0.2]), delay=np.array([10.0, 20.0]),
+                     weight=np.array([1.0, -3.0]))
+    geo = synth.Geometry(grid=grid, maps=[m])
+    assert oracle.throughput_age_boundary(geo, 0.999) == 20.0
+    assert oracle.throughput_age_boundary(geo, 0.5) == 16.0
+    assert oracle.throughput_age_boundary(geo, 0.2) == 10.0
+    assert oracle.throughput_age_boundary(geo, 0.1) == 6.0
+
+
+def test_reach_statistics_hand_example():
+    rows, expect = [], None
+    with open(os.path.join(os.path.dirname(__file__), "golden", "age_reach_example.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if not line:
+                continue
+            if line[0] == "expect":
+                expect = [float(v) for v in line[1:]]
+            else:
+                rows.append([float(v) for v in line])
+    ages, info, sup = zip(*rows)
+    rho, boundary, t_reach, anchor, l_anchor, longest, j_old = expect
+    r = oracle.reach(ages, info, rho=rho, supported=[bool(s) for s in sup], boundary=boundary)
+    assert r["t_reach"] == t_reach and r["anchor"] == int(anchor)
+    assert r["l_anchor"] == l_anchor and r["longest"] == longest
+    assert abs(r["j_old"] - j_old) < 1e-12
+    # no supported centre passing: no anchor-connected span
+    r2 = oracle.reach(ages, info, rho=rho, supported=[i == 3 for i in range(len(ages))], boundary=boundary)
+    assert r2["anchor"] == 3 and r2["l_anchor"] is None
