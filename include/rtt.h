@@ -364,6 +364,74 @@ int mix_adjoint(const rtt_mixer* mixer, const float* d, float* y, int32_t nvec, 
  */
 int mix_covariance(const rtt_mixer* mixer, const float* var, float* var_out, void* stream);
 
+/* ------------------------------------------------------- age information */
+/*
+ * reference_response -- s_ref of Sec. 3.5 eq. (17) for every geometry g of
+ * the handle: sqrt(||A_{g,0} j_ref||^2 / m_0) with the constant reference
+ * emissivity j_ref = 1 on every coefficient (the bilinear cells and the hats
+ * both reproduce constants) and m_0 the direct-order rows of g.  The noise
+ * density of a sweep point is sigma_Omega = s_ref / SNR0 (eq. (18)).
+ * s_ref: host double[G].  Blocking.  Errors: RTT_EINVAL, RTT_ENOMEM,
+ * RTT_EDEVICE.
+ */
+int reference_response(const rtt_geometry* geom, double* s_ref, void* stream);
+
+/*
+ * age_information -- the squared responses of eq. (12) / (29) to the
+ * age-localised probes of Sec. 3.3 eq. (10)-(11): for every age a the probe
+ * q_a, flat over the annulus and exp(-(t + a)^2 / (2 h^2)) / N_h in source
+ * time, N_h^2 = pi (r_out^2 - r_in^2) h sqrt(pi), is set on the coefficient
+ * nodes (every cell, hat k at s_k) and A is applied to it.
+ * mixer == NULL: energy (host double [n_ages][G][8]) receives ||A_{g,n} q_a||^2
+ * for every geometry g and order n (0 for n >= n_orders): the direct arm is
+ * n = 0, the resolved stack the sum over n.  mixer != NULL (built on this
+ * geometry): energy (host double [n_ages][G]) receives
+ * ||C_L^{-1/2} (L kron I) A_g q_a||^2 with C_L = diag((L kron I) var), the
+ * covariance of eq. (4) propagated from per-datum variances var (device FP32
+ * [n_rows]; NULL = 1, i.e. whitened rows).  Rows are as loaded (whitened by
+ * eq. (16) when pixel areas were given).  Multiply by SNR0^2 / s_ref^2 for the
+ * information at a sweep point.  ages: host double[n_ages]; h > 0 (the paper
+ * uses 3M).  Blocking; scratch of at most about 1 GiB is allocated per call.
+ * Errors: RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE.
+ */
+int age_information(const rtt_geometry* geom, const double* ages, int32_t n_ages, double h,
+                    const rtt_mixer* mixer, const float* var, double* energy, void* stream);
+
+/*
+ * age_window -- for geometry g and the orders in order_mask (0 = all):
+ * [*a_min, *a_max], the ages whose probe support |t + a| <= 3h lies inside
+ * the source-time window that those orders reach (eq. (13)); a_min > a_max
+ * when none does.  boundary (nullable): A_{0,q} of eq. (35), the smallest age
+ * of a direct datum (ray p, frame f: age Delta_p - t_f) such that the data of
+ * that age or younger carry the fraction q of the direct throughput, every
+ * datum weighted by |w_p| as loaded; NaN without direct rays.  Host only
+ * (tables kept at load).  Errors: RTT_EINVAL (bad handle, index, h, q).
+ */
+int age_window(const rtt_geometry* geom, int32_t g, uint32_t order_mask, double h, double q,
+               double* a_min, double* a_max, double* boundary);
+
+typedef struct {
+    double t_reach;     /* oldest passing age (eq. (30)); NaN if none passes        */
+    double l_anchor;    /* extent of the passing run that starts at the anchor;   */
+                        /* NaN if there is no anchor or it does not pass          */
+    double longest;     /* extent of the longest passing run; NaN if none          */
+    double j_old;       /* eq. (35): sum over ages > boundary of log(1 + info)     */
+                        /* times the grid step; NaN if boundary is NaN            */
+    int32_t anchor;     /* index of the youngest age in [a_min, a_max]; -1: none  */
+    int32_t n_pass;     /* passing ages                                          */
+} rtt_reach;
+
+/*
+ * age_reach -- threshold statistics of Sec. 4.4 on an age grid (ascending,
+ * equally spaced ages[n]) from the information info[n] at one sweep point
+ * (SNR0^2 / s_ref^2 times age_information's energy): an age passes when
+ * info >= rho^2 (eq. (30)); the anchor is the youngest age inside
+ * [a_min, a_max] (age_window).  mask (nullable): n bytes, 1 = passes.  Host
+ * only.  Errors: RTT_EINVAL.
+ */
+int age_reach(const double* ages, const double* info, int32_t n, double rho, double a_min, double a_max,
+              double boundary, uint8_t* mask, rtt_reach* out);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);
 

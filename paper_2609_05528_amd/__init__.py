@@ -24,7 +24,8 @@ RTT_EACH_GEOMETRY = -2
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
             "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
-            "mix_apply", "mix_adjoint", "mix_covariance", "last_error")
+            "mix_apply", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
+            "age_reach", "last_error")
 
 
 class RttError(RuntimeError):
@@ -132,6 +133,11 @@ def require_native():
         "mix_apply": [vp, vp, vp, i32, vp],
         "mix_adjoint": [vp, vp, vp, i32, vp],
         "mix_covariance": [vp, vp, vp, vp],
+        "reference_response": [vp, _dp, vp],
+        "age_information": [vp, _dp, i32, ctypes.c_double, vp, vp, _dp, vp],
+        "age_window": [vp, i32, u32, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp],
+        "age_reach": [_dp, _dp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                      ctypes.POINTER(ctypes.c_uint8), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -318,3 +324,4 @@ def op_apply_adjoint(geom: Geometry, y, x=None, order_mask: int = 0, stream=None
 from .svd import SVD, rsvd, tsvd_solve, ridge_solve  # noqa: E402,F401
 from .autograd import RetardedTimeOp, retarded_time_apply  # noqa: E402,F401
 from .mixer import Mixer, mixer_create, mix_apply, mix_adjoint, mix_covariance  # noqa: E402,F401
+from .age import reference_response, age_information, age_window, age_reach  # noqa: E402,F401

@@ -269,6 +269,17 @@ int check_mix_call(const rtt_mixer* m, const void* a, const void* b, int32_t nve
     return RTT_OK;
 }
 
+void release(rtt_mixer* m)
+{
+    for (int64_t** p : {&m->d_chunk, &m->d_list, &m->d_multi, &m->d_slots, &m->d_src})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+}
+
+}  // namespace
+
 int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, int64_t d_stride, int nvec,
                 hipStream_t s)
 {
@@ -308,16 +319,15 @@ int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, 
     return RTT_OK;
 }
 
-void release(rtt_mixer* m)
+bool mixer_ok(const rtt_mixer* m) { return valid_mixer(m); }
+int64_t mixer_rows(const rtt_mixer* m) { return m->n_rows; }
+int64_t mixer_src_rows(const rtt_mixer* m) { return m->n_src_rows; }
+
+void mixer_segments(const rtt_mixer* m, std::vector<int64_t>& seg)
 {
-    for (int64_t** p : {&m->d_chunk, &m->d_list, &m->d_multi, &m->d_slots, &m->d_src})
-        if (*p) {
-            (void)hipFree(*p);
-            *p = nullptr;
-        }
+    for (size_t g = 0; g < m->g_off.size(); ++g) seg.insert(seg.end(), {m->g_off[g], m->g_rows[g]});
 }
 
-}  // namespace
 }  // namespace rtt
 
 using namespace rtt;

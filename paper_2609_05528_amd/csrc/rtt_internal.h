@@ -89,6 +89,8 @@ struct Member {
     int32_t nseg[3];         // sweep segments per cell row
     int32_t vseg[3];         // columns per sweep segment
     int32_t k0_min, k0_max;  // range of the hat origins k0 of the member's rays
+    // per order: smallest and largest delay of the rays with non-zero weight (+inf / -inf if none)
+    double delay_min[8], delay_max[8];
 };
 
 struct Workspace;
@@ -111,6 +113,9 @@ struct rtt_geometry {
     // up to 16 members, 2 = the same as a persistent launch (one block per resident slot)
     int32_t batch_apply_mode = 1, batch_adjoint_mode = 1;
     int device = 0;
+    // per member: delays and |weights| of the order-0 rays with non-zero weight (host copies for the
+    // direct throughput age boundary)
+    std::vector<std::vector<double>> dir_delay, dir_weight;
     uint32_t magic = 0x52545447u;
 };
 
@@ -154,5 +159,15 @@ uint32_t effective_mask(const Member& m, uint32_t mask);
 // block-diagonal operator (full-length vectors).
 int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, float* out, int nvec,
              uint32_t mask, hipStream_t s);
+
+// order mixers (mixer.hip) ---------------------------------------------------------------------
+bool mixer_ok(const rtt_mixer* m);
+int64_t mixer_rows(const rtt_mixer* m);       // rows of a mixed data vector
+int64_t mixer_src_rows(const rtt_mixer* m);   // rows of the order-resolved vectors it reads
+// (offset, length) of every geometry's mixed rows, appended to seg
+void mixer_segments(const rtt_mixer* m, std::vector<int64_t>& seg);
+// d = (L kron I) y on nvec vectors (strides in floats), stream-ordered
+int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, int64_t d_stride, int nvec,
+                hipStream_t s);
 
 }  // namespace rtt

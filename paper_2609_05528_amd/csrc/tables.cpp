@@ -122,6 +122,7 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     if (opts && !(opts->sigma_omega >= 0.0)) return fail(RTT_EINVAL, "sigma_omega must be >= 0");
 
     std::vector<Member> members(n_geometries);
+    std::vector<std::vector<double>> dir_delay(n_geometries), dir_weight(n_geometries);
     std::vector<RayRec> recs;
     std::vector<int32_t> cstart;
     std::vector<Visit> visits;
@@ -137,6 +138,10 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
         Member& m = members[gi];
         std::memset(&m, 0, sizeof(m));
         m.grid = g;
+        for (int n = 0; n < 8; ++n) {
+            m.delay_min[n] = HUGE_VAL;
+            m.delay_max[n] = -HUGE_VAL;
+        }
         exact_ratio(g.dt_obs, g.dt_src, g.n_frames, &m.P, &m.Q);
         const double dr = (g.r_out - g.r_in) / g.n_r;
         const double dphi = two_pi / g.n_phi;
@@ -171,6 +176,14 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
                     }
                     w = 0.0;  // chi = 0: the row is kept and reads as zero
                     r = std::min(std::max(r, g.r_in), g.r_out);
+                }
+                if (w != 0.0) {
+                    m.delay_min[n] = std::min(m.delay_min[n], dl);
+                    m.delay_max[n] = std::max(m.delay_max[n], dl);
+                    if (n == 0) {
+                        dir_delay[gi].push_back(dl);
+                        dir_weight[gi].push_back(std::fabs(w));
+                    }
                 }
                 // bilinear stencil on cell centres (uniform in r, periodic in phi)
                 double ur = (r - g.r_in) / dr - 0.5;
@@ -341,6 +354,8 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     rtt_geometry* h = new (std::nothrow) rtt_geometry();
     if (!h) return fail(RTT_ENOMEM, "host allocation failed");
     h->members = std::move(members);
+    h->dir_delay = std::move(dir_delay);
+    h->dir_weight = std::move(dir_weight);
     h->n_rows = row_off;
     h->n_cols = col_off;
     h->n_rays = (int64_t)recs.size();

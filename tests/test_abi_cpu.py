@@ -109,3 +109,26 @@ def test_bench_script_parses_and_refuses_several_gpus():
     r = subprocess.run([_sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_age_reach_matches_the_oracle_on_random_masks():
+    """The host-only threshold statistics of the library against the oracle's plain loops."""
+    import oracle
+    rng = np.random.default_rng(17)
+    ages = np.arange(0.0, 256.0, 4.0)
+    for trial in range(200):
+        info = rng.exponential(1.0, ages.size) * rng.choice([0.3, 1.0, 3.0])
+        lo, hi = sorted(rng.uniform(-20, 270, 2))
+        boundary = rng.uniform(-10, 260) if trial % 7 else math.nan
+        got = rtt.age_reach(ages, info, rho=1.0, a_min=lo, a_max=hi, boundary=boundary)
+        sup = [(lo <= a <= hi) for a in ages]
+        want = oracle.reach(ages, info, rho=1.0, supported=sup, boundary=None if math.isnan(boundary) else boundary)
+        assert list(got["mask"]) == want["mask"]
+        assert got["t_reach"] == want["t_reach"] and got["anchor"] == want["anchor"]
+        assert got["l_anchor"] == want["l_anchor"] and got["longest"] == want["longest"]
+        if want["j_old"] is None:
+            assert got["j_old"] is None
+        else:
+            assert abs(got["j_old"] - want["j_old"]) <= 1e-12 * max(1.0, want["j_old"])
+    with pytest.raises(rtt.RttError, match="equally spaced"):
+        rtt.age_reach([0.0, 4.0, 9.0], [1.0, 1.0, 1.0])
