@@ -117,6 +117,54 @@ def mixer_section(torch, rtt, oracle, geo, G, Y, reps=10):
     return out
 
 
+def age_section(torch, rtt, geos, G, snr0=100.0, rho=1.0, h=3.0):
+    """Age-probe information over the 0-252M grid (4M steps) for every geometry of G: the direct,
+    resolved, unresolved and total-flux arms (Sec. 3.3, 4.4, 6.4), each arm one library call timed
+    end to end, then the reach statistics at SNR0 with s_ref of each geometry (eq. (17)-(18))."""
+    ages = np.arange(0.0, 256.0, 4.0)
+    pix = [np.asarray(m.pixel, dtype=np.int64) for geo in geos for m in geo.maps]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sref = rtt.reference_response(G)
+    t_sref = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    E = rtt.age_information(G, ages, h=h)
+    t_orders = time.perf_counter() - t0
+    arms = {"direct": E[:, :, 0], "resolved": E.sum(axis=2)}
+    t_mix = {}
+    for kind in ("unresolved", "total_flux"):
+        M = rtt.Mixer(G, kind, pix if kind == "unresolved" else None)
+        t0 = time.perf_counter()
+        arms[kind] = rtt.age_information(G, ages, h=h, mixer=M)
+        t_mix[kind] = time.perf_counter() - t0
+        del M
+    stats = {}
+    for arm, e in arms.items():
+        per = []
+        for g in range(G.n_geometries):
+            a0, a1, bnd = rtt.age_window(G, g, order_mask=1 if arm == "direct" else 0, h=h, q=0.999)
+            r = rtt.age_reach(ages, snr0 ** 2 * e[:, g] / sref[g] ** 2, rho, a0, a1, bnd)
+            per.append(r)
+
+        def med(key):
+            v = [r[key] for r in per if r[key] is not None]
+            return float(np.median(v)) if v else None
+
+        stats[arm] = {"median_t_reach": med("t_reach"), "median_l_anchor": med("l_anchor"),
+                      "median_j_old": med("j_old")}
+        if G.n_geometries == 1:
+            stats[arm].update({"t_reach": per[0]["t_reach"], "l_anchor": per[0]["l_anchor"],
+                               "j_old": per[0]["j_old"], "anchor_age": None if per[0]["anchor"] is None
+                               else float(ages[per[0]["anchor"]])})
+    out = {"ages": "0-252M step 4M (64 centres), h = %gM, SNR0 = %g, rho = %g" % (h, snr0, rho),
+           "seconds": {"s_ref": t_sref, "orders": t_orders, **t_mix},
+           "probe_applies_per_s": ages.size * G.n_geometries / t_orders, "arms": stats}
+    log("age information: orders %.3f s, unresolved %.3f s, total flux %.3f s; %s" % (
+        t_orders, t_mix["unresolved"], t_mix["total_flux"],
+        {a: (v["median_l_anchor"], v["median_j_old"]) for a, v in stats.items()}))
+    return out
+
+
 def calibrate(torch, dev, gib=2):
     """Streaming bandwidth of torch's plain copy and fill kernels on 2 GiB (HBM reference)."""
     n = gib * (1 << 30) // 4
@@ -283,6 +331,7 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
     ms_graph = gev[0].elapsed_time(gev[1]) / greps
     del graph, sv
     torch.cuda.empty_cache()
+    ages = age_section(torch, rtt, geos, G)
     out = {
         "workload": "12 geometries (spins 0/0.3/0.6/0.94 x incl 20/50/75, 96^2-256^2, 64-160 frames, "
                     "orders 0-2) x 60 Gaussian-blob histories on a shared 64x64x96 basis",
@@ -297,6 +346,7 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
         "graph_step": {"ms_replay": ms_graph, "s_eager": t_eager, "replay_equals_eager": same,
                        "ridge_iterations": ridge_iters, "tsvd_t": k,
                        "contents": "A + A^T + TSVD + ridge CG on every (geometry, history) pair"},
+        "age_information": ages,
     }
     log("batch: A %.2f ms A^T %.2f ms (%.0f / %.0f GB/s); batched %.0f vs plain %.0f applies/s; "
         "autograd %.0f vs %.0f pairs/s; graph %.1f ms" % (ms_a, ms_at, out["op_apply"]["GBps"],
@@ -321,6 +371,7 @@ def main():
     ap.add_argument("--no-rsvd", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixer", action="store_true")
+    ap.add_argument("--no-age", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -408,6 +459,7 @@ def main():
               "tol": 1e-5}
 
     mixers = None if args.no_mixer else mixer_section(torch, rtt, oracle, geo, G, Y)
+    ages = None if args.no_age else age_section(torch, rtt, [geo], G)
 
     # plain per-instance loop on the same GPU (one vector per call)
     plain = None
@@ -510,6 +562,7 @@ def main():
         "rsvd": rs,
         "batch": batch,
         "mixers": mixers,
+        "age_information": ages,
         "parity": parity,
         "cpu_baseline": cpu,
     }
