@@ -979,6 +979,136 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
                            xcd_remap(blockIdx.x, gridDim.x), blockIdx.z);
 }
 
+// --------------------------------------------------------------------------------------------
+// A, absolute-hat form of the lean forward, for n_hat <= 128 and dt_obs/dt_src = 1/Q.  Gather
+// lane l of pass it holds hat k = l + 64 it of a corner row whatever the ray's time origin, so
+// the rays of one base cell need exactly the same x values: consecutive rays of a cell (the
+// records are sorted by base cell) share one set of gathers.  Each ray's combined series over
+// all K hats goes to an LDS row and its whole frame range is written from it (no frame chunks);
+// hats outside [0, K) read as 0.  The products and the order of the sums are those of the lean
+// form (the two agree to rounding: FMA contraction may differ).
+// --------------------------------------------------------------------------------------------
+constexpr int ABS_KMAX = 2 * WAVE;
+
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs(LeanArgs a)
+{
+    const float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
+    float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    float(*zs_all)[NB][LEAN_ZS] = lean_lds<NB>();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t r0 = (blk * A_WAVES + wave) * NB;
+    if (r0 >= a.n_rays) return;
+    float(*zs)[LEAN_ZS] = zs_all[wave];
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
+    const int K = a.K;
+    const bool two = K > WAVE;   // second gather pass (hats 64..127)
+
+    FwdRec rc[NB];
+    bool on[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int64_t ri = r0 + j;
+        rc[j] = load_const_rec(a.rec + __builtin_amdgcn_readfirstlane((int)(ri < a.n_rays ? ri : r0)));
+    }
+    float xv[NB][2][4];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        on[j] = (r0 + j < a.n_rays) && ((a.mask >> rc[j].order) & 1u);
+        if (j > 0 && rc[j].c00k == rc[j - 1].c00k && rc[j].d01k == rc[j - 1].d01k) {
+            // same base cell as the previous ray (uniform branch): same corner rows, same hats
+#pragma unroll
+            for (int it = 0; it < 2; ++it)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xv[j][it][c] = xv[j - 1][it][c];
+            continue;
+        }
+        const int s10 = a.nk * 4;
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            if (it == 1 && !two) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xv[j][it][c] = 0.f;
+                continue;
+            }
+            const int k = lane + it * WAVE;
+            const bool in = k < K;
+            // lanes past the last hat read past the end of x (0, no memory access); the column
+            // step to the periodic neighbour can be negative, so it stays in the vector offset
+            const int off0 = in ? (rc[j].c00k + k) * 4 : 0x7FFFFFF0;
+            const int off1 = in ? off0 + rc[j].d01k * 4 : 0x7FFFFFF0;
+            xv[j][it][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off0, 0, 0));
+            xv[j][it][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off0, s10, 0));
+            xv[j][it][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off1, 0, 0));
+            xv[j][it][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(xr, off1, s10, 0));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int it = 0; it < 2; ++it)
+            zs[j][lane + it * WAVE] = rc[j].b00 * xv[j][it][0] + rc[j].b10 * xv[j][it][1] +
+                                      rc[j].b01 * xv[j][it][2] + rc[j].b11 * xv[j][it][3];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const int F = a.F;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (!on[j]) continue;
+        const float* zr = zs[j];
+        // z at hat k, 0 outside [0, K)
+        auto zat = [&](int k) { return (unsigned)k < (unsigned)K ? zr[k] : 0.f; };
+        const float th = rc[j].th0;
+        const int k0 = rc[j].k0;
+        float* yr = y + (int64_t)rc[j].row * F;
+        if (VEC4 && Q == 1) {
+            typedef float f2 __attribute__((ext_vector_type(2)));
+            for (int f = 2 * lane; f < F; f += 2 * WAVE) {
+                const float z0 = zat(k0 + f), z1 = zat(k0 + f + 1), z2 = zat(k0 + f + 2);
+                f2 v;
+                v[0] = z0 + th * (z1 - z0);
+                v[1] = z1 + th * (z2 - z1);
+                __builtin_nontemporal_store(v, (f2*)(yr + f));
+            }
+        } else if (VEC4) {
+            const bool c1 = th >= 0.5f;
+            const float th1 = c1 ? th - 0.5f : th + 0.5f;
+            for (int g = lane; 4 * g < F; g += WAVE) {
+                const int kb = k0 + 2 * g;
+                const float z0 = zat(kb), z1 = zat(kb + 1), z2 = zat(kb + 2), z3 = zat(kb + 3);
+                const float a1 = c1 ? z1 : z0, b1 = c1 ? z2 : z1;
+                const float a3 = c1 ? z2 : z1, b3 = c1 ? z3 : z2;
+                f4 v;
+                v[0] = z0 + th * (z1 - z0);
+                v[1] = a1 + th1 * (b1 - a1);
+                v[2] = z1 + th * (z2 - z1);
+                v[3] = a3 + th1 * (b3 - a3);
+                __builtin_nontemporal_store(v, (f4*)(yr + 4 * g));
+            }
+        } else {
+            for (int q = lane; q < F; q += WAVE) {
+                int jz;
+                float t;
+                if (Q == 1) {
+                    jz = q;
+                    t = th;
+                } else {
+                    const bool odd = q & 1;
+                    const bool c1 = th >= 0.5f;
+                    jz = (q >> 1) + ((odd && c1) ? 1 : 0);
+                    t = odd ? (c1 ? th - 0.5f : th + 0.5f) : th;
+                }
+                const float za = zat(k0 + jz), zb = zat(k0 + jz + 1);
+                __builtin_nontemporal_store(za + t * (zb - za), yr + q);
+            }
+        }
+    }
+}
+
 // Every member of a handle (up to MULTI_MAX) in one launch.  Tasks are (vector, member, frame
 // chunk, ray block), numbered with the ray block fastest; a member's tasks start at blk_begin
 // inside each vector.  With gridDim.x < total the launch is persistent: block b takes tasks
@@ -2190,11 +2320,11 @@ constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 11; }
+int n_apply_variants() { return 13; }
 const char* apply_variant_name(int v)
 {
     static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8", "reg1", "reg2", "strip16",
-                                  "strip8", "lean4q"};
+                                  "strip8", "lean4q", "abs4", "abs8"};
     return names[v];
 }
 bool lean_supported(const Member& m)
@@ -2228,6 +2358,7 @@ bool apply_variant_ok(const Member& m, int v)
     if (v >= 4 && !lean_supported(m)) return false;      // lean / reg / strip need dt_obs/dt_src = 1 or 1/2
     if ((v == 8 || v == 9) && strip_lds_bytes(m, v == 8 ? 16 : 8) > 65536) return false;
     if (v == 10 && m.grid.n_hat % 4 != 0) return false;   // quad gathers need 16-byte aligned x rows
+    if ((v == 11 || v == 12) && m.grid.n_hat > ABS_KMAX) return false;   // absolute hats: two gather passes
     return true;
 }
 
@@ -2423,6 +2554,42 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
             if (variant == 6) reg_dispatch<2, 1>(ra, nvec, vec4, s);
             else reg_dispatch<2, 2>(ra, nvec, vec4, s);
         }
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
+    if (variant == 11 || variant == 12) {
+        if (m.grid.n_hat > ABS_KMAX) return fail(RTT_EINVAL, "absolute-hat forward needs n_hat <= 128");
+        LeanArgs la;
+        la.rec = g->d_fwd + m.ray_begin;
+        la.n_rays = m.n_rays;
+        la.K = m.grid.n_hat;
+        la.F = m.grid.n_frames;
+        la.nk = m.grid.n_phi * m.grid.n_hat;
+        la.x = x;
+        la.y = y;
+        la.x_stride = x_stride;
+        la.y_stride = y_stride;
+        la.x_bytes = (int)(m.n_cols * 4);
+        la.mask = mask;
+        la.fc = m.grid.n_frames;
+        const int wa = m.Q == 1 ? 2 : 4;
+        const bool vec4 = (la.F % wa) == 0 && (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (y_stride % wa) == 0);
+        const int nb = variant == 11 ? 4 : 8;
+        const dim3 grid((unsigned)((la.n_rays + (int64_t)A_WAVES * nb - 1) / ((int64_t)A_WAVES * nb)), (unsigned)nvec);
+        const dim3 blk(A_WAVES * WAVE);
+#define RTT_ABS(Q_, NB_)                                                                      \
+    do {                                                                                      \
+        if (vec4) hipLaunchKernelGGL((k_apply_abs<Q_, NB_, true>), grid, blk, 0, s, la);      \
+        else hipLaunchKernelGGL((k_apply_abs<Q_, NB_, false>), grid, blk, 0, s, la);          \
+    } while (0)
+        if (m.Q == 1) {
+            if (nb == 4) RTT_ABS(1, 4);
+            else RTT_ABS(1, 8);
+        } else {
+            if (nb == 4) RTT_ABS(2, 4);
+            else RTT_ABS(2, 8);
+        }
+#undef RTT_ABS
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }

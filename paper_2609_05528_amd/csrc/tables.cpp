@@ -455,8 +455,8 @@ extern "C" int geometry_set_variant(rtt_geometry* g, int32_t idx, int32_t apply_
         if ((apply_variant == 2 || apply_variant == 3) && m.P > m.Q)
             return fail(RTT_EINVAL, "batch/stream forward variants need dt_obs <= dt_src");
         if (apply_variant >= 0 && !apply_variant_ok(m, apply_variant))
-            return fail(RTT_EINVAL, "lean/reg/strip forward variants need dt_obs/dt_src = 1 or 1/2 "
-                                    "(lean4q: n_hat a multiple of 4)");
+            return fail(RTT_EINVAL, "lean/reg/strip/abs forward variants need dt_obs/dt_src = 1 or 1/2 "
+                                    "(lean4q: n_hat a multiple of 4; abs: n_hat <= 128)");
         if (apply_variant >= 0) m.apply_variant = apply_variant;
         if (adjoint_variant >= 0 && !adjoint_variant_ok(m, adjoint_variant))
             return fail(RTT_EINVAL, "visit/rows adjoint variants need dt_obs/dt_src = 1 or 1/2 (rows: n_hat <= 256)");
