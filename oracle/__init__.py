@@ -23,6 +23,11 @@ with the GPU library.
   ``throughput_age_boundary``, ``reach``: the age-localised probes of Sec. 3.3
   eq. (10)-(13), age information eq. (12)/(29) per observation arm, and the
   threshold statistics T_reach, L_anchor (eq. (30)) and J_old (eq. (35)).
+* ``ridge_normal_solve``, ``ridge_data_gradient``, ``tsvd_project``: what the
+  derivatives of the Sec. 9 estimators with respect to the data need (dense).
+* ``age_window_error``: E(a) of eq. (32).
+* ``philox4x32_10``, ``normal_draws``: the counter-based generator behind the
+  seeded noise draws, written from its published definition.
 
 Every function here is pinned by the "not gpu" tests against facts that do
 not come from this module (see the tests' docstrings).
@@ -463,3 +468,90 @@ def reach(ages, info, rho=1.0, supported=None, boundary=None):
             if ages[i] > boundary:
                 j_old += math.log(1.0 + info[i]) * step
     return dict(mask=mask, t_reach=t_reach, anchor=anchor, l_anchor=l_anchor, longest=longest, j_old=j_old)
+
+
+# ------------------------------------------------------------------ differentiating through the estimators (Sec. 9)
+def ridge_normal_solve(geom, b, lam, order_mask=None):
+    """Solves (A^T A + lambda I) x = b for a coefficient-space right-hand side b, with the dense
+    matrix of A (tiny grids only)."""
+    A = dense(geom, order_mask)
+    M = A.T @ A + lam * np.eye(A.shape[1])
+    return np.linalg.solve(M, np.asarray(b, dtype=np.float64).T).T
+
+
+def ridge_data_gradient(geom, g_x, lam, order_mask=None):
+    """Gradient with respect to the data y of <g_x, x_hat(y)> for the ridge estimate
+    x_hat(y) = (A^T A + lambda I)^{-1} A^T y: A (A^T A + lambda I)^{-1} g_x (the normal matrix is
+    symmetric).  Dense, tiny grids only."""
+    A = dense(geom, order_mask)
+    return (A @ ridge_normal_solve(geom, g_x, lam, order_mask).T).T
+
+
+def tsvd_project(V, sigma, b, t):
+    """V_t diag(sigma_t^-2) V_t^T b with the t leading right singular vectors (rows of V)."""
+    Vt = np.asarray(V, dtype=np.float64)[:t]
+    s = np.asarray(sigma, dtype=np.float64)[:t]
+    b = np.asarray(b, dtype=np.float64)
+    c = Vt @ np.atleast_2d(b).T                  # [t][B]
+    out = (c / (s * s)[:, None]).T @ Vt          # [B][n]
+    return out[0] if b.ndim == 1 else out
+
+
+def age_window_error(grid, x_hat, x, ages, half_width=2.0, eta=1e-12):
+    """E(a) of eq. (32) with W_a keeping the coefficients of every cell at the hats whose centre s_k
+    lies in the age window |s_k + a| <= half_width (source time -a): ||W_a (x_hat - x)|| /
+    max(||W_a x||, eta).  x_hat, x: [n_cols] or [B][n_cols]; returns [len(ages)] or [B][len(ages)]."""
+    xh = np.atleast_2d(np.asarray(x_hat, dtype=np.float64))
+    xt = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    s_k = grid.s0 + grid.dt_src * np.arange(grid.n_hat)
+    out = np.zeros((xh.shape[0], len(ages)))
+    for b in range(xh.shape[0]):
+        D = (xh[b] - xt[b]).reshape(grid.n_cells, grid.n_hat)
+        X = xt[b].reshape(grid.n_cells, grid.n_hat)
+        for i, a in enumerate(ages):
+            num, den = 0.0, 0.0
+            for k in range(grid.n_hat):
+                if abs(s_k[k] + a) <= half_width:
+                    num += float(np.sum(D[:, k] ** 2))
+                    den += float(np.sum(X[:, k] ** 2))
+            out[b, i] = math.sqrt(num) / max(math.sqrt(den), eta)
+    return out[0] if np.asarray(x_hat).ndim == 1 else out
+
+
+# ------------------------------------------------------------------ seeded noise draws
+_PHILOX_M0, _PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+_PHILOX_W0, _PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(counter, key):
+    """Philox-4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11): the S-box round
+    multiplies words 0 and 2 by the two round constants, takes the high halves XORed with the
+    other words and the key, and the key is bumped by the Weyl constants after every round."""
+    c = [int(v) & 0xFFFFFFFF for v in counter]
+    k0, k1 = int(key[0]) & 0xFFFFFFFF, int(key[1]) & 0xFFFFFFFF
+    for _ in range(10):
+        p0 = _PHILOX_M0 * c[0]
+        p1 = _PHILOX_M1 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k1) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+        k0 = (k0 + _PHILOX_W0) & 0xFFFFFFFF
+        k1 = (k1 + _PHILOX_W1) & 0xFFFFFFFF
+    return c
+
+
+def normal_draws(n, seed):
+    """N(0, 1) draws: group i of four uses the Philox-4x32-10 block of counter (i mod 2^32, i >> 32,
+    0, 0) and key (seed mod 2^32, seed >> 32); the words map to uniforms (w + 1/2) 2^-32 and pairs
+    (u0, u1), (u2, u3) to Box-Muller normals r cos(2 pi u'), r sin(2 pi u'), r = sqrt(-2 ln u).
+    FP64 here."""
+    out = np.empty(n)
+    for i in range((n + 3) // 4):
+        w = philox4x32_10([i & 0xFFFFFFFF, i >> 32, 0, 0], [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
+        u = [(v + 0.5) * 2.0 ** -32 for v in w]
+        r0, r1 = math.sqrt(-2.0 * math.log(u[0])), math.sqrt(-2.0 * math.log(u[2]))
+        v = [r0 * math.cos(2 * math.pi * u[1]), r0 * math.sin(2 * math.pi * u[1]),
+             r1 * math.cos(2 * math.pi * u[3]), r1 * math.sin(2 * math.pi * u[3])]
+        for t in range(4):
+            if 4 * i + t < n:
+                out[4 * i + t] = v[t]
+    return out

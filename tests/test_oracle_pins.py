@@ -533,3 +533,81 @@ def test_reach_statistics_hand_example():
     # no supported centre passing: no anchor-connected span
     r2 = oracle.reach(ages, info, rho=rho, supported=[i == 3 for i in range(len(ages))], boundary=boundary)
     assert r2["anchor"] == 3 and r2["l_anchor"] is None
+
+
+# ----------------------------------------------------------------------------- estimator derivatives, noise
+def _tiny_dense_geo():
+    return tiny_geometry(seed=61, rays=(7, 4), n_r=3, n_phi=3, n_frames=4)
+
+
+def test_ridge_data_gradient_matches_central_differences_of_the_cg_solve():
+    """d/dy <g, x_hat(y)> against central differences of the CG ridge solve (a different route
+    from the dense normal-matrix solve the gradient uses)."""
+    geo = _tiny_dense_geo()
+    rng = np.random.default_rng(62)
+    lam = 0.05
+    y = rng.standard_normal(geo.n_rows)
+    g = rng.standard_normal(geo.grid.n_cols)
+    d = rng.standard_normal(geo.n_rows)
+    grad = oracle.ridge_data_gradient(geo, g, lam)
+    eps = 1e-4
+    xp, _ = oracle.ridge_solve(geo, y + eps * d, lam)
+    xm, _ = oracle.ridge_solve(geo, y - eps * d, lam)
+    fd = float(g @ (xp - xm)) / (2 * eps)
+    assert abs(fd - float(grad @ d)) <= 1e-7 * max(1.0, abs(fd))
+    # the normal-equation solve with b = A^T y is the ridge estimate itself
+    x_cg, _ = oracle.ridge_solve(geo, y, lam)
+    b = oracle.adjoint(geo, y)
+    assert np.allclose(oracle.ridge_normal_solve(geo, b, lam), x_cg, rtol=1e-8, atol=1e-10)
+
+
+def test_tsvd_projection_of_a_full_rank_factorisation_is_the_pseudo_inverse():
+    """With every nonzero singular triplet kept, V diag(sigma^-2) V^T A^T y = pinv(A) y."""
+    geo = _tiny_dense_geo()
+    A = oracle.dense(geo)
+    U, s, Vt = np.linalg.svd(A, full_matrices=False)
+    r = int(np.sum(s > 1e-10 * s[0]))
+    y = np.random.default_rng(63).standard_normal(geo.n_rows)
+    got = oracle.tsvd_project(Vt, s, oracle.adjoint(geo, y), r)
+    assert np.allclose(got, np.linalg.pinv(A, rcond=1e-10) @ y, rtol=1e-8, atol=1e-10)
+
+
+def test_age_window_error_hand_example():
+    grid = synth.Grid(n_orders=1, n_frames=1, t0=0.0, dt_obs=4.0, n_r=2, n_phi=1, r_in=6.0, r_out=20.0,
+                      n_hat=4, s0=-12.0, dt_src=4.0)
+    x = np.array([1, 2, 3, 4, 5, 6, 7, 8], dtype=np.float64)
+    d = np.array([0, 1, 0, 0, 0, 0, 3, -4], dtype=np.float64)
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "age_window_error_example.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if line:
+                rows.append([float(v) for v in line])
+    ages, want = zip(*rows)
+    got = oracle.age_window_error(grid, x + d, x, ages, half_width=2.0, eta=0.5)
+    assert np.allclose(got, want, rtol=1e-14, atol=1e-15)
+    # eta takes over when the window holds nothing of x
+    assert oracle.age_window_error(grid, 0 * x + 1.0, 0 * x, [0.0], 2.0, eta=0.5)[0] == math.sqrt(2.0) / 0.5
+
+
+def test_philox_known_answers():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "philox_kat.txt")) as f:
+        n = 0
+        for line in f:
+            line = line.split("#")[0].split()
+            if not line:
+                continue
+            w = [int(v, 16) for v in line]
+            assert oracle.philox4x32_10(w[0:4], w[4:6]) == w[6:10]
+            n += 1
+    assert n == 3
+
+
+def test_normal_draws_are_standard_normal():
+    """Moments and a Kolmogorov-Smirnov test against scipy's normal CDF; different seeds give
+    different streams."""
+    from scipy import stats
+    z = oracle.normal_draws(40000, seed=1234)
+    assert abs(z.mean()) < 0.03 and abs(z.var() - 1.0) < 0.03
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert not np.allclose(oracle.normal_draws(16, seed=1235), z[:16])
