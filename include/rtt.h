@@ -241,14 +241,15 @@ int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, const float** 
 int tsvd_solve(const rtt_geometry* geom, const rtt_svd* s, const float* y, int32_t nrhs,
                int32_t t, double sigma_min, float* x, void* stream);
 
-enum { RTT_SOLVE_ASYNC = 1 };
+enum { RTT_SOLVE_ASYNC = 1, RTT_SOLVE_NORMAL_RHS = 2 };
 
 typedef struct {
     float tol;          /* stop when ||r|| <= tol ||A^T y|| (per right-hand side
                            and geometry)                                         */
     int32_t maxit;      /* iteration cap (RTT_SOLVE_ASYNC: iteration count)      */
     uint32_t order_mask;
-    int32_t flags;      /* RTT_SOLVE_ASYNC: stream-ordered, see ridge_solve      */
+    int32_t flags;      /* RTT_SOLVE_ASYNC: stream-ordered, see ridge_solve;     */
+                        /* RTT_SOLVE_NORMAL_RHS: y is a right-hand side b        */
     float* resid_dev;   /* nullable device FP32 [nrhs][G]: final ||r||/||A^T y||  */
     int32_t reserved[2];
 } rtt_cg_opts;
@@ -280,6 +281,34 @@ typedef struct {
  */
 int ridge_solve(const rtt_geometry* geom, const float* y, int32_t nrhs, float lambda,
                 const rtt_cg_opts* opts, float* x, rtt_solve_info* info, void* stream);
+/* With flags & RTT_SOLVE_NORMAL_RHS, ridge_solve solves (A^T A + lambda I) x = b
+ * for a coefficient block b passed in place of y (device [nrhs][n_cols]); the
+ * relative residual is then ||r|| / ||b||.  This is the one extra solve that
+ * the derivative of the ridge estimate with respect to the data needs:
+ * d<g, x_hat(y)>/dy = A (A^T A + lambda I)^{-1} g (the normal matrix is
+ * symmetric). */
+
+/*
+ * tsvd_project -- x = V_t diag(sigma_t^-2) V_t^T b for a coefficient block b
+ * (device [nrhs][n_cols]; must not overlap x), the map that tsvd_solve applies
+ * after A^T (Sec. 9): tsvd_solve(y) = tsvd_project(A^T y), and the derivative
+ * of <g, tsvd_solve(y)> with respect to y is A tsvd_project(g).  Arguments,
+ * truncation and stream behaviour as tsvd_solve.
+ */
+int tsvd_project(const rtt_geometry* geom, const rtt_svd* s, const float* b, int32_t nrhs, int32_t t,
+                 double sigma_min, float* x, void* stream);
+
+/*
+ * noise_add -- y[i] += sigma * z_i, i < n, with seeded N(0, 1) draws z (white
+ * data noise; at a sweep point sigma = sigma_Omega = s_ref / SNR0 of
+ * eq. (18) for whitened rows).  Draws: group i of four takes the
+ * Philox-4x32-10 block (Salmon et al., SC'11) of counter (i mod 2^32,
+ * i >> 32, 0, 0) and key (seed mod 2^32, seed >> 32); words w map to uniforms
+ * (w + 1/2) 2^-32 and the pairs (u0, u1), (u2, u3) to Box-Muller normals
+ * r cos(2 pi u'), r sin(2 pi u'), r = sqrt(-2 ln u), in FP32.  The same seed
+ * gives the same draws for any n.  Stream-ordered.  Errors: RTT_EINVAL.
+ */
+int noise_add(float* y, int64_t n, uint64_t seed, float sigma, void* stream);
 
 /* -------------------------------------------------------------- order mixer */
 /*
@@ -431,6 +460,19 @@ typedef struct {
  */
 int age_reach(const double* ages, const double* info, int32_t n, double rho, double a_min, double a_max,
               double boundary, uint8_t* mask, rtt_reach* out);
+
+/*
+ * age_window_error -- E(a) of Sec. 4.4 eq. (32) for reconstructions x_hat of
+ * x (device [nvec][n_cols]): for every vector, geometry g and age a,
+ * ||W_a (x_hat - x)|| / max(||W_a x||, eta), W_a keeping every cell's
+ * coefficients at the hats whose centre s_k satisfies |s_k + a| <= half_width
+ * (the age window around source time -a; 2M for the paper's 4M grid).  Sums
+ * of squares in FP64, fixed order.  err: host double [nvec][G][n_ages].
+ * Blocking.  Errors: RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE.
+ */
+int age_window_error(const rtt_geometry* geom, const float* x_hat, const float* x, int32_t nvec,
+                     const double* ages, int32_t n_ages, double half_width, double eta, double* err,
+                     void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);

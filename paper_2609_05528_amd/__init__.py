@@ -19,13 +19,14 @@ LIB_PATH = os.path.join(_HERE, "librtt.so")
 RTT_OK, RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE, RTT_ENOCONV, RTT_ESTATE = 0, -1, -2, -3, -4, -5
 RTT_SVD_RSVD, RTT_SVD_BLOCK_LANCZOS = 0, 1
 RTT_SOLVE_ASYNC = 1
+RTT_SOLVE_NORMAL_RHS = 2
 RTT_EACH_GEOMETRY = -2
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
             "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
             "mix_apply", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
-            "age_reach", "last_error")
+            "age_reach", "age_window_error", "tsvd_project", "noise_add", "last_error")
 
 
 class RttError(RuntimeError):
@@ -138,6 +139,9 @@ def require_native():
         "age_window": [vp, i32, u32, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp],
         "age_reach": [_dp, _dp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                       ctypes.POINTER(ctypes.c_uint8), vp],
+        "age_window_error": [vp, vp, vp, i32, _dp, i32, ctypes.c_double, ctypes.c_double, _dp, vp],
+        "tsvd_project": [vp, vp, vp, i32, i32, ctypes.c_double, vp, vp],
+        "noise_add": [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -321,7 +325,8 @@ def op_apply_adjoint(geom: Geometry, y, x=None, order_mask: int = 0, stream=None
     return x
 
 
-from .svd import SVD, rsvd, tsvd_solve, ridge_solve  # noqa: E402,F401
+from .svd import SVD, rsvd, tsvd_solve, tsvd_project, ridge_solve  # noqa: E402,F401
 from .autograd import RetardedTimeOp, retarded_time_apply  # noqa: E402,F401
 from .mixer import Mixer, mixer_create, mix_apply, mix_adjoint, mix_covariance  # noqa: E402,F401
-from .age import reference_response, age_information, age_window, age_reach  # noqa: E402,F401
+from .age import (reference_response, age_information, age_window, age_reach,  # noqa: E402,F401
+                  age_window_error, noise_add)

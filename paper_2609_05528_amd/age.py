@@ -66,3 +66,23 @@ def age_reach(ages, info, rho: float = 1.0, a_min: float = -math.inf, a_max: flo
 
     return dict(mask=mask.astype(bool), t_reach=opt(r.t_reach), anchor=None if r.anchor < 0 else r.anchor,
                 l_anchor=opt(r.l_anchor), longest=opt(r.longest), j_old=opt(r.j_old), n_pass=r.n_pass)
+
+
+def age_window_error(geom: Geometry, x_hat, x, ages, half_width: float = 2.0, eta: float = 1e-12, stream=None):
+    """E(a) of eq. (32): numpy [nvec][G][n_ages] (x_hat, x: float32 CUDA [nvec][n_cols])."""
+    from . import _nvec
+    ages = np.ascontiguousarray(ages, dtype=np.float64)
+    nvec = _nvec(x, geom.n_cols)
+    out = np.zeros((nvec, geom.n_geometries, ages.size))
+    _check(require_native().age_window_error(geom.handle, _dev_ptr(x_hat, nvec * geom.n_cols, "x_hat"),
+                                             _dev_ptr(x, nvec * geom.n_cols, "x"), nvec, ages.ctypes.data_as(_dp),
+                                             ages.size, float(half_width), float(eta), out.ctypes.data_as(_dp),
+                                             _stream(stream)))
+    return out
+
+
+def noise_add(y, seed: int, sigma: float, stream=None):
+    """y += sigma * N(0, 1) seeded draws (Philox-4x32-10 + Box-Muller; see include/rtt.h), in place."""
+    _check(require_native().noise_add(_dev_ptr(y, None, "y"), y.numel(), int(seed) & (2 ** 64 - 1), float(sigma),
+                                      _stream(stream)))
+    return y

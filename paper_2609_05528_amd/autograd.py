@@ -48,3 +48,46 @@ def ridge_loss(x, y, geom, lam, order_mask=0):
     """1/2 ||A x - y||^2 + lam/2 ||x||^2 summed over the batch (differentiable)."""
     r = RetardedTimeOp.apply(x, geom, order_mask) - y
     return 0.5 * (r * r).sum() + 0.5 * lam * (x * x).sum()
+
+
+class _RidgeNormalSolve(torch.autograd.Function):
+    """x = (A^T A + lam I)^{-1} b on coefficient blocks; the matrix is symmetric, so the backward is
+    the same solve (and derivatives of any order follow)."""
+
+    @staticmethod
+    def forward(ctx, b, geom, lam, tol, maxit):
+        from .svd import ridge_solve
+        ctx.args = (geom, lam, tol, maxit)
+        x, _ = ridge_solve(geom, b.contiguous(), lam, tol=tol, maxit=maxit, normal_rhs=True)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        geom, lam, tol, maxit = ctx.args
+        return _RidgeNormalSolve.apply(gx.contiguous(), geom, lam, tol, maxit), None, None, None, None
+
+
+class _TsvdProject(torch.autograd.Function):
+    """x = V_t diag(sigma_t^-2) V_t^T b; symmetric, so the backward is the same map."""
+
+    @staticmethod
+    def forward(ctx, b, geom, svd, t, sigma_min):
+        from .svd import tsvd_project
+        ctx.args = (geom, svd, t, sigma_min)
+        return tsvd_project(geom, svd, b.contiguous(), t=t, sigma_min=sigma_min)
+
+    @staticmethod
+    def backward(ctx, gx):
+        geom, svd, t, sigma_min = ctx.args
+        return _TsvdProject.apply(gx.contiguous(), geom, svd, t, sigma_min), None, None, None, None
+
+
+def ridge_estimate(y, geom, lam, tol=1e-6, maxit=1000):
+    """Ridge estimate x_hat = (A^T A + lam I)^{-1} A^T y (Sec. 9), differentiable in y: the backward
+    is A applied to one more normal-equation solve."""
+    return _RidgeNormalSolve.apply(RetardedTimeAdjointOp.apply(y.contiguous(), geom, 0), geom, lam, tol, maxit)
+
+
+def tsvd_estimate(y, geom, svd, t=0, sigma_min=0.0):
+    """TSVD estimate x_hat = V_t diag(sigma_t^-2) V_t^T A^T y (Sec. 9), differentiable in y."""
+    return _TsvdProject.apply(RetardedTimeAdjointOp.apply(y.contiguous(), geom, 0), geom, svd, t, sigma_min)

@@ -41,6 +41,29 @@ __global__ void k_div_rows(const float* __restrict__ D, const float* __restrict_
     W[v * n + i] = q != 0.f ? D[v * n + i] / q : 0.f;
 }
 
+// Partial per-hat sums over a slice of cells: S[v][z][k] = sum (xh - x)^2, T[v][z][k] = sum x^2 (FP64)
+__global__ void k_hat_sums(const float* __restrict__ xh, const float* __restrict__ x, int64_t ld, int64_t col_off,
+                           int n_cells, int K, int cells_per_slice, double* __restrict__ S, double* __restrict__ T)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const int64_t v = blockIdx.y;
+    const int z = blockIdx.z;
+    const float* a = xh + v * ld + col_off;
+    const float* b = x + v * ld + col_off;
+    const int c0 = z * cells_per_slice, c1 = min(n_cells, c0 + cells_per_slice);
+    double s = 0.0, t = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        const double xb = (double)b[(int64_t)c * K + k];
+        const double d = (double)a[(int64_t)c * K + k] - xb;
+        s += d * d;
+        t += xb * xb;
+    }
+    const int64_t o = (v * gridDim.z + z) * K + k;
+    S[o] = s;
+    T[o] = t;
+}
+
 // N_h of eq. (11)
 double probe_norm(const rtt_grid& g, double h)
 {
@@ -300,5 +323,60 @@ extern "C" int age_reach(const double* ages, const double* info, int32_t n, doub
     for (int i = 0; i < n; ++i)
         if (ages[i] > boundary) jo += std::log1p(info[i]) * step;
     out->j_old = std::isnan(boundary) ? nan : jo;
+    return RTT_OK;
+}
+
+extern "C" int age_window_error(const rtt_geometry* g, const float* x_hat, const float* x, int32_t nvec,
+                                const double* ages, int32_t n_ages, double half_width, double eta, double* err,
+                                void* stream)
+{
+    if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
+    if (nvec < 0 || nvec > 65535 || n_ages < 0) return fail(RTT_EINVAL, "nvec must be 0..65535, n_ages >= 0");
+    if (nvec > 0 && n_ages > 0 && (!x_hat || !x || !ages || !err)) return fail(RTT_EINVAL, "NULL pointer");
+    if (!(half_width >= 0.0) || !(eta >= 0.0)) return fail(RTT_EINVAL, "half_width and eta must be >= 0");
+    if (nvec == 0 || n_ages == 0) return RTT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    RTT_HIP(hipSetDevice(g->device));
+    const int G = (int)g->members.size();
+    int maxK = 1;
+    for (const Member& m : g->members) maxK = std::max(maxK, (int)m.grid.n_hat);
+    const int nsl = 64;
+    Workspace ws;
+    double* S = (double*)ws.get("S", sizeof(double) * (size_t)nvec * nsl * maxK);
+    double* T = (double*)ws.get("T", sizeof(double) * (size_t)nvec * nsl * maxK);
+    if (!S || !T) return fail(RTT_ENOMEM, "age_window_error scratch");
+    std::vector<double> hS((size_t)nvec * nsl * maxK), hT(hS.size());
+    for (int gi = 0; gi < G; ++gi) {
+        const Member& m = g->members[gi];
+        const int K = m.grid.n_hat, nc = m.grid.n_r * m.grid.n_phi;
+        const int cps = (nc + nsl - 1) / nsl;
+        const int z = (nc + cps - 1) / cps;
+        hipLaunchKernelGGL(k_hat_sums, dim3((unsigned)((K + 63) / 64), (unsigned)nvec, (unsigned)z), dim3(64), 0, s,
+                           x_hat, x, g->n_cols, m.col_offset, nc, K, cps, S, T);
+        RTT_HIP(hipGetLastError());
+        RTT_HIP(hipMemcpyAsync(hS.data(), S, sizeof(double) * (size_t)nvec * z * K, hipMemcpyDeviceToHost, s));
+        RTT_HIP(hipMemcpyAsync(hT.data(), T, sizeof(double) * (size_t)nvec * z * K, hipMemcpyDeviceToHost, s));
+        RTT_HIP(hipStreamSynchronize(s));
+        for (int v = 0; v < nvec; ++v) {
+            // per-hat sums: slices added in slice order
+            std::vector<double> sk(K, 0.0), tk(K, 0.0);
+            for (int zz = 0; zz < z; ++zz)
+                for (int k = 0; k < K; ++k) {
+                    sk[k] += hS[((size_t)v * z + zz) * K + k];
+                    tk[k] += hT[((size_t)v * z + zz) * K + k];
+                }
+            for (int i = 0; i < n_ages; ++i) {
+                double num = 0.0, den = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    const double sc = m.grid.s0 + m.grid.dt_src * k;
+                    if (std::fabs(sc + ages[i]) <= half_width) {
+                        num += sk[k];
+                        den += tk[k];
+                    }
+                }
+                err[((size_t)v * G + gi) * n_ages + i] = std::sqrt(num) / std::max(std::sqrt(den), eta);
+            }
+        }
+    }
     return RTT_OK;
 }

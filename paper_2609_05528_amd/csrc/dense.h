@@ -39,6 +39,8 @@ int scale_inv_sq(const double* Cd, const double* sigma_dev, int sets, int t, int
                  float* C, hipStream_t s);
 // N(0,1) FP32 draws from Philox-4x32-10 counters (seeded).
 int normal_fill(float* out, int64_t n, uint64_t seed, hipStream_t s);
+// y[i] += sigma * (the same draws)
+int normal_add(float* y, int64_t n, uint64_t seed, float sigma, hipStream_t s);
 
 // host FP64 small dense linear algebra (column-major n x n unless stated)
 // Cholesky G = R^T R of a symmetric n x n (row-major) matrix; pivots below

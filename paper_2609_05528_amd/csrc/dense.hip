@@ -163,6 +163,23 @@ __global__ void k_normal(float* __restrict__ out, int64_t n, uint64_t seed, uint
     for (int t = 0; t < 4 && base + t < n; ++t) out[base + t] = v[t];
 }
 
+// y[i] += sigma * z_i with z the draws of k_normal (same counters, same mapping)
+__global__ void k_normal_add(float* __restrict__ y, int64_t n, uint64_t seed, float sigma)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t base = 4 * i;
+    if (base >= n) return;
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0u, 0u};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float two_pi = 6.2831853071795864769f;
+    const float inv = 2.3283064365386963e-10f;   // 2^-32
+    float u0 = ((float)c[0] + 0.5f) * inv, u1 = ((float)c[1] + 0.5f) * inv;
+    float u2 = ((float)c[2] + 0.5f) * inv, u3 = ((float)c[3] + 0.5f) * inv;
+    float r0 = sqrtf(-2.0f * logf(u0)), r1 = sqrtf(-2.0f * logf(u2));
+    float v[4] = {r0 * cosf(two_pi * u1), r0 * sinf(two_pi * u1), r1 * cosf(two_pi * u3), r1 * sinf(two_pi * u3)};
+    for (int t = 0; t < 4 && base + t < n; ++t) y[base + t] += sigma * v[t];
+}
+
 // per-vector dot products in FP64, deterministic: partials of fixed slices, then a fixed-order sum
 __global__ void k_dot_partial(const float* __restrict__ a, int64_t lda, const float* __restrict__ b,
                               int64_t ldb, int64_t n, int64_t slice, double* __restrict__ part)
@@ -305,6 +322,15 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         default: combine_launch<9>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
         }
     }
+    RTT_HIP(hipGetLastError());
+    return RTT_OK;
+}
+
+int normal_add(float* y, int64_t n, uint64_t seed, float sigma, hipStream_t s)
+{
+    if (n <= 0) return RTT_OK;
+    const int64_t q = (n + 3) / 4;
+    hipLaunchKernelGGL(k_normal_add, dim3((unsigned)((q + 255) / 256)), dim3(256), 0, s, y, n, seed, sigma);
     RTT_HIP(hipGetLastError());
     return RTT_OK;
 }

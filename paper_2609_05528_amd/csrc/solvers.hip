@@ -108,7 +108,8 @@ extern "C" int ridge_solve(const rtt_geometry* g, const float* y, int32_t nrhs, 
     float* resid_dev = opts ? opts->resid_dev : nullptr;
     const bool async = (flags & RTT_SOLVE_ASYNC) != 0;
     if (!(tol > 0.0f) || maxit < 1) return fail(RTT_EINVAL, "need tol > 0 and maxit >= 1");
-    if (flags & ~RTT_SOLVE_ASYNC) return fail(RTT_EINVAL, "unknown ridge_solve flags");
+    if (flags & ~(RTT_SOLVE_ASYNC | RTT_SOLVE_NORMAL_RHS)) return fail(RTT_EINVAL, "unknown ridge_solve flags");
+    const bool normal_rhs = (flags & RTT_SOLVE_NORMAL_RHS) != 0;
     if (info) *info = rtt_solve_info{0, 0, 0.f, 0};
     if (nrhs == 0) return RTT_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -138,9 +139,13 @@ extern "C" int ridge_solve(const rtt_geometry* g, const float* y, int32_t nrhs, 
     auto pair_dots = [&](const float* a, const float* b, double* out) {
         return dots_seg(ws, a, n, b, n, seg, G, max_cols, nrhs, out, s);
     };
-    // x = 0, r = A^T y, p = r
+    // x = 0, r = A^T y (or the given normal-equation right-hand side), p = r
     if ((rc = fill(x, (int64_t)nrhs * n, 0.f, s))) return rc;
-    if ((rc = apply_op(g, -1, true, y, r, nrhs, mask, s))) return rc;
+    if (normal_rhs) {
+        RTT_HIP(hipMemcpyAsync(r, y, sizeof(float) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, s));
+    } else if ((rc = apply_op(g, -1, true, y, r, nrhs, mask, s))) {
+        return rc;
+    }
     RTT_HIP(hipMemcpyAsync(p, r, sizeof(float) * (size_t)nrhs * n, hipMemcpyDeviceToDevice, s));
     if ((rc = pair_dots(r, r, rr))) return rc;
     hipLaunchKernelGGL(k_cg_init, sgrid, dim3(128), 0, s, rr, bb, done, npair);
@@ -194,4 +199,12 @@ extern "C" int ridge_solve(const rtt_geometry* g, const float* y, int32_t nrhs, 
     if (info) *info = rtt_solve_info{it, ndone, (float)worst, 0};
     if (ndone < npair) return fail(RTT_ENOCONV, "ridge_solve: CG did not reach tol within maxit");
     return RTT_OK;
+}
+
+extern "C" int noise_add(float* y, int64_t n, uint64_t seed, float sigma, void* stream)
+{
+    if (n < 0) return fail(RTT_EINVAL, "n must be >= 0");
+    if (n > 0 && !y) return fail(RTT_EINVAL, "NULL data pointer");
+    if (!std::isfinite(sigma)) return fail(RTT_EINVAL, "sigma must be finite");
+    return normal_add(y, n, seed, sigma, (hipStream_t)stream);
 }

@@ -424,8 +424,9 @@ extern "C" int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, con
     return RTT_OK;
 }
 
-extern "C" int tsvd_solve(const rtt_geometry* g, const rtt_svd* sv, const float* y, int32_t nrhs, int32_t t,
-                          double sigma_min, float* x, void* stream)
+// x = V_t diag(sigma_t^-2) V_t^T b with b = A^T y (from_data) or b = y (a coefficient block)
+static int tsvd_apply(const rtt_geometry* g, const rtt_svd* sv, const float* y, int32_t nrhs, int32_t t,
+                      double sigma_min, float* x, void* stream, bool from_data)
 {
     if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
     if (!sv || sv->magic != 0x53564431u) return fail(RTT_EINVAL, "invalid svd handle");
@@ -433,8 +434,8 @@ extern "C" int tsvd_solve(const rtt_geometry* g, const rtt_svd* sv, const float*
     if (nrhs > 0 && (!y || !x)) return fail(RTT_EINVAL, "NULL data pointer");
     if (sv->member >= (int)g->members.size() || (sv->member == RTT_EACH_GEOMETRY && sv->sets != (int)g->members.size()) ||
         sv->n_cols != (sv->member >= 0 ? g->members[sv->member].n_cols : g->n_cols))
-        return fail(RTT_EINVAL, "tsvd_solve: the factors belong to another geometry");
-    if (t > sv->k) return fail(RTT_EINVAL, "tsvd_solve: t exceeds the number of singular triplets");
+        return fail(RTT_EINVAL, "tsvd: the factors belong to another geometry");
+    if (t > sv->k) return fail(RTT_EINVAL, "tsvd: t exceeds the number of singular triplets");
     if (nrhs == 0) return RTT_OK;
     // kept components: i < t (t > 0), or sigma_i >= sigma_min (t <= 0); zero singular values never
     int tt = t;
@@ -459,12 +460,16 @@ extern "C" int tsvd_solve(const rtt_geometry* g, const rtt_svd* sv, const float*
     double* Cd = (double*)ws.get("ts_c", sizeof(double) * (size_t)sets * tt * nrhs);
     float* Cf = (float*)ws.get("ts_cf", sizeof(float) * (size_t)sets * tt * nrhs);
     if (!Cd || !Cf) return fail(RTT_ENOMEM, "tsvd workspace");
-    // x = A^T y, then per set c = V_t x (coefficients), c_i /= sigma_i^2, x = V_t^T c
-    if ((rc = apply_op(g, sv->member >= 0 ? sv->member : -1, true, y, x, nrhs, 0, s))) return rc;
+    // b = A^T y (or the given block), then per set c = V_t b (coefficients), c_i /= sigma_i^2, x = V_t^T c
+    const float* b = y;
+    if (from_data) {
+        if ((rc = apply_op(g, sv->member >= 0 ? sv->member : -1, true, y, x, nrhs, 0, s))) return rc;
+        b = x;
+    }
     for (int q = 0; q < sets; ++q) {
         const int64_t off = sets > 1 ? g->members[q].col_offset : 0;
         const int64_t len = sets > 1 ? g->members[q].n_cols : n;
-        if ((rc = gram(ws, sv->V + off, n, x + off, n, tt, nrhs, len, Cd + (size_t)q * tt * nrhs, s))) return rc;
+        if ((rc = gram(ws, sv->V + off, n, b + off, n, tt, nrhs, len, Cd + (size_t)q * tt * nrhs, s))) return rc;
     }
     if ((rc = scale_inv_sq(Cd, sv->d_sigma, sets, tt, sv->k, nrhs, smin, Cf, s))) return rc;
     for (int q = 0; q < sets; ++q) {
@@ -473,4 +478,17 @@ extern "C" int tsvd_solve(const rtt_geometry* g, const rtt_svd* sv, const float*
         if ((rc = combine(Cf + (size_t)q * tt * nrhs, tt, nrhs, sv->V + off, n, x + off, n, len, 0.f, s))) return rc;
     }
     return RTT_OK;
+}
+
+extern "C" int tsvd_solve(const rtt_geometry* g, const rtt_svd* sv, const float* y, int32_t nrhs, int32_t t,
+                          double sigma_min, float* x, void* stream)
+{
+    return tsvd_apply(g, sv, y, nrhs, t, sigma_min, x, stream, true);
+}
+
+extern "C" int tsvd_project(const rtt_geometry* g, const rtt_svd* sv, const float* b, int32_t nrhs, int32_t t,
+                            double sigma_min, float* x, void* stream)
+{
+    if (b && b == x) return fail(RTT_EINVAL, "tsvd_project: b and x must not overlap");
+    return tsvd_apply(g, sv, b, nrhs, t, sigma_min, x, stream, false);
 }

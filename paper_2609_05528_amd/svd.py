@@ -5,7 +5,7 @@ import ctypes
 
 import numpy as np
 
-from . import (RTT_EACH_GEOMETRY, RTT_SOLVE_ASYNC, RTT_SVD_BLOCK_LANCZOS, RTT_SVD_RSVD, _check, _dev_ptr, _nvec,
+from . import (RTT_EACH_GEOMETRY, RTT_SOLVE_ASYNC, RTT_SOLVE_NORMAL_RHS, RTT_SVD_BLOCK_LANCZOS, RTT_SVD_RSVD, _check, _dev_ptr, _nvec,
                _stream, require_native, rtt_cg_opts, rtt_solve_info, rtt_svd_opts)
 
 
@@ -136,23 +136,38 @@ def tsvd_solve(geom, svd: SVD, y, t=0, sigma_min=0.0, x=None, stream=None):
     return x
 
 
+def tsvd_project(geom, svd: SVD, b, t=0, sigma_min=0.0, x=None, stream=None):
+    """x = V_t diag(sigma_t^-2) V_t^T b for a coefficient block b (the map tsvd_solve applies after A^T)."""
+    import torch
+    n_cols = svd.geom_cols
+    nrhs = _nvec(b, n_cols)
+    if x is None:
+        x = torch.empty(b.shape[:-1] + (n_cols,), dtype=torch.float32, device=b.device)
+    _check(require_native().tsvd_project(geom.handle, svd._h, _dev_ptr(b, nrhs * n_cols, "b"), nrhs, int(t),
+                                         float(sigma_min), _dev_ptr(x, nrhs * n_cols, "x"), _stream(stream)))
+    return x
+
+
 def ridge_solve(geom, y, lam, tol=1e-6, maxit=1000, order_mask=0, x=None, stream=None, raise_on_noconv=True,
-                async_mode=False, resid=None):
+                async_mode=False, resid=None, normal_rhs=False):
     """Ridge estimate by CG on (A^T A + lam I) x = A^T y, one CG per (right-hand side, geometry);
     returns (x, info dict).
 
     async_mode: stream-ordered solve of exactly ``maxit`` iterations with no host
     synchronisation (capturable into a graph once its scratch exists); ``resid``
     (float32 CUDA [nrhs * n_geometries]) then receives the final relative residuals.
+    normal_rhs: ``y`` is a coefficient block b and the solve is (A^T A + lam I) x = b.
     """
     import torch
-    nrhs = _nvec(y, geom.n_rows)
+    n_in = geom.n_cols if normal_rhs else geom.n_rows
+    nrhs = _nvec(y, n_in)
     if x is None:
         x = torch.empty(y.shape[:-1] + (geom.n_cols,), dtype=torch.float32, device=y.device)
     rp = None if resid is None else _dev_ptr(resid, nrhs * geom.n_geometries, "resid").value
-    opts = rtt_cg_opts(float(tol), int(maxit), int(order_mask), RTT_SOLVE_ASYNC if async_mode else 0, rp)
+    flags = (RTT_SOLVE_ASYNC if async_mode else 0) | (RTT_SOLVE_NORMAL_RHS if normal_rhs else 0)
+    opts = rtt_cg_opts(float(tol), int(maxit), int(order_mask), flags, rp)
     info = rtt_solve_info()
-    rc = require_native().ridge_solve(geom.handle, _dev_ptr(y, nrhs * geom.n_rows, "y"), nrhs, float(lam),
+    rc = require_native().ridge_solve(geom.handle, _dev_ptr(y, nrhs * n_in, "y"), nrhs, float(lam),
                                       ctypes.byref(opts), _dev_ptr(x, nrhs * geom.n_cols, "x"),
                                       ctypes.byref(info), _stream(stream))
     out = dict(iterations=info.iterations, converged=info.converged, rel_residual=info.rel_residual)
