@@ -165,6 +165,48 @@ def age_section(torch, rtt, geos, G, snr0=100.0, rho=1.0, h=3.0):
     return out
 
 
+def estimator_section(torch, rtt, synth, geo, G, snr0=100.0, nh=16, lam=1e-3):
+    """Held-out-style recovery on the benchmark geometry: nh Gaussian-blob histories, data
+    y = A x + seeded noise at sigma_Omega = s_ref / SNR0 (eq. (18)); the ridge estimate and its
+    derivative with respect to the data (forward CG + one more CG), the TSVD estimate and its
+    derivative from the rSVD factors, and the age-window error E(a) of eq. (32) over 0-252M."""
+    from paper_2609_05528_amd.autograd import ridge_estimate, tsvd_estimate
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(synth.blob_histories(geo.grid, nh, dtype=np.float32)).to(dev)
+    sref = float(rtt.reference_response(G)[0])
+    Y = rtt.op_apply(G, X)
+    rtt.noise_add(Y, seed=4242, sigma=sref / snr0)
+    ages = np.arange(0.0, 256.0, 4.0)
+    out = {"histories": nh, "lambda": lam, "sigma_omega": sref / snr0}
+    y = Y.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xr = ridge_estimate(y, G, lam, tol=1e-4, maxit=400)
+    loss = 0.5 * ((xr - X) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    out["ridge_forward_backward_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    E = rtt.age_window_error(G, xr.detach(), X, ages, half_width=2.0, eta=1e-6)
+    out["age_window_error_s"] = time.perf_counter() - t0
+    out["ridge_median_E"] = {str(int(a)): float(np.median(E[:, 0, i])) for i, a in enumerate(ages) if a in (0, 20, 40, 60)}
+    sv = rtt.rsvd(G, k=256, p=8, q=2, seed=2001)
+    y2 = Y.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xt = tsvd_estimate(y2, G, sv, t=0, sigma_min=sref / snr0)
+    (0.5 * ((xt - X) ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    out["tsvd_forward_backward_s"] = time.perf_counter() - t0
+    Et = rtt.age_window_error(G, xt.detach(), X, ages, half_width=2.0, eta=1e-6)
+    out["tsvd_median_E"] = {str(int(a)): float(np.median(Et[:, 0, i])) for i, a in enumerate(ages) if a in (0, 20, 40, 60)}
+    log("estimators: ridge fwd+bwd %.3f s, tsvd fwd+bwd %.3f s, E(a) %.4f s" % (
+        out["ridge_forward_backward_s"], out["tsvd_forward_backward_s"], out["age_window_error_s"]))
+    del sv, y, y2, xr, xt, Y, X
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate(torch, dev, gib=2):
     """Streaming bandwidth of torch's plain copy and fill kernels on 2 GiB (HBM reference)."""
     n = gib * (1 << 30) // 4
@@ -372,6 +414,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixer", action="store_true")
     ap.add_argument("--no-age", action="store_true")
+    ap.add_argument("--no-estimators", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -460,6 +503,7 @@ def main():
 
     mixers = None if args.no_mixer else mixer_section(torch, rtt, oracle, geo, G, Y)
     ages = None if args.no_age else age_section(torch, rtt, [geo], G)
+    estimators = None if args.no_estimators else estimator_section(torch, rtt, synth, geo, G)
 
     # plain per-instance loop on the same GPU (one vector per call)
     plain = None
@@ -563,6 +607,7 @@ def main():
         "batch": batch,
         "mixers": mixers,
         "age_information": ages,
+        "estimators": estimators,
         "parity": parity,
         "cpu_baseline": cpu,
     }
