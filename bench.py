@@ -138,6 +138,13 @@ def age_section(torch, rtt, geos, G, snr0=100.0, rho=1.0, h=3.0):
         arms[kind] = rtt.age_information(G, ages, h=h, mixer=M)
         t_mix[kind] = time.perf_counter() - t0
         del M
+    # the pairing-destroyed control (Sec. 6.4): delays permuted within each order, same noise density
+    import synth
+    Gc = rtt.Geometry([synth.pairing_destroyed(geo, seed=600 + i) for i, geo in enumerate(geos)])
+    t0 = time.perf_counter()
+    arms["pairing_destroyed"] = rtt.age_information(Gc, ages, h=h).sum(axis=2)
+    t_mix["pairing_destroyed"] = time.perf_counter() - t0
+    del Gc
     stats = {}
     for arm, e in arms.items():
         per = []

@@ -208,3 +208,17 @@ def random_geometry(grid: Grid, rays_per_order, seed: int,
         maps.append(RayMap(r=r, phi=phi, delay=delay, weight=w,
                            pixel=np.arange(cnt, dtype=np.int32)))
     return Geometry(grid=grid, maps=maps, label=f"random-{seed}")
+
+
+def pairing_destroyed(geom: Geometry, seed: int) -> Geometry:
+    """The pairing-destroyed control of Sec. 6.4 as an input transform: within every order the
+    delays are permuted among the rays by a seeded permutation, so each order keeps its delay
+    marginal while the association of delay with source position and transfer weight is lost.
+    Radii, azimuths, weights and pixels stay with their rays."""
+    rng = np.random.default_rng(seed)
+    maps = []
+    for m in geom.maps:
+        perm = rng.permutation(m.n_rays)
+        maps.append(dataclasses.replace(m, delay=np.ascontiguousarray(m.delay[perm])))
+    return Geometry(grid=geom.grid, maps=maps, label=(geom.label or "") + "-pairing-destroyed",
+                    image_side=geom.image_side)

@@ -132,3 +132,13 @@ def test_age_reach_matches_the_oracle_on_random_masks():
             assert abs(got["j_old"] - want["j_old"]) <= 1e-12 * max(1.0, want["j_old"])
     with pytest.raises(rtt.RttError, match="equally spaced"):
         rtt.age_reach([0.0, 4.0, 9.0], [1.0, 1.0, 1.0])
+
+
+def test_pairing_destroyed_control_keeps_delay_marginals():
+    geo = tiny_geometry(seed=5, rays=(30, 12, 9))
+    ctl = synth.pairing_destroyed(geo, seed=1)
+    for m, c in zip(geo.maps, ctl.maps):
+        assert np.array_equal(np.sort(m.delay), np.sort(c.delay))
+        assert np.array_equal(m.r, c.r) and np.array_equal(m.weight, c.weight) and np.array_equal(m.pixel, c.pixel)
+    assert not np.array_equal(geo.maps[0].delay, ctl.maps[0].delay)
+    assert np.array_equal(synth.pairing_destroyed(geo, seed=1).maps[1].delay, ctl.maps[1].delay)

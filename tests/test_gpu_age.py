@@ -125,3 +125,16 @@ def test_age_statistics_on_the_kerr_128_workload(gpu_lib):
         say(arm, got["t_reach"], got["l_anchor"], got["j_old"])
         assert got["t_reach"] == want["t_reach"] and got["l_anchor"] == want["l_anchor"]
         assert abs(got["j_old"] - want["j_old"]) <= 1e-12 * max(1.0, want["j_old"])
+
+
+def test_age_information_of_the_pairing_destroyed_control(gpu_lib):
+    """The control of Sec. 6.4 (delays permuted within each order) through the same path: every
+    order's energy against the oracle run on the same permuted maps."""
+    rtt = gpu_lib
+    geo = synth.pairing_destroyed(tiny_geometry(seed=95, rays=(50, 20, 10), n_frames=7, delay_hi=30.0), seed=3)
+    G = rtt.Geometry(geo)
+    ages = np.arange(0.0, 64.0, 4.0) + 0.21
+    say("case pairing-destroyed control")
+    E = rtt.age_information(G, ages, h=3.0)
+    assert relerr(E[:, 0, :3].sum(axis=1), oracle.age_energy(geo, ages, arm="resolved")) < TOL
+    assert relerr(E[:, 0, 0], oracle.age_energy(geo, ages, arm="direct")) < TOL
