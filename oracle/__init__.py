@@ -28,6 +28,9 @@ with the GPU library.
 * ``age_window_error``: E(a) of eq. (32).
 * ``philox4x32_10``, ``normal_draws``: the counter-based generator behind the
   seeded noise draws, written from its published definition.
+* ``synthesis_matrix``, ``synthesis_audit``: the representation synthesis Q_d of
+  Sec. 3.2 eq. (7)-(8) (radial B-splines x azimuthal modes x DCT-II or compact
+  temporal functions) on the coefficient nodes, and the rank audit of A Q_d.
 
 Every function here is pinned by the "not gpu" tests against facts that do
 not come from this module (see the tests' docstrings).
@@ -555,3 +558,60 @@ def normal_draws(n, seed):
             if 4 * i + t < n:
                 out[4 * i + t] = v[t]
     return out
+
+
+# ------------------------------------------------------------------ representation synthesis (Sec. 3.2, eq. (5)-(8); Sec. 7)
+def _radial_bsplines(r, r_in, r_out, n_radial):
+    """Clamped cubic B-splines on uniform knots in log r over [r_in, r_out] (scipy's BSpline
+    evaluates them): [len(r)][n_radial]."""
+    from scipy.interpolate import BSpline
+    u = (np.log(r) - math.log(r_in)) / (math.log(r_out) - math.log(r_in))
+    inner = [j / (n_radial - 3) for j in range(1, n_radial - 3)]
+    t = np.r_[[0.0] * 4, inner, [1.0] * 4]
+    out = np.zeros((len(u), n_radial))
+    for a in range(n_radial):
+        c = np.zeros(n_radial)
+        c[a] = 1.0
+        out[:, a] = BSpline(t, c, 3, extrapolate=False)(np.clip(u, 0.0, 1.0))
+    return np.nan_to_num(out)
+
+
+def synthesis_matrix(grid, n_radial=4, m_max=3, n_temporal=8, temporal="dct", window=None):
+    """Q_d of eq. (7)-(8) evaluated on the coefficient nodes: column (a, b, c) (radial slowest,
+    temporal fastest) holds R_a(r_i) Phi_b(phi_j) T_c(s_k) at node (i, j, k).  R_a: clamped cubic
+    B-splines on uniform knots in log r; Phi_b: 1, cos m phi, sin m phi (m <= m_max); T_c over the
+    source-time window [t_lo, t_hi] (default [s0 - dt/2, s0 + (K - 1/2) dt], where the DCT-II modes
+    on the nodes are exactly the discrete DCT-II vectors): "dct" = cos(pi c (t - t_lo)/(t_hi - t_lo)),
+    "hats" = degree-one B-splines on n_temporal uniform knots from t_lo to t_hi.  [n_cols][d]."""
+    rc = grid.r_in + (np.arange(grid.n_r) + 0.5) * (grid.r_out - grid.r_in) / grid.n_r
+    pc = (np.arange(grid.n_phi) + 0.5) * 2.0 * math.pi / grid.n_phi
+    sk = grid.s0 + grid.dt_src * np.arange(grid.n_hat)
+    t_lo, t_hi = window if window is not None else (grid.s0 - 0.5 * grid.dt_src,
+                                                   grid.s0 + (grid.n_hat - 0.5) * grid.dt_src)
+    R = _radial_bsplines(rc, grid.r_in, grid.r_out, n_radial)                  # [n_r][n_radial]
+    az = [np.ones_like(pc)]
+    for m in range(1, m_max + 1):
+        az += [np.cos(m * pc), np.sin(m * pc)]
+    P = np.stack(az, axis=1)                                                   # [n_phi][2 m_max + 1]
+    if temporal == "dct":
+        T = np.stack([np.cos(math.pi * c * (sk - t_lo) / (t_hi - t_lo)) for c in range(n_temporal)], axis=1)
+    elif temporal == "hats":
+        knots = np.linspace(t_lo, t_hi, n_temporal)
+        w = (t_hi - t_lo) / (n_temporal - 1)
+        T = np.stack([np.maximum(0.0, 1.0 - np.abs(sk - knots[c]) / w) for c in range(n_temporal)], axis=1)
+    else:
+        raise ValueError("temporal must be 'dct' or 'hats'")
+    Q = np.einsum("ia,jb,kc->ijkabc", R, P, T)
+    return Q.reshape(grid.n_cols, R.shape[1] * P.shape[1] * T.shape[1])
+
+
+def synthesis_audit(geom, Q, order_mask=None, rel_tol=1e-7):
+    """Rank audit of A^(d) = A Q_d (eq. (7)) restricted to the selected orders' rows: the indices of
+    exactly zero columns, the singular values (LAPACK SVD of the dense FP64 product) and the
+    numerical rank at rel_tol * sigma_max."""
+    A = dense(geom, order_mask)
+    AQ = A @ Q
+    zero = [int(c) for c in range(AQ.shape[1]) if not np.any(AQ[:, c])]
+    s = np.linalg.svd(AQ, compute_uv=False)
+    rank = int(np.sum(s > rel_tol * s[0])) if s.size and s[0] > 0 else 0
+    return dict(zero_columns=zero, sigma=s, rank=rank)

@@ -611,3 +611,52 @@ def test_normal_draws_are_standard_normal():
     assert abs(z.mean()) < 0.03 and abs(z.var() - 1.0) < 0.03
     assert stats.kstest(z, "norm").pvalue > 1e-3
     assert not np.allclose(oracle.normal_draws(16, seed=1235), z[:16])
+
+
+# ----------------------------------------------------------------------------- representation synthesis (Sec. 3.2, 7)
+def test_radial_bsplines_are_the_bernstein_basis_and_a_partition_of_unity():
+    """Clamped cubic B-splines without interior knots are the cubic Bernstein polynomials in
+    u = log(r / r_in) / log(r_out / r_in); with interior knots they still sum to one."""
+    r = np.linspace(6.0, 20.0, 57)
+    u = np.log(r / 6.0) / math.log(20.0 / 6.0)
+    B = oracle._radial_bsplines(r, 6.0, 20.0, 4)
+    bern = np.stack([math.comb(3, a) * u ** a * (1 - u) ** (3 - a) for a in range(4)], axis=1)
+    assert np.allclose(B, bern, atol=1e-13)
+    B7 = oracle._radial_bsplines(r, 6.0, 20.0, 7)
+    assert np.allclose(B7.sum(axis=1), 1.0, atol=1e-13)
+    assert B7[0, 0] == 1.0 and abs(B7[-1, -1] - 1.0) < 1e-13 and np.all(B7 >= 0)
+
+
+def test_synthesis_temporal_and_azimuthal_factors():
+    """On the default window the DCT columns at the hat nodes are scipy's DCT-II vectors; the
+    azimuthal factors are orthogonal over the node grid."""
+    from scipy.fft import dct
+    g = tiny_geometry(seed=1, n_phi=9).grid
+    Q = oracle.synthesis_matrix(g, n_radial=4, m_max=3, n_temporal=8, temporal="dct")
+    T = Q.reshape(g.n_r, g.n_phi, g.n_hat, 4, 7, 8)[0, 0, :, 0, 0, :]      # R_0(r_0) Phi_0 = R_0(r_0)
+    T = T / T[0, 0]
+    x = np.random.default_rng(3).standard_normal(g.n_hat)
+    assert np.allclose(T.T @ x, dct(x, type=2)[:8] / 2.0, atol=1e-12)
+    P = Q.reshape(g.n_r, g.n_phi, g.n_hat, 4, 7, 8)[0, :, 0, 0, :, 0]
+    PtP = P.T @ P
+    assert np.allclose(PtP - np.diag(np.diag(PtP)), 0.0, atol=1e-12 * np.abs(PtP).max())
+
+
+def test_compact_temporal_class_has_exact_zero_columns_where_the_direct_footprint_is_missed():
+    """Sec. 7 / Thm 4.1: a temporal function whose node support is farther than one hat width from
+    every direct retarded time t_f - Delta_p gives an exactly zero column of A_0 Q for each of the
+    28 spatial functions; counted by brute force over the data."""
+    geo = tiny_geometry(seed=41, rays=(15, 6, 4), n_frames=3, n_r=4, n_phi=8, delay_hi=6.0)
+    g = geo.grid
+    Q = oracle.synthesis_matrix(g, temporal="hats", n_temporal=8)
+    audit = oracle.synthesis_audit(geo, Q, order_mask=1)
+    sk = g.s0 + g.dt_src * np.arange(g.n_hat)
+    T = Q.reshape(g.n_r, g.n_phi, g.n_hat, 4, 7, 8)[0, 0, :, 0, 0, :]
+    t_ret = np.array([g.t0 + g.dt_obs * f - d for d in geo.maps[0].delay for f in range(g.n_frames)])
+    blind = [c for c in range(8)
+             if not any(T[k, c] != 0 and np.any(np.abs(sk[k] - t_ret) < g.dt_src) for k in range(g.n_hat))]
+    assert 0 < len(blind) < 8
+    assert len(audit["zero_columns"]) == 28 * len(blind)
+    assert sorted({c % 8 for c in audit["zero_columns"]}) == blind
+    # the resolved stack reaches further back: fewer zero columns
+    assert len(oracle.synthesis_audit(geo, Q)["zero_columns"]) < len(audit["zero_columns"])
