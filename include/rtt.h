@@ -474,6 +474,57 @@ int age_window_error(const rtt_geometry* geom, const float* x_hat, const float* 
                      const double* ages, int32_t n_ages, double half_width, double eta, double* err,
                      void* stream);
 
+/* ------------------------------------------------- representation synthesis */
+/*
+ * A synthesis map Q_d (Sec. 3.2 eq. (5)-(8)) evaluated on the coefficient
+ * nodes of one geometry g: column (a, b, c), index (a * n_az + b) * n_temporal
+ * + c with n_az = 2 m_max + 1, holds R_a(r_i) Phi_b(phi_j) T_c(s_k) at node
+ * (cell centre (r_i, phi_j), hat centre s_k).  R_a: clamped cubic B-splines on
+ * uniform knots in log r over [r_in, r_out]; Phi_b: 1, cos m phi, sin m phi
+ * (m = 1..m_max, in that order); T_c: global DCT-II modes
+ * cos(pi c (t - t_lo) / (t_hi - t_lo)), or the compact temporal functions of
+ * Sec. 7 (degree-one B-splines on n_temporal uniform knots from t_lo to
+ * t_hi).  The default window [s0 - dt_src/2, s0 + (K - 1/2) dt_src] makes the
+ * DCT-II modes on the hat nodes the discrete DCT-II vectors.  The paper's
+ * S_224 is n_radial = 4, m_max = 3, n_temporal = 8.  A^(d) = A Q_d (eq. (7))
+ * is op_apply after synth_expand.
+ */
+typedef struct rtt_synthesis rtt_synthesis; /* opaque; owns the rows of Q on the device */
+enum { RTT_SYNTH_DCT = 0, RTT_SYNTH_HATS = 1 };
+typedef struct {
+    int32_t n_radial;    /* radial B-splines, 4..64                            */
+    int32_t m_max;       /* highest azimuthal mode, 0..32                      */
+    int32_t n_temporal;  /* temporal functions, 1..256 (hats: >= 2)            */
+    int32_t temporal;    /* RTT_SYNTH_DCT or RTT_SYNTH_HATS                    */
+    double t_lo, t_hi;   /* source-time window; t_hi <= t_lo: the default      */
+    int32_t reserved[4];
+} rtt_synthesis_spec;
+
+/* Build Q for geometry g of geom (d = n_radial (2 m_max + 1) n_temporal <= 4096
+ * columns; d x n_cols floats on the device).  Blocking.  Errors: RTT_EINVAL,
+ * RTT_ENOMEM, RTT_EDEVICE. */
+int synthesis_create(const rtt_geometry* geom, int32_t g, const rtt_synthesis_spec* spec, rtt_synthesis** out);
+int synthesis_free(rtt_synthesis* synth);
+/* d, the geometry's n_cols, and the device rows of Q ([d][n_cols], column c of Q
+ * as row c); any output may be NULL. */
+int synthesis_info(const rtt_synthesis* synth, int32_t* d, int64_t* n_cols, const float** rows);
+/* x = Q_d c: c device [nvec][d], x device [nvec][n_cols] (MFMA combine).  Keeps a
+ * small scratch (d x nvec floats) in the handle; calls must not overlap. */
+int synth_expand(const rtt_synthesis* synth, const float* c, float* x, int32_t nvec, void* stream);
+/* c = Q_d^T x (the transpose, so Q_d^T A^T is the adjoint of A^(d)): x device
+ * [nvec][n_cols], c device [nvec][d]; FP64 accumulation (MFMA Gram). */
+int synth_project(const rtt_synthesis* synth, const float* x, float* c, int32_t nvec, void* stream);
+/*
+ * synthesis_audit -- rank audit of A^(d) = A Q_d restricted to the rows of
+ * the orders in order_mask (0 = all): zero (nullable, host uint8[d]) flags the
+ * columns that are exactly zero (every datum 0, the Sec. 7 blindness); sigma
+ * (nullable, host double[d]) receives the singular values, descending, as the
+ * square roots of the eigenvalues of the FP64 Gram (A^(d))^T A^(d) — resolved
+ * down to about 1e-7 of sigma_1.  Blocking; allocates d x rows floats.
+ */
+int synthesis_audit(const rtt_geometry* geom, const rtt_synthesis* synth, uint32_t order_mask, double* sigma,
+                    uint8_t* zero, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);
 

@@ -26,7 +26,8 @@ EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member"
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
             "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
             "mix_apply", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
-            "age_reach", "age_window_error", "tsvd_project", "noise_add", "last_error")
+            "age_reach", "age_window_error", "tsvd_project", "noise_add", "synthesis_create", "synthesis_free",
+            "synthesis_info", "synth_expand", "synth_project", "synthesis_audit", "last_error")
 
 
 class RttError(RuntimeError):
@@ -142,6 +143,12 @@ def require_native():
         "age_window_error": [vp, vp, vp, i32, _dp, i32, ctypes.c_double, ctypes.c_double, _dp, vp],
         "tsvd_project": [vp, vp, vp, i32, i32, ctypes.c_double, vp, vp],
         "noise_add": [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, vp],
+        "synthesis_create": [vp, i32, vp, ctypes.POINTER(vp)],
+        "synthesis_free": [vp],
+        "synthesis_info": [vp, vp, vp, vp],
+        "synth_expand": [vp, vp, vp, i32, vp],
+        "synth_project": [vp, vp, vp, i32, vp],
+        "synthesis_audit": [vp, vp, u32, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -328,5 +335,6 @@ def op_apply_adjoint(geom: Geometry, y, x=None, order_mask: int = 0, stream=None
 from .svd import SVD, rsvd, tsvd_solve, tsvd_project, ridge_solve  # noqa: E402,F401
 from .autograd import RetardedTimeOp, retarded_time_apply  # noqa: E402,F401
 from .mixer import Mixer, mixer_create, mix_apply, mix_adjoint, mix_covariance  # noqa: E402,F401
+from .synthesis import Synthesis  # noqa: E402,F401
 from .age import (reference_response, age_information, age_window, age_reach,  # noqa: E402,F401
                   age_window_error, noise_add)

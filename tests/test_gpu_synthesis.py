@@ -1,0 +1,85 @@
+"""Representation synthesis Q_d (Sec. 3.2, Sec. 7) and the rank audit of A Q_d on the GPU against the
+FP64 oracle: the rows of Q, the synthesis and its transpose, exactly zero columns and singular
+values on a small geometry (DCT-II and compact temporal classes; singular values >= 1e-2 sigma_1 to
+1e-4, the accuracy FP32 responses allow), and the S_224 audit of the 128^2 x 128-frame Kerr workload
+(zero columns exactly, leading singular values to 1e-4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tinygeo import tiny_geometry
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("temporal,n_radial,n_temporal", [("dct", 4, 8), ("hats", 6, 8), ("dct", 5, 3)])
+def test_synthesis_rows_expand_and_project_match_oracle(gpu_lib, temporal, n_radial, n_temporal):
+    import torch
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=41, rays=(15, 6, 4), n_frames=3, n_r=4, n_phi=8, delay_hi=6.0)
+    G = rtt.Geometry(geo)
+    say("case synthesis", temporal, n_radial, n_temporal)
+    S = rtt.Synthesis(G, 0, n_radial=n_radial, m_max=3, n_temporal=n_temporal, temporal=temporal)
+    Q = oracle.synthesis_matrix(geo.grid, n_radial=n_radial, m_max=3, n_temporal=n_temporal, temporal=temporal)
+    assert S.d == Q.shape[1] and S.n_cols == geo.grid.n_cols
+    rows = S.expand(torch.eye(S.d, device="cuda")).cpu().numpy()
+    assert rel(rows, Q.T) < 1e-6
+    rng = np.random.default_rng(42)
+    c = rng.standard_normal((5, S.d))
+    x = rng.standard_normal((5, S.n_cols))
+    assert rel(S.expand(to_dev(c)).cpu().numpy(), c.astype(np.float32) @ Q.T) < 1e-5
+    assert rel(S.project(to_dev(x)).cpu().numpy(), x.astype(np.float32) @ Q) < 1e-5
+    for mask in (1, 0):
+        got = S.audit(G, order_mask=mask)
+        want = oracle.synthesis_audit(geo, Q, order_mask=None if mask == 0 else mask)
+        assert got["zero_columns"] == want["zero_columns"], (mask, len(got["zero_columns"]), len(want["zero_columns"]))
+        s_w = want["sigma"]
+        keep = s_w >= 1e-2 * s_w[0]          # FP32 responses: sigma_i good to ~1e-7 sigma_1 / sigma_i
+        assert np.max(np.abs(got["sigma"][:keep.sum()] - s_w[keep]) / s_w[keep]) < 1e-4
+    if temporal == "hats":
+        assert len(S.audit(G, order_mask=1)["zero_columns"]) > 0
+
+
+def test_s224_audit_on_the_kerr_128_workload(gpu_lib):
+    """S_224 on the 128^2 workload: direct and resolved arms.  Zero columns against the oracle's
+    responses to every column of Q; the leading singular values against the FP64 Gram of those
+    responses."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg2")
+    G = rtt.Geometry(geo)
+    say("case S224 cfg2")
+    for temporal in ("dct", "hats"):
+        S = rtt.Synthesis(G, 0, temporal=temporal)
+        Q = oracle.synthesis_matrix(geo.grid, temporal=temporal)
+        m0 = geo.maps[0].n_rays * geo.grid.n_frames
+        Ys = [oracle.forward(geo, Q[:, b:b + 32].T) for b in range(0, S.d, 32)]
+        Y = np.concatenate(Ys, axis=0)                       # [d][rows], FP64
+        for mask, rows in ((1, slice(0, m0)), (0, slice(0, Y.shape[1]))):
+            got = S.audit(G, order_mask=mask)
+            Ym = Y[:, rows]
+            zero = [int(c) for c in range(S.d) if not np.any(Ym[c])]
+            assert got["zero_columns"] == zero, (temporal, mask)
+            Gm = Ym @ Ym.T
+            s_w = np.sqrt(np.maximum(np.linalg.eigvalsh(Gm)[::-1], 0.0))
+            say(temporal, mask, "zero", len(zero), "rank", got["rank"], "sigma1", got["sigma"][0])
+            assert np.max(np.abs(got["sigma"][:10] - s_w[:10]) / s_w[:10]) < 1e-4
