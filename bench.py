@@ -214,6 +214,51 @@ def estimator_section(torch, rtt, synth, geo, G, snr0=100.0, nh=16, lam=1e-3):
     return out
 
 
+def synthesis_section(torch, rtt, G, snr0=100.0):
+    """Table-4-style audit of the benchmark geometry (Sec. 3.2, Sec. 7): A Q_d for S_224 with global
+    DCT-II and with compact temporal functions, direct and resolved arms: exactly zero columns,
+    numerical rank (1e-6 sigma_1) and operational rank at SNR0 (sigma >= s_ref / SNR0, eq. (31));
+    and the throughput of A^(d) = A Q_d on a block of 264 coefficient vectors."""
+    sref = float(rtt.reference_response(G)[0])
+    out = {"snr0": snr0}
+    for temporal in ("dct", "hats"):
+        S = rtt.Synthesis(G, 0, temporal=temporal)
+        for arm, mask in (("direct", 1), ("resolved", 0)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a = S.audit(G, order_mask=mask)
+            dt = time.perf_counter() - t0
+            out["%s_%s" % (temporal, arm)] = {
+                "d": S.d, "zero_columns": len(a["zero_columns"]), "rank": a["rank"],
+                "operational_rank": int(np.sum(a["sigma"] >= sref / snr0)), "sigma_1": float(a["sigma"][0]),
+                "audit_s": dt}
+        if temporal == "dct":
+            C = torch.randn(264, S.d, device="cuda")
+            X = torch.empty(264, S.n_cols, device="cuda")
+            Y = torch.empty(264, G.n_rows, device="cuda")
+            S.expand(C, X)
+            rtt.op_apply(G, X, Y)
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            for _ in range(5):
+                S.expand(C, X)
+            e[1].record()
+            for _ in range(5):
+                rtt.op_apply(G, X, Y)
+            e[2].record()
+            torch.cuda.synchronize()
+            ms_q, ms_a = e[0].elapsed_time(e[1]) / 5, e[1].elapsed_time(e[2]) / 5
+            out["expand_ms"] = ms_q
+            out["a_of_q_applies_per_s"] = 264 / ((ms_q + ms_a) * 1e-3)
+            del C, X, Y
+        del S
+        torch.cuda.empty_cache()
+    log("synthesis audit: %s" % {k: (v["zero_columns"], v["rank"], v["operational_rank"])
+                                  for k, v in out.items() if isinstance(v, dict)})
+    return out
+
+
 def calibrate(torch, dev, gib=2):
     """Streaming bandwidth of torch's plain copy and fill kernels on 2 GiB (HBM reference)."""
     n = gib * (1 << 30) // 4
@@ -422,6 +467,7 @@ def main():
     ap.add_argument("--no-mixer", action="store_true")
     ap.add_argument("--no-age", action="store_true")
     ap.add_argument("--no-estimators", action="store_true")
+    ap.add_argument("--no-synthesis", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -511,6 +557,7 @@ def main():
     mixers = None if args.no_mixer else mixer_section(torch, rtt, oracle, geo, G, Y)
     ages = None if args.no_age else age_section(torch, rtt, [geo], G)
     estimators = None if args.no_estimators else estimator_section(torch, rtt, synth, geo, G)
+    synthesis = None if args.no_synthesis else synthesis_section(torch, rtt, G)
 
     # plain per-instance loop on the same GPU (one vector per call)
     plain = None
@@ -615,6 +662,7 @@ def main():
         "mixers": mixers,
         "age_information": ages,
         "estimators": estimators,
+        "synthesis": synthesis,
         "parity": parity,
         "cpu_baseline": cpu,
     }

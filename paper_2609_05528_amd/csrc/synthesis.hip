@@ -29,6 +29,10 @@ struct rtt_synthesis {
     double t_lo = 0.0, t_hi = 0.0;
     int64_t n_cols = 0;       // the member's coefficient length
     float* d_Q = nullptr;     // [d][n_cols]: row (a, b, c) = column (a, b, c) of Q
+    // FP32 factor tables of the separable path: R [n_radial][n_r], P [n_az][n_phi], T [n_temporal][K]
+    float *d_R = nullptr, *d_P = nullptr, *d_T = nullptr;
+    int32_t n_r = 0, n_phi = 0, K = 0;
+    bool separable = false;   // the factor-by-factor kernels fit their LDS limits
     int device = 0;
     mutable rtt::Workspace ws;
     uint32_t magic = rtt::SYN_MAGIC;
@@ -93,6 +97,96 @@ __global__ __launch_bounds__(GT * GT) void k_gram_f64(const float* __restrict__ 
         __syncthreads();
     }
     if (u0 + ty < d && v0 + tx < d) G[(int64_t)(u0 + ty) * d + v0 + tx] = acc;
+}
+
+// Separable synthesis x = Q c, one block per (radial node i, vector v): W[a][b][k] = sum_c T[c][k]
+// c[a][b][c], V[b][k] = sum_a R[a][i] W[a][b][k], x[i][j][k] = sum_b P[b][j] V[b][k] (fixed order).
+constexpr int SYN_LDS = 16384;   // floats of dynamic LDS the separable kernels may use (64 KiB)
+__global__ __launch_bounds__(256) void k_synth_expand(const float* __restrict__ R, const float* __restrict__ P,
+                                                      const float* __restrict__ T, int nR, int nA, int nT, int n_r,
+                                                      int n_phi, int K, const float* __restrict__ c, float* __restrict__ x,
+                                                      int64_t n_cols)
+{
+    extern __shared__ float lds[];
+    const int d = nR * nA * nT;
+    float* cs = lds;                  // d
+    float* W = cs + d;                // nR * nA * K
+    float* V = W + nR * nA * K;       // nA * K
+    const int i = blockIdx.x;
+    const int64_t v = blockIdx.y;
+    for (int q = threadIdx.x; q < d; q += blockDim.x) cs[q] = c[v * d + q];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nR * nA * K; e += blockDim.x) {
+        const int k = e % K, ab = e / K;
+        float acc = 0.f;
+        for (int q = 0; q < nT; ++q) acc += T[q * K + k] * cs[ab * nT + q];
+        W[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nA * K; e += blockDim.x) {
+        const int k = e % K, b = e / K;
+        float acc = 0.f;
+        for (int a = 0; a < nR; ++a) acc += R[a * n_r + i] * W[(a * nA + b) * K + k];
+        V[e] = acc;
+    }
+    __syncthreads();
+    float* xr = x + v * n_cols + (int64_t)i * n_phi * K;
+    for (int e = threadIdx.x; e < n_phi * K; e += blockDim.x) {
+        const int k = e % K, j = e / K;
+        float acc = 0.f;
+        for (int b = 0; b < nA; ++b) acc += P[b * n_phi + j] * V[b * K + k];
+        xr[e] = acc;
+    }
+}
+
+// Separable transpose, one block per (radial node i, vector v): U[j][c] = sum_k T[c][k] x[i][j][k],
+// Z[b][c] = sum_j P[b][j] U[j][c], part[v][i][a][b][c] = R[a][i] Z[b][c]; then the radial sum.
+__global__ __launch_bounds__(256) void k_synth_project_part(const float* __restrict__ R, const float* __restrict__ P,
+                                                            const float* __restrict__ T, int nR, int nA, int nT,
+                                                            int n_r, int n_phi, int K, const float* __restrict__ x,
+                                                            int64_t n_cols, float* __restrict__ part)
+{
+    extern __shared__ float lds[];
+    float* xs = lds;                  // n_phi * K
+    float* U = xs + n_phi * K;        // n_phi * nT
+    float* Z = U + n_phi * nT;        // nA * nT
+    const int i = blockIdx.x;
+    const int64_t v = blockIdx.y;
+    const float* xr = x + v * n_cols + (int64_t)i * n_phi * K;
+    for (int e = threadIdx.x; e < n_phi * K; e += blockDim.x) xs[e] = xr[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n_phi * nT; e += blockDim.x) {
+        const int q = e % nT, j = e / nT;
+        float acc = 0.f;
+        for (int k = 0; k < K; ++k) acc += T[q * K + k] * xs[j * K + k];
+        U[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nA * nT; e += blockDim.x) {
+        const int q = e % nT, b = e / nT;
+        float acc = 0.f;
+        for (int j = 0; j < n_phi; ++j) acc += P[b * n_phi + j] * U[j * nT + q];
+        Z[e] = acc;
+    }
+    __syncthreads();
+    const int d = nR * nA * nT;
+    float* pr = part + (v * n_r + i) * d;
+    for (int e = threadIdx.x; e < d; e += blockDim.x) {
+        const int bq = e % (nA * nT), a = e / (nA * nT);
+        pr[e] = R[a * n_r + i] * Z[bq];
+    }
+}
+
+// c[v][q] = sum over radial nodes i (ascending) of part[v][i][q], in FP64
+__global__ void k_synth_project_sum(const float* __restrict__ part, int n_r, int d, int nvec, float* __restrict__ c)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)d * nvec) return;
+    const int64_t v = t / d;
+    const int q = (int)(t % d);
+    double acc = 0.0;
+    for (int i = 0; i < n_r; ++i) acc += (double)part[(v * n_r + i) * d + q];
+    c[t] = (float)acc;
 }
 
 bool valid_syn(const rtt_synthesis* s) { return s && s->magic == SYN_MAGIC; }
@@ -218,8 +312,25 @@ extern "C" int synthesis_create(const rtt_geometry* g, int32_t gi, const rtt_syn
     if (e == hipSuccess) e = hipDeviceSynchronize();
     for (double* p : {dR, dP, dT})
         if (p) (void)hipFree(p);
+    s->n_r = gr.n_r;
+    s->n_phi = gr.n_phi;
+    s->K = gr.n_hat;
+    s->separable = d + (int64_t)nR * nA * gr.n_hat + (int64_t)nA * gr.n_hat <= SYN_LDS &&
+                   (int64_t)gr.n_phi * gr.n_hat + (int64_t)gr.n_phi * nT + (int64_t)nA * nT <= SYN_LDS;
+    if (e == hipSuccess) {
+        std::vector<float> fR(R.begin(), R.end()), fP(P.begin(), P.end()), fT(T.begin(), T.end());
+        auto up = [&](float** dst, const std::vector<float>& h) {
+            if (e != hipSuccess) return;
+            e = hipMalloc((void**)dst, sizeof(float) * h.size());
+            if (e == hipSuccess) e = hipMemcpy(*dst, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice);
+        };
+        up(&s->d_R, fR);
+        up(&s->d_P, fP);
+        up(&s->d_T, fT);
+    }
     if (e != hipSuccess) {
-        if (s->d_Q) (void)hipFree(s->d_Q);
+        for (float* p : {s->d_Q, s->d_R, s->d_P, s->d_T})
+            if (p) (void)hipFree(p);
         s->magic = 0;
         delete s;
         return e == hipErrorOutOfMemory ? fail(RTT_ENOMEM, "synthesis tables") : hip_fail(e, "synthesis_create");
@@ -233,7 +344,8 @@ extern "C" int synthesis_free(rtt_synthesis* s)
     if (!s) return RTT_OK;
     if (!valid_syn(s)) return fail(RTT_EINVAL, "invalid synthesis handle");
     (void)hipSetDevice(s->device);
-    if (s->d_Q) (void)hipFree(s->d_Q);
+    for (float* p : {s->d_Q, s->d_R, s->d_P, s->d_T})
+        if (p) (void)hipFree(p);
     s->ws.release();
     s->magic = 0;
     delete s;
@@ -257,6 +369,13 @@ extern "C" int synth_expand(const rtt_synthesis* s, const float* c, float* x, in
     if (!c || !x) return fail(RTT_EINVAL, "NULL data pointer");
     hipStream_t st = (hipStream_t)stream;
     RTT_HIP(hipSetDevice(s->device));
+    if (s->separable) {
+        const size_t lds = sizeof(float) * ((size_t)s->d + (size_t)s->n_radial * s->n_az * s->K + (size_t)s->n_az * s->K);
+        hipLaunchKernelGGL(k_synth_expand, dim3((unsigned)s->n_r, (unsigned)nvec), dim3(256), lds, st, s->d_R, s->d_P,
+                           s->d_T, s->n_radial, s->n_az, s->n_temporal, s->n_r, s->n_phi, s->K, c, x, s->n_cols);
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     float* Ct = (float*)s->ws.get("ct", sizeof(float) * (size_t)s->d * nvec);
     if (!Ct) return fail(RTT_ENOMEM, "synth_expand scratch");
     const int64_t tot = (int64_t)s->d * nvec;
@@ -273,6 +392,20 @@ extern "C" int synth_project(const rtt_synthesis* s, const float* x, float* c, i
     if (!c || !x) return fail(RTT_EINVAL, "NULL data pointer");
     hipStream_t st = (hipStream_t)stream;
     RTT_HIP(hipSetDevice(s->device));
+    if (s->separable) {
+        float* part = (float*)s->ws.get("part", sizeof(float) * (size_t)nvec * s->n_r * s->d);
+        if (!part) return fail(RTT_ENOMEM, "synth_project scratch");
+        const size_t lds = sizeof(float) * ((size_t)s->n_phi * s->K + (size_t)s->n_phi * s->n_temporal +
+                                            (size_t)s->n_az * s->n_temporal);
+        hipLaunchKernelGGL(k_synth_project_part, dim3((unsigned)s->n_r, (unsigned)nvec), dim3(256), lds, st, s->d_R,
+                           s->d_P, s->d_T, s->n_radial, s->n_az, s->n_temporal, s->n_r, s->n_phi, s->K, x, s->n_cols,
+                           part);
+        const int64_t tot = (int64_t)s->d * nvec;
+        hipLaunchKernelGGL(k_synth_project_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, s->n_r,
+                           s->d, nvec, c);
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     double* G = (double*)s->ws.get("g", sizeof(double) * (size_t)s->d * nvec);
     if (!G) return fail(RTT_ENOMEM, "synth_project scratch");
     if ((rc = gram(s->ws, s->d_Q, s->n_cols, x, s->n_cols, s->d, nvec, s->n_cols, G, st))) return rc;
