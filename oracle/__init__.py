@@ -28,6 +28,8 @@ with the GPU library.
 * ``age_window_error``: E(a) of eq. (32).
 * ``philox4x32_10``, ``normal_draws``: the counter-based generator behind the
   seeded noise draws, written from its published definition.
+* ``localized_probe_norms``, ``age_fisher``: the 28-direction localised probe
+  class of eq. (14) and its age-local Fisher matrix M(a) = P^T P.
 * ``synthesis_matrix``, ``synthesis_audit``: the representation synthesis Q_d of
   Sec. 3.2 eq. (7)-(8) (radial B-splines x azimuthal modes x DCT-II or compact
   temporal functions) on the coefficient nodes, and the rank audit of A Q_d.
@@ -615,3 +617,36 @@ def synthesis_audit(geom, Q, order_mask=None, rel_tol=1e-7):
     s = np.linalg.svd(AQ, compute_uv=False)
     rank = int(np.sum(s > rel_tol * s[0])) if s.size and s[0] > 0 else 0
     return dict(zero_columns=zero, sigma=s, rank=rank)
+
+
+def localized_probe_norms(grid, n_radial=4, m_max=3, h=3.0):
+    """N_{h,l} of eq. (14) for the spatial functions psi_l = R_a Phi_b (l = a (2 m_max + 1) + b): the
+    L2 norm of psi_l(r, phi) exp(-(t + a)^2 / (2 h^2)) over the annulus (area measure) and time,
+    with the radial integral of the continuum B-spline by adaptive quadrature."""
+    from scipy.integrate import quad
+    out = []
+    for a in range(n_radial):
+        rad = quad(lambda r: _radial_bsplines(np.array([r]), grid.r_in, grid.r_out, n_radial)[0, a] ** 2 * r,
+                   grid.r_in, grid.r_out, limit=200, epsabs=0.0, epsrel=1e-12)[0]
+        for b in range(2 * m_max + 1):
+            az = 2.0 * math.pi if b == 0 else math.pi
+            out.append(math.sqrt(rad * az * h * math.sqrt(math.pi)))
+    return np.array(out)
+
+
+def age_fisher(geom, ages, h=3.0, n_radial=4, m_max=3, order_mask=None):
+    """M(a) = P(a)^T P(a) of eq. (14) for the localised probes q_{a,l} = psi_l g_a / N_{h,l} set on the
+    coefficient nodes (psi_l = R_a Phi_b from the synthesis factors, g_a the Gaussian of eq. (10)),
+    P(a) = A q_{a,l} column by column (C = I).  Returns [len(ages)][L][L], L = n_radial (2 m_max + 1)."""
+    g = geom.grid
+    Q = synthesis_matrix(g, n_radial=n_radial, m_max=m_max, n_temporal=1, temporal="dct")   # T_0 = 1
+    norms = localized_probe_norms(g, n_radial, m_max, h)
+    sk = g.s0 + g.dt_src * np.arange(g.n_hat)
+    S = Q.reshape(g.n_cells, g.n_hat, -1)[:, 0, :]                 # psi_l at the cell nodes: [cells][L]
+    out = []
+    for a in ages:
+        gt = np.exp(-((sk + a) ** 2) / (2.0 * h * h))
+        X = np.einsum("sl,k->lsk", S, gt).reshape(S.shape[1], g.n_cols) / norms[:, None]
+        P = forward(geom, X, order_mask=order_mask)                  # [L][rows]
+        out.append(P @ P.T)
+    return np.array(out)

@@ -660,3 +660,38 @@ def test_compact_temporal_class_has_exact_zero_columns_where_the_direct_footprin
     assert sorted({c % 8 for c in audit["zero_columns"]}) == blind
     # the resolved stack reaches further back: fewer zero columns
     assert len(oracle.synthesis_audit(geo, Q)["zero_columns"]) < len(audit["zero_columns"])
+
+
+def test_localized_probes_have_unit_norm():
+    """eq. (14): psi_l g_a / N_{h,l} has unit L2 norm, by a 2-D quadrature over the annulus (in
+    Cartesian-free polar form r dr dphi) that does not separate the radial and azimuthal factors."""
+    from scipy.integrate import dblquad
+    g = tiny_geometry(seed=1).grid
+    n = oracle.localized_probe_norms(g, 4, 3, h=3.0)
+    for l in (0, 5, 13, 27):
+        a, b = divmod(l, 7)
+        m = (b + 1) // 2
+
+        def psi2(phi, r):
+            R = oracle._radial_bsplines(np.array([r]), g.r_in, g.r_out, 4)[0, a]
+            P = 1.0 if b == 0 else (math.cos(m * phi) if b % 2 == 1 else math.sin(m * phi))
+            return (R * P) ** 2 * r
+        sp = dblquad(psi2, g.r_in, g.r_out, 0.0, 2.0 * math.pi, epsabs=0.0, epsrel=1e-10)[0]
+        assert abs(sp * 3.0 * math.sqrt(math.pi) / n[l] ** 2 - 1.0) < 1e-8
+
+
+def test_fisher_reproduces_the_flat_probe_information():
+    """The radial B-splines sum to one on the nodes, so the flat probe of eq. (10) is the combination
+    sum_a (N_{h,(a,0)} / N_h) q_{a,(a,0)} of localised probes and its information (computed by the
+    separate flat-probe routine) is the matching quadratic form of M(a)."""
+    geo = tiny_geometry(seed=9, rays=(14, 8, 5), n_frames=5)
+    ages = np.array([0.0, 7.0, 20.0])
+    M = oracle.age_fisher(geo, ages, h=3.0)
+    assert np.allclose(M, np.transpose(M, (0, 2, 1)), rtol=1e-12, atol=1e-15)
+    assert np.all(np.linalg.eigvalsh(M) > -1e-12 * np.abs(M).max())
+    nl = oracle.localized_probe_norms(geo.grid, 4, 3, 3.0)
+    w = np.zeros(28)
+    for a in range(4):
+        w[a * 7] = nl[a * 7] / oracle.probe_norm(geo.grid, 3.0)
+    flat = oracle.age_energy(geo, ages, h=3.0, arm="resolved")
+    assert np.allclose(np.einsum("l,alm,m->a", w, M, w), flat, rtol=1e-10)
