@@ -254,8 +254,21 @@ def synthesis_section(torch, rtt, G, snr0=100.0):
             del C, X, Y
         del S
         torch.cuda.empty_cache()
+    # localised probe class of eq. (14): M(a) over the 64-centre grid; localised directional reach =
+    # deepest age at which some normalised direction clears threshold (SNR0^2 M_ll / s_ref^2 >= 1)
+    S = rtt.Synthesis(G, 0)
+    ages = np.arange(0.0, 256.0, 4.0)
+    for arm, mask in (("direct", 1), ("resolved", 0)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = S.age_fisher(G, ages, h=3.0, order_mask=mask)
+        dt = time.perf_counter() - t0
+        diag = snr0 ** 2 * np.einsum("all->al", M) / sref ** 2
+        passing = ages[np.any(diag >= 1.0, axis=1)]
+        out["fisher_%s" % arm] = {"seconds": dt, "localized_reach": float(passing.max()) if passing.size else None}
+    del S
     log("synthesis audit: %s" % {k: (v["zero_columns"], v["rank"], v["operational_rank"])
-                                  for k, v in out.items() if isinstance(v, dict)})
+                                  for k, v in out.items() if isinstance(v, dict) and "rank" in v})
     return out
 
 

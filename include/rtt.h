@@ -525,6 +525,21 @@ int synth_project(const rtt_synthesis* synth, const float* x, float* c, int32_t 
 int synthesis_audit(const rtt_geometry* geom, const rtt_synthesis* synth, uint32_t order_mask, double* sigma,
                     uint8_t* zero, void* stream);
 
+/*
+ * age_fisher -- the age-local Fisher matrix M(a) = P(a)^T P(a) of Sec. 3.3
+ * eq. (14) for the localised probes q_{a,l} = psi_l(r, phi) g_a(t) / N_{h,l},
+ * psi_l = R_a Phi_b the spatial functions of the synthesis `spatial` (l =
+ * a (2 m_max + 1) + b; its temporal functions are not used), g_a the Gaussian
+ * of eq. (10) with width h, N_{h,l} their continuum L2 norm over the annulus
+ * and time (radial integral by Gauss-Legendre quadrature), set on the
+ * coefficient nodes of the synthesis' geometry; P(a) = A q_{a,l} on the rows
+ * of the orders in order_mask (0 = all), C = I (rows as loaded).  M: host
+ * double [n_ages][L][L], L = n_radial (2 m_max + 1); FP64 Gram of the FP32
+ * responses.  Blocking.  Errors: RTT_EINVAL, RTT_ENOMEM, RTT_EDEVICE.
+ */
+int age_fisher(const rtt_geometry* geom, const rtt_synthesis* spatial, const double* ages, int32_t n_ages, double h,
+               uint32_t order_mask, double* M, void* stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);
 

@@ -27,7 +27,7 @@ EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member"
             "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
             "mix_apply", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
             "age_reach", "age_window_error", "tsvd_project", "noise_add", "synthesis_create", "synthesis_free",
-            "synthesis_info", "synth_expand", "synth_project", "synthesis_audit", "last_error")
+            "synthesis_info", "synth_expand", "synth_project", "synthesis_audit", "age_fisher", "last_error")
 
 
 class RttError(RuntimeError):
@@ -149,6 +149,7 @@ def require_native():
         "synth_expand": [vp, vp, vp, i32, vp],
         "synth_project": [vp, vp, vp, i32, vp],
         "synthesis_audit": [vp, vp, u32, vp, vp, vp],
+        "age_fisher": [vp, vp, _dp, i32, ctypes.c_double, u32, _dp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -80,6 +80,9 @@ __global__ __launch_bounds__(GT * GT) void k_gram_f64(const float* __restrict__ 
                                                      double* __restrict__ G)
 {
     __shared__ double su[GT][GL + 1], sv[GT][GL + 1];
+    // blockIdx.z: independent row sets (d rows each, consecutive), one d x d output each
+    Y += (int64_t)blockIdx.z * d * ld;
+    G += (int64_t)blockIdx.z * d * d;
     const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
     const int u0 = blockIdx.y * GT, v0 = blockIdx.x * GT;
     if (v0 + GT <= u0) return;   // lower tiles: mirrored from the upper ones on the host
@@ -187,6 +190,25 @@ __global__ void k_synth_project_sum(const float* __restrict__ part, int n_r, int
     double acc = 0.0;
     for (int i = 0; i < n_r; ++i) acc += (double)part[(v * n_r + i) * d + q];
     c[t] = (float)acc;
+}
+
+// Localised probes of eq. (14) on one geometry's nodes: row (age v, direction l = a n_az + b) holds
+// R[a][i] P[b][j] exp(-(s_k + age_v)^2 / (2 h^2)) / N_l
+__global__ void k_local_probe(const float* __restrict__ R, const float* __restrict__ P, const double* __restrict__ inv_n,
+                              const double* __restrict__ ages, int nR, int nA, int n_r, int n_phi, int K, double s0,
+                              double dt_src, double h, int64_t n_cols, float* __restrict__ X)
+{
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n_cols) return;
+    const int L = nR * nA;
+    const int row = blockIdx.y;                 // v * L + l
+    const int v = row / L, l = row % L, a = l / nA, b = l % nA;
+    const int k = (int)(col % K);
+    const int64_t cell = col / K;
+    const int j = (int)(cell % n_phi), i = (int)(cell / n_phi);
+    const double t = s0 + dt_src * k + ages[v];
+    X[(int64_t)row * n_cols + col] =
+        (float)((double)R[a * n_r + i] * (double)P[b * n_phi + j] * exp(-t * t / (2.0 * h * h)) * inv_n[l]);
 }
 
 bool valid_syn(const rtt_synthesis* s) { return s && s->magic == SYN_MAGIC; }
@@ -457,6 +479,79 @@ extern "C" int synthesis_audit(const rtt_geometry* g, const rtt_synthesis* s, ui
         std::vector<double> U, sv, W;
         jacobi_svd(hG, d, U, sv, W);
         for (int i = 0; i < d; ++i) sigma[i] = std::sqrt(std::max(0.0, sv[i]));
+    }
+    return RTT_OK;
+}
+
+extern "C" int age_fisher(const rtt_geometry* g, const rtt_synthesis* s, const double* ages, int32_t n_ages, double h,
+                          uint32_t order_mask, double* M, void* stream)
+{
+    if (!valid_handle(g)) return fail(RTT_EINVAL, "invalid geometry handle");
+    int rc = check_syn(s, 0);
+    if (rc) return rc;
+    if (s->member >= (int)g->members.size() || g->members[s->member].n_cols != s->n_cols)
+        return fail(RTT_EINVAL, "the synthesis belongs to another geometry");
+    if (n_ages < 0 || (n_ages > 0 && (!ages || !M))) return fail(RTT_EINVAL, "bad ages or output");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(RTT_EINVAL, "h must be positive and finite");
+    if (n_ages == 0) return RTT_OK;
+    const Member& m = g->members[s->member];
+    const rtt_grid& gr = m.grid;
+    const int nR = s->n_radial, nA = s->n_az, L = nR * nA;
+    // N_l of eq. (14): h sqrt(pi) * int R_a(r)^2 r dr * int Phi_b^2 dphi (2 pi or pi); the radial
+    // integral of the continuum B-spline by composite 8-point Gauss-Legendre on 256 panels
+    static const double gx[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290, -0.1834346424956498,
+                                 0.1834346424956498,  0.5255324099163290,  0.7966664774136267,  0.9602898564975363};
+    static const double gw[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873, 0.3626837833783620,
+                                 0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    std::vector<double> rad(nR, 0.0), bs(nR);
+    const double lr = std::log(gr.r_in), lw = std::log(gr.r_out) - lr;
+    const int panels = 256;
+    const double hp = (gr.r_out - gr.r_in) / panels;
+    for (int p = 0; p < panels; ++p)
+        for (int q = 0; q < 8; ++q) {
+            const double r = gr.r_in + hp * (p + 0.5 + 0.5 * gx[q]);
+            cubic_bsplines(std::min(1.0, std::max(0.0, (std::log(r) - lr) / lw)), nR, bs.data());
+            for (int a = 0; a < nR; ++a) rad[a] += 0.5 * hp * gw[q] * bs[a] * bs[a] * r;
+        }
+    const double pi = 3.14159265358979323846264338327950288;
+    std::vector<double> inv_n(L);
+    for (int a = 0; a < nR; ++a)
+        for (int b = 0; b < nA; ++b)
+            inv_n[a * nA + b] = 1.0 / std::sqrt(rad[a] * (b == 0 ? 2.0 * pi : pi) * h * std::sqrt(pi));
+    hipStream_t st = (hipStream_t)stream;
+    RTT_HIP(hipSetDevice(s->device));
+    const int64_t per_age = (int64_t)L * (m.n_rows + m.n_cols) * 4;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(std::min(n_ages, 2048 / L), (int64_t(1) << 30) / per_age));
+    Workspace ws;
+    float* X = (float*)ws.get("x", sizeof(float) * (size_t)chunk * L * m.n_cols);
+    float* Y = (float*)ws.get("y", sizeof(float) * (size_t)chunk * L * m.n_rows);
+    double* dn = (double*)ws.get("n", sizeof(double) * L);
+    double* da = (double*)ws.get("a", sizeof(double) * n_ages);
+    double* G = (double*)ws.get("g", sizeof(double) * (size_t)chunk * L * L);
+    if (!X || !Y || !dn || !da || !G) return fail(RTT_ENOMEM, "age_fisher scratch");
+    RTT_HIP(hipMemcpyAsync(dn, inv_n.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
+    RTT_HIP(hipMemcpyAsync(da, ages, sizeof(double) * n_ages, hipMemcpyHostToDevice, st));
+    std::vector<double> hG((size_t)chunk * L * L);
+    for (int a0 = 0; a0 < n_ages; a0 += chunk) {
+        const int nv = std::min(chunk, n_ages - a0);
+        hipLaunchKernelGGL(k_local_probe, dim3((unsigned)((m.n_cols + 255) / 256), (unsigned)(nv * L)), dim3(256), 0, st,
+                           s->d_R, s->d_P, dn, da + a0, nR, nA, gr.n_r, gr.n_phi, gr.n_hat, gr.s0, gr.dt_src, h,
+                           m.n_cols, X);
+        RTT_HIP(hipGetLastError());
+        if ((rc = fill(Y, (int64_t)nv * L * m.n_rows, 0.f, st))) return rc;
+        if ((rc = apply_op(g, s->member, false, X, Y, nv * L, order_mask, st))) return rc;
+        const int tiles = (L + GT - 1) / GT;
+        hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)tiles, (unsigned)tiles, (unsigned)nv), dim3(GT * GT), 0, st, Y,
+                           m.n_rows, L, m.n_rows, G);
+        RTT_HIP(hipGetLastError());
+        RTT_HIP(hipMemcpyAsync(hG.data(), G, sizeof(double) * (size_t)nv * L * L, hipMemcpyDeviceToHost, st));
+        RTT_HIP(hipStreamSynchronize(st));
+        for (int v = 0; v < nv; ++v) {
+            double* out = M + (size_t)(a0 + v) * L * L;
+            const double* gv = hG.data() + (size_t)v * L * L;
+            for (int u = 0; u < L; ++u)
+                for (int w = 0; w < L; ++w) out[(size_t)u * L + w] = u <= w ? gv[(size_t)u * L + w] : gv[(size_t)w * L + u];
+        }
     }
     return RTT_OK;
 }

@@ -36,6 +36,7 @@ class Synthesis:
         d, n = ctypes.c_int32(), ctypes.c_int64()
         _check(lib.synthesis_info(h, ctypes.byref(d), ctypes.byref(n), None))
         self.d, self.n_cols, self.member = d.value, n.value, int(g)
+        self.n_temporal = int(n_temporal)
 
     @property
     def handle(self):
@@ -72,6 +73,17 @@ class Synthesis:
                                                 zero.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _stream(stream)))
         rank = int(np.sum(sigma > rel_tol * sigma[0])) if sigma[0] > 0 else 0
         return dict(zero_columns=[int(c) for c in np.nonzero(zero)[0]], sigma=sigma, rank=rank)
+
+    def age_fisher(self, geom: Geometry, ages, h: float = 3.0, order_mask: int = 0, stream=None):
+        """M(a) of eq. (14) for the localised probes built on this synthesis' spatial functions:
+        numpy [n_ages][L][L], L = n_radial (2 m_max + 1)."""
+        ages = np.ascontiguousarray(ages, dtype=np.float64)
+        L = self.d // self.n_temporal
+        out = np.zeros((ages.size, L, L))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(require_native().age_fisher(geom.handle, self.handle, ages.ctypes.data_as(dp), ages.size, float(h),
+                                           int(order_mask), out.ctypes.data_as(dp), _stream(stream)))
+        return out
 
     def free(self):
         from . import _lib

@@ -83,3 +83,38 @@ def test_s224_audit_on_the_kerr_128_workload(gpu_lib):
             s_w = np.sqrt(np.maximum(np.linalg.eigvalsh(Gm)[::-1], 0.0))
             say(temporal, mask, "zero", len(zero), "rank", got["rank"], "sigma1", got["sigma"][0])
             assert np.max(np.abs(got["sigma"][:10] - s_w[:10]) / s_w[:10]) < 1e-4
+
+
+def test_age_fisher_matches_oracle(gpu_lib):
+    """M(a) of eq. (14) against the oracle on a small geometry (direct and resolved rows), and the
+    flat-probe information as its quadratic form (the radial B-splines sum to one on the nodes)."""
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=9, rays=(14, 8, 5), n_frames=5)
+    G = rtt.Geometry(geo)
+    S = rtt.Synthesis(G, 0)
+    ages = np.array([0.0, 7.0, 20.0, 33.5])
+    say("case age fisher")
+    for mask in (1, 0):
+        M = S.age_fisher(G, ages, h=3.0, order_mask=mask)
+        W = oracle.age_fisher(geo, ages, h=3.0, order_mask=None if mask == 0 else mask)
+        for i in range(ages.size):
+            assert rel(M[i], W[i]) < 1e-5, (mask, i, rel(M[i], W[i]))
+    nl = oracle.localized_probe_norms(geo.grid, 4, 3, 3.0)
+    w = np.zeros(28)
+    for a in range(4):
+        w[a * 7] = nl[a * 7] / oracle.probe_norm(geo.grid, 3.0)
+    E = rtt.age_information(G, ages, h=3.0)[:, 0, :3].sum(axis=1)
+    assert rel(np.einsum("l,alm,m->a", w, S.age_fisher(G, ages), w), E) < 1e-5
+
+
+def test_age_fisher_on_the_kerr_128_workload(gpu_lib):
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg2")
+    G = rtt.Geometry(geo)
+    S = rtt.Synthesis(G, 0)
+    ages = np.array([0.0, 40.0])
+    say("case age fisher cfg2")
+    M = S.age_fisher(G, np.arange(0.0, 256.0, 4.0), h=3.0, order_mask=0)
+    W = oracle.age_fisher(geo, ages, h=3.0)
+    for i, a in enumerate(ages):
+        assert rel(M[int(a) // 4], W[i]) < 1e-5
