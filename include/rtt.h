@@ -137,8 +137,9 @@ int geometry_set_variant(rtt_geometry* geom, int32_t g, int32_t apply_variant, i
  * geometry; 1 (default) = one launch for up to 16 geometries, their blocks
  * numbered consecutively; 2 = the same launch made persistent (2048 blocks
  * that stride over the work).  Modes 1 and 2 apply when every geometry of the
- * group uses the lean forward / visit-list adjoint variant with one common
- * dt_obs/dt_src; otherwise the call falls back to one launch per geometry.
+ * group uses one lean, absolute-hat (abs4) or register forward variant and a
+ * visit-list adjoint variant, with one common dt_obs/dt_src; otherwise the
+ * call falls back to one launch per geometry.
  * -1 leaves a mode unchanged.  geometry_tune picks the fastest.  All modes give
  * bitwise identical results.  Errors: RTT_EINVAL for other values.
  */

@@ -990,18 +990,22 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean(LeanArgs a)
 // --------------------------------------------------------------------------------------------
 constexpr int ABS_KMAX = 2 * WAVE;
 
+// One block of the absolute-hat forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, one
+// vector (x, y already offset to the member's blocks), every frame.
 template <int Q, int NB, bool VEC4>
-__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs(LeanArgs a)
+__device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restrict__ x, float* __restrict__ y,
+                                         int64_t blk)
 {
-    const float* __restrict__ x = a.x + (int64_t)blockIdx.y * a.x_stride;
-    float* __restrict__ y = a.y + (int64_t)blockIdx.y * a.y_stride;
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     float(*zs_all)[NB][LEAN_ZS] = lean_lds<NB>();
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t r0 = (blk * A_WAVES + wave) * NB;
     if (r0 >= a.n_rays) return;
     float(*zs)[LEAN_ZS] = zs_all[wave];
+    // the previous task of a persistent block may still be reading this wave's LDS rows
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
     const int K = a.K;
     const bool two = K > WAVE;   // second gather pass (hats 64..127)
@@ -1109,6 +1113,13 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs(LeanArgs a)
     }
 }
 
+template <int Q, int NB, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs(LeanArgs a)
+{
+    abs_body<Q, NB, VEC4>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
+                          xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // Every member of a handle (up to MULTI_MAX) in one launch.  Tasks are (vector, member, frame
 // chunk, ray block), numbered with the ray block fastest; a member's tasks start at blk_begin
 // inside each vector.  With gridDim.x < total the launch is persistent: block b takes tasks
@@ -1162,6 +1173,37 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_lean_multi(LeanMulti a
             lean_body<Q, NB, true>(la, xv, yv, (int64_t)(b - chunk * mm.nrb), (int)chunk);
         else
             lean_body<Q, NB, false>(la, xv, yv, (int64_t)(b - chunk * mm.nrb), (int)chunk);
+    }
+}
+
+// The absolute-hat forward of every member in one launch: tasks are (vector, member, ray block),
+// numbered as in k_apply_lean_multi with a single frame chunk per member.
+template <int Q, bool VEC4>
+__global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs_multi(LeanMulti a)
+{
+    for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
+        const uint32_t lt = xcd_remap32(t, a.total);
+        const uint32_t v = lt / a.per_vec;
+        uint32_t b = lt - v * a.per_vec;
+        int g = 0;
+        while (g + 1 < a.G && b >= a.m[g + 1].blk_begin) ++g;
+        const LeanMember& mm = a.m[g];
+        b -= mm.blk_begin;
+        LeanArgs la;
+        la.rec = mm.rec;
+        la.n_rays = mm.n_rays;
+        la.K = mm.K;
+        la.F = mm.F;
+        la.nk = mm.nk;
+        la.x_bytes = mm.x_bytes;
+        la.mask = mm.mask;
+        la.fc = mm.fc;
+        const float* xv = a.x + (int64_t)v * a.x_stride + mm.x_off;
+        float* yv = a.y + (int64_t)v * a.y_stride + mm.y_off;
+        if (VEC4 && mm.wide)
+            abs_body<Q, 4, true>(la, xv, yv, (int64_t)b);
+        else
+            abs_body<Q, 4, false>(la, xv, yv, (int64_t)b);
     }
 }
 
@@ -2901,13 +2943,17 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     // wide output stores (8-byte aligned rows at Q = 1, 16-byte at Q = 2), decided per member
     const int wa = m0.Q == 1 ? 2 : 4;
     const bool vec4 = (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (g->n_rows % wa) == 0);
-    bool all8 = true;
+    bool all8 = true, use_abs = m0.apply_variant == 11;
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
+        if (use_abs) {
+            if (!apply_variant_ok(m, 11) || m.Q != m0.Q || m.apply_variant != 11) return false;
+            continue;
+        }
         if (!lean_supported(m) || m.Q != m0.Q || (m.apply_variant != 4 && m.apply_variant != 5)) return false;
         all8 = all8 && m.apply_variant == 5;
     }
-    const int NB = all8 ? 8 : 4;
+    const int NB = all8 && !use_abs ? 8 : 4;
     LeanMulti a;
     a.G = e - b;
     int64_t nb = 0;
@@ -2926,7 +2972,8 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
         d.nrb = (uint32_t)((m.n_rays + (int64_t)A_WAVES * NB - 1) / ((int64_t)A_WAVES * NB));
         d.mask = effective_mask(m, mask);
         int nch = 1;
-        lean_chunks(m.grid.n_frames, m.Q, &nch, &d.fc);
+        if (use_abs) d.fc = m.grid.n_frames;   // one task covers every frame
+        else lean_chunks(m.grid.n_frames, m.Q, &nch, &d.fc);
         d.wide = (m.grid.n_frames % wa) == 0 && (m.row_offset % wa) == 0;
         nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
     }
@@ -2940,6 +2987,18 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     *rc = RTT_OK;
     if (a.total == 0) return true;
     const dim3 grid(multi_grid(a.total, persist)), blk(A_WAVES * WAVE);
+    if (use_abs) {
+        if (m0.Q == 1) {
+            if (vec4) hipLaunchKernelGGL((k_apply_abs_multi<1, true>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_apply_abs_multi<1, false>), grid, blk, 0, s, a);
+        } else {
+            if (vec4) hipLaunchKernelGGL((k_apply_abs_multi<2, true>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_apply_abs_multi<2, false>), grid, blk, 0, s, a);
+        }
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) *rc = hip_fail(err, "k_apply_abs_multi");
+        return true;
+    }
     if (m0.Q == 1) {
         if (NB == 4) {
             if (vec4) hipLaunchKernelGGL((k_apply_lean_multi<1, 4, true>), grid, blk, 0, s, a);

@@ -203,7 +203,7 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
                 for (const Member& m : g->members) tuned.push_back(adj ? m.adj_variant : m.apply_variant);
                 // candidates: -1 = the per-member choices; then the single-launch variants
                 std::vector<int> cands = {-1};
-                for (int v : adj ? std::vector<int>{11, 16, 19} : std::vector<int>{4, 6, 7}) {
+                for (int v : adj ? std::vector<int>{11, 16, 19} : std::vector<int>{4, 6, 7, 11}) {
                     bool ok = true;
                     for (const Member& m : g->members) ok = ok && (adj ? adjoint_variant_ok(m, v) : apply_variant_ok(m, v));
                     if (ok) cands.push_back(v);
@@ -216,7 +216,8 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
                         slot = u >= 0 ? u : tuned[i];
                     }
                     for (int mode = 0; mode <= 2; ++mode) {
-                        if (u >= 0 && mode == 0) continue;   // the per-member launches are covered by u = -1
+                        // a shared variant is timed in every mode: launched per member (mode 0) it can beat
+                        // the per-member choices, each timed alone with noise at small sizes
                         float ms;
                         rc = adj ? time_mode(g, true, mode, ya, xa, nvec, reps, s, &ms)
                                  : time_mode(g, false, mode, xa, ya, nvec, reps, s, &ms);

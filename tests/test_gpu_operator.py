@@ -322,7 +322,8 @@ BATCH_CASES = {
 }
 
 
-@pytest.mark.parametrize("fwd,adj", [("lean4", "visit"), ("reg1", "visitd"), ("reg2", "visit"), ("strip16", "visitd"), ("lean8", "visitp2v")])
+@pytest.mark.parametrize("fwd,adj", [("lean4", "visit"), ("reg1", "visitd"), ("reg2", "visit"), ("strip16", "visitd"),
+                                     ("lean8", "visitp2v"), ("abs4", "visitp4v")])
 @pytest.mark.parametrize("name", list(BATCH_CASES))
 def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd, adj):
     """One launch for all geometries (plain and persistent) equals one launch per geometry."""
