@@ -37,8 +37,8 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip
 # (FETCH_SIZE scaled by 2.0, the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only
 # for the kernel source digest and variant they were taken on (see profiles/).
 MEASURED_TRAFFIC = {
-    "op_apply_adjoint": {"bytes": 2052168352, "digest": "1ed651537e6f2cd7", "nvec": 264, "variant": "visitp2v"},
-    "op_apply": {"bytes": 2105347456, "digest": "1ed651537e6f2cd7", "nvec": 264, "variant": "abs4"},
+    "op_apply_adjoint": {"bytes": 2050789488, "digest": "2475b31d9f92872d", "nvec": 264, "variant": "visitp2v"},
+    "op_apply": {"bytes": 2105012096, "digest": "2475b31d9f92872d", "nvec": 264, "variant": "abs4"},
 }
 
 

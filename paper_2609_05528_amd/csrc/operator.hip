@@ -992,7 +992,7 @@ constexpr int ABS_KMAX = 2 * WAVE;
 
 // One block of the absolute-hat forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, one
 // vector (x, y already offset to the member's blocks), every frame.
-template <int Q, int NB, bool VEC4>
+template <int Q, int NB, bool VEC4, bool REUSE>
 __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restrict__ x, float* __restrict__ y,
                                          int64_t blk)
 {
@@ -1002,10 +1002,12 @@ __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restr
     const int64_t r0 = (blk * A_WAVES + wave) * NB;
     if (r0 >= a.n_rays) return;
     float(*zs)[LEAN_ZS] = zs_all[wave];
-    // the previous task of a persistent block may still be reading this wave's LDS rows
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (REUSE) {
+        // the previous task of a persistent block may still be reading this wave's LDS rows
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc((void*)x, (short)0, a.x_bytes, 0x00020000);
     const int K = a.K;
     const bool two = K > WAVE;   // second gather pass (hats 64..127)
@@ -1116,8 +1118,8 @@ __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restr
 template <int Q, int NB, bool VEC4>
 __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs(LeanArgs a)
 {
-    abs_body<Q, NB, VEC4>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
-                          xcd_remap(blockIdx.x, gridDim.x));
+    abs_body<Q, NB, VEC4, false>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
+                                 xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Every member of a handle (up to MULTI_MAX) in one launch.  Tasks are (vector, member, frame
@@ -1201,9 +1203,9 @@ __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs_multi(LeanMulti a)
         const float* xv = a.x + (int64_t)v * a.x_stride + mm.x_off;
         float* yv = a.y + (int64_t)v * a.y_stride + mm.y_off;
         if (VEC4 && mm.wide)
-            abs_body<Q, 4, true>(la, xv, yv, (int64_t)b);
+            abs_body<Q, 4, true, true>(la, xv, yv, (int64_t)b);
         else
-            abs_body<Q, 4, false>(la, xv, yv, (int64_t)b);
+            abs_body<Q, 4, false, true>(la, xv, yv, (int64_t)b);
     }
 }
 
