@@ -75,24 +75,29 @@ __global__ void k_transpose_f32(const float* __restrict__ c, int nvec, int d, fl
 
 // FP64 Gram of d rows of length L (row stride ld): G[u][v] = sum_l Y[u][l] Y[v][l], FP32 inputs
 // widened to FP64 before the products; 16 x 16 output tiles, rows staged through LDS in chunks.
+// blockIdx.z = set * nsl + slice: independent row sets (d rows each, consecutive), each split into
+// nsl slices of the row length with one partial d x d output per (set, slice), summed afterwards
+// in slice order.
 constexpr int GT = 16, GL = 64;
 __global__ __launch_bounds__(GT * GT) void k_gram_f64(const float* __restrict__ Y, int64_t ld, int d, int64_t L,
-                                                     double* __restrict__ G)
+                                                     int nsl, double* __restrict__ G)
 {
     __shared__ double su[GT][GL + 1], sv[GT][GL + 1];
-    // blockIdx.z: independent row sets (d rows each, consecutive), one d x d output each
-    Y += (int64_t)blockIdx.z * d * ld;
+    const int set = blockIdx.z / nsl, sl = blockIdx.z % nsl;
+    Y += (int64_t)set * d * ld;
     G += (int64_t)blockIdx.z * d * d;
+    const int64_t span = ((L + nsl - 1) / nsl + GL - 1) / GL * GL;
+    const int64_t lb = (int64_t)sl * span, le = min(L, lb + span);
     const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
     const int u0 = blockIdx.y * GT, v0 = blockIdx.x * GT;
     if (v0 + GT <= u0) return;   // lower tiles: mirrored from the upper ones on the host
     double acc = 0.0;
-    for (int64_t l0 = 0; l0 < L; l0 += GL) {
+    for (int64_t l0 = lb; l0 < le; l0 += GL) {
         for (int e = threadIdx.x; e < GT * GL; e += GT * GT) {
             const int r = e / GL, q = e % GL;
             const int64_t l = l0 + q;
-            su[r][q] = (u0 + r < d && l < L) ? (double)Y[(int64_t)(u0 + r) * ld + l] : 0.0;
-            sv[r][q] = (v0 + r < d && l < L) ? (double)Y[(int64_t)(v0 + r) * ld + l] : 0.0;
+            su[r][q] = (u0 + r < d && l < le) ? (double)Y[(int64_t)(u0 + r) * ld + l] : 0.0;
+            sv[r][q] = (v0 + r < d && l < le) ? (double)Y[(int64_t)(v0 + r) * ld + l] : 0.0;
         }
         __syncthreads();
 #pragma unroll 8
@@ -212,6 +217,17 @@ __global__ void k_local_probe(const float* __restrict__ R, const float* __restri
 }
 
 bool valid_syn(const rtt_synthesis* s) { return s && s->magic == SYN_MAGIC; }
+
+// row-length slices for the FP64 Gram: enough blocks to fill the chip, slices of >= 16384 rows
+int gram_slices(int d, int64_t L, int sets)
+{
+    const int tiles = (d + GT - 1) / GT;
+    const int64_t blocks = (int64_t)tiles * (tiles + 1) / 2 * sets;
+    int64_t nsl = std::max<int64_t>(1, 4096 / std::max<int64_t>(blocks, 1));
+    nsl = std::min<int64_t>(nsl, std::max<int64_t>(1, L / 16384));
+    nsl = std::min<int64_t>(nsl, 65535 / std::max(sets, 1));
+    return (int)std::max<int64_t>(1, nsl);
+}
 
 // clamped cubic B-splines with n functions on uniform knots of [0, 1], at u in [0, 1] (Cox-de Boor)
 void cubic_bsplines(double u, int n, double* out)
@@ -453,10 +469,9 @@ extern "C" int synthesis_audit(const rtt_geometry* g, const rtt_synthesis* s, ui
     const int64_t rows = m.n_rows;
     Workspace ws;
     float* Y = (float*)ws.get("y", sizeof(float) * (size_t)d * rows);
-    double* G = (double*)ws.get("g", sizeof(double) * (size_t)d * d);
     double* nrm = (double*)ws.get("n", sizeof(double) * (size_t)d);
     int64_t* seg = (int64_t*)ws.get("seg", sizeof(int64_t) * 2);
-    if (!Y || !G || !nrm || !seg) return fail(RTT_ENOMEM, "synthesis_audit scratch");
+    if (!Y || !nrm || !seg) return fail(RTT_ENOMEM, "synthesis_audit scratch");
     // A^(d) rows: A applied to the rows of Q (rows of orders outside the mask stay zero)
     if ((rc = fill(Y, (int64_t)d * rows, 0.f, st))) return rc;
     if ((rc = apply_op(g, s->member, false, s->d_Q, Y, d, order_mask, st))) return rc;
@@ -464,12 +479,18 @@ extern "C" int synthesis_audit(const rtt_geometry* g, const rtt_synthesis* s, ui
     RTT_HIP(hipMemcpyAsync(seg, hs, sizeof(hs), hipMemcpyHostToDevice, st));
     if ((rc = dots_seg(ws, Y, rows, Y, rows, seg, 1, rows, d, nrm, st))) return rc;
     const int tiles = (d + GT - 1) / GT;
-    hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)tiles, (unsigned)tiles), dim3(GT * GT), 0, st, Y, rows, d, rows, G);
+    const int nsl = gram_slices(d, rows, 1);
+    double* Gp = (double*)ws.get("gp", sizeof(double) * (size_t)nsl * d * d);
+    if (!Gp) return fail(RTT_ENOMEM, "synthesis_audit scratch");
+    hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)tiles, (unsigned)tiles, (unsigned)nsl), dim3(GT * GT), 0, st, Y, rows,
+                       d, rows, nsl, Gp);
     RTT_HIP(hipGetLastError());
-    std::vector<double> hG((size_t)d * d), hn(d);
-    RTT_HIP(hipMemcpyAsync(hG.data(), G, sizeof(double) * hG.size(), hipMemcpyDeviceToHost, st));
+    std::vector<double> hGp((size_t)nsl * d * d), hG((size_t)d * d, 0.0), hn(d);
+    RTT_HIP(hipMemcpyAsync(hGp.data(), Gp, sizeof(double) * hGp.size(), hipMemcpyDeviceToHost, st));
     RTT_HIP(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * d, hipMemcpyDeviceToHost, st));
     RTT_HIP(hipStreamSynchronize(st));
+    for (int z = 0; z < nsl; ++z)
+        for (size_t e = 0; e < hG.size(); ++e) hG[e] += hGp[(size_t)z * d * d + e];
     if (zero)
         for (int c = 0; c < d; ++c) zero[c] = hn[c] == 0.0 ? 1 : 0;
     if (sigma) {
@@ -527,8 +548,7 @@ extern "C" int age_fisher(const rtt_geometry* g, const rtt_synthesis* s, const d
     float* Y = (float*)ws.get("y", sizeof(float) * (size_t)chunk * L * m.n_rows);
     double* dn = (double*)ws.get("n", sizeof(double) * L);
     double* da = (double*)ws.get("a", sizeof(double) * n_ages);
-    double* G = (double*)ws.get("g", sizeof(double) * (size_t)chunk * L * L);
-    if (!X || !Y || !dn || !da || !G) return fail(RTT_ENOMEM, "age_fisher scratch");
+    if (!X || !Y || !dn || !da) return fail(RTT_ENOMEM, "age_fisher scratch");
     RTT_HIP(hipMemcpyAsync(dn, inv_n.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
     RTT_HIP(hipMemcpyAsync(da, ages, sizeof(double) * n_ages, hipMemcpyHostToDevice, st));
     std::vector<double> hG((size_t)chunk * L * L);
@@ -541,16 +561,22 @@ extern "C" int age_fisher(const rtt_geometry* g, const rtt_synthesis* s, const d
         if ((rc = fill(Y, (int64_t)nv * L * m.n_rows, 0.f, st))) return rc;
         if ((rc = apply_op(g, s->member, false, X, Y, nv * L, order_mask, st))) return rc;
         const int tiles = (L + GT - 1) / GT;
-        hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)tiles, (unsigned)tiles, (unsigned)nv), dim3(GT * GT), 0, st, Y,
-                           m.n_rows, L, m.n_rows, G);
+        const int nsl = gram_slices(L, m.n_rows, nv);
+        double* Gp = (double*)ws.get("gp", sizeof(double) * (size_t)chunk * nsl * L * L);
+        if (!Gp) return fail(RTT_ENOMEM, "age_fisher scratch");
+        hipLaunchKernelGGL(k_gram_f64, dim3((unsigned)tiles, (unsigned)tiles, (unsigned)(nv * nsl)), dim3(GT * GT), 0, st,
+                           Y, m.n_rows, L, m.n_rows, nsl, Gp);
         RTT_HIP(hipGetLastError());
-        RTT_HIP(hipMemcpyAsync(hG.data(), G, sizeof(double) * (size_t)nv * L * L, hipMemcpyDeviceToHost, st));
+        std::vector<double> hGp((size_t)nv * nsl * L * L);
+        RTT_HIP(hipMemcpyAsync(hGp.data(), Gp, sizeof(double) * hGp.size(), hipMemcpyDeviceToHost, st));
         RTT_HIP(hipStreamSynchronize(st));
         for (int v = 0; v < nv; ++v) {
             double* out = M + (size_t)(a0 + v) * L * L;
-            const double* gv = hG.data() + (size_t)v * L * L;
+            std::fill(hG.begin(), hG.begin() + (size_t)L * L, 0.0);
+            for (int z = 0; z < nsl; ++z)
+                for (size_t e = 0; e < (size_t)L * L; ++e) hG[e] += hGp[((size_t)v * nsl + z) * L * L + e];
             for (int u = 0; u < L; ++u)
-                for (int w = 0; w < L; ++w) out[(size_t)u * L + w] = u <= w ? gv[(size_t)u * L + w] : gv[(size_t)w * L + u];
+                for (int w = 0; w < L; ++w) out[(size_t)u * L + w] = u <= w ? hG[(size_t)u * L + w] : hG[(size_t)w * L + u];
         }
     }
     return RTT_OK;
