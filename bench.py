@@ -138,13 +138,18 @@ def age_section(torch, rtt, geos, G, snr0=100.0, rho=1.0, h=3.0):
         arms[kind] = rtt.age_information(G, ages, h=h, mixer=M)
         t_mix[kind] = time.perf_counter() - t0
         del M
-    # the pairing-destroyed control (Sec. 6.4): delays permuted within each order, same noise density
+    # mechanism arms of Sec. 6.4 as input transforms, with the noise density of the original geometry:
+    # pairing destroyed (delays permuted within each order), spatial only (higher orders shifted to the
+    # direct order's median delay), delay only (higher orders at direct-order source positions)
     import synth
-    Gc = rtt.Geometry([synth.pairing_destroyed(geo, seed=600 + i) for i, geo in enumerate(geos)])
-    t0 = time.perf_counter()
-    arms["pairing_destroyed"] = rtt.age_information(Gc, ages, h=h).sum(axis=2)
-    t_mix["pairing_destroyed"] = time.perf_counter() - t0
-    del Gc
+    for arm, tf in (("pairing_destroyed", lambda i, geo: synth.pairing_destroyed(geo, seed=600 + i)),
+                    ("spatial_only", lambda i, geo: synth.spatial_only(geo)),
+                    ("delay_only", lambda i, geo: synth.delay_only(geo, seed=700 + i))):
+        Gc = rtt.Geometry([tf(i, geo) for i, geo in enumerate(geos)])
+        t0 = time.perf_counter()
+        arms[arm] = rtt.age_information(Gc, ages, h=h).sum(axis=2)
+        t_mix[arm] = time.perf_counter() - t0
+        del Gc
     stats = {}
     for arm, e in arms.items():
         per = []

@@ -9,5 +9,6 @@ sharing any code of the method itself.
 """
 from .configs import (CONFIGS, config, grid_for, geometry_for, batch_members,  # noqa: F401
                       batch_geometries, BATCH_S0, BATCH_HISTORIES)
-from .geometry import Grid, RayMap, Geometry, screen_raymaps, random_geometry, pairing_destroyed  # noqa: F401
+from .geometry import (Grid, RayMap, Geometry, screen_raymaps, random_geometry, pairing_destroyed,  # noqa: F401
+                       spatial_only, delay_only)
 from .histories import uniform_emissivity, blob_histories, gaussian_block  # noqa: F401

@@ -222,3 +222,30 @@ def pairing_destroyed(geom: Geometry, seed: int) -> Geometry:
         maps.append(dataclasses.replace(m, delay=np.ascontiguousarray(m.delay[perm])))
     return Geometry(grid=geom.grid, maps=maps, label=(geom.label or "") + "-pairing-destroyed",
                     image_side=geom.image_side)
+
+
+def spatial_only(geom: Geometry) -> Geometry:
+    """Spatial-only mechanism arm (Sec. 6.4) as an input transform: every order n >= 1 keeps its rays'
+    source positions and weights, but its delays are shifted by the difference of the order's median
+    delay and the direct order's, so the higher orders add new source positions at the direct
+    image's epochs."""
+    d0 = float(np.median(geom.maps[0].delay)) if geom.maps[0].n_rays else 0.0
+    maps = [geom.maps[0]]
+    for m in geom.maps[1:]:
+        shift = float(np.median(m.delay)) - d0 if m.n_rays else 0.0
+        maps.append(dataclasses.replace(m, delay=np.ascontiguousarray(m.delay - shift)))
+    return Geometry(grid=geom.grid, maps=maps, label=(geom.label or "") + "-spatial-only", image_side=geom.image_side)
+
+
+def delay_only(geom: Geometry, seed: int) -> Geometry:
+    """Delay-only mechanism arm (Sec. 6.4) as an input transform: every order n >= 1 keeps its rays'
+    delays and weights, but each ray's source position is replaced by that of a direct-order ray
+    drawn uniformly (seeded), so the higher orders sample the direct image's spatial distribution
+    and can add only retarded-time information."""
+    rng = np.random.default_rng(seed)
+    m0 = geom.maps[0]
+    maps = [m0]
+    for m in geom.maps[1:]:
+        pick = rng.integers(0, m0.n_rays, m.n_rays) if m0.n_rays else np.zeros(m.n_rays, dtype=np.int64)
+        maps.append(dataclasses.replace(m, r=np.ascontiguousarray(m0.r[pick]), phi=np.ascontiguousarray(m0.phi[pick])))
+    return Geometry(grid=geom.grid, maps=maps, label=(geom.label or "") + "-delay-only", image_side=geom.image_side)

@@ -142,3 +142,18 @@ def test_pairing_destroyed_control_keeps_delay_marginals():
         assert np.array_equal(m.r, c.r) and np.array_equal(m.weight, c.weight) and np.array_equal(m.pixel, c.pixel)
     assert not np.array_equal(geo.maps[0].delay, ctl.maps[0].delay)
     assert np.array_equal(synth.pairing_destroyed(geo, seed=1).maps[1].delay, ctl.maps[1].delay)
+
+
+def test_spatial_only_and_delay_only_arms():
+    geo = tiny_geometry(seed=6, rays=(30, 12, 9))
+    sp = synth.spatial_only(geo)
+    for n, (m, s) in enumerate(zip(geo.maps, sp.maps)):
+        assert np.array_equal(m.r, s.r) and np.array_equal(m.phi, s.phi) and np.array_equal(m.weight, s.weight)
+        assert abs(np.median(s.delay) - np.median(geo.maps[0].delay)) < 1e-9
+        assert np.allclose(np.diff(np.sort(s.delay)), np.diff(np.sort(m.delay)))
+    do = synth.delay_only(geo, seed=2)
+    r0 = set(geo.maps[0].r.tolist())
+    for m, d in zip(geo.maps[1:], do.maps[1:]):
+        assert np.array_equal(m.delay, d.delay) and np.array_equal(m.weight, d.weight)
+        assert set(d.r.tolist()) <= r0
+    assert np.array_equal(do.maps[0].r, geo.maps[0].r)

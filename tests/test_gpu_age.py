@@ -127,14 +127,18 @@ def test_age_statistics_on_the_kerr_128_workload(gpu_lib):
         assert abs(got["j_old"] - want["j_old"]) <= 1e-12 * max(1.0, want["j_old"])
 
 
-def test_age_information_of_the_pairing_destroyed_control(gpu_lib):
-    """The control of Sec. 6.4 (delays permuted within each order) through the same path: every
-    order's energy against the oracle run on the same permuted maps."""
+@pytest.mark.parametrize("arm", ["pairing_destroyed", "spatial_only", "delay_only"])
+def test_age_information_of_the_mechanism_arms(gpu_lib, arm):
+    """The mechanism arms of Sec. 6.4 as input transforms through the same path: every order's
+    energy against the oracle run on the same transformed maps."""
     rtt = gpu_lib
-    geo = synth.pairing_destroyed(tiny_geometry(seed=95, rays=(50, 20, 10), n_frames=7, delay_hi=30.0), seed=3)
+    base = tiny_geometry(seed=95, rays=(50, 20, 10), n_frames=7, delay_hi=30.0)
+    geo = {"pairing_destroyed": lambda: synth.pairing_destroyed(base, seed=3),
+           "spatial_only": lambda: synth.spatial_only(base),
+           "delay_only": lambda: synth.delay_only(base, seed=4)}[arm]()
     G = rtt.Geometry(geo)
     ages = np.arange(0.0, 64.0, 4.0) + 0.21
-    say("case pairing-destroyed control")
+    say("case mechanism arm", arm)
     E = rtt.age_information(G, ages, h=3.0)
     assert relerr(E[:, 0, :3].sum(axis=1), oracle.age_energy(geo, ages, arm="resolved")) < TOL
     assert relerr(E[:, 0, 0], oracle.age_energy(geo, ages, arm="direct")) < TOL
