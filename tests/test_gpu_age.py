@@ -102,6 +102,12 @@ def test_age_statistics_on_the_kerr_128_workload(gpu_lib):
     ages = np.arange(0.0, 256.0, 4.0)
     say("case age cfg2")
     E = rtt.age_information(G, ages, h=3.0)
+    # 300 centres on a 0.85M grid take three passes of the library's age chunks: same values
+    fine = np.arange(300) * 0.85
+    Ef = rtt.age_information(G, fine, h=3.0)
+    Xf = oracle.age_probes(geo.grid, fine[[0, 150, 299]], 3.0)
+    Yf = oracle.forward(geo, Xf)
+    assert relerr(Ef[[0, 150, 299], 0, :3].sum(axis=1), np.einsum("ar,ar->a", Yf, Yf)) < TOL
     sample = [0, 9, 21, 40, 63]
     X = oracle.age_probes(geo.grid, ages[sample], 3.0)
     Y = oracle.forward(geo, X)
