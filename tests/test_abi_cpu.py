@@ -84,6 +84,23 @@ def test_null_arguments_are_errors():
     assert lib.mix_covariance(None, None, None, None) == rtt.RTT_EINVAL
     assert b"invalid mixer handle" in lib.last_error()
     assert lib.mixer_free(None) == rtt.RTT_OK
+    d = ctypes.c_double()
+    dp = ctypes.byref(d)
+    assert lib.reference_response(None, dp, None) == rtt.RTT_EINVAL
+    assert lib.age_information(None, dp, 1, 3.0, None, None, dp, None) == rtt.RTT_EINVAL
+    assert lib.age_window(None, 0, 0, 3.0, 0.999, dp, dp, dp) == rtt.RTT_EINVAL
+    assert lib.age_window_error(None, None, None, 1, dp, 1, 2.0, 0.0, dp, None) == rtt.RTT_EINVAL
+    assert b"invalid geometry handle" in lib.last_error()
+    assert lib.tsvd_project(None, None, None, 1, 1, 0.0, None, None) == rtt.RTT_EINVAL
+    assert lib.noise_add(None, 5, 1, 1.0, None) == rtt.RTT_EINVAL
+    assert lib.noise_add(None, 0, 1, 1.0, None) == rtt.RTT_OK
+    h = ctypes.c_void_p()
+    assert lib.synthesis_create(None, 0, None, ctypes.byref(h)) == rtt.RTT_EINVAL and not h.value
+    assert lib.synth_expand(None, None, None, 1, None) == rtt.RTT_EINVAL
+    assert lib.synth_project(None, None, None, 1, None) == rtt.RTT_EINVAL
+    assert lib.synthesis_audit(None, None, 0, None, None, None) == rtt.RTT_EINVAL
+    assert lib.age_fisher(None, None, dp, 1, 3.0, 0, dp, None) == rtt.RTT_EINVAL
+    assert lib.synthesis_free(None) == rtt.RTT_OK
 
 
 def test_synthetic_workload_shapes():
