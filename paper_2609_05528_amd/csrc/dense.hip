@@ -10,9 +10,10 @@
 //           sums the partials of every entry in FP64 in slice order, so the
 //           result does not depend on scheduling.
 //  combine: Out[m][l] = sum_k C[k][m] Y[k][l]      (Out = C^T Y; e.g. Q = Y R^-1)
-//           C (K x M, small) is staged in LDS 32 rows at a time; each wave
-//           owns 32 columns l and up to MG 32-row blocks of Out, so every
-//           element of Y is read once per pass.
+//           C (K x M, small) and the matching rows of Y are staged in LDS 16
+//           rows at a time, double buffered with the next chunk's loads in
+//           flight; each wave owns 32 columns l and up to MG 32-row blocks of
+//           Out, so every element of Y is read once per pass.
 //
 // MFMA operand layout used (32x32x2 f32): lane t supplies A[t%32][t/32] and
 // B[t/32][t%32]; accumulator register r of lane t holds
@@ -28,13 +29,17 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 constexpr int GB = 64;   // gram output block
 constexpr int GK = 32;   // k-chunk staged in LDS
 
+template <bool VL>
 __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ A, int64_t lda,
                                                       const float* __restrict__ B, int64_t ldb, int M, int N,
                                                       int64_t L, int64_t slice, int nbn, int sym,
                                                       float* __restrict__ part)
 {
-    __shared__ float As[GB][GK + 1];
-    __shared__ float Bs[GB][GK + 1];
+    // 64 x 64 output block of one L slice; the slice runs in chunks of GK columns staged in LDS,
+    // double buffered: the next chunk's global loads (16-byte when VL) are issued into registers
+    // before the current chunk's MFMAs.
+    __shared__ float As[2][GB][GK + 1];
+    __shared__ float Bs[2][GB][GK + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
     const int s = blockIdx.y;
@@ -43,26 +48,62 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
     const int64_t l0 = (int64_t)s * slice;
     const int64_t l1 = min(L, l0 + slice);
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f16v acc = {};
-    for (int64_t lc = l0; lc < l1; lc += GK) {
-        // stage A[bm*64 .. +64][lc .. lc+32) and the same rows of B
-        for (int e = tid; e < GB * GK; e += 256) {
-            const int r = e / GK, c = e % GK;
+    f4v ra[2], rb[2];
+    // element group e (0..511): row e / 8, columns 4 (e % 8) .. +3 of the chunk
+    auto load = [&](int64_t lc) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * 256;
+            const int r = e >> 3, c = (e & 7) * 4;
             const int64_t l = lc + c;
             const int ia = bm * GB + r, ib = bn * GB + r;
-            As[r][c] = (ia < M && l < l1) ? A[(int64_t)ia * lda + l] : 0.f;
-            Bs[r][c] = (ib < N && l < l1) ? B[(int64_t)ib * ldb + l] : 0.f;
+            if (VL && ia < M && l + 3 < l1) {
+                ra[q] = *(const f4v*)(A + (int64_t)ia * lda + l);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) ra[q][t] = (ia < M && l + t < l1) ? A[(int64_t)ia * lda + l + t] : 0.f;
+            }
+            if (VL && ib < N && l + 3 < l1) {
+                rb[q] = *(const f4v*)(B + (int64_t)ib * ldb + l);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) rb[q][t] = (ib < N && l + t < l1) ? B[(int64_t)ib * ldb + l + t] : 0.f;
+            }
         }
-        __syncthreads();
-        const int half = lane >> 5, row = lane & 31;
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * 256;
+            const int r = e >> 3, c = (e & 7) * 4;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                As[buf][r][c + t] = ra[q][t];
+                Bs[buf][r][c + t] = rb[q][t];
+            }
+        }
+    };
+    f16v acc = {};
+    if (l0 < l1) {
+        load(l0);
+        store(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    const int half = lane >> 5, row = lane & 31;
+    for (int64_t lc = l0; lc < l1; lc += GK) {
+        const bool more = lc + GK < l1;
+        if (more) load(lc + GK);
 #pragma unroll
         for (int j = 0; j < GK / 2; ++j) {
             // step j covers k = j and k = j + 16 (half selects which)
-            const float a = As[wm + row][16 * half + j];
-            const float b = Bs[wn + row][16 * half + j];
+            const float a = As[buf][wm + row][16 * half + j];
+            const float b = Bs[buf][wn + row][16 * half + j];
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
         }
+        if (more) store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
     const int col = lane & 31, hi = lane >> 5;
 #pragma unroll
@@ -86,41 +127,81 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M,
     G[e] = s;
 }
 
-template <int MG>
+template <int MG, bool VY>
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, int K, int M, int m0,
                                                  const float* __restrict__ Y, int64_t ldy,
                                                  float* __restrict__ Out, int64_t ldo, int64_t L, float beta)
 {
-    __shared__ float Cs[32][MG * 32 + 1];
+    // The block owns 128 columns l (32 per wave) and MG 32-row blocks of Out.  k runs in chunks of
+    // CK: the chunk's rows of C and Y are staged in LDS (double buffered), and the next chunk's global
+    // loads are issued into registers before the current chunk's MFMAs, so they overlap.
+    constexpr int CK = 16;
+    constexpr int MW = MG * 32;
+    constexpr int NC = (CK * MW + 255) / 256;     // C elements per thread per chunk
+    __shared__ float Cs[2][CK][MW + 1];
+    __shared__ __attribute__((aligned(16))) float Ys[2][CK][128 + 4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t lb = ((int64_t)blockIdx.x * 4 + wave) * 32;
+    const int64_t lb = (int64_t)blockIdx.x * 128;
     const int col = lane & 31, half = lane >> 5;
-    const int64_t l = lb + col;
-    const bool lin = l < L;
+    float cr[NC];
+    f4v yr[2];
+    auto load = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int e = tid + q * 256;
+            const int kr = e / MW, mc = e % MW;
+            const int k = kc + kr, m = m0 + mc;
+            cr[q] = (e < CK * MW && k < K && m < M) ? C[(int64_t)k * M + m] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * 256;          // 512 four-column groups: 16 rows x 32 groups
+            const int kr = e >> 5, c4 = (e & 31) * 4;
+            const int k = kc + kr;
+            const int64_t l = lb + c4;
+            if (VY && k < K && l + 3 < L) {
+                yr[q] = *(const f4v*)(Y + (int64_t)k * ldy + l);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) yr[q][t] = (k < K && l + t < L) ? Y[(int64_t)k * ldy + l + t] : 0.f;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const int e = tid + q * 256;
+            if (e < CK * MW) Cs[buf][e / MW][e % MW] = cr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * 256;
+            *(f4v*)&Ys[buf][e >> 5][(e & 31) * 4] = yr[q];
+        }
+    };
     f16v acc[MG];
 #pragma unroll
     for (int g = 0; g < MG; ++g) acc[g] = (f16v){};
-    for (int kc = 0; kc < K; kc += 32) {
-        for (int e = tid; e < 32 * MG * 32; e += 256) {
-            const int kr = e / (MG * 32), mc = e % (MG * 32);
-            const int k = kc + kr, m = m0 + mc;
-            Cs[kr][mc] = (k < K && m < M) ? C[(int64_t)k * M + m] : 0.f;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int j = 0; j < 16; ++j) {
-            const int kr = 2 * j + half;
-            const int k = kc + kr;
-            const float b = (lin && k < K) ? Y[(int64_t)k * ldy + l] : 0.f;
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int kc = 0; kc < K; kc += CK) {
+        const bool more = kc + CK < K;
+        if (more) load(kc + CK);
 #pragma unroll
-            for (int g = 0; g < MG; ++g) {
-                const float a = Cs[kr][g * 32 + col];
-                acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[g], 0, 0, 0);
-            }
+        for (int j = 0; j < CK / 2; ++j) {
+            const int kr = 2 * j + half;
+            const float bv = Ys[buf][kr][wave * 32 + col];
+#pragma unroll
+            for (int g = 0; g < MG; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(Cs[buf][kr][g * 32 + col], bv, acc[g], 0, 0, 0);
         }
+        if (more) store(buf ^ 1);
         __syncthreads();
+        buf ^= 1;
     }
-    if (!lin) return;
+    const int64_t l = lb + wave * 32 + col;
+    if (l >= L) return;
 #pragma unroll
     for (int g = 0; g < MG; ++g) {
 #pragma unroll
@@ -288,7 +369,12 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
     float* part = (float*)ws.get("gram_part", sizeof(float) * (size_t)nsplit * M * N);
     if (!part) return fail(RTT_ENOMEM, "gram workspace");
     dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit);
-    hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part);
+    // 16-byte loads need 16-byte aligned rows (slice starts are multiples of GK)
+    const bool vl = (((uintptr_t)A) & 15) == 0 && (((uintptr_t)B) & 15) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
+    if (vl)
+        hipLaunchKernelGGL(k_gram_partial<true>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part);
+    else
+        hipLaunchKernelGGL(k_gram_partial<false>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part);
     const int64_t tot = (int64_t)M * N;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit, M, N,
                        sym, G_dev);
@@ -301,7 +387,10 @@ static void combine_launch(const float* C, int K, int M, int m0, const float* Y,
                            int64_t ldo, int64_t L, float beta, hipStream_t s)
 {
     dim3 grid((unsigned)((L + 127) / 128));
-    hipLaunchKernelGGL((k_combine<MG>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta);
+    // 16-byte loads of Y need 16-byte aligned rows
+    const bool vy = (((uintptr_t)Y) & 15) == 0 && (ldy % 4) == 0;
+    if (vy) hipLaunchKernelGGL((k_combine<MG, true>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta);
+    else hipLaunchKernelGGL((k_combine<MG, false>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta);
 }
 
 int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Out, int64_t ldo, int64_t L,
