@@ -245,3 +245,23 @@ def test_mixer_replays_in_a_captured_graph(gpu_lib):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(d, ref_d) and torch.equal(yt, ref_t)
+
+
+def test_mixer_at_the_largest_block(gpu_lib):
+    """nvec = 65535 (the largest block a call takes) on a small geometry: every vector equals the same
+    vector mixed alone; nvec = 65536 is rejected."""
+    import torch
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=96, rays=(9, 4, 3), n_frames=5)
+    G = rtt.Geometry(geo)
+    say("case mixer largest block")
+    for kind in ("unresolved", "total_flux"):
+        M = rtt.Mixer(G, kind, pixel_arrays([geo]) if kind == "unresolved" else None)
+        y = torch.randn(65535, G.n_rows, device="cuda")
+        d = rtt.mix_apply(M, y)
+        t = rtt.mix_adjoint(M, d)
+        for v in (0, 12345, 65534):
+            assert torch.equal(d[v], rtt.mix_apply(M, y[v].contiguous()))
+            assert torch.equal(t[v], rtt.mix_adjoint(M, d[v].contiguous()))
+        with pytest.raises(rtt.RttError):
+            rtt.mix_apply(M, torch.zeros(65536, G.n_rows, device="cuda"))
