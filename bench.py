@@ -648,8 +648,13 @@ def main():
         t0r = time.perf_counter()
         sv = rtt.rsvd(G, k=p.get("rsvd_k", 256), p=p.get("rsvd_p", 8), q=p.get("rsvd_q", 2), seed=2001)
         torch.cuda.synchronize()
-        rs = {"seconds": time.perf_counter() - t0r, "k": sv.k, "sigma_1": float(sv.sigma[0]),
-              "sigma_k": float(sv.sigma[-1]), "block_applies": 6 * (p.get("rsvd_k", 256) + p.get("rsvd_p", 8))}
+        t_rs = time.perf_counter() - t0r
+        # (q + 1) block applies of A and of A^T on l = k + p vectors; the rest is the dense part
+        # (MFMA Gram / combine, FP64 small factorisations on the host)
+        t_app = (p.get("rsvd_q", 2) + 1) * (ms_a + ms_at) * 1e-3
+        rs = {"seconds": t_rs, "k": sv.k, "sigma_1": float(sv.sigma[0]),
+              "sigma_k": float(sv.sigma[-1]), "block_applies": 6 * (p.get("rsvd_k", 256) + p.get("rsvd_p", 8)),
+              "apply_seconds_est": t_app, "dense_seconds_est": t_rs - t_app}
         log("rsvd: %.2f s, sigma_1 %.4g sigma_k %.4g" % (rs["seconds"], rs["sigma_1"], rs["sigma_k"]))
         del sv
 
@@ -676,8 +681,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": dom_gbps / HBM_PEAK_GBPS, "traffic": traffic, "bytes_per_launch": dom_bytes,
                      "kernel_source_digest": digest},
-        "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a},
-                    "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at}},
+        "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a,
+                                 "ms_p10_median_p90": [float(np.percentile(t_a, q)) for q in (10, 50, 90)],
+                                 "frac_of_copy": gbps_a / calib["copy_gbps"]},
+                    "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at,
+                                         "ms_p10_median_p90": [float(np.percentile(t_at, q)) for q in (10, 50, 90)],
+                                         "frac_of_copy": gbps_at / calib["copy_gbps"]}},
         "hbm_gbps": (b_a + b_at) / ((ms_a + ms_at) * 1e-3) / 1e9,
         "variants": variants,
         "plain_value": plain,
