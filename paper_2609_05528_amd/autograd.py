@@ -91,3 +91,36 @@ def ridge_estimate(y, geom, lam, tol=1e-6, maxit=1000):
 def tsvd_estimate(y, geom, svd, t=0, sigma_min=0.0):
     """TSVD estimate x_hat = V_t diag(sigma_t^-2) V_t^T A^T y (Sec. 9), differentiable in y."""
     return _TsvdProject.apply(RetardedTimeAdjointOp.apply(y.contiguous(), geom, 0), geom, svd, t, sigma_min)
+
+
+class MixOp(torch.autograd.Function):
+    """d = (L kron I) y for an order mixer of eq. (4); the backward is the transpose (L^T kron I)."""
+
+    @staticmethod
+    def forward(ctx, y, mixer):
+        from .mixer import mix_apply
+        ctx.mixer = mixer
+        return mix_apply(mixer, y.contiguous())
+
+    @staticmethod
+    def backward(ctx, gd):
+        return MixAdjointOp.apply(gd.contiguous(), ctx.mixer), None
+
+
+class MixAdjointOp(torch.autograd.Function):
+    """y = (L^T kron I) d; the backward is the mixer itself."""
+
+    @staticmethod
+    def forward(ctx, d, mixer):
+        from .mixer import mix_adjoint
+        ctx.mixer = mixer
+        return mix_adjoint(mixer, d.contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        return MixOp.apply(gy.contiguous(), ctx.mixer), None
+
+
+def mixed_apply(x, geom, mixer, order_mask=0):
+    """The mixed-arm operator (L kron I) A x (eq. (4) after eq. (3)), differentiable in x."""
+    return MixOp.apply(RetardedTimeOp.apply(x.contiguous(), geom, order_mask), mixer)

@@ -265,3 +265,25 @@ def test_mixer_at_the_largest_block(gpu_lib):
             assert torch.equal(t[v], rtt.mix_adjoint(M, d[v].contiguous()))
         with pytest.raises(rtt.RttError):
             rtt.mix_apply(M, torch.zeros(65536, G.n_rows, device="cuda"))
+
+
+def test_mixed_arm_operator_gradient_matches_oracle(gpu_lib):
+    """The mixed-arm operator (L kron I) A behind autograd: forward and the gradient of <g, (L kron I) A x>,
+    A^T (L^T kron I) g, against the oracle's A, A^T and mixer."""
+    import torch
+    from paper_2609_05528_amd.autograd import mixed_apply
+    rtt = gpu_lib
+    geo = ragged_geometries()[0]
+    G = rtt.Geometry(geo)
+    M = rtt.Mixer(G, "unresolved", pixel_arrays([geo]))
+    say("case mixed-arm autograd")
+    rng = np.random.default_rng(97)
+    x64 = rng.random((2, geo.grid.n_cols))
+    g64 = rng.standard_normal((2, M.n_rows))
+    x = to_dev(x64).requires_grad_(True)
+    d = mixed_apply(x, G, M)
+    want = oracle.mix(geo, oracle.forward(geo, x64.astype(np.float32).astype(np.float64)), "unresolved")
+    assert rel(d.detach().cpu().numpy(), want) < TOL
+    (gx,) = torch.autograd.grad((d * to_dev(g64)).sum(), x)
+    want_g = oracle.adjoint(geo, oracle.mix_adjoint(geo, g64.astype(np.float32).astype(np.float64), "unresolved"))
+    assert rel(gx.cpu().numpy(), want_g) < TOL
