@@ -628,7 +628,18 @@ def main():
         g5 = geo5.grid
         b5 = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, False)
         b5t = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, True)
+        # block Lanczos on the large geometry (512 right vectors: 16 steps of 32), wall time
+        torch.cuda.synchronize()
+        t0l = time.perf_counter()
+        svl = rtt.rsvd(G5, method="lanczos", k=64, block=32, steps=16, seed=5001)
+        torch.cuda.synchronize()
+        t_lz = time.perf_counter() - t0l
+        lz = {"seconds": t_lz, "block": 32, "steps": 16, "theta_1": float(svl.sigma[0]),
+              "residual_1": float(svl.residual[0])}
+        del svl
+        log("lanczos (512 vectors, large geometry): %.2f s" % t_lz)
         large = {"workload": "cfg5: " + synth.config("cfg5")["label"] + ", one vector per launch",
+                 "block_lanczos_512": lz,
                  "op_apply": {"ms": ta5, "GBps": b5 / (ta5 * 1e-3) / 1e9,
                               "frac": b5 / (ta5 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                               "variant": rtt.variant_names(False)[G5.members[0]["apply_variant"]]},
