@@ -57,5 +57,7 @@ void jacobi_svd(const std::vector<double>& M, int n, std::vector<double>& U, std
                 std::vector<double>& W);
 // C = A B for n x n row-major matrices.
 void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C);
+// C = A B for upper triangular A and B (n x n row-major); the strictly lower part of C is zero.
+void matmul_upper(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C);
 
 }  // namespace rtt

@@ -4,11 +4,114 @@
 // Gram matrix.  Row-major storage.
 #include <algorithm>
 #include <cmath>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "dense.h"
 
 namespace rtt {
+
+// A pool of host worker threads (at most 15, started on first use and kept to the end of the
+// process).  run(parts, f) calls f(0) .. f(parts - 1), each once, on the caller and the workers,
+// and returns when all have finished.  A job lives on the caller's stack until every worker that
+// picked it up has let it go.  Concurrent callers do not wait for each other: a caller that finds
+// the pool busy does its parts alone.
+class HostPool {
+  public:
+    static HostPool& get()
+    {
+        static HostPool* p = new HostPool();   // never destroyed: workers may still wait at exit
+        return *p;
+    }
+    template <class F>
+    void run(int parts, F&& f)
+    {
+        std::unique_lock<std::mutex> busy(run_m_, std::try_to_lock);
+        if (parts <= 1 || nworkers_ == 0 || !busy.owns_lock()) {
+            for (int i = 0; i < parts; ++i) f(i);
+            return;
+        }
+        Job j;
+        j.f = [&f](int i) { f(i); };
+        j.parts = parts;
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            cur_ = &j;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work(j);
+        while (j.done.load(std::memory_order_acquire) < parts) std::this_thread::yield();
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            cur_ = nullptr;
+        }
+        while (j.users.load(std::memory_order_acquire) > 0) std::this_thread::yield();
+    }
+    int threads() const { return nworkers_ + 1; }
+
+  private:
+    struct Job {
+        std::function<void(int)> f;
+        int parts = 0;
+        std::atomic<int> next{0}, done{0}, users{0};
+    };
+    HostPool()
+    {
+        const int hw = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+        nworkers_ = hw - 1;
+        for (int t = 0; t < nworkers_; ++t) std::thread([this] { loop(); }).detach();
+    }
+    static void work(Job& j)
+    {
+        for (;;) {
+            const int i = j.next.fetch_add(1, std::memory_order_relaxed);
+            if (i >= j.parts) break;
+            j.f(i);
+            j.done.fetch_add(1, std::memory_order_release);
+        }
+    }
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            Job* j;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+                j = cur_;
+                if (!j) continue;
+                j->users.fetch_add(1, std::memory_order_acq_rel);
+            }
+            work(*j);
+            j->users.fetch_sub(1, std::memory_order_acq_rel);
+        }
+    }
+    std::mutex run_m_, m_;
+    std::condition_variable cv_;
+    Job* cur_ = nullptr;
+    uint64_t gen_ = 0;
+    int nworkers_ = 0;
+};
+
+// f(lo, hi) over [0, n) split into contiguous parts, one per pool thread (parts of at least
+// `grain` items).  The parts touch disjoint data, so the result does not depend on the split.
+template <class F>
+static void parallel_for(int n, int grain, F f)
+{
+    HostPool& pool = HostPool::get();
+    const int parts = std::max(1, std::min(pool.threads(), n / std::max(1, grain)));
+    if (parts == 1) {
+        f(0, n);
+        return;
+    }
+    pool.run(parts, [&](int t) { f((int)((int64_t)n * t / parts), (int)((int64_t)n * (t + 1) / parts)); });
+}
 
 int cholesky_upper(const std::vector<double>& G, int n, double shift, double dead_tol, std::vector<double>& R,
                    std::vector<char>& dead)
@@ -17,24 +120,30 @@ int cholesky_upper(const std::vector<double>& G, int n, double shift, double dea
     dead.assign(n, 0);
     double maxdiag = 0.0;
     for (int j = 0; j < n; ++j) maxdiag = std::max(maxdiag, G[(size_t)j * n + j]);
+    // right-looking form: S holds the upper triangle of G + shift I minus the rank-one terms of
+    // the rows of R already formed.  Each entry receives its terms in increasing row order, the
+    // order of the textbook column formula, and every update runs along a contiguous row.
+    std::vector<double> S(G.begin(), G.begin() + (size_t)n * n);
+    for (int j = 0; j < n; ++j) S[(size_t)j * n + j] += shift;
     int ndead = 0;
     for (int j = 0; j < n; ++j) {
-        double d = G[(size_t)j * n + j] + shift;
-        for (int k = 0; k < j; ++k) d -= R[(size_t)k * n + j] * R[(size_t)k * n + j];
+        const double d = S[(size_t)j * n + j];
         if (!(d > dead_tol * maxdiag) || maxdiag <= 0.0) {
             // dependent column: keep its projection coefficients R[k][j] (k < j),
             // zero diagonal, zero row (it spans no new direction)
             dead[j] = 1;
             ++ndead;
-            R[(size_t)j * n + j] = 0.0;
             continue;
         }
         const double rjj = std::sqrt(d);
-        R[(size_t)j * n + j] = rjj;
+        double* rj = &R[(size_t)j * n];
+        const double* sj = &S[(size_t)j * n];
+        rj[j] = rjj;
+        for (int i = j + 1; i < n; ++i) rj[i] = sj[i] / rjj;
         for (int i = j + 1; i < n; ++i) {
-            double v = G[(size_t)j * n + i];
-            for (int k = 0; k < j; ++k) v -= R[(size_t)k * n + j] * R[(size_t)k * n + i];
-            R[(size_t)j * n + i] = v / rjj;
+            const double r = rj[i];
+            double* si = &S[(size_t)i * n];
+            for (int l = i; l < n; ++l) si[l] -= r * rj[l];
         }
     }
     return ndead;
@@ -43,16 +152,24 @@ int cholesky_upper(const std::vector<double>& G, int n, double shift, double dea
 void upper_inverse(const std::vector<double>& R, int n, const std::vector<char>& dead, std::vector<double>& Ri)
 {
     Ri.assign((size_t)n * n, 0.0);
-    // column by column back substitution: R * Ri[:, j] = e_j
-    for (int j = 0; j < n; ++j) {
-        if (dead[j]) continue;
-        Ri[(size_t)j * n + j] = 1.0 / R[(size_t)j * n + j];
-        for (int i = j - 1; i >= 0; --i) {
-            if (dead[i]) continue;
-            double v = 0.0;
-            for (int k = i + 1; k <= j; ++k) v += R[(size_t)i * n + k] * Ri[(size_t)k * n + j];
-            Ri[(size_t)i * n + j] = -v / R[(size_t)i * n + i];
+    // back substitution row by row from the bottom: R[i][i] Ri[i][j] = delta_ij - sum_{k>i} R[i][k] Ri[k][j],
+    // the sum taken in increasing k along contiguous rows of Ri.  Dependent rows stay zero, and so
+    // do dependent columns (their entries only ever receive zeros).
+    std::vector<double> t(n);
+    for (int i = n - 1; i >= 0; --i) {
+        if (dead[i]) continue;
+        std::fill(t.begin() + i, t.end(), 0.0);
+        const double* ri = &R[(size_t)i * n];
+        for (int k = i + 1; k < n; ++k) {
+            const double r = ri[k];
+            if (r == 0.0 || dead[k]) continue;
+            const double* rk = &Ri[(size_t)k * n];
+            for (int j = k; j < n; ++j) t[j] += r * rk[j];
         }
+        double* o = &Ri[(size_t)i * n];
+        const double inv = 1.0 / ri[i];
+        o[i] = inv;
+        for (int j = i + 1; j < n; ++j) o[j] = t[j] == 0.0 ? 0.0 : -t[j] / ri[i];
     }
 }
 
@@ -69,6 +186,19 @@ void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, s
         }
 }
 
+void matmul_upper(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C)
+{
+    C.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = i; k < n; ++k) {
+            const double a = A[(size_t)i * n + k];
+            if (a == 0.0) continue;
+            const double* b = &B[(size_t)k * n];
+            double* c = &C[(size_t)i * n];
+            for (int j = k; j < n; ++j) c[j] += a * b[j];
+        }
+}
+
 // Eigenvectors of a symmetric n x n matrix S (row-major, destroyed): Householder reduction to
 // tridiagonal form T = Q^T S Q with Q accumulated, then implicit symmetric QR steps with the
 // Wilkinson shift on T (Golub and Van Loan, Matrix Computations, Sec. 8.3), the Givens rotations
@@ -81,6 +211,8 @@ static void sym_eigvectors(std::vector<double>& S, int n, std::vector<double>& Z
     Z.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
     std::vector<double> d(n, 0.0), e(n, 0.0), v(n), p(n), w(n), q(n);
+    // reflector k: beta_k and v_k (length n - k - 1) kept for the back-transformation
+    std::vector<double> hv((size_t)n * n, 0.0), hbeta(n, 0.0);
     auto A = [&](int i, int j) -> double& { return S[(size_t)i * n + j]; };
     // reduction: step k annihilates A[k+2:, k] with a reflector H = I - beta v v^T on rows k+1..
     for (int k = 0; k + 2 < n; ++k) {
@@ -104,27 +236,24 @@ static void sym_eigvectors(std::vector<double>& S, int n, std::vector<double>& Z
         e[k] = alpha;
         if (beta == 0.0) continue;
         // A22 <- H A22 H = A22 - v w^T - w v^T with p = beta A22 v, w = p - (beta/2)(p^T v) v
+        // A22 is exactly symmetric (its updates add the same two products in either order), so
+        // A22 v is summed along contiguous rows: the same terms in the same order per entry.
+        std::fill(q.begin(), q.begin() + m, 0.0);
+        for (int j = 0; j < m; ++j) {
+            const double vj = v[j];
+            const double* aj = &A(k + 1 + j, k + 1);
+            for (int i = 0; i < m; ++i) q[i] += vj * aj[i];
+        }
         double pv = 0.0;
         for (int i = 0; i < m; ++i) {
-            double t = 0.0;
-            for (int j = 0; j < m; ++j) t += A(k + 1 + i, k + 1 + j) * v[j];
-            p[i] = beta * t;
+            p[i] = beta * q[i];
             pv += p[i] * v[i];
         }
         for (int i = 0; i < m; ++i) w[i] = p[i] - 0.5 * beta * pv * v[i];
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) A(k + 1 + i, k + 1 + j) -= v[i] * w[j] + w[i] * v[j];
-        // Q <- Q H on columns k+1.. (rows k+1.. of Qt)
-        for (int r = 0; r < n; ++r) q[r] = 0.0;
-        for (int j = 0; j < m; ++j) {
-            const double* zj = &Z[(size_t)(k + 1 + j) * n];
-            for (int r = 0; r < n; ++r) q[r] += zj[r] * v[j];
-        }
-        for (int j = 0; j < m; ++j) {
-            double* zj = &Z[(size_t)(k + 1 + j) * n];
-            const double bv = beta * v[j];
-            for (int r = 0; r < n; ++r) zj[r] -= q[r] * bv;
-        }
+        hbeta[k] = beta;
+        std::copy(v.begin(), v.begin() + m, hv.begin() + (size_t)k * n);
     }
     if (n >= 2) {
         d[n - 2] = A(n - 2, n - 2);
@@ -132,7 +261,15 @@ static void sym_eigvectors(std::vector<double>& S, int n, std::vector<double>& Z
     }
     d[n - 1] = A(n - 1, n - 1);
     e[n - 1] = 0.0;
-    // implicit QR on the tridiagonal (d, e): e[i] couples i and i+1
+    // implicit QR on the tridiagonal (d, e): e[i] couples i and i+1.  The rotations are recorded.
+    // Q (the reflectors, then the rotations, in order) is formed afterwards, a range of columns of
+    // Qt at a time: every column sees the same updates in the same order.
+    struct Rot {
+        int k;
+        double c, s;
+    };
+    std::vector<Rot> rots;
+    rots.reserve((size_t)8 * n * n);
     const double eps = 2.3e-16;
     int hi = n - 1, guard = 0;
     while (hi > 0 && guard < 64 * n) {
@@ -165,15 +302,55 @@ static void sym_eigvectors(std::vector<double>& S, int n, std::vector<double>& Z
                 e[k + 1] *= c;
                 x = e[k];
             }
-            double* zk = &Z[(size_t)k * n];
-            double* zk1 = &Z[(size_t)(k + 1) * n];
-            for (int r2 = 0; r2 < n; ++r2) {
+            rots.push_back({k, c, sn});
+        }
+    }
+    // one contiguous range of columns of Qt per host thread, worked on in a private copy (no
+    // cache line is shared between threads while the updates run)
+    parallel_for(n, 8, [&](int r0, int r1) {
+        const int w = r1 - r0;
+        std::vector<double> L((size_t)n * w), ql(w);
+        for (int i = 0; i < n; ++i) std::copy(&Z[(size_t)i * n + r0], &Z[(size_t)i * n + r1], &L[(size_t)i * w]);
+        // Q <- Q H_k on columns k+1.. (rows k+1.. of Qt), k ascending
+        for (int k = 0; k + 2 < n; ++k) {
+            const double beta = hbeta[k];
+            if (beta == 0.0) continue;
+            const int m = n - k - 1;
+            const double* vk = &hv[(size_t)k * n];
+            std::fill(ql.begin(), ql.end(), 0.0);
+            for (int j = 0; j < m; ++j) {
+                const double* zj = &L[(size_t)(k + 1 + j) * w];
+                for (int r2 = 0; r2 < w; ++r2) ql[r2] += zj[r2] * vk[j];
+            }
+            for (int j = 0; j < m; ++j) {
+                double* zj = &L[(size_t)(k + 1 + j) * w];
+                const double bv = beta * vk[j];
+                for (int r2 = 0; r2 < w; ++r2) zj[r2] -= ql[r2] * bv;
+            }
+        }
+        for (const Rot& g : rots) {
+            double* zk = &L[(size_t)g.k * w];
+            double* zk1 = zk + w;
+            const double c = g.c, sn = g.s;
+            for (int r2 = 0; r2 < w; ++r2) {
                 const double u0 = zk[r2], u1 = zk1[r2];
                 zk[r2] = c * u0 + sn * u1;
                 zk1[r2] = -sn * u0 + c * u1;
             }
         }
-    }
+        for (int i = 0; i < n; ++i) std::copy(&L[(size_t)i * w], &L[(size_t)(i + 1) * w], &Z[(size_t)i * n + r0]);
+    });
+}
+
+// <a, b> with eight partial sums (a fixed order, vectorisable)
+static double dot8(const double* a, const double* b, int n)
+{
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = 0;
+    for (; i + 8 <= n; i += 8)
+        for (int u = 0; u < 8; ++u) s[u] += a[i + u] * b[i + u];
+    for (; i < n; ++i) s[i & 7] += a[i] * b[i];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 void jacobi_svd(const std::vector<double>& M, int n, std::vector<double>& U, std::vector<double>& s,
@@ -185,78 +362,100 @@ void jacobi_svd(const std::vector<double>& M, int n, std::vector<double>& U, std
     std::vector<double> a((size_t)n * n, 0.0), v((size_t)n * n, 0.0);
     {
         std::vector<double> G((size_t)n * n, 0.0), Z;
-        for (int k = 0; k < n; ++k) {
-            const double* mk = &M[(size_t)k * n];
-            for (int i = 0; i < n; ++i) {
-                const double mi = mk[i];
-                if (mi == 0.0) continue;
-                double* gi = &G[(size_t)i * n];
-                for (int j = 0; j < n; ++j) gi[j] += mi * mk[j];
+        parallel_for(n, 16, [&](int i0, int i1) {
+            for (int k = 0; k < n; ++k) {
+                const double* mk = &M[(size_t)k * n];
+                for (int i = i0; i < i1; ++i) {
+                    const double mi = mk[i];
+                    if (mi == 0.0) continue;
+                    double* gi = &G[(size_t)i * n];
+                    for (int j = 0; j < n; ++j) gi[j] += mi * mk[j];
+                }
             }
-        }
+        });
         sym_eigvectors(G, n, Z);   // row j of Z: eigenvector j
         v = Z;
-        for (int i = 0; i < n; ++i) {
-            const double* mi = &M[(size_t)i * n];
-            for (int j = 0; j < n; ++j) {
+        // a[j] = M z_j, accumulated along rows of M^T
+        std::vector<double> Mt((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) Mt[(size_t)k * n + i] = M[(size_t)i * n + k];
+        parallel_for(n, 16, [&](int j0, int j1) {
+            for (int j = j0; j < j1; ++j) {
                 const double* zj = &v[(size_t)j * n];
-                double t = 0.0;
-                for (int k = 0; k < n; ++k) t += mi[k] * zj[k];
-                a[(size_t)j * n + i] = t;
+                double* aj = &a[(size_t)j * n];
+                for (int k = 0; k < n; ++k) {
+                    const double z = zj[k];
+                    if (z == 0.0) continue;
+                    const double* mk = &Mt[(size_t)k * n];
+                    for (int i = 0; i < n; ++i) aj[i] += z * mk[i];
+                }
             }
-        }
+        });
     }
     std::vector<double> nrm(n);
-    for (int j = 0; j < n; ++j) {
-        double t = 0.0;
-        for (int i = 0; i < n; ++i) t += a[(size_t)j * n + i] * a[(size_t)j * n + i];
-        nrm[j] = t;
-    }
+    for (int j = 0; j < n; ++j) nrm[j] = dot8(&a[(size_t)j * n], &a[(size_t)j * n], n);
     const double eps = 1e-15;
+    // one rotation of columns p < q; returns 1 if it was needed
+    auto rotate = [&](int p, int q) -> int {
+        double* ap = &a[(size_t)p * n];
+        double* aq = &a[(size_t)q * n];
+        const double g = dot8(ap, aq, n);
+        const double al = nrm[p], be = nrm[q];
+        if (std::fabs(g) <= eps * std::sqrt(al * be) || g == 0.0) return 0;
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < n; ++i) {
+            const double x = ap[i], y = aq[i];
+            ap[i] = c * x - sn * y;
+            aq[i] = sn * x + c * y;
+        }
+        nrm[p] = dot8(ap, ap, n);
+        nrm[q] = dot8(aq, aq, n);
+        double* vp = &v[(size_t)p * n];
+        double* vq = &v[(size_t)q * n];
+        for (int i = 0; i < n; ++i) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = c * x - sn * y;
+            vq[i] = sn * x + c * y;
+        }
+        return 1;
+    };
+    // Sweeps in block round-robin order: the columns form NB blocks; in round r of a sweep the
+    // blocks meet in NB/2 disjoint pairs (the circle method), and each pair rotates every column
+    // of one block against every column of the other, the pairs inside each block in the first
+    // round.  Every pair of columns is visited once per sweep.  The pairs of a round touch
+    // disjoint columns and run on separate host threads; NB is fixed, so the result does not
+    // depend on the number of threads.
+    constexpr int NB = 16;
+    auto blk = [n](int b) { return (int)((int64_t)n * b / NB); };
+    std::vector<int> rot_task(NB / 2);
     for (int sweep = 0; sweep < 60; ++sweep) {
         int rot = 0;
-        for (int p = 0; p < n - 1; ++p) {
-            for (int q = p + 1; q < n; ++q) {
-                double* ap = &a[(size_t)p * n];
-                double* aq = &a[(size_t)q * n];
-                double g = 0.0;
-                for (int i = 0; i < n; ++i) g += ap[i] * aq[i];
-                const double al = nrm[p], be = nrm[q];
-                if (std::fabs(g) <= eps * std::sqrt(al * be) || g == 0.0) continue;
-                ++rot;
-                const double zeta = (be - al) / (2.0 * g);
-                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
-                double np = 0.0, nq = 0.0;
-                for (int i = 0; i < n; ++i) {
-                    const double x = ap[i], y = aq[i];
-                    const double xn = c * x - sn * y, yn = sn * x + c * y;
-                    ap[i] = xn;
-                    aq[i] = yn;
-                    np += xn * xn;
-                    nq += yn * yn;
+        for (int r = 0; r < NB - 1; ++r) {
+            parallel_for(NB / 2, n >= 128 ? 1 : NB, [&](int t0, int t1) {
+                for (int t = t0; t < t1; ++t) {
+                    int P = t == 0 ? r : (r + t) % (NB - 1);
+                    int Q = t == 0 ? NB - 1 : (r - t + NB - 1) % (NB - 1);
+                    if (P > Q) std::swap(P, Q);
+                    int cnt = 0;
+                    if (r == 0)
+                        for (int B : {P, Q})
+                            for (int p = blk(B); p < blk(B + 1); ++p)
+                                for (int q = p + 1; q < blk(B + 1); ++q) cnt += rotate(p, q);
+                    for (int p = blk(P); p < blk(P + 1); ++p)
+                        for (int q = blk(Q); q < blk(Q + 1); ++q) cnt += rotate(p, q);
+                    rot_task[t] = cnt;
                 }
-                nrm[p] = np;
-                nrm[q] = nq;
-                double* vp = &v[(size_t)p * n];
-                double* vq = &v[(size_t)q * n];
-                for (int i = 0; i < n; ++i) {
-                    const double x = vp[i], y = vq[i];
-                    vp[i] = c * x - sn * y;
-                    vq[i] = sn * x + c * y;
-                }
-            }
+            });
+            for (int c : rot_task) rot += c;
         }
         if (rot == 0) break;
     }
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::vector<double> sv(n);
-    for (int j = 0; j < n; ++j) {
-        double t = 0.0;
-        for (int i = 0; i < n; ++i) t += a[(size_t)j * n + i] * a[(size_t)j * n + i];
-        sv[j] = std::sqrt(t);
-    }
+    for (int j = 0; j < n; ++j) sv[j] = std::sqrt(dot8(&a[(size_t)j * n], &a[(size_t)j * n], n));
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sv[x] > sv[y]; });
     U.assign((size_t)n * n, 0.0);
     W.assign((size_t)n * n, 0.0);

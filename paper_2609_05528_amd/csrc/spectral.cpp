@@ -6,10 +6,12 @@
 // R^T = Ur S W^T, so B = Ur S (Qb W)^T.  Every block is orthonormalised by
 // Cholesky QR: the Gram matrix comes from the FP32 MFMA kernel with FP64
 // slice reduction, the Cholesky factor and its inverse are FP64 (host), the
-// triangular apply is the MFMA combine kernel.  Two passes (CholQR2); when the
-// first Gram matrix is too ill-conditioned for FP32 a diagonal shift is added
-// in the first pass and a third pass follows (shifted CholQR3, Fukaya et al.
-// 2020).  Columns that are numerically dependent are dropped (zeroed).
+// triangular apply is the MFMA combine kernel.  Two passes (CholQR2) for the
+// final bases Q and Qb; one for the intermediate bases of the power iterations,
+// which only carry a span.  When the first Gram matrix is too ill-conditioned
+// for FP32 a diagonal shift is added in the first pass and one more pass
+// follows (shifted CholQR3, Fukaya et al. 2020).  Columns that are numerically
+// dependent are dropped (zeroed).
 //
 // rsvd, RTT_SVD_BLOCK_LANCZOS: block Golub-Kahan bidiagonalisation with the
 // right (coefficient-space) basis stored and reorthogonalised twice against
@@ -91,21 +93,24 @@ int upload_f32(Ctx& c, const char* name, const std::vector<double>& h, size_t n,
 // Orthonormalise, independently on every segment, the l (padded to lp) vectors stored in *Y
 // (row stride n), using *T as ping-pong storage; on return *Y holds Q.  R_total[seg] (lp x lp,
 // row-major, upper) receives the accumulated triangular factor with Y = Q R_total on the
-// retained columns of that segment.
+// retained columns of that segment.  final_basis false: the basis only carries a span to the next
+// product (the intermediate steps of subspace iteration), so one Cholesky QR pass is made (two
+// when the first is shifted) and R_total is left as the identity.
 int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>& segs,
-         std::vector<std::vector<double>>& R_total)
+         std::vector<std::vector<double>>& R_total, bool final_basis = true)
 {
+    const int base = final_basis ? 2 : 1;
     double* Gd = (double*)c.ws.get("orth_gram", sizeof(double) * lp * lp);
     if (!Gd) return fail(RTT_ENOMEM, "orth gram");
     const size_t ns = segs.size();
     R_total.assign(ns, std::vector<double>((size_t)lp * lp, 0.0));
-    std::vector<int> passes(ns, 2);
+    std::vector<int> passes(ns, base);
     for (size_t q = 0; q < ns; ++q)
         for (int i = 0; i < lp; ++i) R_total[q][(size_t)i * lp + i] = 1.0;
     std::vector<double> G, R, Ri, Rt;
     std::vector<char> dead;
     for (int pass = 0; pass < 3; ++pass) {
-        if (pass == 2 && std::none_of(passes.begin(), passes.end(), [](int p) { return p > 2; })) break;
+        if (std::all_of(passes.begin(), passes.end(), [pass](int p) { return p <= pass; })) break;
         for (size_t q = 0; q < ns; ++q) {
             const Seg sg = segs[q];
             float* Ys = *Y + sg.off;
@@ -131,15 +136,17 @@ int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>
                     if (!dead[i]) minpiv = std::min(minpiv, R[(size_t)i * lp + i] * R[(size_t)i * lp + i]);
                 if (minpiv < 1e-5 * maxdiag) {
                     cholesky_upper(G, lp, 1e-6 * maxdiag, dead_tol, R, dead);
-                    passes[q] = 3;
+                    passes[q] = base + 1;
                 }
             }
             upper_inverse(R, lp, dead, Ri);
             float* Cd = nullptr;
             if ((rc = upload_f32(c, "orth_rinv", Ri, (size_t)lp * lp, &Cd))) return rc;
             if ((rc = combine(Cd, lp, lp, Ys, n, Ts, n, sg.len, 0.f, c.s))) return rc;
-            matmul(R, R_total[q], lp, Rt);
-            R_total[q].swap(Rt);
+            if (final_basis) {
+                matmul_upper(R, R_total[q], lp, Rt);
+                R_total[q].swap(Rt);
+            }
         }
         std::swap(*Y, *T);
     }
@@ -175,12 +182,12 @@ int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
     std::vector<std::vector<double>> R;
     // Y = A Omega; Q = orth(Y)
     if ((rc = apply(c, false, X, Y, l))) return rc;
-    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R))) return rc;
+    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, false))) return rc;
     for (int it = 0; it < o.q; ++it) {
         if ((rc = apply(c, true, Y, X, l))) return rc;
-        if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R))) return rc;
+        if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R, false))) return rc;
         if ((rc = apply(c, false, X, Y, l))) return rc;
-        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R))) return rc;
+        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, false))) return rc;
     }
     // B^T = A^T Q = Qb R
     if ((rc = apply(c, true, Y, X, l))) return rc;
