@@ -22,9 +22,10 @@ struct Workspace {
 // G (device, FP64, M x N row-major) = A B^T with A: M rows, B: N rows of length L.
 int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb, int M, int N, int64_t L,
          double* G_dev, hipStream_t s);
-// Out[m][l] = beta*Out[m][l] + sum_k C[k][m] Y[k][l]; C device FP32 K x M row-major.
+// Out[m][l] = beta*Out[m][l] + sum_k C[k][m] Y[k][l]; C device FP32 K x M row-major.  upper: the
+// caller guarantees C[k][m] = 0 for k > m (e.g. an upper triangular R^-1), and those terms are skipped.
 int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Out, int64_t ldo, int64_t L,
-            float beta, hipStream_t s);
+            float beta, hipStream_t s, bool upper = false);
 // out[v] = <a_v, b_v> in FP64 for nvec vectors of length n.
 int dots(Workspace& ws, const float* a, int64_t lda, const float* b, int64_t ldb, int64_t n, int nvec,
          double* out_dev, hipStream_t s);

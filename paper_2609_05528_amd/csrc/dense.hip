@@ -130,11 +130,14 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M,
 template <int MG, bool VY>
 __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, int K, int M, int m0,
                                                  const float* __restrict__ Y, int64_t ldy,
-                                                 float* __restrict__ Out, int64_t ldo, int64_t L, float beta)
+                                                 float* __restrict__ Out, int64_t ldo, int64_t L, float beta,
+                                                 int upper)
 {
     // The block owns 128 columns l (32 per wave) and MG 32-row blocks of Out.  k runs in chunks of
     // CK: the chunk's rows of C and Y are staged in LDS (double buffered), and the next chunk's global
-    // loads are issued into registers before the current chunk's MFMAs, so they overlap.
+    // loads are issued into registers before the current chunk's MFMAs, so they overlap.  upper:
+    // C[k][m] = 0 for k > m, so the row blocks that end at or before a chunk's first k are skipped
+    // (their products are exact zeros).
     constexpr int CK = 16;
     constexpr int MW = MG * 32;
     constexpr int NC = (CK * MW + 255) / 256;     // C elements per thread per chunk
@@ -186,15 +189,19 @@ __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, in
     store(0);
     __syncthreads();
     int buf = 0;
-    for (int kc = 0; kc < K; kc += CK) {
-        const bool more = kc + CK < K;
+    const int kend = upper ? min(K, m0 + MW) : K;
+    for (int kc = 0; kc < kend; kc += CK) {
+        const bool more = kc + CK < kend;
         if (more) load(kc + CK);
+        const int gmin = (upper && kc > m0) ? (kc - m0) >> 5 : 0;   // first row block reached
 #pragma unroll
         for (int j = 0; j < CK / 2; ++j) {
             const int kr = 2 * j + half;
             const float bv = Ys[buf][kr][wave * 32 + col];
 #pragma unroll
-            for (int g = 0; g < MG; ++g) acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(Cs[buf][kr][g * 32 + col], bv, acc[g], 0, 0, 0);
+            for (int g = 0; g < MG; ++g)
+                if (g >= gmin)
+                    acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(Cs[buf][kr][g * 32 + col], bv, acc[g], 0, 0, 0);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -384,31 +391,34 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
 
 template <int MG>
 static void combine_launch(const float* C, int K, int M, int m0, const float* Y, int64_t ldy, float* Out,
-                           int64_t ldo, int64_t L, float beta, hipStream_t s)
+                           int64_t ldo, int64_t L, float beta, int upper, hipStream_t s)
 {
     dim3 grid((unsigned)((L + 127) / 128));
     // 16-byte loads of Y need 16-byte aligned rows
     const bool vy = (((uintptr_t)Y) & 15) == 0 && (ldy % 4) == 0;
-    if (vy) hipLaunchKernelGGL((k_combine<MG, true>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta);
-    else hipLaunchKernelGGL((k_combine<MG, false>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta);
+    if (vy)
+        hipLaunchKernelGGL((k_combine<MG, true>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta, upper);
+    else
+        hipLaunchKernelGGL((k_combine<MG, false>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta, upper);
 }
 
 int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Out, int64_t ldo, int64_t L,
-            float beta, hipStream_t s)
+            float beta, hipStream_t s, bool upper)
 {
+    const int up = upper ? 1 : 0;
     if (M <= 0 || L <= 0) return RTT_OK;
     for (int m0 = 0; m0 < M; m0 += 9 * 32) {
         const int mg = std::min(9, (M - m0 + 31) / 32);
         switch (mg) {
-        case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 4: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 5: combine_launch<5>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 6: combine_launch<6>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 7: combine_launch<7>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        case 8: combine_launch<8>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
-        default: combine_launch<9>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, s); break;
+        case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 4: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 5: combine_launch<5>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 6: combine_launch<6>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 7: combine_launch<7>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 8: combine_launch<8>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        default: combine_launch<9>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         }
     }
     RTT_HIP(hipGetLastError());

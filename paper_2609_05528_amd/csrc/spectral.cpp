@@ -142,7 +142,7 @@ int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>
             upper_inverse(R, lp, dead, Ri);
             float* Cd = nullptr;
             if ((rc = upload_f32(c, "orth_rinv", Ri, (size_t)lp * lp, &Cd))) return rc;
-            if ((rc = combine(Cd, lp, lp, Ys, n, Ts, n, sg.len, 0.f, c.s))) return rc;
+            if ((rc = combine(Cd, lp, lp, Ys, n, Ts, n, sg.len, 0.f, c.s, true))) return rc;
             if (final_basis) {
                 matmul_upper(R, R_total[q], lp, Rt);
                 R_total[q].swap(Rt);
@@ -174,20 +174,25 @@ int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
     float* Y2 = dev_alloc(c, "rs_y2", (size_t)lp * m);
     if (!X || !X2 || !Y || !Y2) return fail(RTT_ENOMEM, "rsvd block buffers");
     int rc;
-    if ((rc = fill(X, (int64_t)lp * n, 0.f, c.s)) || (rc = fill(Y, (int64_t)lp * m, 0.f, c.s)) ||
-        (rc = fill(X2, (int64_t)lp * n, 0.f, c.s)) || (rc = fill(Y2, (int64_t)lp * m, 0.f, c.s)))
-        return rc;
+    // Rows l .. lp of X and Y are padding that the Gram and combine kernels read: zero them.  Rows
+    // below l are written by the test block and the products before they are read (all of a row of
+    // X; of a row of Y only the entries of the selected orders, so with an order mask Y is zeroed
+    // whole), and X2 / Y2 are written in full by the combine kernel before they are read.
+    if (lp > l && (rc = fill(X + (size_t)l * n, (int64_t)(lp - l) * n, 0.f, c.s))) return rc;
+    const int y_from = c.mask != 0 ? 0 : l;
+    if (lp > y_from && (rc = fill(Y + (size_t)y_from * m, (int64_t)(lp - y_from) * m, 0.f, c.s))) return rc;
     if (omega) RTT_HIP(hipMemcpyAsync(X, omega, sizeof(float) * l * n, hipMemcpyDeviceToDevice, c.s));
     else if ((rc = normal_fill(X, (int64_t)l * n, o.seed, c.s))) return rc;
     std::vector<std::vector<double>> R;
     // Y = A Omega; Q = orth(Y)
     if ((rc = apply(c, false, X, Y, l))) return rc;
-    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, false))) return rc;
+    // the last basis of the range (Q) is final: U = Q Ur and B^T = A^T Q need it orthonormal
+    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, o.q == 0))) return rc;
     for (int it = 0; it < o.q; ++it) {
         if ((rc = apply(c, true, Y, X, l))) return rc;
         if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R, false))) return rc;
         if ((rc = apply(c, false, X, Y, l))) return rc;
-        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, false))) return rc;
+        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, it == o.q - 1))) return rc;
     }
     // B^T = A^T Q = Qb R
     if ((rc = apply(c, true, Y, X, l))) return rc;

@@ -96,6 +96,50 @@ def test_rsvd_workload_block_matches_oracle(gpu_lib):
     assert proj_dist(V[:8], V_o[:8]) <= 1e-2
 
 
+def test_rsvd_sketch_wider_than_one_combine_launch(gpu_lib):
+    """l = k + p = 320 test vectors: the triangular factors span two row-block launches of the
+    combine kernel (288 + 32 rows).  Singular values against the oracle on the same draw; the
+    returned right vectors orthonormal."""
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=57, rays=(400, 120, 90), n_r=8, n_phi=12, n_frames=16)
+    say("case rsvd l=320", geo.grid.n_cols, geo.n_rows)
+    G = rtt.Geometry(geo)
+    k, p = 300, 20
+    om = np.random.default_rng(3).standard_normal((k + p, geo.grid.n_cols)).astype(np.float32)
+    sv = rtt.rsvd(G, k=k, p=p, q=2, omega=to_dev(om))
+    s_o, _, _ = oracle.rsvd(geo, om.astype(np.float64), q=2)
+    assert np.max(np.abs(sv.sigma - s_o[:k]) / s_o[:k]) <= 1e-4
+    V = sv.V().double().cpu().numpy()
+    assert np.max(np.abs(V @ V.T - np.eye(k))) <= 1e-4
+
+
+@pytest.mark.parametrize("mask", [0b001, 0b110])
+def test_rsvd_with_order_mask_matches_oracle(gpu_lib, mask):
+    """rSVD of the rows of some orders only (the other rows are never written by the operator):
+    singular values against the oracle on the same draw and against LAPACK on the dense rows;
+    the left vectors vanish on the rows left out."""
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=58, rays=(60, 20, 15), n_r=5, n_phi=8, n_frames=12)
+    say("case rsvd order mask", mask)
+    G = rtt.Geometry(geo)
+    k, p = 24, 16
+    om = np.random.default_rng(4).standard_normal((k + p, geo.grid.n_cols)).astype(np.float32)
+    sv = rtt.rsvd(G, k=k, p=p, q=2, omega=to_dev(om), order_mask=mask, keep_u=True)
+    s_o, _, _ = oracle.rsvd(geo, om.astype(np.float64), q=2, order_mask=mask)
+    s_true = np.linalg.svd(oracle.dense(geo, order_mask=mask), compute_uv=False)
+    ok = s_o[:k] >= 1e-3 * s_o[0]
+    assert np.max(np.abs(sv.sigma[ok] - s_o[:k][ok]) / s_o[:k][ok]) <= 1e-4
+    assert np.all(sv.sigma <= s_true[:k] * (1 + 1e-5))
+    U = sv.U().cpu().numpy()
+    kept = np.zeros(geo.n_rows, dtype=bool)
+    off = 0
+    for n, mp in enumerate(geo.maps):
+        rows = mp.n_rays * geo.grid.n_frames
+        kept[off:off + rows] = bool(mask >> n & 1)
+        off += rows
+    assert np.all(np.isfinite(U)) and np.all(U[:, ~kept] == 0.0)
+
+
 def test_block_lanczos_tiny_exhausts_space(gpu_lib):
     rtt = gpu_lib
     geo = tiny_geometry(seed=53, rays=(40, 12, 10), n_r=4, n_phi=8, n_frames=8)
