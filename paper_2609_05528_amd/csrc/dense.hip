@@ -15,6 +15,16 @@
 //           flight; each wave owns 32 columns l and up to MG 32-row blocks of
 //           Out, so every element of Y is read once per pass.
 //
+//  skinny forms (N <= 32 for gram, M <= 32 for combine; 16-byte aligned rows):
+//           no LDS staging.  gram: a wave owns a 32-row tile of A against all
+//           of B over part of an L slice; each lane feeds 16 consecutive l of
+//           its row per chunk (the contraction order is free, so lane (r, h)
+//           gives the MFMA k-pair member h the l values 16h .. 16h+15 of the
+//           chunk, one per step).  combine: a wave owns 128 columns l as four
+//           32-column tiles interleaved by 4, so every lane reads 4 adjacent
+//           columns of a row of Y with one 16-byte load and writes 4 adjacent
+//           outputs with one 16-byte store.
+//
 // MFMA operand layout used (32x32x2 f32): lane t supplies A[t%32][t/32] and
 // B[t/32][t%32]; accumulator register r of lane t holds
 // C[8(r/4) + 4(t/32) + r%4][t%32].
@@ -222,6 +232,139 @@ __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, in
     }
 }
 
+// G partials for N <= 32: block (tile, slice) with four waves taking every fourth 32-column
+// chunk of the slice; the waves' sums are added in wave order and written as the block's partial.
+__global__ __launch_bounds__(256) void k_gram_skinny(const float* __restrict__ A, int64_t lda,
+                                                     const float* __restrict__ B, int64_t ldb, int M, int N,
+                                                     int64_t L, int64_t slice, float* __restrict__ part)
+{
+    __shared__ float red[3][64][17];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile = blockIdx.x, s = blockIdx.y;
+    const int64_t l0 = (int64_t)s * slice, l1 = min(L, l0 + slice);
+    const int r = lane & 31, h = lane >> 5;
+    const int ia = tile * 32 + r;
+    const bool va = ia < M, vb = r < N;
+    const float* __restrict__ pa = A + (int64_t)(va ? ia : 0) * lda;   // rows past the end read row 0,
+    const float* __restrict__ pb = B + (int64_t)(vb ? r : 0) * ldb;    // and their values are zeroed
+    f16v acc = {};
+    for (int64_t lc = l0 + (int64_t)wave * 32; lc < l1; lc += 128) {
+        const int64_t l = lc + 16 * h;
+        float av[16], bv[16];
+        if (l + 16 <= l1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f4v xa = *(const f4v*)(pa + l + 4 * q);
+                const f4v xb = *(const f4v*)(pb + l + 4 * q);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    av[4 * q + t] = va ? xa[t] : 0.f;
+                    bv[4 * q + t] = vb ? xb[t] : 0.f;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const bool in = l + t < l1;
+                av[t] = (va && in) ? pa[l + t] : 0.f;
+                bv[t] = (vb && in) ? pb[l + t] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], acc, 0, 0, 0);
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[wave - 1][lane][q] = acc[q];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += red[w][lane][q];
+    float* __restrict__ out = part + (int64_t)s * M * N;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = tile * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+        if (i < M && r < N) out[(int64_t)i * N + r] = acc[q];
+    }
+}
+
+// Sum of the slice partials of the skinny Gram in FP64: a block takes 64 entries; thread group g
+// (of 16) sums, in slice order, the g-th of 16 contiguous ranges of slices; the 16 group sums are
+// added in group order.  Deterministic; many slices are summed in parallel.
+__global__ __launch_bounds__(1024) void k_gram_reduce_wide(const float* __restrict__ part, int nsplit, int64_t MN,
+                                                           double* __restrict__ G)
+{
+    __shared__ double sum[16][64];
+    const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + e;
+    const int t0 = (int)((int64_t)nsplit * g / 16), t1 = (int)((int64_t)nsplit * (g + 1) / 16);
+    double acc = 0.0;
+    if (i < MN) {
+#pragma unroll 8
+        for (int t = t0; t < t1; ++t) acc += (double)part[(int64_t)t * MN + i];
+    }
+    sum[g][e] = acc;
+    __syncthreads();
+    if (g != 0 || i >= MN) return;
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) tot += sum[q][e];
+    G[i] = tot;
+}
+
+// Out = beta Out + C^T Y for M <= 32: a wave owns columns l0 .. l0 + 127; lane (j, h) reads
+// Y[k][l0 + 4j .. 4j + 3] for k = 2 s + h and feeds tile q (columns l0 + 4j + q) with element q.
+__global__ __launch_bounds__(256) void k_combine_skinny(const float* __restrict__ C, int K, int M,
+                                                        const float* __restrict__ Y, int64_t ldy,
+                                                        float* __restrict__ Out, int64_t ldo, int64_t L, float beta)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & 31, h = lane >> 5;
+    const int64_t l0 = ((int64_t)blockIdx.x * 4 + wave) * 128;
+    if (l0 >= L) return;
+    const int64_t lj = l0 + 4 * j;
+    const bool full = lj + 3 < L;
+    const bool vm = j < M;
+    f16v acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = (f16v){};
+#pragma unroll 8
+    for (int kc = 0; kc < K; kc += 2) {
+        const int k = kc + h;
+        float a = 0.f;
+        f4v y = {0.f, 0.f, 0.f, 0.f};
+        if (k < K) {
+            a = vm ? C[(int64_t)k * M + j] : 0.f;
+            const float* __restrict__ py = Y + (int64_t)k * ldy + lj;
+            if (full) {
+                y = *(const f4v*)py;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) y[t] = lj + t < L ? py[t] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, y[q], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int m = 8 * (q >> 2) + 4 * h + (q & 3);
+        if (m >= M) continue;
+        float* __restrict__ o = Out + (int64_t)m * ldo + lj;
+        f4v v = {acc[0][q], acc[1][q], acc[2][q], acc[3][q]};
+        if (full) {
+            if (beta != 0.f) v += beta * *(const f4v*)o;
+            *(f4v*)o = v;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (lj + t < L) o[t] = (beta == 0.f) ? v[t] : beta * o[t] + v[t];
+        }
+    }
+}
+
 // Philox-4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11) and Box-Muller normals.
 __device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
 {
@@ -364,6 +507,24 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
          double* G_dev, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return RTT_OK;
+    const bool aligned = (((uintptr_t)A) & 15) == 0 && (((uintptr_t)B) & 15) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
+    if (N <= 32 && aligned) {
+        // skinny form: slices of whole 128-column steps, about 4096 blocks in all
+        const int tiles = (M + 31) / 32;
+        int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, 4096 / tiles), L / 1024));
+        int64_t slice = (L + nsplit - 1) / nsplit;
+        slice = std::max<int64_t>(128, ((slice + 127) / 128) * 128);
+        nsplit = (int)std::max<int64_t>(1, (L + slice - 1) / slice);   // L = 0: one empty slice
+        float* part = (float*)ws.get("gram_part", sizeof(float) * (size_t)nsplit * M * N);
+        if (!part) return fail(RTT_ENOMEM, "gram workspace");
+        hipLaunchKernelGGL(k_gram_skinny, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s, A, lda, B, ldb, M, N,
+                           L, slice, part);
+        const int64_t tot = (int64_t)M * N;
+        hipLaunchKernelGGL(k_gram_reduce_wide, dim3((unsigned)((tot + 63) / 64)), dim3(1024), 0, s, part, nsplit, tot,
+                           G_dev);
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     const int nbm = (M + GB - 1) / GB, nbn = (N + GB - 1) / GB;
     const int sym = (A == B && lda == ldb && M == N) ? 1 : 0;
     int nsplit = (int)std::min<int64_t>(std::max<int64_t>(1, L / 2048), 512);
@@ -407,6 +568,13 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
 {
     const int up = upper ? 1 : 0;
     if (M <= 0 || L <= 0) return RTT_OK;
+    if (M <= 32 && (((uintptr_t)Y) & 15) == 0 && (ldy % 4) == 0 && (((uintptr_t)Out) & 15) == 0 && (ldo % 4) == 0) {
+        const int64_t waves = (L + 127) / 128;
+        hipLaunchKernelGGL(k_combine_skinny, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, C, K, M, Y, ldy, Out,
+                           ldo, L, beta);
+        RTT_HIP(hipGetLastError());
+        return RTT_OK;
+    }
     for (int m0 = 0; m0 < M; m0 += 9 * 32) {
         const int mg = std::min(9, (M - m0 + 31) / 32);
         switch (mg) {
