@@ -232,61 +232,82 @@ __global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, in
     }
 }
 
-// G partials for N <= 32: block (tile, slice) with four waves taking every fourth 32-column
-// chunk of the slice; the waves' sums are added in wave order and written as the block's partial.
+// G partials for N <= 32: block (tile group, slice) with four waves taking every fourth 32-column
+// chunk of the slice; a wave owns TM consecutive 32-row tiles of A, so each chunk of B is read once
+// for all of them.  The waves' sums are added in wave order and written as the block's partial.
+template <int TM>
 __global__ __launch_bounds__(256) void k_gram_skinny(const float* __restrict__ A, int64_t lda,
                                                      const float* __restrict__ B, int64_t ldb, int M, int N,
                                                      int64_t L, int64_t slice, float* __restrict__ part)
 {
     __shared__ float red[3][64][17];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tile = blockIdx.x, s = blockIdx.y;
+    const int s = blockIdx.y;
     const int64_t l0 = (int64_t)s * slice, l1 = min(L, l0 + slice);
     const int r = lane & 31, h = lane >> 5;
-    const int ia = tile * 32 + r;
-    const bool va = ia < M, vb = r < N;
-    const float* __restrict__ pa = A + (int64_t)(va ? ia : 0) * lda;   // rows past the end read row 0,
-    const float* __restrict__ pb = B + (int64_t)(vb ? r : 0) * ldb;    // and their values are zeroed
-    f16v acc = {};
+    const bool vb = r < N;
+    const float* __restrict__ pb = B + (int64_t)(vb ? r : 0) * ldb;    // rows past the end read row 0,
+    bool va[TM];                                                       // and their values are zeroed
+    const float* __restrict__ pa[TM];
+#pragma unroll
+    for (int u = 0; u < TM; ++u) {
+        const int ia = (blockIdx.x * TM + u) * 32 + r;
+        va[u] = ia < M;
+        pa[u] = A + (int64_t)(va[u] ? ia : 0) * lda;
+    }
+    f16v acc[TM];
+#pragma unroll
+    for (int u = 0; u < TM; ++u) acc[u] = (f16v){};
     for (int64_t lc = l0 + (int64_t)wave * 32; lc < l1; lc += 128) {
         const int64_t l = lc + 16 * h;
-        float av[16], bv[16];
+        float av[TM][16], bv[16];
         if (l + 16 <= l1) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const f4v xa = *(const f4v*)(pa + l + 4 * q);
                 const f4v xb = *(const f4v*)(pb + l + 4 * q);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    av[4 * q + t] = va ? xa[t] : 0.f;
-                    bv[4 * q + t] = vb ? xb[t] : 0.f;
+                for (int t = 0; t < 4; ++t) bv[4 * q + t] = vb ? xb[t] : 0.f;
+#pragma unroll
+                for (int u = 0; u < TM; ++u) {
+                    const f4v xa = *(const f4v*)(pa[u] + l + 4 * q);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) av[u][4 * q + t] = va[u] ? xa[t] : 0.f;
                 }
             }
         } else {
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 const bool in = l + t < l1;
-                av[t] = (va && in) ? pa[l + t] : 0.f;
                 bv[t] = (vb && in) ? pb[l + t] : 0.f;
+#pragma unroll
+                for (int u = 0; u < TM; ++u) av[u][t] = (va[u] && in) ? pa[u][l + t] : 0.f;
             }
         }
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t], bv[t], acc, 0, 0, 0);
+        for (int t = 0; t < 16; ++t)
+#pragma unroll
+            for (int u = 0; u < TM; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u][t], bv[t], acc[u], 0, 0, 0);
     }
-    if (wave > 0)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) red[wave - 1][lane][q] = acc[q];
-    __syncthreads();
-    if (wave != 0) return;
-#pragma unroll
-    for (int w = 0; w < 3; ++w)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += red[w][lane][q];
     float* __restrict__ out = part + (int64_t)s * M * N;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = tile * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
-        if (i < M && r < N) out[(int64_t)i * N + r] = acc[q];
+    for (int u = 0; u < TM; ++u) {
+        if (wave > 0)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) red[wave - 1][lane][q] = acc[u][q];
+        __syncthreads();
+        if (wave == 0) {
+            f16v sum = acc[u];
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) sum[q] += red[w][lane][q];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = (blockIdx.x * TM + u) * 32 + 8 * (q >> 2) + 4 * h + (q & 3);
+                if (i < M && r < N) out[(int64_t)i * N + r] = sum[q];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -510,15 +531,20 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
     const bool aligned = (((uintptr_t)A) & 15) == 0 && (((uintptr_t)B) & 15) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
     if (N <= 32 && aligned) {
         // skinny form: slices of whole 128-column steps, about 4096 blocks in all
-        const int tiles = (M + 31) / 32;
+        const int tm = M > 96 ? 4 : 1;                       // 32-row tiles per wave
+        const int tiles = (M + 32 * tm - 1) / (32 * tm);      // tile groups
         int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, 4096 / tiles), L / 1024));
         int64_t slice = (L + nsplit - 1) / nsplit;
         slice = std::max<int64_t>(128, ((slice + 127) / 128) * 128);
         nsplit = (int)std::max<int64_t>(1, (L + slice - 1) / slice);   // L = 0: one empty slice
         float* part = (float*)ws.get("gram_part", sizeof(float) * (size_t)nsplit * M * N);
         if (!part) return fail(RTT_ENOMEM, "gram workspace");
-        hipLaunchKernelGGL(k_gram_skinny, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s, A, lda, B, ldb, M, N,
-                           L, slice, part);
+        if (tm == 4)
+            hipLaunchKernelGGL(k_gram_skinny<4>, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s, A, lda, B, ldb,
+                               M, N, L, slice, part);
+        else
+            hipLaunchKernelGGL(k_gram_skinny<1>, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s, A, lda, B, ldb,
+                               M, N, L, slice, part);
         const int64_t tot = (int64_t)M * N;
         hipLaunchKernelGGL(k_gram_reduce_wide, dim3((unsigned)((tot + 63) / 64)), dim3(1024), 0, s, part, nsplit, tot,
                            G_dev);
