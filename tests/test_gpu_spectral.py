@@ -189,6 +189,26 @@ def test_tsvd_matches_oracle_and_pinv(gpu_lib):
     assert rel(x, xe) <= 1e-3
 
 
+def test_tsvd_many_components_few_rhs_ragged_columns(gpu_lib):
+    """t = 110 components and 5 right-hand sides on a geometry whose column count is not a multiple
+    of the kernels' 128-column steps (but of 4, so rows are 16-byte aligned): the projections run
+    through the skinny Gram with four row tiles per wave and a ragged tail, the synthesis through
+    the skinny combine.  Against the oracle
+    on the same factors."""
+    rtt = gpu_lib
+    geo = tiny_geometry(seed=59, rays=(300, 90, 70), n_r=8, n_phi=10, n_frames=14)
+    say("case tsvd t=110 nrhs=5", geo.grid.n_cols, geo.n_rows)
+    assert geo.grid.n_cols % 128 != 0 and geo.grid.n_cols % 4 == 0   # 16-byte rows, ragged tail
+    G = rtt.Geometry(geo)
+    sv = rtt.rsvd(G, k=120, p=16, q=2, seed=13)
+    y = np.random.default_rng(6).standard_normal((5, geo.n_rows)).astype(np.float32)
+    t = 110
+    x = rtt.tsvd_solve(G, sv, to_dev(y), t=t).cpu().numpy()
+    Vg = sv.V().double().cpu().numpy()
+    xo = oracle.tsvd_solve(geo, Vg, sv.sigma, y.astype(np.float64), t)
+    assert rel(x, xo) <= 1e-5
+
+
 def test_ridge_matches_dense_solve_tiny(gpu_lib):
     rtt = gpu_lib
     geo = tiny_geometry(seed=55, rays=(40, 12, 10), n_r=4, n_phi=6, n_frames=10)
