@@ -2,6 +2,7 @@
 // small FP64 factorisations on the host in smallla.cpp).
 #pragma once
 
+#include <functional>
 #include <map>
 #include <string>
 #include <utility>
@@ -56,6 +57,9 @@ void upper_inverse(const std::vector<double>& R, int n, const std::vector<char>&
 // One-sided Jacobi SVD of an n x n row-major matrix M = U diag(s) W^T, s descending.
 void jacobi_svd(const std::vector<double>& M, int n, std::vector<double>& U, std::vector<double>& s,
                 std::vector<double>& W);
+// f(0) .. f(n - 1), each once, on the host thread pool (at most 16 threads); returns when all have
+// finished.  Calls made from inside f run serially in their thread.
+void host_for(int n, const std::function<void(int)>& f);
 // C = A B for n x n row-major matrices.
 void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C);
 // C = A B for upper triangular A and B (n x n row-major); the strictly lower part of C is zero.

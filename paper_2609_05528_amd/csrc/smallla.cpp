@@ -19,7 +19,7 @@ namespace rtt {
 // process).  run(parts, f) calls f(0) .. f(parts - 1), each once, on the caller and the workers,
 // and returns when all have finished.  A job lives on the caller's stack until every worker that
 // picked it up has let it go.  Concurrent callers do not wait for each other: a caller that finds
-// the pool busy does its parts alone.
+// the pool busy does its parts alone, and so does a call made from inside a job of the pool.
 class HostPool {
   public:
     static HostPool& get()
@@ -30,8 +30,13 @@ class HostPool {
     template <class F>
     void run(int parts, F&& f)
     {
+        // a call from inside a job of the pool (nested) runs its parts in the calling thread
+        if (parts <= 1 || nworkers_ == 0 || in_job()) {
+            for (int i = 0; i < parts; ++i) f(i);
+            return;
+        }
         std::unique_lock<std::mutex> busy(run_m_, std::try_to_lock);
-        if (parts <= 1 || nworkers_ == 0 || !busy.owns_lock()) {
+        if (!busy.owns_lock()) {
             for (int i = 0; i < parts; ++i) f(i);
             return;
         }
@@ -66,14 +71,23 @@ class HostPool {
         nworkers_ = hw - 1;
         for (int t = 0; t < nworkers_; ++t) std::thread([this] { loop(); }).detach();
     }
+    static bool& in_job()
+    {
+        static thread_local bool v = false;
+        return v;
+    }
     static void work(Job& j)
     {
+        bool& ij = in_job();
+        const bool prev = ij;
+        ij = true;
         for (;;) {
             const int i = j.next.fetch_add(1, std::memory_order_relaxed);
             if (i >= j.parts) break;
             j.f(i);
             j.done.fetch_add(1, std::memory_order_release);
         }
+        ij = prev;
     }
     void loop()
     {
@@ -111,6 +125,11 @@ static void parallel_for(int n, int grain, F f)
         return;
     }
     pool.run(parts, [&](int t) { f((int)((int64_t)n * t / parts), (int)((int64_t)n * (t + 1) / parts)); });
+}
+
+void host_for(int n, const std::function<void(int)>& f)
+{
+    HostPool::get().run(n, [&f](int i) { f(i); });
 }
 
 int cholesky_upper(const std::vector<double>& G, int n, double shift, double dead_tol, std::vector<double>& R,

@@ -100,53 +100,64 @@ int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>
          std::vector<std::vector<double>>& R_total, bool final_basis = true)
 {
     const int base = final_basis ? 2 : 1;
-    double* Gd = (double*)c.ws.get("orth_gram", sizeof(double) * lp * lp);
-    if (!Gd) return fail(RTT_ENOMEM, "orth gram");
     const size_t ns = segs.size();
-    R_total.assign(ns, std::vector<double>((size_t)lp * lp, 0.0));
+    const size_t lp2 = (size_t)lp * lp;
+    // every pass: the Gram matrices of all active segments, one download, their factors on host
+    // threads (one segment per task), one upload, the combines
+    double* Gd = (double*)c.ws.get("orth_gram", sizeof(double) * lp2 * ns);
+    if (!Gd) return fail(RTT_ENOMEM, "orth gram");
+    R_total.assign(ns, std::vector<double>(lp2, 0.0));
     std::vector<int> passes(ns, base);
     for (size_t q = 0; q < ns; ++q)
         for (int i = 0; i < lp; ++i) R_total[q][(size_t)i * lp + i] = 1.0;
-    std::vector<double> G, R, Ri, Rt;
-    std::vector<char> dead;
+    std::vector<double> G, Ri_all(lp2 * ns, 0.0);
     for (int pass = 0; pass < 3; ++pass) {
         if (std::all_of(passes.begin(), passes.end(), [pass](int p) { return p <= pass; })) break;
+        std::vector<size_t> act;
+        int rc;
         for (size_t q = 0; q < ns; ++q) {
             const Seg sg = segs[q];
-            float* Ys = *Y + sg.off;
-            float* Ts = *T + sg.off;
             if (pass >= passes[q]) {
                 // this segment is finished: carry it over to the buffer that becomes *Y
                 if (sg.len > 0)
-                    RTT_HIP(hipMemcpy2DAsync(Ts, n * sizeof(float), Ys, n * sizeof(float), sg.len * sizeof(float),
-                                             lp, hipMemcpyDeviceToDevice, c.s));
+                    RTT_HIP(hipMemcpy2DAsync(*T + sg.off, n * sizeof(float), *Y + sg.off, n * sizeof(float),
+                                             sg.len * sizeof(float), lp, hipMemcpyDeviceToDevice, c.s));
                 continue;
             }
-            int rc = gram(c.ws, Ys, n, Ys, n, lp, lp, sg.len, Gd, c.s);
-            if (rc) return rc;
-            if ((rc = download(c, Gd, G, (size_t)lp * lp))) return rc;
+            act.push_back(q);
+            if ((rc = gram(c.ws, *Y + sg.off, n, *Y + sg.off, n, lp, lp, sg.len, Gd + q * lp2, c.s))) return rc;
+        }
+        if ((rc = download(c, Gd, G, lp2 * ns))) return rc;
+        const double dead_tol = pass == 0 ? 1e-12 : 1e-8;
+        host_for((int)act.size(), [&](int a) {
+            const size_t q = act[a];
+            std::vector<double> Gq(G.begin() + q * lp2, G.begin() + (q + 1) * lp2), R, Ri, Rt;
+            std::vector<char> dead;
             double maxdiag = 0.0;
-            for (int i = 0; i < lp; ++i) maxdiag = std::max(maxdiag, G[(size_t)i * lp + i]);
-            const double dead_tol = pass == 0 ? 1e-12 : 1e-8;
-            cholesky_upper(G, lp, 0.0, dead_tol, R, dead);
+            for (int i = 0; i < lp; ++i) maxdiag = std::max(maxdiag, Gq[(size_t)i * lp + i]);
+            cholesky_upper(Gq, lp, 0.0, dead_tol, R, dead);
             if (pass == 0) {
-                // a pivot below the FP32 Gram accuracy: shift the first pass and add a third one
+                // a pivot below the FP32 Gram accuracy: shift the first pass and add one more
                 double minpiv = INFINITY;
                 for (int i = 0; i < lp; ++i)
                     if (!dead[i]) minpiv = std::min(minpiv, R[(size_t)i * lp + i] * R[(size_t)i * lp + i]);
                 if (minpiv < 1e-5 * maxdiag) {
-                    cholesky_upper(G, lp, 1e-6 * maxdiag, dead_tol, R, dead);
+                    cholesky_upper(Gq, lp, 1e-6 * maxdiag, dead_tol, R, dead);
                     passes[q] = base + 1;
                 }
             }
             upper_inverse(R, lp, dead, Ri);
-            float* Cd = nullptr;
-            if ((rc = upload_f32(c, "orth_rinv", Ri, (size_t)lp * lp, &Cd))) return rc;
-            if ((rc = combine(Cd, lp, lp, Ys, n, Ts, n, sg.len, 0.f, c.s, true))) return rc;
+            std::copy(Ri.begin(), Ri.end(), Ri_all.begin() + q * lp2);
             if (final_basis) {
                 matmul_upper(R, R_total[q], lp, Rt);
                 R_total[q].swap(Rt);
             }
+        });
+        float* Cd = nullptr;
+        if ((rc = upload_f32(c, "orth_rinv", Ri_all, lp2 * ns, &Cd))) return rc;
+        for (size_t q : act) {
+            const Seg sg = segs[q];
+            if ((rc = combine(Cd + q * lp2, lp, lp, *Y + sg.off, n, *T + sg.off, n, sg.len, 0.f, c.s, true))) return rc;
         }
         std::swap(*Y, *T);
     }
@@ -204,12 +215,16 @@ int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
     res->resid.assign((size_t)sets * k, 0.0);
     RTT_HIP(hipMalloc((void**)&res->V, sizeof(float) * (size_t)k * n));
     if (o.keep_u) RTT_HIP(hipMalloc((void**)&res->U, sizeof(float) * (size_t)k * m));
-    for (int q = 0; q < sets; ++q) {
-        // SVD of R^T (l x l leading block) of this set
-        std::vector<double> Mt((size_t)l * l), Ur, sv, W;
+    // SVD of R^T (l x l leading block) of every set, the sets on host threads
+    std::vector<std::vector<double>> Urs(sets), svs(sets), Ws(sets);
+    host_for(sets, [&](int q) {
+        std::vector<double> Mt((size_t)l * l);
         for (int i = 0; i < l; ++i)
             for (int j = 0; j < l; ++j) Mt[(size_t)i * l + j] = R[q][(size_t)j * lp + i];
-        jacobi_svd(Mt, l, Ur, sv, W);
+        jacobi_svd(Mt, l, Urs[q], svs[q], Ws[q]);
+    });
+    for (int q = 0; q < sets; ++q) {
+        const std::vector<double>&Ur = Urs[q], &sv = svs[q], &W = Ws[q];
         std::copy(sv.begin(), sv.begin() + k, res->sigma.begin() + (size_t)q * k);
         // V = Qb W[:, :k] ; U = Q Ur[:, :k]
         std::vector<double> Wk((size_t)l * k), Uk((size_t)l * k);
