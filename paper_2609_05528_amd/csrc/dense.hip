@@ -138,7 +138,7 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M,
 }
 
 template <int MG, bool VY>
-__global__ __launch_bounds__(256) void k_combine(const float* __restrict__ C, int K, int M, int m0,
+__global__ __launch_bounds__(256, 2) void k_combine(const float* __restrict__ C, int K, int M, int m0,
                                                  const float* __restrict__ Y, int64_t ldy,
                                                  float* __restrict__ Out, int64_t ldo, int64_t L, float beta,
                                                  int upper)
@@ -601,8 +601,9 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
-    for (int m0 = 0; m0 < M; m0 += 9 * 32) {
-        const int mg = std::min(9, (M - m0 + 31) / 32);
+    // at most 8 row blocks per launch: the accumulators of 8 fit two waves per SIMD
+    for (int m0 = 0; m0 < M; m0 += 8 * 32) {
+        const int mg = std::min(8, (M - m0 + 31) / 32);
         switch (mg) {
         case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
@@ -611,8 +612,7 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         case 5: combine_launch<5>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         case 6: combine_launch<6>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         case 7: combine_launch<7>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 8: combine_launch<8>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        default: combine_launch<9>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        default: combine_launch<8>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         }
     }
     RTT_HIP(hipGetLastError());
