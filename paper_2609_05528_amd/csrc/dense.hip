@@ -133,6 +133,7 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M,
     int si = i, sj = j;
     if (sym && (j / GB) < (i / GB)) { si = j; sj = i; }   // read the mirrored upper block
     double s = 0.0;
+#pragma unroll 8
     for (int t = 0; t < nsplit; ++t) s += (double)part[(int64_t)t * M * N + (int64_t)si * N + sj];
     G[e] = s;
 }
