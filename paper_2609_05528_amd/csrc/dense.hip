@@ -603,8 +603,8 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         return RTT_OK;
     }
     // at most 8 row blocks per launch: the accumulators of 8 fit two waves per SIMD
-    for (int m0 = 0; m0 < M; m0 += 8 * 32) {
-        const int mg = std::min(8, (M - m0 + 31) / 32);
+    for (int m0 = 0; m0 < M; m0 += 4 * 32) {
+        const int mg = std::min(4, (M - m0 + 31) / 32);
         switch (mg) {
         case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
