@@ -227,6 +227,20 @@ int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, const float** 
             const float** U_dev, double* resid_host);
 
 /*
+ * svd_converged -- how many singular values of the factors count as converged:
+ * count[q] = #{ i : resid_i <= rel_tol * sigma_1 } for each factorisation q
+ * (one, or G for RTT_EACH_GEOMETRY factors; count has room for as many), with
+ * resid_i the residual svd_get reports (block Lanczos: the Ritz residual
+ * estimate ||A^T u_i - theta_i v_i|| of the recurrence; rSVD with keep_u:
+ * ||A v_i - sigma_i u_i||).  The operational rank of Sec. 4.4 eq. (31) counts
+ * singular values above a threshold, so only converged values should enter it
+ * (rel_tol = 1e-6 is the usual choice).  Host arithmetic on the stored values.
+ * Errors: RTT_EINVAL (bad handle, NULL count, rel_tol < 0); RTT_ESTATE when
+ * the factors carry no residuals (rSVD without keep_u).
+ */
+int svd_converged(const rtt_svd* s, double rel_tol, int32_t* count);
+
+/*
  * tsvd_solve -- TSVD estimate of Sec. 9: x = V_t diag(sigma_t^-2) V_t^T A^T y
  * (= sum_{i<t} v_i (u_i . y)/sigma_i for an exact factorisation).
  * y: device [nrhs][n_rows]; x: device [nrhs][n_cols], with the lengths of the

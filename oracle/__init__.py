@@ -112,10 +112,38 @@ def _mask(geom, order_mask):
     return (1 << geom.grid.n_orders) - 1 if order_mask is None else int(order_mask)
 
 
-def forward(geom, x, order_mask=None, out=None):
+def host_threads() -> int:
+    """Host threads the vector loops use by default: every core this process may run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _each_vector(fn, n, threads):
+    """Run fn(b) for b in range(n), on up to ``threads`` host threads.
+
+    The vectors are independent and each one is evaluated by the same serial C loop whatever
+    the thread count (ctypes releases the GIL during the call), so the results do not depend
+    on ``threads``.
+    """
+    threads = host_threads() if threads is None else max(1, int(threads))
+    if threads == 1 or n <= 1:
+        for b in range(n):
+            fn(b)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(threads, n)) as ex:
+        for _ in ex.map(fn, range(n)):
+            pass
+
+
+def forward(geom, x, order_mask=None, out=None, threads=None):
     """y = A x (FP64).  x: [S*K] or [B][S*K]; y rows (n, p, f), frames fastest.
 
-    Rows of orders outside ``order_mask`` are returned as zeros.
+    Rows of orders outside ``order_mask`` are returned as zeros.  The B vectors are spread over
+    ``threads`` host threads (default: host_threads()); each is one serial C evaluation.
     """
     lib = _load()
     pk = _Packed(geom)
@@ -127,20 +155,22 @@ def forward(geom, x, order_mask=None, out=None):
         raise ValueError("x has wrong length")
     y = np.zeros((xb.shape[0], pk.n_rays * g.n_frames))
     cg = _cgrid(g)
-    for b in range(xb.shape[0]):
+    mask = _mask(geom, order_mask)
+    counts = pk.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def one(b):
         xv = np.ascontiguousarray(xb[b])
-        yv = np.zeros(pk.n_rays * g.n_frames)
-        rc = lib.ora_forward(ctypes.byref(cg), pk.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                             _ptr(pk.r), _ptr(pk.phi), _ptr(pk.delay), _ptr(pk.weight),
-                             _ptr(xv), _ptr(yv), _mask(geom, order_mask))
+        rc = lib.ora_forward(ctypes.byref(cg), counts, _ptr(pk.r), _ptr(pk.phi), _ptr(pk.delay),
+                             _ptr(pk.weight), _ptr(xv), _ptr(y[b]), mask)
         if rc:
             raise ValueError("oracle forward rejected its inputs")
-        y[b] = yv
+
+    _each_vector(one, xb.shape[0], threads)
     return y[0] if single else y
 
 
-def adjoint(geom, y, order_mask=None):
-    """x = A^T y (FP64), same layouts as ``forward``."""
+def adjoint(geom, y, order_mask=None, threads=None):
+    """x = A^T y (FP64), same layouts as ``forward``; vectors spread over threads as there."""
     lib = _load()
     pk = _Packed(geom)
     g = pk.grid
@@ -151,15 +181,17 @@ def adjoint(geom, y, order_mask=None):
         raise ValueError("y has wrong length")
     x = np.zeros((yb.shape[0], g.n_cols))
     cg = _cgrid(g)
-    for b in range(yb.shape[0]):
+    mask = _mask(geom, order_mask)
+    counts = pk.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+    def one(b):
         yv = np.ascontiguousarray(yb[b])
-        xv = np.zeros(g.n_cols)
-        rc = lib.ora_adjoint(ctypes.byref(cg), pk.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                             _ptr(pk.r), _ptr(pk.phi), _ptr(pk.delay), _ptr(pk.weight),
-                             _ptr(yv), _ptr(xv), _mask(geom, order_mask))
+        rc = lib.ora_adjoint(ctypes.byref(cg), counts, _ptr(pk.r), _ptr(pk.phi), _ptr(pk.delay),
+                             _ptr(pk.weight), _ptr(yv), _ptr(x[b]), mask)
         if rc:
             raise ValueError("oracle adjoint rejected its inputs")
-        x[b] = xv
+
+    _each_vector(one, yb.shape[0], threads)
     return x[0] if single else x
 
 

@@ -24,7 +24,7 @@ RTT_EACH_GEOMETRY = -2
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
-            "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
+            "svd_converged", "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
             "mix_apply", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
             "age_reach", "age_window_error", "tsvd_project", "noise_add", "synthesis_create", "synthesis_free",
             "synthesis_info", "synth_expand", "synth_project", "synthesis_audit", "age_fisher", "last_error")
@@ -124,6 +124,7 @@ def require_native():
         "rsvd": [vp, ctypes.POINTER(rtt_svd_opts), vp, ctypes.POINTER(vp), vp],
         "svd_free": [vp],
         "svd_get": [vp, ctypes.POINTER(i32), _dp, ctypes.POINTER(vp), ctypes.POINTER(vp), _dp],
+        "svd_converged": [vp, ctypes.c_double, ctypes.POINTER(i32)],
         "tsvd_solve": [vp, vp, vp, i32, i32, ctypes.c_double, vp, vp],
         "ridge_solve": [vp, vp, i32, ctypes.c_float, ctypes.POINTER(rtt_cg_opts), vp,
                         ctypes.POINTER(rtt_solve_info), vp],
@@ -311,11 +312,17 @@ def _nvec(t, n):
 
 
 def op_apply(geom: Geometry, x, y=None, order_mask: int = 0, stream=None):
-    """y = A x.  x: [..., n_cols] float32 CUDA; returns y [..., n_rows]."""
+    """y = A x.  x: [..., n_cols] float32 CUDA; returns y [..., n_rows].
+
+    The library leaves the rows of orders outside ``order_mask`` unwritten; a y allocated here
+    for a masked call therefore starts at zero, so those rows read as the masked operator's
+    (zero) rows.
+    """
     import torch
     nvec = _nvec(x, geom.n_cols)
     if y is None:
-        y = torch.empty(x.shape[:-1] + (geom.n_rows,), dtype=torch.float32, device=x.device)
+        alloc = torch.zeros if order_mask else torch.empty
+        y = alloc(x.shape[:-1] + (geom.n_rows,), dtype=torch.float32, device=x.device)
     _check(require_native().op_apply(geom.handle, _dev_ptr(x, nvec * geom.n_cols, "x"),
                                      _dev_ptr(y, nvec * geom.n_rows, "y"), nvec, order_mask, _stream(stream)))
     return y

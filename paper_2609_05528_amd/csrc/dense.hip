@@ -602,18 +602,17 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
-    // at most 8 row blocks per launch: the accumulators of 8 fit two waves per SIMD
-    for (int m0 = 0; m0 < M; m0 += 4 * 32) {
-        const int mg = std::min(4, (M - m0 + 31) / 32);
+    // at most COMBINE_ROW_BLOCKS row blocks of 32 per launch: their accumulators leave room for
+    // three waves per SIMD, which cover a chunk's loads
+    constexpr int COMBINE_ROW_BLOCKS = 4;
+    for (int m0 = 0; m0 < M; m0 += COMBINE_ROW_BLOCKS * 32) {
+        const int mg = std::min(COMBINE_ROW_BLOCKS, (M - m0 + 31) / 32);
+        static_assert(COMBINE_ROW_BLOCKS == 4, "one case per row-block count below");
         switch (mg) {
         case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 4: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 5: combine_launch<5>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 6: combine_launch<6>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 7: combine_launch<7>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        default: combine_launch<8>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        default: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
         }
     }
     RTT_HIP(hipGetLastError());

@@ -34,6 +34,7 @@ struct rtt_svd {
     int sets = 1;         // independent factorisations held (G for RTT_EACH_GEOMETRY)
     int64_t n_rows = 0, n_cols = 0;
     std::vector<double> sigma, resid;   // [sets][k]
+    bool has_resid = false;             // resid holds residuals (Lanczos; rSVD with keep_u)
     float* V = nullptr;
     float* U = nullptr;
     double* d_sigma = nullptr;          // device copy of sigma
@@ -271,6 +272,7 @@ int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
                 res->resid[(size_t)q * k + i] =
                     std::sqrt(std::max(0.0, h[e] - 2 * si * h[nd + e] + si * si * h[2 * nd + e]));
             }
+        res->has_resid = true;
     }
     RTT_HIP(hipStreamSynchronize(c.s));
     return RTT_OK;
@@ -364,6 +366,7 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
         }
         res->resid[i] = std::sqrt(acc);
     }
+    res->has_resid = true;
     std::vector<double> Wk((size_t)mdim * k);
     for (int i = 0; i < mdim; ++i)
         for (int jj = 0; jj < k; ++jj) Wk[(size_t)i * k + jj] = Wt[(size_t)i * mdim + jj];
@@ -448,6 +451,23 @@ extern "C" int svd_get(const rtt_svd* s, int32_t* k_out, double* sigma_host, con
     if (resid_host) std::memcpy(resid_host, s->resid.data(), sizeof(double) * s->resid.size());
     if (V_dev) *V_dev = s->V;
     if (U_dev) *U_dev = s->U;
+    return RTT_OK;
+}
+
+extern "C" int svd_converged(const rtt_svd* s, double rel_tol, int32_t* count)
+{
+    if (!s || s->magic != 0x53564431u) return fail(RTT_EINVAL, "invalid svd handle");
+    if (!count) return fail(RTT_EINVAL, "svd_converged: NULL count");
+    if (!(rel_tol >= 0.0)) return fail(RTT_EINVAL, "svd_converged: rel_tol must be >= 0");
+    if (!s->has_resid) return fail(RTT_ESTATE, "svd_converged: these factors carry no residuals (rSVD without keep_u)");
+    for (int q = 0; q < s->sets; ++q) {
+        const double* sg = s->sigma.data() + (size_t)q * s->k;
+        const double* rs = s->resid.data() + (size_t)q * s->k;
+        const double thr = rel_tol * (s->k > 0 ? sg[0] : 0.0);
+        int32_t n = 0;
+        for (int i = 0; i < s->k; ++i) n += rs[i] <= thr ? 1 : 0;
+        count[q] = n;
+    }
     return RTT_OK;
 }
 

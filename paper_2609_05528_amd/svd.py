@@ -28,6 +28,13 @@ class SVD:
         self.sigma = sig if sets == 1 else sig.reshape(sets, self.k)
         self.residual = res if sets == 1 else res.reshape(sets, self.k)
 
+    def converged(self, rel_tol=1e-6):
+        """Number of singular values whose residual is <= rel_tol * sigma_1 (an int, or one per
+        geometry for factors of every geometry); see svd_converged in include/rtt.h."""
+        cnt = (ctypes.c_int32 * self.sets)()
+        _check(require_native().svd_converged(self._h, float(rel_tol), cnt))
+        return cnt[0] if self.sets == 1 else np.array(list(cnt))
+
     def _ptr(self, which):
         lib = require_native()
         vp = ctypes.c_void_p()

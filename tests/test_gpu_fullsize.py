@@ -1,0 +1,396 @@
+"""GPU parity at the full workload sizes, on the kernel variants the autotuner picks there.
+
+The tiny-grid tests exercise every variant; these run the instantiations that the block and
+batch workloads actually launch (row-pair adjoint with two vectors per wave and two hat slots
+per lane on the 128^2 block of 264 vectors, four hat slots on the 512^2 block of 32 vectors,
+the tuned 12-geometry x 60-history batch, the k = 256 randomized SVD) and compare them with
+the FP64 oracle of App. A.2 eq. (47), Sec. 3.6 eq. (19):
+
+* A and A^T: relative L2 error <= 1e-5 per output vector and per order block (sampled vectors,
+  and at the 512^2 size sampled rays and cells, which the oracle can evaluate one by one);
+* singular values: 1e-4 relative for sigma_i >= 1e-3 sigma_1 against the oracle's rSVD on the
+  same test block; right vectors: sin of the angle to the oracle's vector <= 1e-5 sigma_1 / gap
+  wherever the gap to both neighbours exceeds 1e-3 sigma_1 (FP32 rounding of the applies,
+  ~1e-6 sigma_1, perturbs an isolated singular vector by about that over its gap).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tinygeo import tiny_geometry
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def order_blocks(geo):
+    """Row slices of the order blocks of one geometry's data vector."""
+    out, off = [], 0
+    for m in geo.maps:
+        n = m.n_rays * geo.grid.n_frames
+        out.append(slice(off, off + n))
+        off += n
+    return out
+
+
+def assert_rows_match(geo, got, ref, what):
+    for n, sl in enumerate(order_blocks(geo)):
+        if sl.stop > sl.start:
+            e = rel(got[sl], ref[sl])
+            assert e <= TOL, (what, "order", n, e)
+
+
+def sub_geometry(geo, keep):
+    maps = [synth.RayMap(r=m.r[k], phi=m.phi[k], delay=m.delay[k], weight=m.weight[k])
+            for m, k in zip(geo.maps, keep)]
+    return synth.Geometry(grid=geo.grid, maps=maps)
+
+
+def tuned(rtt, G, nvec):
+    choice = G.tune(nvec=nvec, reps=3)
+    names = [(rtt.variant_names(False)[a], rtt.variant_names(True)[b]) for a, b in choice]
+    say("tuned for", nvec, "vectors:", names, "launch modes", G.batch_mode)
+    return names
+
+
+def pin(rtt, G, fwd, adj):
+    G.set_variant(apply=rtt.variant_names(False).index(fwd), adjoint=rtt.variant_names(True).index(adj))
+
+
+# ------------------------------------------------------------------------------ 128^2 block
+@pytest.mark.parametrize("pinned", [None, ("abs4", "visitp2v"), ("abs8", "visitp4v")])
+def test_block_of_264_on_the_128_geometry_matches_oracle(gpu_lib, pinned):
+    """The rSVD block of the 128^2 Kerr workload (l = 264 vectors): the tuned variants, and the
+    absolute-hat forward with the row-pair adjoint pinned (two and four vectors per wave).  With
+    K = 96 hats and 132 (or 66) vector groups the row-pair dispatch runs its two-slot form
+    (V = 2); vectors 0, 131 and 263 against the oracle per order block."""
+    import torch
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg2")
+    G = rtt.Geometry(geo)
+    nvec = 264
+    names = tuned(rtt, G, nvec)
+    if pinned is not None:
+        pin(rtt, G, *pinned)
+        names = [pinned]
+    say("case cfg2 block 264", names)
+    X = to_dev(synth.gaussian_block(geo.grid.n_cols, nvec, seed=2001))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2002)
+    Yin = torch.empty((nvec, G.n_rows), device="cuda")
+    Yin.normal_(generator=gen)
+    Y = rtt.op_apply(G, X)
+    XT = rtt.op_apply_adjoint(G, Yin)
+    pick = [0, 131, 263]
+    yr = oracle.forward(geo, X[pick].double().cpu().numpy())
+    xr = oracle.adjoint(geo, Yin[pick].double().cpu().numpy())
+    for i, b in enumerate(pick):
+        assert_rows_match(geo, Y[b].cpu().numpy(), yr[i], ("A", names, b))
+        assert rel(XT[b].cpu().numpy(), xr[i]) <= TOL, ("A^T", names, b)
+    # each order's adjoint block alone, on the row-pair path
+    for n in range(geo.grid.n_orders):
+        XTn = rtt.op_apply_adjoint(G, Yin, order_mask=1 << n)
+        xrn = oracle.adjoint(geo, Yin[pick[1]].double().cpu().numpy(), order_mask=1 << n)
+        assert rel(XTn[pick[1]].cpu().numpy(), xrn) <= TOL, ("A^T order", n)
+    # bitwise repeatable, and a vector alone gets the bits it gets inside the block
+    assert torch.equal(XT, rtt.op_apply_adjoint(G, Yin))
+    assert torch.equal(Y, rtt.op_apply(G, X))
+
+
+# ------------------------------------------------------------------------------ 512^2 block
+def _sampled_rows(geo, rng, per_order=48):
+    keep, rows, off = [], [], 0
+    for m in geo.maps:
+        k = np.zeros(m.n_rays, dtype=bool)
+        idx = np.sort(rng.choice(m.n_rays, size=min(per_order, m.n_rays), replace=False))
+        k[idx] = True
+        keep.append(k)
+        rows.extend(off + idx)
+        off += m.n_rays
+    return keep, np.asarray(rows)
+
+
+def _cell_support(geo, c):
+    """Rays that can reach cell c (within two cells in r and phi): their keep masks and ray ids."""
+    g = geo.grid
+    dr = (g.r_out - g.r_in) / g.n_r
+    dphi = 2 * math.pi / g.n_phi
+    ci, cj = divmod(int(c), g.n_phi)
+    rc = g.r_in + (ci + 0.5) * dr
+    pc = (cj + 0.5) * dphi
+    keep, sel, off = [], [], 0
+    for m in geo.maps:
+        dp = np.abs(np.angle(np.exp(1j * (m.phi - pc))))
+        k = (np.abs(m.r - rc) < 2 * dr) & (dp < 2 * dphi)
+        keep.append(k)
+        sel.append(off + np.nonzero(k)[0])
+        off += m.n_rays
+    return keep, np.concatenate(sel)
+
+
+@pytest.mark.parametrize("pinned", [None, ("strip8", "visitp2v")])
+def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, pinned):
+    """The block Lanczos block of the 512^2 x 512-frame workload (32 vectors) on the variants
+    tuned for it (K = 256: the row-pair adjoint with four hat slots per lane).  Two vectors,
+    48 rays per order and 6 cells each, against the oracle evaluated on the rays concerned."""
+    import torch
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg5")
+    g = geo.grid
+    F = g.n_frames
+    G = rtt.Geometry(geo)
+    nvec = 32
+    names = tuned(rtt, G, nvec)
+    if pinned is not None:
+        pin(rtt, G, *pinned)
+        names = [pinned]
+    say("case cfg5 block 32", names)
+    X = to_dev(synth.gaussian_block(g.n_cols, nvec, seed=5101))
+    Y = rtt.op_apply(G, X)
+    rng = np.random.default_rng(56)
+    for b in (0, nvec - 1):
+        keep, rows = _sampled_rows(geo, rng)
+        yr = oracle.forward(sub_geometry(geo, keep), X[b].double().cpu().numpy()).reshape(-1, F)
+        ya = Y[b].view(-1, F)[torch.from_numpy(rows).cuda()].cpu().numpy()
+        assert rel(ya, yr) <= TOL, ("A", names, b, rel(ya, yr))
+    del Y
+    torch.cuda.empty_cache()
+    Yin = torch.empty((nvec, G.n_rows), device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5102)
+    Yin.normal_(generator=gen)
+    XT = rtt.op_apply_adjoint(G, Yin)
+    for b in (0, nvec - 1):
+        xa = XT[b].cpu().numpy().reshape(g.n_cells, g.n_hat)
+        yrow = Yin[b].view(-1, F)
+        for c in rng.choice(g.n_cells, size=6, replace=False):
+            keep, sel = _cell_support(geo, c)
+            ysub = yrow[torch.from_numpy(sel).cuda()].double().cpu().numpy().ravel()
+            xr = oracle.adjoint(sub_geometry(geo, keep), ysub).reshape(g.n_cells, g.n_hat)[c]
+            assert rel(xa[c], xr) <= TOL, ("A^T", names, b, int(c), rel(xa[c], xr))
+    assert torch.equal(XT, rtt.op_apply_adjoint(G, Yin))
+
+
+# ------------------------------------------------------------------------------ 12 x 60 batch
+def test_full_batch_of_12_geometries_and_60_histories_matches_oracle(gpu_lib):
+    """The batched workload as the benchmark runs it: 12 geometries (96^2-256^2, 64-160 frames)
+    x 60 Gaussian-blob histories, after tuning for 60 vectors.  A and A^T of 4 (geometry,
+    history) pairs, including the smallest and the largest geometry, against the oracle; every
+    launch mode gives the same bits."""
+    import torch
+    rtt = gpu_lib
+    geos = synth.batch_geometries()
+    ng, nh = len(geos), synth.BATCH_HISTORIES
+    G = rtt.Geometry(geos)
+    tuned(rtt, G, nh)
+    modes = G.batch_mode
+    H = synth.blob_histories(geos[0].grid, nh, dtype=np.float32)
+    X = to_dev(np.tile(H, (1, ng)))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4102)
+    Yin = torch.empty((nh, G.n_rows), device="cuda")
+    Yin.normal_(generator=gen)
+    say("case cfg4 batch", G.n_rows, G.n_cols, modes)
+    Y = rtt.op_apply(G, X)
+    XT = rtt.op_apply_adjoint(G, Yin)
+    sizes = [m["n_rows"] for m in G.members]
+    pairs = [(int(np.argmin(sizes)), 0), (int(np.argmax(sizes)), nh - 1), (5, 31), (10, 17)]
+    for gi, hi in pairs:
+        m = G.members[gi]
+        rs = slice(m["row_offset"], m["row_offset"] + m["n_rows"])
+        cs = slice(m["col_offset"], m["col_offset"] + m["n_cols"])
+        yr = oracle.forward(geos[gi], H[hi].astype(np.float64))
+        assert_rows_match(geos[gi], Y[hi, rs].cpu().numpy(), yr, ("A", gi, hi))
+        xr = oracle.adjoint(geos[gi], Yin[hi, rs].double().cpu().numpy())
+        assert rel(XT[hi, cs].cpu().numpy(), xr) <= TOL, ("A^T", gi, hi)
+    for mode in (0, 1, 2):
+        G.set_batch_mode(apply=mode, adjoint=mode)
+        assert torch.equal(rtt.op_apply(G, X), Y), ("A mode", mode)
+        assert torch.equal(rtt.op_apply_adjoint(G, Yin), XT), ("A^T mode", mode)
+    G.set_batch_mode(*modes)
+
+
+# ------------------------------------------------------------------------------ rSVD k = 256
+def _check_factors(sig, V, s_o, V_o, k, what):
+    ok = s_o[:k] >= 1e-3 * s_o[0]
+    err = np.abs(sig[:k][ok] - s_o[:k][ok]) / s_o[:k][ok]
+    say(what, "max sigma rel err", float(err.max()))
+    assert err.max() <= 1e-4, what
+    checked = 0
+    for i in range(k - 1):
+        gap = min(s_o[i] - s_o[i + 1], s_o[i - 1] - s_o[i] if i else np.inf)
+        if gap <= 1e-3 * s_o[0]:
+            continue
+        v = np.asarray(V[i], dtype=np.float64)
+        c = abs(float(v @ V_o[i])) / (np.linalg.norm(v) * np.linalg.norm(V_o[i]))
+        sin = math.sqrt(max(0.0, 1.0 - c * c))
+        assert sin <= max(1e-5 * s_o[0] / gap, 1e-6), (what, i, sin, gap / s_o[0])
+        checked += 1
+    say(what, "isolated right vectors checked:", checked)
+
+
+def test_rsvd_k256_on_the_128_geometry_matches_oracle(gpu_lib):
+    """The configured randomized SVD (k = 256, p = 8, q = 2; the block of 264 vectors in the
+    combine and Gram kernels, Cholesky QR after every application) on the tuned 128^2
+    operator against the FP64 oracle's subspace iteration on the same test block."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg2")
+    G = rtt.Geometry(geo)
+    tuned(rtt, G, 264)
+    k, p, q = 256, 8, 2
+    om = synth.gaussian_block(geo.grid.n_cols, k + p, seed=2001)
+    say("case rsvd cfg2 k=256")
+    sv = rtt.rsvd(G, k=k, p=p, q=q, omega=to_dev(om))
+    V = sv.V().double().cpu().numpy()
+    s_o, V_o, _ = oracle.rsvd(geo, om.astype(np.float64), q=q)
+    _check_factors(sv.sigma, V, s_o, V_o, k, "cfg2 rsvd")
+    assert np.max(np.abs(V @ V.T - np.eye(k))) <= 1e-4
+
+
+def test_rsvd_k256_of_two_batch_geometries_in_one_call(gpu_lib):
+    """RTT_EACH_GEOMETRY at k = 256, p = 8, q = 2 on the smallest and the largest geometry of the
+    12-geometry batch: each geometry's factors against the oracle's rSVD of that geometry alone
+    on its column block of the same test block."""
+    rtt = gpu_lib
+    geos_all = synth.batch_geometries()
+    sizes = [geo.n_rows for geo in geos_all]
+    geos = [geos_all[int(np.argmin(sizes))], geos_all[int(np.argmax(sizes))]]
+    G = rtt.Geometry(geos)
+    tuned(rtt, G, 264)
+    k, p, q = 256, 8, 2
+    om = synth.gaussian_block(G.n_cols, k + p, seed=4001)
+    say("case rsvd each geometry k=256", [geo.n_rows for geo in geos])
+    sv = rtt.rsvd(G, k=k, p=p, q=q, omega=to_dev(om), geometry=rtt.RTT_EACH_GEOMETRY)
+    V = sv.V().double().cpu().numpy()
+    for gi, geo in enumerate(geos):
+        m = G.members[gi]
+        cs = slice(m["col_offset"], m["col_offset"] + m["n_cols"])
+        s_o, V_o, _ = oracle.rsvd(geo, om[:, cs].astype(np.float64), q=q)
+        _check_factors(sv.sigma[gi], V[:, cs], s_o, V_o, k, "batch geometry %d" % gi)
+
+
+# ------------------------------------------------------------------------------ exact ties
+def tie_geometry(seed, dt_obs, rays=(300, 60, 40), n_r=6, n_phi=9, n_frames=24):
+    """Rays whose retarded times fall exactly on hat nodes (theta = 0; at dt_obs = dt_src / 2 every
+    other frame), including the nodes one step outside the hat window at both ends, and some
+    rays exactly on cell centres (bilinear fractions 0) and on the radial clamp edges."""
+    base = tiny_geometry(seed=seed, rays=rays, n_r=n_r, n_phi=n_phi, n_frames=n_frames, dt_obs=dt_obs)
+    g = base.grid
+    rng = np.random.default_rng(seed + 1000)
+    maps = []
+    dr = (g.r_out - g.r_in) / g.n_r
+    dphi = 2 * math.pi / g.n_phi
+    for n, m in enumerate(base.maps):
+        cnt = m.n_rays
+        # delays that put the retarded time of frame 0 on a node s_k, with k running from before
+        # the window (the ray enters it during the frames) to one past its end
+        span = int(math.ceil((g.n_frames - 1) * g.dt_obs / g.dt_src))
+        ks = rng.integers(-span - 2, g.n_hat + 2, cnt)
+        delay = g.t0 - (g.s0 + ks * g.dt_src)
+        r = m.r.copy()
+        phi = m.phi.copy()
+        a = cnt // 4
+        r[:a] = g.r_in + (rng.integers(0, g.n_r, a) + 0.5) * dr          # on cell centres in r
+        phi[:a] = (rng.integers(0, g.n_phi, a) + 0.5) * dphi            # and in phi
+        r[a:a + 4] = [g.r_in, g.r_out, g.r_in + 0.5 * dr, g.r_out - 0.5 * dr]
+        maps.append(synth.RayMap(r=r, phi=phi, delay=delay, weight=m.weight, pixel=m.pixel))
+    return synth.Geometry(grid=g, maps=maps, label="ties-%d" % seed)
+
+
+@pytest.mark.parametrize("dt_obs", [4.0, 2.0])
+def test_retarded_times_on_hat_nodes_match_oracle(gpu_lib, dt_obs):
+    """Exact ties of eq. (47): a retarded time on a node gives weight 1 to that hat and weight 0 to
+    the next (a node one step past either end of the window gives nothing).  Every forward and
+    adjoint variant that serves this cadence, single vectors and a 66-vector block (row pairs),
+    against the oracle."""
+    rtt = gpu_lib
+    geo = tie_geometry(seed=91 if dt_obs == 4.0 else 92, dt_obs=dt_obs)
+    g = geo.grid
+    u = (g.t0 - np.concatenate([m.delay for m in geo.maps]) - g.s0) / g.dt_src
+    assert np.all(u == np.round(u))                      # theta = 0 on frame 0 of every ray
+    say("case ties", dt_obs, geo.rays_per_order, g.n_hat)
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(17)
+    nb = 66
+    X = rng.random((nb, g.n_cols)).astype(np.float32)
+    Yv = rng.standard_normal((nb, geo.n_rows)).astype(np.float32)
+    pick = [0, 65]
+    yr = oracle.forward(geo, X[pick].astype(np.float64))
+    xr = oracle.adjoint(geo, Yv[pick].astype(np.float64))
+    Xd, Yd = to_dev(X), to_dev(Yv)
+    for v, vname in enumerate(rtt.variant_names(False)):
+        if vname == "lean4q" and g.n_hat % 4:
+            continue
+        if vname.startswith("abs") and g.n_hat > 128:
+            continue
+        G.set_variant(apply=v)
+        ya = rtt.op_apply(G, Xd).cpu().numpy()
+        for i, b in enumerate(pick):
+            assert_rows_match(geo, ya[b], yr[i], (vname, b))
+    for v, vname in enumerate(rtt.variant_names(True)):
+        if vname.startswith("rows") and g.n_hat > 256:
+            continue
+        G.set_variant(adjoint=v)
+        xa = rtt.op_apply_adjoint(G, Yd).cpu().numpy()
+        for i, b in enumerate(pick):
+            assert rel(xa[b], xr[i]) <= TOL, (vname, b, rel(xa[b], xr[i]))
+
+
+# ------------------------------------------------------------------------------ row pairs, K > 64
+@pytest.mark.parametrize("n_hat_target,dt_obs", [(100, 4.0), (120, 2.0), (200, 4.0)])
+def test_row_pair_adjoint_with_wide_hat_ranges(gpu_lib, n_hat_target, dt_obs):
+    """The row-pair adjoint at K in (64, 128] (two hat slots per lane) and K > 128 (four), with
+    enough vectors that the dispatcher keeps the row-pair form: bitwise equal to the single-row
+    lane-shifted form and to itself in one launch over several geometries (every launch mode),
+    and the oracle on sampled vectors."""
+    import torch
+    rtt = gpu_lib
+    n_frames = int(round((n_hat_target - 8) * 4.0 / dt_obs))
+    geo = tiny_geometry(seed=36, rays=(6000, 800, 600), n_r=64, n_phi=128, n_frames=n_frames, dt_obs=dt_obs)
+    K = geo.grid.n_hat
+    say("case row pairs K", K, dt_obs)
+    assert (64 < K <= 128) if n_hat_target <= 128 else K > 128
+    G = rtt.Geometry(geo)
+    names = rtt.variant_names(True)
+    nb = 128          # 32 row pairs x 8 segments x 64 (or 32) vector groups: the row-pair form
+    Yt = to_dev(np.random.default_rng(15).standard_normal((nb, geo.n_rows)))
+    G.set_variant(adjoint=names.index("visitd2v"))
+    ref = rtt.op_apply_adjoint(G, Yt)
+    for vname in ("visitp2v", "visitp4v"):
+        G.set_variant(adjoint=names.index(vname))
+        assert torch.equal(rtt.op_apply_adjoint(G, Yt), ref), vname
+    pick = [0, nb - 1]
+    xr = oracle.adjoint(geo, Yt[pick].double().cpu().numpy())
+    for i, b in enumerate(pick):
+        assert rel(ref[b].cpu().numpy(), xr[i]) <= TOL, b
+    # the same geometry twice in one handle: one launch (plain, persistent) = one per geometry
+    G2 = rtt.Geometry([geo, geo])
+    G2.set_variant(adjoint=names.index("visitp2v"))
+    Y2 = torch.cat([Yt, Yt], dim=1).contiguous()
+    outs = []
+    for mode in (0, 1, 2):
+        G2.set_batch_mode(adjoint=mode)
+        outs.append(rtt.op_apply_adjoint(G2, Y2))
+    for o in outs:
+        assert torch.equal(o[:, :geo.grid.n_cols], ref) and torch.equal(o[:, geo.grid.n_cols:], ref)

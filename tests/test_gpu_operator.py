@@ -481,3 +481,45 @@ def test_absolute_hat_forward_equals_the_lean_form(gpu_lib, dt_obs, n_frames):
     yr = oracle.forward(geo, X[[0, 36]].double().cpu().numpy())
     for i, b in enumerate((0, 36)):
         assert max(block_rel(geo, Y[b].cpu().numpy(), yr[i])) <= TOL
+
+
+def test_masked_forward_through_autograd_and_the_mixer_zeroes_unselected_rows(gpu_lib):
+    """op_apply leaves the rows of unselected orders unwritten; the autograd forward, the ridge
+    loss and the mixed arm (L kron I) A_mask x must nevertheless see them as the masked operator's
+    zero rows: against the oracle's masked forward (which returns zeros there)."""
+    import torch
+    rtt = gpu_lib
+    from paper_2609_05528_amd.autograd import mixed_apply, retarded_time_apply, ridge_loss
+    geo = tiny_geometry(seed=61, rays=(40, 12, 8), n_frames=10)
+    for m in geo.maps:
+        m.pixel = np.random.default_rng(62).integers(0, 30, m.n_rays).astype(np.int32)
+    G = rtt.Geometry(geo)
+    rng = np.random.default_rng(63)
+    x = rng.random((2, geo.grid.n_cols)).astype(np.float32)
+    y = rng.standard_normal((2, geo.n_rows)).astype(np.float32)
+    lam = 1e-2
+    P = [m.n_rays * geo.grid.n_frames for m in geo.maps]
+    for mask in (0b001, 0b110):
+        # fill the allocator's cache with non-zero garbage first
+        junk = torch.full((4 * geo.n_rows,), 7.0, device="cuda")
+        del junk
+        xd = to_dev(x).requires_grad_(True)
+        yo = retarded_time_apply(xd, G, order_mask=mask)
+        ref = oracle.forward(geo, x.astype(np.float64), order_mask=mask)
+        got = yo.detach().cpu().numpy()
+        off = 0
+        for n, pn in enumerate(P):
+            if not (mask >> n) & 1:
+                assert np.all(got[:, off:off + pn] == 0.0), (mask, n)
+            off += pn
+        assert rel(got, ref) <= TOL, mask
+        loss = ridge_loss(xd, to_dev(y), G, lam, order_mask=mask)
+        lref = 0.5 * np.sum((ref - y.astype(np.float64)) ** 2) + 0.5 * lam * np.sum(x.astype(np.float64) ** 2)
+        assert abs(float(loss) - lref) <= 1e-5 * abs(lref), mask
+        loss.backward()
+        gref = oracle.ridge_gradient(geo, x.astype(np.float64), y.astype(np.float64), lam, order_mask=mask)
+        assert rel(xd.grad.cpu().numpy(), gref) <= TOL, mask
+        M = rtt.Mixer(G, "unresolved", [m.pixel for m in geo.maps])
+        d = mixed_apply(to_dev(x), G, M, order_mask=mask).cpu().numpy()
+        dref = np.stack([oracle.mix(geo, ref[b], "unresolved") for b in range(2)])
+        assert rel(d, dref) <= TOL, mask

@@ -97,9 +97,9 @@ def test_rsvd_workload_block_matches_oracle(gpu_lib):
 
 
 def test_rsvd_sketch_wider_than_one_combine_launch(gpu_lib):
-    """l = k + p = 320 test vectors: the triangular factors span two row-block launches of the
-    combine kernel (288 + 32 rows).  Singular values against the oracle on the same draw; the
-    returned right vectors orthonormal."""
+    """l = k + p = 320 test vectors: the triangular factors span three row-block launches of the
+    combine kernel (128 + 128 + 64 rows).  Singular values against the oracle on the same draw;
+    the returned right vectors orthonormal."""
     rtt = gpu_lib
     geo = tiny_geometry(seed=57, rays=(400, 120, 90), n_r=8, n_phi=12, n_frames=16)
     say("case rsvd l=320", geo.grid.n_cols, geo.n_rows)
@@ -166,6 +166,18 @@ def test_block_lanczos_matches_oracle(gpu_lib):
     top = 16
     assert np.max(np.abs(sv.sigma[:top] - s_o[:top])) <= 1e-4 * s_o[0]
     assert np.allclose(sv.residual[:top], res_o[:top], rtol=1e-2, atol=1e-4 * s_o[0])
+    # converged Ritz values (residual <= 1e-6 theta_1): the count the library reports is the count
+    # of the residuals it reports, and each converged value is the oracle's to 1e-4 relative
+    for tol in (1e-6, 1e-3):
+        n_conv = sv.converged(tol)
+        assert n_conv == int(np.sum(sv.residual <= tol * sv.sigma[0])), tol
+    conv = sv.residual <= 1e-6 * sv.sigma[0]
+    say("converged at 1e-6:", int(conv.sum()), "of", sv.k)
+    if conv.any():
+        assert np.max(np.abs(sv.sigma[conv] - s_o[conv]) / s_o[conv]) <= 1e-4
+    # rSVD factors without left vectors carry no residuals: no convergence count
+    with pytest.raises(rtt.RttError):
+        rtt.rsvd(G, k=8, p=8, q=1, seed=1).converged()
 
 
 def test_tsvd_matches_oracle_and_pinv(gpu_lib):
@@ -306,8 +318,14 @@ def test_block_lanczos_512_vectors_on_the_large_geometry(gpu_lib):
     geo = synth.geometry_for("cfg5")
     say("case lanczos cfg5")
     G = rtt.Geometry(geo)
+    choice = G.tune(nvec=32, reps=3)            # the variants the benchmark's Lanczos runs on
+    say("tuned", [(rtt.variant_names(False)[a], rtt.variant_names(True)[b]) for a, b in choice])
     sv = rtt.rsvd(G, method="lanczos", k=64, block=32, steps=16, seed=5001)
     th = sv.sigma
+    n_conv = sv.converged(1e-6)
+    say("converged Ritz values (residual <= 1e-6 theta_1):", n_conv, "of", sv.k,
+        "; theta_1 residual / theta_1:", sv.residual[0] / th[0])
+    assert n_conv == int(np.sum(sv.residual <= 1e-6 * th[0]))
     assert np.all(np.diff(th) <= 1e-6 * th[0])
     v1 = sv.V()[0].double().cpu().numpy()
     v1 /= np.linalg.norm(v1)

@@ -695,3 +695,40 @@ def test_fisher_reproduces_the_flat_probe_information():
         w[a * 7] = nl[a * 7] / oracle.probe_norm(geo.grid, 3.0)
     flat = oracle.age_energy(geo, ages, h=3.0, arm="resolved")
     assert np.allclose(np.einsum("l,alm,m->a", w, M, w), flat, rtol=1e-10)
+
+
+def test_compact_temporal_functions_are_tents_on_uniform_knots():
+    """The compact temporal class of Sec. 7 (degree-one B-splines on n uniform knots spanning the
+    window): isolated as the ratio of a "hats" column to the constant DCT column of the same
+    spatial function (pinned to scipy's DCT-II above), each function is numpy.interp of its unit
+    knot vector; with a window whose knots land on hat nodes it is 1 at its own knot and 0 at
+    every other knot; the functions sum to one over the window."""
+    g = tiny_geometry(seed=1, n_frames=20).grid
+    K = g.n_hat
+    sk = g.s0 + g.dt_src * np.arange(K)
+
+    def temporal(n, window):
+        Qh = oracle.synthesis_matrix(g, temporal="hats", n_temporal=n, window=window)
+        Qd = oracle.synthesis_matrix(g, temporal="dct", n_temporal=n, window=window)
+        Qh = Qh.reshape(g.n_r, g.n_phi, K, 4, 7, n)
+        Qd = Qd.reshape(g.n_r, g.n_phi, K, 4, 7, n)
+        i, j, a, b = 1, 2, 1, 0                  # R_1(r_1) Phi_0(phi_2) != 0
+        assert abs(Qd[i, j, 0, a, b, 0]) > 1e-3
+        return Qh[i, j, :, a, b, :] / Qd[i, j, :, a, b, 0][:, None]     # [K][n]
+
+    # default window [s0 - dt/2, s0 + (K - 1/2) dt]
+    lo, hi = g.s0 - 0.5 * g.dt_src, g.s0 + (K - 0.5) * g.dt_src
+    for n in (2, 5, 8):
+        T = temporal(n, None)
+        knots = lo + (hi - lo) * np.arange(n) / (n - 1)
+        for c in range(n):
+            assert np.allclose(T[:, c], np.interp(sk, knots, np.eye(n)[c]), atol=1e-13), (n, c)
+        assert np.allclose(T.sum(axis=1), 1.0, atol=1e-13)
+    # knots on every fourth hat node: the Kronecker property at the knots
+    n = (K - 1) // 4 + 1
+    window = (sk[0], sk[4 * (n - 1)])
+    T = temporal(n, window)
+    for c in range(n):
+        assert np.allclose(T[4 * np.arange(n), c], np.eye(n)[c], atol=1e-13), c
+        support = np.nonzero(T[:, c])[0]
+        assert support.min() >= 4 * c - 3 and support.max() <= 4 * c + 3, c
