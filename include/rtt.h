@@ -393,6 +393,24 @@ int mixer_set_variant(rtt_mixer* mixer, int32_t apply_vectors, int32_t adjoint_v
 int mix_apply(const rtt_mixer* mixer, const float* y, float* d, int32_t nvec, void* stream);
 
 /*
+ * mix_apply_noalloc -- mix_apply for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same bits as mix_apply, with the
+ * partial rows of multi-chunk mixed rows (the total flux) in a library-static
+ * device array of RTT_MIX_NOALLOC_SCRATCH_BYTES per GPU (held by every GPU the
+ * library runs on until the process ends) instead of a buffer owned by the
+ * mixer.  Calls no allocating routine.  A call needs
+ * (number of chunks) x (largest n_frames rounded up to 4) x nvec x 4 bytes of
+ * it; larger calls are rejected with RTT_EINVAL (nothing launched) and the
+ * message names the vector limit.  Every call on one GPU shares that GPU's
+ * array (each call writes what it reads), so calls that overlap in time on
+ * one GPU -- on different streams or threads -- race; serialise them.
+ * Errors: as mix_apply, RTT_EDEVICE when the array's address cannot be taken.
+ */
+#define RTT_MIX_NOALLOC_SCRATCH_BYTES (16u << 20)
+int mix_apply_noalloc(const rtt_mixer* mixer, const float* y, float* d, int32_t nvec, void* stream);
+
+/*
  * mix_adjoint -- y = (L^T kron I) d: every order-resolved row receives the
  * mixed row its ray feeds.  d: device [nvec][n_rows]; y: device
  * [nvec][n_src_rows], every row overwritten.  Allocates nothing.

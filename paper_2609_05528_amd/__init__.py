@@ -25,7 +25,7 @@ RTT_EACH_GEOMETRY = -2
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
             "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
             "svd_converged", "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
-            "mix_apply", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
+            "mix_apply", "mix_apply_noalloc", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
             "age_reach", "age_window_error", "tsvd_project", "noise_add", "synthesis_create", "synthesis_free",
             "synthesis_info", "synth_expand", "synth_project", "synthesis_audit", "age_fisher", "last_error")
 
@@ -134,6 +134,7 @@ def require_native():
         "mixer_member": [vp, i32, vp, vp, vp],
         "mixer_set_variant": [vp, i32, i32],
         "mix_apply": [vp, vp, vp, i32, vp],
+        "mix_apply_noalloc": [vp, vp, vp, i32, vp],
         "mix_adjoint": [vp, vp, vp, i32, vp],
         "mix_covariance": [vp, vp, vp, vp],
         "reference_response": [vp, _dp, vp],
@@ -342,7 +343,7 @@ def op_apply_adjoint(geom: Geometry, y, x=None, order_mask: int = 0, stream=None
 
 from .svd import SVD, rsvd, tsvd_solve, tsvd_project, ridge_solve  # noqa: E402,F401
 from .autograd import RetardedTimeOp, retarded_time_apply  # noqa: E402,F401
-from .mixer import Mixer, mixer_create, mix_apply, mix_adjoint, mix_covariance  # noqa: E402,F401
+from .mixer import Mixer, mixer_create, mix_apply, mix_apply_noalloc, mix_adjoint, mix_covariance  # noqa: E402,F401
 from .synthesis import Synthesis  # noqa: E402,F401
 from .age import (reference_response, age_information, age_window, age_reach,  # noqa: E402,F401
                   age_window_error, noise_add)

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "rtt.h"
@@ -280,17 +282,14 @@ void release(rtt_mixer* m)
 
 }  // namespace
 
-int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, int64_t d_stride, int nvec,
-                hipStream_t s)
+namespace {
+
+// The forward with the partial rows of multi-chunk mixed rows in `part` (n_slots * pitch * nvec
+// floats, NULL when the mixer has none); the device of m is current.
+int mix_forward_parts(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, int64_t d_stride, int nvec,
+                      float* part, hipStream_t s)
 {
-    if (nvec == 0 || m->n_chunks == 0) return RTT_OK;
-    RTT_HIP(hipSetDevice(m->device));
     const int64_t part_stride = m->n_slots * m->pitch;
-    float* part = nullptr;
-    if (m->n_multi > 0) {
-        part = (float*)m->ws.get("mix_partials", sizeof(float) * (size_t)part_stride * nvec);
-        if (!part) return fail(RTT_ENOMEM, "mixer partial rows");
-    }
     const int vmax = call_vmax(y, d, y_stride, d_stride);
     const dim3 blk(MIX_WAVES * WAVE);
     // short source lists (the unresolved image: one to a few rays per pixel): 8 vectors a wave so
@@ -317,6 +316,21 @@ int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, 
 #undef RTT_MIX_FWD
     RTT_HIP(hipGetLastError());
     return RTT_OK;
+}
+
+}  // namespace
+
+int mix_forward(const rtt_mixer* m, const float* y, int64_t y_stride, float* d, int64_t d_stride, int nvec,
+                hipStream_t s)
+{
+    if (nvec == 0 || m->n_chunks == 0) return RTT_OK;
+    RTT_HIP(hipSetDevice(m->device));
+    float* part = nullptr;
+    if (m->n_multi > 0) {
+        part = (float*)m->ws.get("mix_partials", sizeof(float) * (size_t)(m->n_slots * m->pitch) * nvec);
+        if (!part) return fail(RTT_ENOMEM, "mixer partial rows");
+    }
+    return mix_forward_parts(m, y, y_stride, d, d_stride, nvec, part, s);
 }
 
 bool mixer_ok(const rtt_mixer* m) { return valid_mixer(m); }
@@ -492,6 +506,56 @@ extern "C" int mix_apply(const rtt_mixer* m, const float* y, float* d, int32_t n
     int rc = check_mix_call(m, y, d, nvec);
     if (rc) return rc;
     return mix_forward(m, y, m->n_src_rows, d, m->n_rows, nvec, (hipStream_t)stream);
+}
+
+// Partial rows of mix_apply_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never passes its name to a kernel: that is a host-side stand-in, not a
+// device address.  The device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static __device__ __align__(256) float scratch[RTT_MIX_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// the device address of the scratch array on device `dev` (current)
+int noalloc_scratch(int dev, float** out)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(RTT_EDEVICE, "mix_apply_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(RTT_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = (float*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return RTT_OK;
+}
+
+}  // namespace
+
+extern "C" int mix_apply_noalloc(const rtt_mixer* m, const float* y, float* d, int32_t nvec, void* stream)
+{
+    int rc = check_mix_call(m, y, d, nvec);
+    if (rc) return rc;
+    const uint64_t need = sizeof(float) * (uint64_t)(m->n_slots * m->pitch) * (uint64_t)nvec;
+    if (m->n_multi > 0 && need > RTT_MIX_NOALLOC_SCRATCH_BYTES) {
+        const uint64_t per = sizeof(float) * (uint64_t)(m->n_slots * m->pitch);
+        return fail(RTT_EINVAL, "mix_apply_noalloc: " + std::to_string(nvec) + " vectors need " +
+                                    std::to_string(need) + " bytes of partial rows, more than the " +
+                                    std::to_string((uint64_t)RTT_MIX_NOALLOC_SCRATCH_BYTES) +
+                                    "-byte scratch (at most " + std::to_string(RTT_MIX_NOALLOC_SCRATCH_BYTES / per) +
+                                    " vectors per call for this mixer)");
+    }
+    if (nvec == 0 || m->n_chunks == 0) return RTT_OK;
+    RTT_HIP(hipSetDevice(m->device));
+    float* part = nullptr;
+    if (m->n_multi > 0 && (rc = noalloc_scratch(m->device, &part))) return rc;
+    return mix_forward_parts(m, y, m->n_src_rows, d, m->n_rows, nvec, part, (hipStream_t)stream);
 }
 
 extern "C" int mix_adjoint(const rtt_mixer* m, const float* d, float* y, int32_t nvec, void* stream)

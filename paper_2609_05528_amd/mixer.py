@@ -98,6 +98,15 @@ def mix_apply(mixer: Mixer, y, d=None, stream=None):
     return d
 
 
+def mix_apply_noalloc(mixer: Mixer, y, d, stream=None):
+    """d = (L kron I) y into the caller's d, through the library entry point that allocates no
+    device memory (partial rows in a fixed per-GPU scratch array; see include/rtt.h)."""
+    nvec = _nvec(y, mixer.n_src_rows)
+    _check(require_native().mix_apply_noalloc(mixer.handle, _dev_ptr(y, nvec * mixer.n_src_rows, "y"),
+                                              _dev_ptr(d, nvec * mixer.n_rows, "d"), nvec, _stream(stream)))
+    return d
+
+
 def mix_adjoint(mixer: Mixer, d, y=None, stream=None):
     """y = (L^T kron I) d.  d: [..., n_rows] float32 CUDA; returns y [..., n_src_rows]."""
     import torch
