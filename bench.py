@@ -1,22 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the retarded-time operator pair A / A^T on one MI355X.
 
-Workload (default): the Kerr a=0.5, i=50 deg geometry with orders n=0,1,2 on a
-128^2 screen, 128 frames at 4M cadence, 64x64 polar cells x 96 hats, and a
-block of l = k + p = 256 + 8 = 264 coefficient vectors (the randomized-SVD
-block).  One step = one block application of A (264 vectors) followed by one
-block application of A^T (264 vectors): 528 applies.  Inputs are synthetic,
-seeded, and resident in HBM before the timed region starts.
+Headline workload: the batch of 12 spin x inclination geometries (orders n = 0, 1, 2; screens
+96^2-256^2, 64-160 frames at 4M cadence) sharing one 64 x 64-cell x 96-hat source basis, and 60
+seeded Gaussian-blob emissivity histories.  One step = one batched sweep of A over every
+(geometry, history) pair -- each history's coefficient block read once and imaged through all 12
+geometries (op_apply_shared) -- followed by one batched sweep of A^T over every pair (one
+coefficient block per pair, as the per-geometry solves need): 720 + 720 applies.  Inputs are
+synthetic, seeded and resident in HBM before the timed region starts.
 
-Printed: one JSON line with the throughput (applies/s), the roofline of the
-dominant kernel (algorithmic bytes / measured kernel time vs the 8 TB/s HBM
-peak), the plain per-vector throughput beside the batched one, parity against
-the FP64 oracle on sampled vectors, and the oracle's own CPU throughput on
-one full step of the same work.  Extra sections: the 512^2 x 512-frame
-geometry one vector at a time, the rSVD wall time, and the batch of 12
-geometries x 60 histories (batched vs per-instance A/A^T and autograd, the
-rSVD of every geometry in one call, and one captured graph of A, A^T, TSVD
-and a fixed-count ridge solve of every (geometry, history) pair).
+Printed: one JSON line with the throughput (applies/s), the roofline of the dominant operator call
+(algorithmic bytes / its mean duration from HIP events on the launch stream, against the 8 TB/s
+HBM peak), the plain per-instance throughput beside the batched one, parity of sampled pairs
+against the FP64 oracle, and the oracle's own CPU throughput on the same step (all host cores,
+and one thread).  Extra sections: the 128^2 Kerr block of 264 vectors (the rSVD block), the
+512^2 x 512-frame geometry one vector at a time and its block Lanczos, the rSVD, mixers, age
+information, estimators and synthesis, and oracle timings of the drivers.
 """
 import argparse
 import json
@@ -33,13 +32,13 @@ METRIC = "A+A^T applies/sec and HBM GB/s; batched vs plain at 1e-5 rel err"
 HBM_PEAK_GBPS = 8000.0
 RAY_RECORD_BYTES = 32
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip")
-# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE on this workload
-# (FETCH_SIZE scaled by 2.0, the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only
-# for the kernel source digest and variant they were taken on (see profiles/).
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (FETCH_SIZE scaled by 2.0,
+# the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only for the kernel source digest,
+# workload, variant and launch modes they were taken on (see profiles/).
 MEASURED_TRAFFIC = {
-    "op_apply_adjoint": [{"bytes": 2050789488, "digest": "2475b31d9f92872d", "nvec": 264, "variant": "visitp2v"}],
-    "op_apply": [{"bytes": 2105012096, "digest": "2475b31d9f92872d", "nvec": 264, "variant": "abs4"},
-                 {"bytes": 2099961088, "digest": "2475b31d9f92872d", "nvec": 264, "variant": "abs8"}],
+    "op_apply_adjoint": [],
+    "op_apply_shared": [],
+    "op_apply": [],
 }
 
 
@@ -304,55 +303,93 @@ def calibrate(torch, dev, gib=2):
     return out
 
 
-def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=2):
-    """The 12-geometry x 60-history batch: batched vs per-instance A/A^T and autograd, and one
-    captured graph of A, A^T, TSVD and a fixed-count ridge solve of every (geometry, history)."""
-    from paper_2609_05528_amd.autograd import ridge_loss
+def batch_algorithmic_bytes(G, nvec, adjoint, n_cells):
+    """Bytes one batched sweep must move: the data of every (geometry, history) pair once and the ray
+    tables once; for A the shared coefficient block of each history once (every geometry reads the
+    same block), for A^T one coefficient block per pair plus each geometry's per-order cell offsets."""
+    b = 4 * nvec * G.n_rows + RAY_RECORD_BYTES * G.n_rays
+    if adjoint:
+        b += 4 * nvec * G.n_cols + 4 * len(G.members) * (n_cells + 1)
+    else:
+        b += 4 * nvec * G.members[0]["n_cols"]
+    return b
+
+
+def batch_headline(torch, rtt, synth, dev, steps, warmup, apply_variant="", adjoint_variant=""):
+    """The headline step on the 12-geometry x 60-history batch: tuned kernels, `warmup` untimed
+    steps, then `steps` timed steps with HIP events around every operator call."""
     geos = synth.batch_geometries()
     ng, nh = len(geos), synth.BATCH_HISTORIES
     G = rtt.Geometry(geos)
-    lam = 1e-3
     t0 = time.perf_counter()
     G.tune(nvec=nh, reps=3)
     t_tune = time.perf_counter() - t0
+    if apply_variant or adjoint_variant:
+        G.set_variant(apply=rtt.variant_names(False).index(apply_variant) if apply_variant else -1,
+                      adjoint=rtt.variant_names(True).index(adjoint_variant) if adjoint_variant else -1)
     H = torch.from_numpy(synth.blob_histories(geos[0].grid, nh, dtype=np.float32)).to(dev)   # [60][S*K]
-    X = H.repeat(1, ng).contiguous()          # history h in every geometry's column block
     Y = torch.empty((nh, G.n_rows), dtype=torch.float32, device=dev)
-    XT = torch.empty_like(X)
-    pairs = ng * nh
-    log("batch: %d geometries, %d histories, rows %d, cols %d, launch modes %s" % (
-        ng, nh, G.n_rows, G.n_cols, G.batch_mode))
+    XT = torch.empty((nh, G.n_cols), dtype=torch.float32, device=dev)
+    log("batch: %d geometries, %d histories, rows %d, cols %d per geometry, launch modes %s, tune %.1f s" % (
+        ng, nh, G.n_rows, G.members[0]["n_cols"], G.batch_mode, t_tune))
 
-    # batched A + A^T over every (geometry, history) pair
-    rtt.op_apply(G, X, Y)
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record()
+        rtt.op_apply_shared(G, H, Y)
+        if evs is not None:
+            evs[1].record()
+        rtt.op_apply_adjoint(G, Y, XT)
+        if evs is not None:
+            evs[2].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_a = [e[0].elapsed_time(e[1]) for e in events]
+    t_at = [e[1].elapsed_time(e[2]) for e in events]
+    fn, an = rtt.variant_names(False), rtt.variant_names(True)
+    variants = sorted({(fn[m["apply_variant"]], an[m["adjoint_variant"]]) for m in G.members})
+    modes = G.batch_mode
+    log("batch step: A %.3f ms, A^T %.3f ms; step %.3f ms" % (np.mean(t_a), np.mean(t_at), 1e3 * wall / steps))
+    return dict(G=G, geos=geos, H=H, Y=Y, XT=XT, wall=wall, t_a=t_a, t_at=t_at, pairs=ng * nh, nh=nh,
+                variants=variants, modes=modes, tune_s=t_tune)
+
+
+def batch_extras(torch, rtt, synth, oracle, dev, hb, ridge_iters=20, k=256, p=8, q=2, no_age=False):
+    """Around the headline batch: parity of sampled pairs against the FP64 oracle, the same work as a
+    plain per-instance loop, batched vs per-instance autograd, the rSVD of every geometry in one
+    call, and one captured graph of A, A^T, TSVD and a fixed-count ridge solve of every pair."""
+    from paper_2609_05528_amd.autograd import ridge_loss
+    G, geos, H, Y, XT, nh = hb["G"], hb["geos"], hb["H"], hb["Y"], hb["XT"], hb["nh"]
+    ng = len(geos)
+    pairs = ng * nh
+    lam = 1e-3
+    rtt.op_apply_shared(G, H, Y)
     rtt.op_apply_adjoint(G, Y, XT)
     torch.cuda.synchronize()
-    reps = 5
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ev[0].record()
-    for _ in range(reps):
-        rtt.op_apply(G, X, Y)
-    ev[1].record()
-    for _ in range(reps):
-        rtt.op_apply_adjoint(G, Y, XT)
-    ev[2].record()
-    torch.cuda.synchronize()
-    ms_a, ms_at = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
-    ncell = sum(g.grid.n_cells for g in geos)
-    b_a = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, ncell, 3, nh, False)
-    b_at = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, ncell, 3, nh, True)
-    batched = 2 * pairs / ((ms_a + ms_at) * 1e-3)
-
     # parity of sampled (geometry, history) pairs against the FP64 oracle
-    par = []
-    for gi, hi in ((0, 0), (ng - 1, nh - 1), (5, 31)):
+    par = {"A": [], "AT": []}
+    sampled = ((0, 0), (ng - 1, nh - 1), (5, 31), (8, 12))
+    for gi, hi in sampled:
         m = G.members[gi]
+        rs = slice(m["row_offset"], m["row_offset"] + m["n_rows"])
+        cs = slice(m["col_offset"], m["col_offset"] + m["n_cols"])
         yr = oracle.forward(geos[gi], H[hi].double().cpu().numpy())
-        ya = Y[hi, m["row_offset"]:m["row_offset"] + m["n_rows"]].double().cpu().numpy()
-        par.append(float(np.linalg.norm(ya - yr) / np.linalg.norm(yr)))
-        xr = oracle.adjoint(geos[gi], Y[hi, m["row_offset"]:m["row_offset"] + m["n_rows"]].double().cpu().numpy())
-        xa = XT[hi, m["col_offset"]:m["col_offset"] + m["n_cols"]].double().cpu().numpy()
-        par.append(float(np.linalg.norm(xa - xr) / np.linalg.norm(xr)))
+        ya = Y[hi, rs].double().cpu().numpy()
+        par["A"].append(float(np.linalg.norm(ya - yr) / np.linalg.norm(yr)))
+        xr = oracle.adjoint(geos[gi], Y[hi, rs].double().cpu().numpy())
+        xa = XT[hi, cs].double().cpu().numpy()
+        par["AT"].append(float(np.linalg.norm(xa - xr) / np.linalg.norm(xr)))
+    parity = {"A_max_rel_err": max(par["A"]), "AT_max_rel_err": max(par["AT"]), "tol": 1e-5,
+              "pairs_geometry_history": [list(x) for x in sampled]}
 
     # the same work as a plain loop: one handle per geometry, one history per call
     singles = [rtt.Geometry(g) for g in geos]
@@ -360,6 +397,9 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
         Gs.tune(nvec=1, reps=3)
     yb = [torch.empty(Gs.n_rows, dtype=torch.float32, device=dev) for Gs in singles]
     xb = [torch.empty(Gs.n_cols, dtype=torch.float32, device=dev) for Gs in singles]
+    for gi, Gs in enumerate(singles):
+        rtt.op_apply(Gs, H[0], yb[gi])
+        rtt.op_apply_adjoint(Gs, yb[gi], xb[gi])
     torch.cuda.synchronize()
     tp0 = time.perf_counter()
     for h in range(nh):
@@ -370,6 +410,7 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
     plain = 2 * pairs / (time.perf_counter() - tp0)
 
     # autograd: ridge loss of every pair and its gradient in one call, vs one pair per call
+    X = H.repeat(1, ng).contiguous()
     Yobs = Y.clone()
     Yobs.add_(0.01)
     Xg = X.clone().requires_grad_(True)
@@ -409,11 +450,13 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
     t_rsvd = time.perf_counter() - tr0
     Xts = torch.empty_like(X)
     Xrg = torch.empty_like(X)
+    Yg = torch.empty_like(Y)
+    XTg = torch.empty_like(X)
     resid = torch.empty(pairs, dtype=torch.float32, device=dev)
 
     def step():
-        rtt.op_apply(G, X, Y)
-        rtt.op_apply_adjoint(G, Yobs, XT)
+        rtt.op_apply_shared(G, H, Yg)
+        rtt.op_apply_adjoint(G, Yobs, XTg)
         rtt.tsvd_solve(G, sv, Yobs, t=k, x=Xts)
         rtt.ridge_solve(G, Yobs, lam, maxit=ridge_iters, x=Xrg, async_mode=True, resid=resid)
 
@@ -427,13 +470,13 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
     step()
     torch.cuda.synchronize()
     t_eager = time.perf_counter() - te0
-    ref = [t.clone() for t in (Y, XT, Xts, Xrg)]
+    ref = [t.clone() for t in (Yg, XTg, Xts, Xrg)]
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         step()
     graph.replay()
     torch.cuda.synchronize()
-    same = all(bool(torch.equal(a, b)) for a, b in zip(ref, (Y, XT, Xts, Xrg)))
+    same = all(bool(torch.equal(a, b)) for a, b in zip(ref, (Yg, XTg, Xts, Xrg)))
     gev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     greps = 3
     gev[0].record()
@@ -442,31 +485,218 @@ def batch_section(torch, rtt, synth, oracle, dev, ridge_iters=20, k=256, p=8, q=
     gev[1].record()
     torch.cuda.synchronize()
     ms_graph = gev[0].elapsed_time(gev[1]) / greps
-    del graph, sv
+    del graph, sv, Xts, Xrg, Yg, XTg, X, Yobs
     torch.cuda.empty_cache()
-    ages = age_section(torch, rtt, geos, G)
+    ages = None if no_age else age_section(torch, rtt, geos, G)
     out = {
-        "workload": "12 geometries (spins 0/0.3/0.6/0.94 x incl 20/50/75, 96^2-256^2, 64-160 frames, "
-                    "orders 0-2) x 60 Gaussian-blob histories on a shared 64x64x96 basis",
-        "pairs": pairs, "rows": G.n_rows, "cols": G.n_cols, "rays": G.n_rays,
-        "launch_modes": list(G.batch_mode), "tune_seconds": t_tune,
-        "op_apply": {"ms": ms_a, "GBps": b_a / (ms_a * 1e-3) / 1e9},
-        "op_apply_adjoint": {"ms": ms_at, "GBps": b_at / (ms_at * 1e-3) / 1e9},
-        "batched_applies_per_s": batched, "plain_applies_per_s": plain,
+        "parity": parity, "plain_applies_per_s": plain,
         "autograd_pairs_per_s": {"batched": ag_batched, "plain": ag_plain, "grad_rel_diff": g_rel},
-        "parity_max_rel_err": max(par),
         "rsvd_each_geometry": {"seconds": t_rsvd, "k": k, "p": p, "q": q},
         "graph_step": {"ms_replay": ms_graph, "s_eager": t_eager, "replay_equals_eager": same,
                        "ridge_iterations": ridge_iters, "tsvd_t": k,
-                       "contents": "A + A^T + TSVD + ridge CG on every (geometry, history) pair"},
+                       "contents": "A (shared blocks) + A^T + TSVD + ridge CG on every (geometry, history) pair"},
         "age_information": ages,
     }
-    log("batch: A %.2f ms A^T %.2f ms (%.0f / %.0f GB/s); batched %.0f vs plain %.0f applies/s; "
-        "autograd %.0f vs %.0f pairs/s; graph %.1f ms" % (ms_a, ms_at, out["op_apply"]["GBps"],
-                                                          out["op_apply_adjoint"]["GBps"], batched, plain,
-                                                          ag_batched, ag_plain, ms_graph))
-    del X, Y, XT, Xts, Xrg, Yobs, H, G
+    log("batch extras: parity A %.2e A^T %.2e; plain %.0f applies/s; autograd %.0f vs %.0f pairs/s; rsvd %.2f s; "
+        "graph %.1f ms" % (parity["A_max_rel_err"], parity["AT_max_rel_err"], plain, ag_batched, ag_plain, t_rsvd,
+                           ms_graph))
+    return out
+
+
+def block_section(torch, rtt, synth, oracle, dev, args):
+    """The 128^2 Kerr geometry (orders 0-2, 128 frames, 64 x 64 x 96) on the rSVD block of
+    l = k + p = 264 vectors: tuned A and A^T on the block, their roofline, parity of two vectors, the
+    plain per-vector loop, and the mixers, age information, estimators, synthesis and rSVD sections."""
+    p = synth.config("cfg2")
+    geo = synth.geometry_for(p)
+    g = geo.grid
+    G = rtt.Geometry(geo)
+    nvec = args.nvec
+    choice = G.tune(nvec=nvec, reps=5)
+    names = [(rtt.variant_names(False)[a], rtt.variant_names(True)[b]) for a, b in choice]
+    log("block: autotuner choice (apply, adjoint) %s" % names)
+    X = torch.from_numpy(synth.gaussian_block(G.n_cols, nvec, seed=p["seed"] + 1)).to(dev)
+    Y = torch.empty((nvec, G.n_rows), dtype=torch.float32, device=dev)
+    XT = torch.empty((nvec, G.n_cols), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        rtt.op_apply(G, X, Y)
+        rtt.op_apply_adjoint(G, Y, XT)
+    torch.cuda.synchronize()
+    reps = 20
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    t0 = time.perf_counter()
+    for e in evs:
+        e[0].record()
+        rtt.op_apply(G, X, Y)
+        e[1].record()
+        rtt.op_apply_adjoint(G, Y, XT)
+        e[2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_a = [e[0].elapsed_time(e[1]) for e in evs]
+    t_at = [e[1].elapsed_time(e[2]) for e in evs]
+    ms_a, ms_at = float(np.mean(t_a)), float(np.mean(t_at))
+    b_a = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, g.n_cells, g.n_orders, nvec, False)
+    b_at = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, g.n_cells, g.n_orders, nvec, True)
+    digest = source_digest()
+    kern = {}
+    for name, ms, b, v in (("op_apply", ms_a, b_a, names[0][0]), ("op_apply_adjoint", ms_at, b_at, names[0][1])):
+        traffic = None
+        for meas in MEASURED_TRAFFIC.get(name, []):
+            if meas["digest"] == digest and meas["nvec"] == nvec and meas["variant"] == v and meas.get("workload") == "cfg2":
+                traffic = meas["bytes"]
+        kern[name] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9, "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                      "bytes": b, "traffic": traffic, "variant": v,
+                      "ms_p10_median_p90": [float(np.percentile(t_a if name == "op_apply" else t_at, q))
+                                            for q in (10, 50, 90)]}
+    log("block: A %.3f ms (%.0f GB/s), A^T %.3f ms (%.0f GB/s)" % (ms_a, kern["op_apply"]["GBps"], ms_at,
+                                                                   kern["op_apply_adjoint"]["GBps"]))
+    par = {"A": [], "AT": []}
+    for b in (0, nvec - 1):
+        yr = oracle.forward(geo, X[b].double().cpu().numpy())
+        par["A"].append(float(np.linalg.norm(Y[b].double().cpu().numpy() - yr) / np.linalg.norm(yr)))
+        xr = oracle.adjoint(geo, Y[b].double().cpu().numpy())
+        par["AT"].append(float(np.linalg.norm(XT[b].double().cpu().numpy() - xr) / np.linalg.norm(xr)))
+    out = {"workload": "128^2 Kerr a=0.5 i=50 n=0-2, 128 frames, 64x64x96; block of %d vectors" % nvec,
+           "rays_per_order": geo.rays_per_order, "rows": G.n_rows, "cols": G.n_cols, "nvec": nvec,
+           "applies_per_s": 2 * nvec * reps / wall, "kernels": kern,
+           "parity": {"A_max_rel_err": max(par["A"]), "AT_max_rel_err": max(par["AT"]), "tol": 1e-5}}
+    if not args.no_plain:
+        xs, ys, xts = [X[b] for b in range(nvec)], [Y[b] for b in range(nvec)], [XT[b] for b in range(nvec)]
+        for b in range(8):
+            rtt.op_apply(G, xs[b], ys[b])
+            rtt.op_apply_adjoint(G, ys[b], xts[b])
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for b in range(nvec):
+            rtt.op_apply(G, xs[b], ys[b])
+            rtt.op_apply_adjoint(G, ys[b], xts[b])
+        torch.cuda.synchronize()
+        out["plain_applies_per_s"] = 2 * nvec / (time.perf_counter() - tp0)
+    out["mixers"] = None if args.no_mixer else mixer_section(torch, rtt, oracle, geo, G, Y)
+    out["age_information"] = None if args.no_age else age_section(torch, rtt, [geo], G)
+    out["estimators"] = None if args.no_estimators else estimator_section(torch, rtt, synth, geo, G)
+    out["synthesis"] = None if args.no_synthesis else synthesis_section(torch, rtt, G)
+    if not args.no_rsvd:
+        del X, Y, XT
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t0r = time.perf_counter()
+        sv = rtt.rsvd(G, k=p["rsvd_k"], p=p["rsvd_p"], q=p["rsvd_q"], seed=2001)
+        torch.cuda.synchronize()
+        t_rs = time.perf_counter() - t0r
+        t_app = (p["rsvd_q"] + 1) * (ms_a + ms_at) * 1e-3
+        out["rsvd"] = {"seconds": t_rs, "k": sv.k, "p": p["rsvd_p"], "q": p["rsvd_q"], "sigma_1": float(sv.sigma[0]),
+                       "sigma_k": float(sv.sigma[-1]), "apply_seconds_est": t_app, "dense_seconds_est": t_rs - t_app}
+        log("block: rsvd %.3f s, sigma_1 %.4g sigma_k %.4g" % (t_rs, sv.sigma[0], sv.sigma[-1]))
+        del sv
+    del G
     torch.cuda.empty_cache()
+    return out
+
+
+def large_section(torch, rtt, synth, dev):
+    """The 512^2 x 512-frame geometry (a=0.94, i=75, orders 0-2, 128 x 128 x 256): A and A^T one
+    vector per launch, then block Lanczos with 512 right vectors (16 steps of 32) on the variants
+    tuned for 32-vector blocks, with the number of converged Ritz values."""
+    geo5 = synth.geometry_for("cfg5")
+    G5 = rtt.Geometry(geo5)
+    G5.tune(nvec=1, reps=3)
+    x5 = torch.from_numpy(synth.uniform_emissivity(geo5.grid, seed=5000).astype(np.float32)).to(dev)
+    y5 = torch.empty(G5.n_rows, dtype=torch.float32, device=dev)
+    xt5 = torch.empty_like(x5)
+    ta5, tat5 = time_pair(torch, rtt, G5, x5, y5, xt5, reps=20)
+    g5 = geo5.grid
+    b5 = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, False)
+    b5t = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, True)
+    v1 = (rtt.variant_names(False)[G5.members[0]["apply_variant"]],
+          rtt.variant_names(True)[G5.members[0]["adjoint_variant"]])
+    G5.tune(nvec=32, reps=3)
+    torch.cuda.synchronize()
+    t0l = time.perf_counter()
+    svl = rtt.rsvd(G5, method="lanczos", k=64, block=32, steps=16, seed=5001)
+    torch.cuda.synchronize()
+    t_lz = time.perf_counter() - t0l
+    conv = {str(t): int(svl.converged(t)) for t in (1e-6, 1e-4, 1e-2)}
+    lz = {"seconds": t_lz, "block": 32, "steps": 16, "theta_1": float(svl.sigma[0]),
+          "residual_1_rel": float(svl.residual[0] / svl.sigma[0]),
+          "converged_of_64_by_rel_residual": conv,
+          "variants": [rtt.variant_names(False)[G5.members[0]["apply_variant"]],
+                       rtt.variant_names(True)[G5.members[0]["adjoint_variant"]]]}
+    del svl
+    log("large: A %.3f ms, A^T %.3f ms; lanczos %.2f s, converged %s" % (ta5, tat5, t_lz, conv))
+    out = {"workload": "512^2 Kerr a=0.94 i=75 n=0-2, 512 frames at 2M, 128x128x256; one vector per launch",
+           "block_lanczos_512": lz,
+           "op_apply": {"ms": ta5, "GBps": b5 / (ta5 * 1e-3) / 1e9, "frac": b5 / (ta5 * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                        "bytes": b5, "variant": v1[0]},
+           "op_apply_adjoint": {"ms": tat5, "GBps": b5t / (tat5 * 1e-3) / 1e9,
+                                "frac": b5t / (tat5 * 1e-3) / 1e9 / HBM_PEAK_GBPS, "bytes": b5t, "variant": v1[1]},
+           "applies_per_s": 2.0 / ((ta5 + tat5) * 1e-3)}
+    del G5, x5, y5, xt5
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def cpu_baseline_section(oracle, hb, one_thread_histories=2):
+    """The FP64 oracle on the headline step: A and A^T of every (geometry, history) pair on all host
+    threads the oracle uses (vectors of one geometry spread over threads; the serial C evaluation of
+    each vector unchanged), and on one thread for a sample of histories (the paper's pinned
+    single-threaded setting)."""
+    G, geos, H, Y = hb["G"], hb["geos"], hb["H"], hb["Y"]
+    Hh = H.double().cpu().numpy()
+    threads = oracle.host_threads()
+    t0 = time.perf_counter()
+    for gi, geo in enumerate(geos):
+        yo = oracle.forward(geo, Hh, threads=threads)
+        oracle.adjoint(geo, yo, threads=threads)
+    t_all = time.perf_counter() - t0
+    n_all = 2 * len(geos) * Hh.shape[0]
+    t0 = time.perf_counter()
+    for gi, geo in enumerate(geos):
+        yo = oracle.forward(geo, Hh[:one_thread_histories], threads=1)
+        oracle.adjoint(geo, yo, threads=1)
+    t_one = time.perf_counter() - t0
+    n_one = 2 * len(geos) * one_thread_histories
+    return {"value": n_all / t_all, "unit": "applies/s", "cores": threads, "kind": "oracle",
+            "sample": "the whole headline step: A and A^T of all %d (geometry, history) pairs in FP64 (plain C "
+                      "per vector, vectors on %d host threads), %.1f s" % (n_all // 2, threads, t_all),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_thread": {"value": n_one / t_one, "unit": "applies/s", "cores": 1,
+                              "sample": "A and A^T of %d histories x 12 geometries, one thread, %.1f s"
+                                        % (one_thread_histories, t_one)}}
+
+
+def oracle_driver_section(oracle, synth):
+    """Wall times of the oracle's drivers on bounded samples: the rSVD of the 128^2 workload (k = 256,
+    p = 8, q = 2, LAPACK QR/SVD), block Lanczos on the same operator (4 steps of 32), and CG
+    iterations of the ridge solve of the 256^2 x 192-frame workload (lambda = 1e-3)."""
+    out = {"threads": oracle.host_threads()}
+    geo = synth.geometry_for("cfg2")
+    om = synth.gaussian_block(geo.grid.n_cols, 264, seed=2001).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.rsvd(geo, om, q=2)
+    out["rsvd_128_k256_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.block_lanczos(geo, om[:32], 4)
+    out["lanczos_128_b32_4steps_s"] = time.perf_counter() - t0
+    geo3 = synth.geometry_for("cfg3")
+    y3 = oracle.forward(geo3, synth.uniform_emissivity(geo3.grid, seed=3000))
+    t0 = time.perf_counter()
+    _, it = oracle.ridge_solve(geo3, y3, 1e-3, tol=0.0, maxit=5)
+    out["ridge_256_cg_s_per_iteration"] = (time.perf_counter() - t0) / max(it, 1)
+    log("oracle drivers: %s" % out)
     return out
 
 
@@ -475,20 +705,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2")
-    ap.add_argument("--nvec", type=int, default=264)
+    ap.add_argument("--nvec", type=int, default=264, help="vectors of the 128^2 block section")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-drivers", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-batch-extras", action="store_true")
+    ap.add_argument("--no-block", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-rsvd", action="store_true")
-    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixer", action="store_true")
     ap.add_argument("--no-age", action="store_true")
     ap.add_argument("--no-estimators", action="store_true")
     ap.add_argument("--no-synthesis", action="store_true")
-    ap.add_argument("--apply-variant", default="", help="pin the forward kernel variant (name) after tuning")
-    ap.add_argument("--adjoint-variant", default="", help="pin the adjoint kernel variant (name) after tuning")
+    ap.add_argument("--apply-variant", default="", help="pin the batch forward variant (name) after tuning")
+    ap.add_argument("--adjoint-variant", default="", help="pin the batch adjoint variant (name) after tuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -498,222 +728,73 @@ def main():
     import torch
     import paper_2609_05528_amd as rtt
     import synth
+    import oracle
 
     rtt.require_native()
     dev = torch.device("cuda:0")
     calib = calibrate(torch, dev)
     log("calibration: %s" % calib)
-    p = synth.config(args.workload)
-    geo = synth.geometry_for(p)
-    g = geo.grid
-    G = rtt.Geometry(geo)
-    nvec = args.nvec
-    log("workload %s: rays %s, rows %d, cols %d, nvec %d" % (args.workload, geo.rays_per_order, G.n_rows,
-                                                             G.n_cols, nvec))
-    if not args.no_tune:
-        choice = G.tune(nvec=nvec, reps=5)
-        log("autotuner choice (apply, adjoint): %s = %s" % (choice, [
-            (rtt.variant_names(False)[a], rtt.variant_names(True)[b]) for a, b in choice]))
-    if args.apply_variant or args.adjoint_variant:
-        G.set_variant(apply=rtt.variant_names(False).index(args.apply_variant) if args.apply_variant else -1,
-                      adjoint=rtt.variant_names(True).index(args.adjoint_variant) if args.adjoint_variant else -1)
-        log("variants pinned: %s / %s" % (args.apply_variant, args.adjoint_variant))
-    om = synth.gaussian_block(G.n_cols, nvec, seed=p["seed"] + 1)
-    X = torch.from_numpy(om).to(dev)
-    del om
-    Y = torch.empty((nvec, G.n_rows), dtype=torch.float32, device=dev)
-    XT = torch.empty((nvec, G.n_cols), dtype=torch.float32, device=dev)
-    torch.cuda.synchronize()
 
-    def step(evs=None):
-        if evs is not None:
-            evs[0].record()
-        rtt.op_apply(G, X, Y)
-        if evs is not None:
-            evs[1].record()
-        rtt.op_apply_adjoint(G, Y, XT)
-        if evs is not None:
-            evs[2].record()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    t_a = [e[0].elapsed_time(e[1]) for e in events]
-    t_at = [e[1].elapsed_time(e[2]) for e in events]
-    ms_a, ms_at = float(np.mean(t_a)), float(np.mean(t_at))
-    applies = 2 * nvec * args.steps
-    value = applies / wall
-    log("A %.3f ms, A^T %.3f ms per block launch; step %.3f ms" % (ms_a, ms_at, 1e3 * wall / args.steps))
-
-    nc = g.n_cells
-    b_a = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, nc, g.n_orders, nvec, False)
-    b_at = algorithmic_bytes(G.n_rows, G.n_cols, G.n_rays, nc, g.n_orders, nvec, True)
-    gbps_a = b_a / (ms_a * 1e-3) / 1e9
-    gbps_at = b_at / (ms_at * 1e-3) / 1e9
-    dom = "op_apply_adjoint" if ms_at >= ms_a else "op_apply"
-    dom_gbps = gbps_at if ms_at >= ms_a else gbps_a
-    dom_bytes = b_at if ms_at >= ms_a else b_a
-
-    variants = {"op_apply": rtt.variant_names(False)[G.members[0]["apply_variant"]],
-                "op_apply_adjoint": rtt.variant_names(True)[G.members[0]["adjoint_variant"]]}
-
-    # parity of two vectors of the block against the FP64 oracle
-    import oracle
-    par = {}
-    for b in (0, nvec - 1):
-        xb = X[b].double().cpu().numpy()
-        yr = oracle.forward(geo, xb)
-        ya = Y[b].double().cpu().numpy()
-        par.setdefault("A", []).append(float(np.linalg.norm(ya - yr) / np.linalg.norm(yr)))
-        xr = oracle.adjoint(geo, Y[b].double().cpu().numpy())
-        xa = XT[b].double().cpu().numpy()
-        par.setdefault("AT", []).append(float(np.linalg.norm(xa - xr) / np.linalg.norm(xr)))
-    parity = {"A_max_rel_err": max(par["A"]), "AT_max_rel_err": max(par["AT"]), "vectors": [0, nvec - 1],
-              "tol": 1e-5}
-
-    mixers = None if args.no_mixer else mixer_section(torch, rtt, oracle, geo, G, Y)
-    ages = None if args.no_age else age_section(torch, rtt, [geo], G)
-    estimators = None if args.no_estimators else estimator_section(torch, rtt, synth, geo, G)
-    synthesis = None if args.no_synthesis else synthesis_section(torch, rtt, G)
-
-    # plain per-instance loop on the same GPU (one vector per call)
-    plain = None
-    if not args.no_plain:
-        xs = [X[b] for b in range(nvec)]
-        ys = [Y[b] for b in range(nvec)]
-        xts = [XT[b] for b in range(nvec)]
-        for b in range(min(nvec, 8)):
-            rtt.op_apply(G, xs[b], ys[b])
-            rtt.op_apply_adjoint(G, ys[b], xts[b])
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        for b in range(nvec):
-            rtt.op_apply(G, xs[b], ys[b])
-            rtt.op_apply_adjoint(G, ys[b], xts[b])
-        torch.cuda.synchronize()
-        plain = 2 * nvec / (time.perf_counter() - tp0)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        n_s = nvec
-        xs = X[:n_s].double().cpu().numpy()
-        tc0 = time.perf_counter()
-        yo = oracle.forward(geo, xs)
-        oracle.adjoint(geo, yo)
-        tc = time.perf_counter() - tc0
-        cpu = {"value": 2 * n_s / tc, "unit": "applies/s", "cores": 1, "kind": "oracle",
-               "sample": "one full step: %d A + %d A^T FP64 applies (plain C, single thread), %.1f s"
-                         % (n_s, n_s, tc)}
-
-    # the large single geometry (512^2 x 512 frames, orders 0-2): one vector per launch
-    large = None
-    if not args.no_large:
-        del X, Y, XT
-        torch.cuda.empty_cache()
-        geo5 = synth.geometry_for("cfg5")
-        G5 = rtt.Geometry(geo5)
-        G5.tune(nvec=1, reps=3)
-        x5 = torch.from_numpy(synth.uniform_emissivity(geo5.grid, seed=5000).astype(np.float32)).to(dev)
-        y5 = torch.empty(G5.n_rows, dtype=torch.float32, device=dev)
-        xt5 = torch.empty_like(x5)
-        ta5, tat5 = time_pair(torch, rtt, G5, x5, y5, xt5, reps=20)
-        g5 = geo5.grid
-        b5 = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, False)
-        b5t = algorithmic_bytes(G5.n_rows, G5.n_cols, G5.n_rays, g5.n_cells, g5.n_orders, 1, True)
-        v1 = (rtt.variant_names(False)[G5.members[0]["apply_variant"]],
-              rtt.variant_names(True)[G5.members[0]["adjoint_variant"]])
-        # block Lanczos on the large geometry (512 right vectors: 16 steps of 32), wall time, with
-        # the kernel variants tuned for its 32-vector blocks
-        G5.tune(nvec=32, reps=3)
-        torch.cuda.synchronize()
-        t0l = time.perf_counter()
-        svl = rtt.rsvd(G5, method="lanczos", k=64, block=32, steps=16, seed=5001)
-        torch.cuda.synchronize()
-        t_lz = time.perf_counter() - t0l
-        lz = {"seconds": t_lz, "block": 32, "steps": 16, "theta_1": float(svl.sigma[0]),
-              "residual_1": float(svl.residual[0]),
-              "variants": [rtt.variant_names(False)[G5.members[0]["apply_variant"]],
-                           rtt.variant_names(True)[G5.members[0]["adjoint_variant"]]]}
-        del svl
-        log("lanczos (512 vectors, large geometry): %.2f s" % t_lz)
-        large = {"workload": "cfg5: " + synth.config("cfg5")["label"] + ", one vector per launch",
-                 "block_lanczos_512": lz,
-                 "op_apply": {"ms": ta5, "GBps": b5 / (ta5 * 1e-3) / 1e9,
-                              "frac": b5 / (ta5 * 1e-3) / 1e9 / HBM_PEAK_GBPS, "variant": v1[0]},
-                 "op_apply_adjoint": {"ms": tat5, "GBps": b5t / (tat5 * 1e-3) / 1e9,
-                                      "frac": b5t / (tat5 * 1e-3) / 1e9 / HBM_PEAK_GBPS, "variant": v1[1]},
-                 "applies_per_s": 2.0 / ((ta5 + tat5) * 1e-3)}
-        log("large geometry: A %.3f ms (%.0f GB/s), A^T %.3f ms (%.0f GB/s)" % (
-            ta5, large["op_apply"]["GBps"], tat5, large["op_apply_adjoint"]["GBps"]))
-        del G5, x5, y5, xt5
-        torch.cuda.empty_cache()
-
-    # randomized SVD of the benchmark geometry (k = 256, p = 8, q = 2), wall time
-    rs = None
-    if not args.no_rsvd:
-        torch.cuda.synchronize()
-        t0r = time.perf_counter()
-        sv = rtt.rsvd(G, k=p.get("rsvd_k", 256), p=p.get("rsvd_p", 8), q=p.get("rsvd_q", 2), seed=2001)
-        torch.cuda.synchronize()
-        t_rs = time.perf_counter() - t0r
-        # (q + 1) block applies of A and of A^T on l = k + p vectors; the rest is the dense part
-        # (MFMA Gram / combine, FP64 small factorisations on the host)
-        t_app = (p.get("rsvd_q", 2) + 1) * (ms_a + ms_at) * 1e-3
-        rs = {"seconds": t_rs, "k": sv.k, "sigma_1": float(sv.sigma[0]),
-              "sigma_k": float(sv.sigma[-1]), "block_applies": 6 * (p.get("rsvd_k", 256) + p.get("rsvd_p", 8)),
-              "apply_seconds_est": t_app, "dense_seconds_est": t_rs - t_app}
-        log("rsvd: %.2f s, sigma_1 %.4g sigma_k %.4g" % (rs["seconds"], rs["sigma_1"], rs["sigma_k"]))
-        del sv
-
-    n_rows, n_cols = G.n_rows, G.n_cols
-    batch = None
-    if not args.no_batch:
-        del G
-        torch.cuda.empty_cache()
-        batch = batch_section(torch, rtt, synth, oracle, dev)
-
+    hb = batch_headline(torch, rtt, synth, dev, args.steps, args.warmup, args.apply_variant, args.adjoint_variant)
+    G, nh = hb["G"], hb["nh"]
+    n_cells = hb["geos"][0].grid.n_cells
+    ms_a, ms_at = float(np.mean(hb["t_a"])), float(np.mean(hb["t_at"]))
+    b_a = batch_algorithmic_bytes(G, nh, False, n_cells)
+    b_at = batch_algorithmic_bytes(G, nh, True, n_cells)
+    gbps_a, gbps_at = b_a / (ms_a * 1e-3) / 1e9, b_at / (ms_at * 1e-3) / 1e9
+    dom = "op_apply_shared" if ms_a >= ms_at else "op_apply_adjoint"
+    dom_ms, dom_bytes, dom_gbps = (ms_a, b_a, gbps_a) if ms_a >= ms_at else (ms_at, b_at, gbps_at)
+    modes = list(hb["modes"])
+    launches = {"op_apply_shared": 1 if modes[0] else len(G.members),
+                "op_apply_adjoint": 1 if modes[1] else len(G.members)}
     digest = source_digest()
+    variants = {"op_apply_shared": sorted({v[0] for v in hb["variants"]}),
+                "op_apply_adjoint": sorted({v[1] for v in hb["variants"]})}
     traffic = None
     for meas in MEASURED_TRAFFIC.get(dom, []):
-        if meas["digest"] == digest and meas["nvec"] == nvec and meas["variant"] == variants[dom]:
+        if (meas["digest"] == digest and meas.get("workload") == "batch" and meas["variant"] == variants[dom]
+                and meas.get("modes") == modes):
             traffic = meas["bytes"]
+    wall, steps, pairs = hb["wall"], args.steps, hb["pairs"]
+    value = 2 * pairs * steps / wall
+    rows, cols_member, rays = G.n_rows, G.members[0]["n_cols"], G.n_rays
+    kernels = {name: {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9, "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                      "bytes": b, "launches_per_call": launches[name], "variants": variants[name],
+                      "ms_p10_median_p90": [float(np.percentile(t, q)) for q in (10, 50, 90)],
+                      "frac_of_copy": b / (ms * 1e-3) / 1e9 / calib["copy_gbps"]}
+               for name, ms, b, t in (("op_apply_shared", ms_a, b_a, hb["t_a"]),
+                                      ("op_apply_adjoint", ms_at, b_at, hb["t_at"]))}
+
+    extras = None if args.no_batch_extras else batch_extras(torch, rtt, synth, oracle, dev, hb, no_age=args.no_age)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_section(oracle, hb)
+    del hb, G
+    torch.cuda.empty_cache()
+    block = None if args.no_block else block_section(torch, rtt, synth, oracle, dev, args)
+    large = None if args.no_large else large_section(torch, rtt, synth, dev)
+    drivers = None if args.no_oracle_drivers else oracle_driver_section(oracle, synth)
 
     out = {
-        "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%s: %s; block of %d vectors (rSVD l=k+p); step = A + A^T on the block"
-                               % (args.workload, p["label"], nvec),
-                   "rays_per_order": geo.rays_per_order, "rows": n_rows, "cols": n_cols, "nvec": nvec},
+        "config": {"workload": "batch: 12 geometries (spins 0/0.3/0.6/0.94 x incl 20/50/75 deg, orders 0-2, "
+                               "96^2-256^2 screens, 64-160 frames at 4M) x 60 Gaussian-blob histories on one shared "
+                               "64x64-cell x 96-hat basis; step = A over all 720 (geometry, history) pairs "
+                               "(each history block read once) + A^T over all 720 pairs",
+                   "geometries": 12, "histories": nh, "rows": rows, "cols_per_geometry": cols_member,
+                   "rays": rays, "launch_modes": modes},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": dom_gbps / HBM_PEAK_GBPS, "traffic": traffic, "bytes_per_launch": dom_bytes,
-                     "kernel_source_digest": digest},
-        "kernels": {"op_apply": {"ms": ms_a, "GBps": gbps_a, "bytes": b_a,
-                                 "ms_p10_median_p90": [float(np.percentile(t_a, q)) for q in (10, 50, 90)],
-                                 "frac_of_copy": gbps_a / calib["copy_gbps"]},
-                    "op_apply_adjoint": {"ms": ms_at, "GBps": gbps_at, "bytes": b_at,
-                                         "ms_p10_median_p90": [float(np.percentile(t_at, q)) for q in (10, 50, 90)],
-                                         "frac_of_copy": gbps_at / calib["copy_gbps"]}},
+                     "launches_per_call": launches[dom], "ms_per_call": dom_ms, "kernel_source_digest": digest},
+        "kernels": kernels,
         "hbm_gbps": (b_a + b_at) / ((ms_a + ms_at) * 1e-3) / 1e9,
-        "variants": variants,
-        "plain_value": plain,
+        "plain_value": None if extras is None else extras["plain_applies_per_s"],
+        "parity": None if extras is None else extras["parity"],
+        "batch": extras,
         "calibration": calib,
+        "block_128": block,
         "large_single_vector": large,
-        "rsvd": rs,
-        "batch": batch,
-        "mixers": mixers,
-        "age_information": ages,
-        "estimators": estimators,
-        "synthesis": synthesis,
-        "parity": parity,
+        "oracle_drivers": drivers,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

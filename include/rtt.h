@@ -171,6 +171,22 @@ int op_apply(const rtt_geometry* geom, const float* x, float* y, int32_t nvec,
              uint32_t order_mask, void* stream);
 
 /*
+ * op_apply_shared -- y = A x for a handle whose G geometries share one source
+ * grid (equal n_r, n_phi, n_hat, r_in, r_out, s0, dt_src): every geometry
+ * images the same coefficient vector, as when one source history is seen
+ * through several spin/inclination geometries.  x: device [nvec][n_cols / G]
+ * (one member's columns); y: device [nvec][n_rows] (every member's rows).
+ * The result is op_apply applied to x repeated in every member's column block,
+ * bit for bit, but each coefficient block is read once per vector instead of
+ * once per geometry.  Its transpose with respect to x is the sum over members
+ * of the column blocks op_apply_adjoint returns.  Rows of orders outside
+ * order_mask are neither written nor read.  Errors: RTT_EINVAL when the
+ * members' source grids differ, as op_apply otherwise.
+ */
+int op_apply_shared(const rtt_geometry* geom, const float* x, float* y, int32_t nvec,
+                    uint32_t order_mask, void* stream);
+
+/*
  * op_apply_adjoint -- x = A^T y, the exact transpose of op_apply (the
  * transposed action whose consistency Sec. 5 validates), computed
  * owner-by-owner without atomics; x is overwritten.  Bitwise reproducible

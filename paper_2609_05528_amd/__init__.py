@@ -23,7 +23,7 @@ RTT_SOLVE_NORMAL_RHS = 2
 RTT_EACH_GEOMETRY = -2
 
 EXPORTED = ("geometry_load", "geometry_free", "geometry_info", "geometry_member", "geometry_set_variant",
-            "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
+            "geometry_set_batch_mode", "variant_name", "geometry_tune", "op_apply", "op_apply_shared", "op_apply_adjoint", "rsvd", "svd_free", "svd_get",
             "svd_converged", "tsvd_solve", "ridge_solve", "mixer_create", "mixer_free", "mixer_info", "mixer_member", "mixer_set_variant",
             "mix_apply", "mix_apply_noalloc", "mix_adjoint", "mix_covariance", "reference_response", "age_information", "age_window",
             "age_reach", "age_window_error", "tsvd_project", "noise_add", "synthesis_create", "synthesis_free",
@@ -120,6 +120,7 @@ def require_native():
         "geometry_set_batch_mode": [vp, i32, i32],
         "geometry_tune": [vp, i32, i32, ctypes.c_char_p, vp],
         "op_apply": [vp, vp, vp, i32, u32, vp],
+        "op_apply_shared": [vp, vp, vp, i32, u32, vp],
         "op_apply_adjoint": [vp, vp, vp, i32, u32, vp],
         "rsvd": [vp, ctypes.POINTER(rtt_svd_opts), vp, ctypes.POINTER(vp), vp],
         "svd_free": [vp],
@@ -326,6 +327,21 @@ def op_apply(geom: Geometry, x, y=None, order_mask: int = 0, stream=None):
         y = alloc(x.shape[:-1] + (geom.n_rows,), dtype=torch.float32, device=x.device)
     _check(require_native().op_apply(geom.handle, _dev_ptr(x, nvec * geom.n_cols, "x"),
                                      _dev_ptr(y, nvec * geom.n_rows, "y"), nvec, order_mask, _stream(stream)))
+    return y
+
+
+def op_apply_shared(geom: Geometry, x, y=None, order_mask: int = 0, stream=None):
+    """y = A x with one coefficient block shared by every geometry of the handle (see
+    include/rtt.h).  x: [..., n_cols / n_geometries]; returns y [..., n_rows]."""
+    import torch
+    ncg = geom.members[0]["n_cols"]
+    nvec = _nvec(x, ncg)
+    if y is None:
+        alloc = torch.zeros if order_mask else torch.empty
+        y = alloc(x.shape[:-1] + (geom.n_rows,), dtype=torch.float32, device=x.device)
+    _check(require_native().op_apply_shared(geom.handle, _dev_ptr(x, nvec * ncg, "x"),
+                                            _dev_ptr(y, nvec * geom.n_rows, "y"), nvec, order_mask,
+                                            _stream(stream)))
     return y
 
 

@@ -2870,7 +2870,7 @@ static void reg_multi_dispatch(RegMulti& a, int lpr, bool vec4, bool persist, hi
 
 // Register forward of members [b, e) in one launch (all members on reg1 or all on reg2).
 static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
-                            hipStream_t s, bool persist, int* rc)
+                            hipStream_t s, bool persist, bool shared, int* rc)
 {
     const Member& m0 = g->members[b];
     const int v0 = m0.apply_variant;
@@ -2904,7 +2904,7 @@ static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x,
         RegMember& d = a.m[i - b];
         d.rec = g->d_fwd + m.ray_begin;
         d.n_rays = m.n_rays;
-        d.x_off = m.col_offset;
+        d.x_off = shared ? 0 : m.col_offset;
         d.y_off = m.row_offset;
         d.K = m.grid.n_hat;
         d.F = m.grid.n_frames;
@@ -2921,7 +2921,7 @@ static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x,
     a.total = (uint32_t)(nb * nvec);
     a.x = x;
     a.y = y;
-    a.x_stride = g->n_cols;
+    a.x_stride = shared ? m0.n_cols : g->n_cols;
     a.y_stride = g->n_rows;
     *rc = RTT_OK;
     if (a.total == 0) return true;
@@ -2938,10 +2938,11 @@ static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x,
 }
 
 static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
-                        hipStream_t s, bool persist, int* rc)
+                        hipStream_t s, bool persist, bool shared, int* rc)
 {
     const Member& m0 = g->members[b];
-    if (m0.apply_variant == 6 || m0.apply_variant == 7) return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, rc);
+    if (m0.apply_variant == 6 || m0.apply_variant == 7)
+        return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, shared, rc);
     // wide output stores (8-byte aligned rows at Q = 1, 16-byte at Q = 2), decided per member
     const int wa = m0.Q == 1 ? 2 : 4;
     const bool vec4 = (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (g->n_rows % wa) == 0);
@@ -2965,7 +2966,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
         d.rec = g->d_fwd + m.ray_begin;
         d.n_rays = m.n_rays;
         d.blk_begin = (uint32_t)nb;
-        d.x_off = m.col_offset;
+        d.x_off = shared ? 0 : m.col_offset;
         d.y_off = m.row_offset;
         d.K = m.grid.n_hat;
         d.F = m.grid.n_frames;
@@ -2984,7 +2985,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     a.total = (uint32_t)(nb * nvec);
     a.x = x;
     a.y = y;
-    a.x_stride = g->n_cols;
+    a.x_stride = shared ? m0.n_cols : g->n_cols;
     a.y_stride = g->n_rows;
     *rc = RTT_OK;
     if (a.total == 0) return true;
@@ -3284,8 +3285,10 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
 namespace rtt {
 
 int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, float* out, int nvec,
-             uint32_t mask, hipStream_t s)
+             uint32_t mask, hipStream_t s, bool shared_x)
 {
+    // shared_x (forward only): every member reads its columns from the one block `in`
+    // ([nvec][member columns]) instead of its own block of a [nvec][n_cols] vector
     if (member >= 0) {
         const Member& m = g->members[member];
         const uint32_t em = effective_mask(m, mask);
@@ -3300,7 +3303,7 @@ int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, f
         if (G > 1 && mode != 0) {
             int rc = RTT_OK;
             const bool done = adjoint ? adjoint_multi(g, b, e, in, out, nvec, mask, s, mode == 2, &rc)
-                                      : apply_multi(g, b, e, in, out, nvec, mask, s, mode == 2, &rc);
+                                      : apply_multi(g, b, e, in, out, nvec, mask, s, mode == 2, shared_x, &rc);
             if (rc) return rc;
             if (done) continue;
         }
@@ -3309,8 +3312,8 @@ int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, f
             const uint32_t em = effective_mask(m, mask);
             int rc = adjoint ? launch_adjoint(g, m, in + m.row_offset, out + m.col_offset, nvec, g->n_rows,
                                               g->n_cols, em, s, -1)
-                             : launch_apply(g, m, in + m.col_offset, out + m.row_offset, nvec, g->n_cols,
-                                            g->n_rows, em, s, -1);
+                             : launch_apply(g, m, in + (shared_x ? 0 : m.col_offset), out + m.row_offset, nvec,
+                                            shared_x ? m.n_cols : g->n_cols, g->n_rows, em, s, -1);
             if (rc) return rc;
         }
     }
@@ -3337,6 +3340,21 @@ extern "C" int op_apply(const rtt_geometry* g, const float* x, float* y, int32_t
     int rc = check_call(g, x, y, nvec);
     if (rc) return rc;
     return apply_op(g, -1, false, x, y, nvec, order_mask, (hipStream_t)stream);
+}
+
+extern "C" int op_apply_shared(const rtt_geometry* g, const float* x, float* y, int32_t nvec, uint32_t order_mask,
+                               void* stream)
+{
+    int rc = check_call(g, x, y, nvec);
+    if (rc) return rc;
+    const rtt_grid& g0 = g->members[0].grid;
+    for (const Member& m : g->members) {
+        const rtt_grid& q = m.grid;
+        if (q.n_r != g0.n_r || q.n_phi != g0.n_phi || q.n_hat != g0.n_hat || q.r_in != g0.r_in ||
+            q.r_out != g0.r_out || q.s0 != g0.s0 || q.dt_src != g0.dt_src)
+            return fail(RTT_EINVAL, "op_apply_shared: the geometries do not share one source grid");
+    }
+    return apply_op(g, -1, false, x, y, nvec, order_mask, (hipStream_t)stream, true);
 }
 
 extern "C" int op_apply_adjoint(const rtt_geometry* g, const float* y, float* x, int32_t nvec,

@@ -158,7 +158,7 @@ uint32_t effective_mask(const Member& m, uint32_t mask);
 // n_cols / n_rows of that member) or, with member = -1, on the whole
 // block-diagonal operator (full-length vectors).
 int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, float* out, int nvec,
-             uint32_t mask, hipStream_t s);
+             uint32_t mask, hipStream_t s, bool shared_x = false);
 
 // order mixers (mixer.hip) ---------------------------------------------------------------------
 bool mixer_ok(const rtt_mixer* m);

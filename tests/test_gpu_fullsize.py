@@ -224,11 +224,23 @@ def test_full_batch_of_12_geometries_and_60_histories_matches_oracle(gpu_lib):
         assert_rows_match(geos[gi], Y[hi, rs].cpu().numpy(), yr, ("A", gi, hi))
         xr = oracle.adjoint(geos[gi], Yin[hi, rs].double().cpu().numpy())
         assert rel(XT[hi, cs].cpu().numpy(), xr) <= TOL, ("A^T", gi, hi)
+    Hd = to_dev(H)
     for mode in (0, 1, 2):
         G.set_batch_mode(apply=mode, adjoint=mode)
         assert torch.equal(rtt.op_apply(G, X), Y), ("A mode", mode)
+        # one history block shared by every geometry: the same bits as the replicated block
+        assert torch.equal(rtt.op_apply_shared(G, Hd), Y), ("shared A mode", mode)
         assert torch.equal(rtt.op_apply_adjoint(G, Yin), XT), ("A^T mode", mode)
     G.set_batch_mode(*modes)
+    # the transpose of the shared forward is the sum of the geometries' adjoint blocks
+    xs = sum(XT[:, m["col_offset"]:m["col_offset"] + m["n_cols"]].double() for m in G.members)
+    lhs = float((rtt.op_apply_shared(G, Hd).double() * Yin.double()).sum())
+    rhs = float((Hd.double() * xs).sum())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    # geometries on different source grids cannot share a block
+    other = tiny_geometry(seed=3, rays=(30, 6, 4))
+    with pytest.raises(rtt.RttError):
+        rtt.op_apply_shared(rtt.Geometry([geos[0], other]), Hd[:1])
 
 
 # ------------------------------------------------------------------------------ rSVD k = 256
