@@ -1523,6 +1523,7 @@ struct VisitArgs {
     int64_t y_stride, x_stride;
     uint32_t mask;
     uint32_t y_bytes, x_bytes;   // the member's data and output block of one vector (bytes)
+    int64_t ntask;               // base-row form: tasks of the launch (vtask: offsets, then descriptors)
 };
 
 // Offset past every buffer range used here (ranges stay below 2^31 - 256, so adding a scalar
@@ -1564,10 +1565,16 @@ struct Taps {
 // One block of the visit-list adjoint: task `lin` = (row group, segment, hat chunk) of one member
 // for NVW consecutive vectors (y0, x0: the first of them, already offset to the member's blocks;
 // nv of them exist).
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, int RR = 1>
+// BR = 0: the wave owns RR rows (RR * t .. RR * t + RR - 1).  BR = 1, 2 (base-row form, RR = 2, visit
+// set 3): the wave sweeps the rays of base row ci = 2 t + BR - 1 only and writes their sums into
+// rows ci and ci + 1; the launch of the even base rows (BR = 1) stores, the following launch of the
+// odd base rows (BR = 2) adds to what is there, so each row's value is (even contribution) + (odd
+// contribution) in that fixed order and the two launches never touch a row at the same time.
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, int RR = 1, int BR = 0>
 __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __restrict__ y0, float* __restrict__ x0,
                                            int nv, int64_t lin)
 {
+    static_assert(BR == 0 || RR == 2, "the base-row form writes two rows");
     static_assert(!DPP || (Q == 1 && !PAIR) || (Q == 2 && PAIR), "lane-shifted taps: Q = 1, or Q = 2 with frame pairs");
     static_assert(DPP || !HALO, "halo lanes serve the lane-shifted taps");
     typedef Taps<Q> TP_;
@@ -1587,12 +1594,25 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     // RR consecutive rows ci .. ci + RR - 1 whose visits carry weights for each of them
     static_assert(RR == 1 || RR == 2, "rows per wave: 1 or 2");
     const int ti = rg * T_WAVES + wave;
-    if (ti >= (a.n_r + RR - 1) / RR) return;
-    const int ci = RR * ti;
-    const int64_t task = (int64_t)ti * a.nseg + sg;
+    int ci, jlo, jhi;
+    int64_t task;
+    if constexpr (BR == 0) {
+        if (ti >= (a.n_r + RR - 1) / RR) return;
+        ci = RR * ti;
+        task = (int64_t)ti * a.nseg + sg;
+        jlo = sg * a.vseg;
+        jhi = min(jlo + a.vseg, a.n_phi);
+    } else {
+        // a task of the launch's list (nseg = 1): its base row and columns from its descriptor
+        task = ti;
+        if (task >= a.ntask) return;
+        const int64_t d = ((ci64p)a.vtask)[a.ntask + 1 + task];
+        const int cell = (int)(d & 0xFFFFFFFF);
+        ci = cell / a.n_phi;
+        jlo = cell - ci * a.n_phi;
+        jhi = jlo + (int)(d >> 32);
+    }
     const int64_t vbeg = ((ci64p)a.vtask)[task], vend = ((ci64p)a.vtask)[task + 1];
-    const int jlo = sg * a.vseg;
-    const int jhi = min(jlo + a.vseg, a.n_phi);
     const int ncol = jhi - jlo + 1;
     const int kc = kch * C;              // first output hat of this wave's chunk
     const unsigned rowbytes = (unsigned)a.F * 4u;
@@ -1646,9 +1666,14 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
                     if (r > 0 && ci + r >= a.n_r) break;
                     const int xr = xo + r * a.n_phi * a.K * 4;
 #pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, acc_a[r][u][v]), rx,
-                                                              (int)st_off[v], sox[u] + xr, 0);
+                    for (int v = 0; v < V; ++v) {
+                        float val = acc_a[r][u][v];
+                        if constexpr (BR == 2)
+                            val = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                                rx, (int)st_off[v], sox[u] + xr, 0)) + val;
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, val), rx, (int)st_off[v],
+                                                              sox[u] + xr, 0);
+                    }
                 }
             }
         }
@@ -1856,14 +1881,23 @@ __device__ __forceinline__ void visit_body(const VisitArgs& a, const float* __re
     while (col < ncol) emit();
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, int RR>
+// rows (or row pairs, or base rows of one parity) a launch of the visit kernel covers
+// wave tasks of one (segment, hat chunk) in a launch of the visit kernel: rows, row pairs, or the
+// base-row form's task list
+template <int RR, int BR>
+__host__ __device__ __forceinline__ int64_t visit_rows(const VisitArgs& a)
+{
+    return BR == 0 ? (a.n_r + RR - 1) / RR : a.ntask;
+}
+
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP, bool HALO, int RR, int BR = 0>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit(VisitArgs a)
 {
-    const int rgroups = ((a.n_r + RR - 1) / RR + T_WAVES - 1) / T_WAVES;
+    const int64_t rgroups = (visit_rows<RR, BR>(a) + T_WAVES - 1) / T_WAVES;
     const int v0 = blockIdx.y * NVW;
-    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO, RR>(a, a.y + (int64_t)v0 * a.y_stride, a.x + (int64_t)v0 * a.x_stride,
-                                                   min(NVW, a.nvec - v0),
-                                                   xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
+    visit_body<Q, V, NB, PAIR, NVW, DPP, HALO, RR, BR>(a, a.y + (int64_t)v0 * a.y_stride,
+                                                       a.x + (int64_t)v0 * a.x_stride, min(NVW, a.nvec - v0),
+                                                       xcd_remap(blockIdx.x, (int64_t)rgroups * a.nseg * a.kchunks));
 }
 
 // Every member of a handle (up to MULTI_MAX) in one launch; tasks numbered as in
@@ -2358,7 +2392,7 @@ static const AdjVariant kAdjVariants[] = {
     {"tb4x8", 2, 4, 8},      {"tb4x4", 2, 4, 4},      {"tb2x4", 2, 2, 4},      {"visit", 3, 0, 0},
     {"rows4", 4, 4, 0},      {"rows8", 4, 8, 0},      {"visit2v", 3, 2, 0},    {"visit4v", 3, 4, 0},
     {"visitd", 3, 1, 1},     {"visitd2v", 3, 2, 1},   {"visitd4v", 3, 4, 1},   {"visitp2v", 3, 2, 2},
-    {"visitp4v", 3, 4, 2},
+    {"visitp4v", 3, 4, 2},   {"visitb", 3, 1, 3},     {"visitb2v", 3, 2, 3},
 };
 constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
@@ -2750,22 +2784,58 @@ static bool visit_halo_fits(int K)
     return (K + C - 1) / C == (K + WAVE * V - 1) / (WAVE * V);
 }
 
-template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false, int RR = 1>
+template <int Q, int V, int NB, bool PAIR, int NVW, bool DPP = false, bool HALO = false, int RR = 1, int BR = 0>
 static void visit_launch(VisitArgs a, int nvec, hipStream_t s)
 {
     if constexpr (DPP && !HALO) {
         if (visit_halo_fits<Q, V>(a.K)) {
-            visit_launch<Q, V, NB, PAIR, NVW, true, true, RR>(a, nvec, s);
+            visit_launch<Q, V, NB, PAIR, NVW, true, true, RR, BR>(a, nvec, s);
             return;
         }
     }
     constexpr int C = visit_chunk<Q, V, DPP, HALO>();
     a.kchunks = (a.K + C - 1) / C;
     a.nvec = nvec;
-    const int rows = (a.n_r + RR - 1) / RR;
-    const int64_t blocks = (int64_t)((rows + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
-    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO, RR>),
+    const int64_t rows = visit_rows<RR, BR>(a);
+    if (rows <= 0) return;
+    const int64_t blocks = ((rows + T_WAVES - 1) / T_WAVES) * a.nseg * a.kchunks;
+    hipLaunchKernelGGL((k_adjoint_visit<Q, V, NB, PAIR, NVW, DPP, HALO, RR, BR>),
                        dim3((unsigned)blocks, (unsigned)((nvec + NVW - 1) / NVW)), dim3(T_WAVES * WAVE), 0, s, a);
+}
+
+// Base-row form (visit set 3, lane-shifted taps): the tasks of the even base rows store, then
+// those of the odd base rows add (two launches on one stream).  vpw vectors per wave; one hat slot
+// per lane unless the launch has enough waves without splitting the hats.
+template <int Q, int V, int NB, int NVW>
+static void visitb_pass(VisitArgs a, const int64_t* vtask0, int64_t ntask0, const int64_t* vtask1, int64_t ntask1,
+                        int nvec, hipStream_t s)
+{
+    constexpr bool P = Q == 2;
+    a.nseg = 1;
+    a.vtask = vtask0;
+    a.ntask = ntask0;
+    visit_launch<Q, V, NB, P, NVW, true, false, 2, 1>(a, nvec, s);
+    a.vtask = vtask1;
+    a.ntask = ntask1;
+    visit_launch<Q, V, NB, P, NVW, true, false, 2, 2>(a, nvec, s);
+}
+
+template <int Q>
+static void visitb_dispatch(const VisitArgs& a, const int64_t* vtask0, int64_t ntask0, const int64_t* vtask1,
+                            int64_t ntask1, int nvec, int vpw, hipStream_t s)
+{
+    const int64_t waves = ntask0 * ((nvec + vpw - 1) / vpw);
+#define RTT_VISITB(V_, NB_, NVW_) visitb_pass<Q, V_, NB_, NVW_>(a, vtask0, ntask0, vtask1, ntask1, nvec, s)
+    if (vpw == 2) {
+        if (a.K <= 64 || waves < 16384) RTT_VISITB(1, 4, 2);
+        else if (a.K <= 128) RTT_VISITB(2, 4, 2);
+        else RTT_VISITB(4, 2, 2);
+        return;
+    }
+    if (a.K <= 64 || waves < 16384) RTT_VISITB(1, 4, 1);
+    else if (a.K <= 128) RTT_VISITB(2, 4, 1);
+    else RTT_VISITB(4, 2, 1);
+#undef RTT_VISITB
 }
 
 // lane-shifted taps (Q = 1, or Q = 2 with frame pairs); vpw vectors per wave
@@ -3218,6 +3288,35 @@ int launch_adjoint(const rtt_geometry* g, const Member& m, const float* y, float
         return RTT_OK;
     }
     if ((variant == 11 || variant >= 14) && !visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, 1)) variant = 2;
+    // base rows (visit set 3): frame pairs at Q = 2; else the single-row lane-shifted form
+    if (variant == 21 || variant == 22) {
+        const bool fpair = m.Q == 1 || ((m.grid.n_frames % 2) == 0 && (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (y_stride % 2) == 0));
+        int vpw = std::min(variant == 22 ? 2 : 1, nvec);
+        if (!visit_fits(m.n_rows, m.n_cols, y_stride, x_stride, vpw)) vpw = 1;
+        if (fpair) {
+            VisitArgs va;
+            va.visits = g->d_visits + m.visit_begin[3];
+            va.n_r = m.grid.n_r;
+            va.n_phi = m.grid.n_phi;
+            va.K = m.grid.n_hat;
+            va.F = m.grid.n_frames;
+            va.vseg = VISIT_SEG_MAX;
+            va.y = y;
+            va.x = x;
+            va.y_stride = y_stride;
+            va.x_stride = x_stride;
+            va.mask = mask;
+            va.y_bytes = (uint32_t)(m.n_rows * 4);
+            va.x_bytes = (uint32_t)(m.n_cols * 4);
+            const int64_t* t0 = g->d_vtask + m.br_task_begin[0];
+            const int64_t* t1 = g->d_vtask + m.br_task_begin[1];
+            if (m.Q == 1) visitb_dispatch<1>(va, t0, m.br_ntask[0], t1, m.br_ntask[1], nvec, vpw, s);
+            else visitb_dispatch<2>(va, t0, m.br_ntask[0], t1, m.br_ntask[1], nvec, vpw, s);
+            RTT_HIP(hipGetLastError());
+            return RTT_OK;
+        }
+        variant = nvec >= 2 ? 17 : 16;
+    }
     // row pairs: frame pairs at Q = 2, and enough (pair, segment, vector group) tasks to fill the
     // chip once; else the single-row form, which narrows its segments for small launches
     if (variant == 19 || variant == 20) {

@@ -83,11 +83,16 @@ struct Member {
     uint64_t digest;       // FNV-1a of the grid and this member's device records
     // visit-list sets: [0] single rows, 16-column segments (many vectors per call); [1] single
     // rows, narrower segments chosen so one vector alone gives enough (row, segment) tasks;
-    // [2] row pairs (VisitHead + weights, 16-column segments, ceil(n_r / 2) * nseg tasks)
-    int64_t visit_begin[3];  // first visit record of each set
+    // [2] row pairs (VisitHead + weights, 16-column segments, ceil(n_r / 2) * nseg tasks);
+    // [3] base rows (VisitHead + weights into the base row and the next one; the rays of one base
+    // row only, in tasks of a few columns cut to about equal visit counts, one task list per
+    // parity of the base row: br_ntask[p] + 1 visit offsets, then br_ntask[p] descriptors
+    // (base row * n_phi + first column) | columns << 32, from d_vtask + br_task_begin[p])
+    int64_t visit_begin[4];  // first visit record of each set
     int64_t vtask_begin[3];  // first entry of each set's task offsets (rows or pairs * nseg + 1 entries)
     int32_t nseg[3];         // sweep segments per cell row
     int32_t vseg[3];         // columns per sweep segment
+    int64_t br_task_begin[2], br_ntask[2];
     int32_t k0_min, k0_max;  // range of the hat origins k0 of the member's rays
     // per order: smallest and largest delay of the rays with non-zero weight (+inf / -inf if none)
     double delay_min[8], delay_max[8];

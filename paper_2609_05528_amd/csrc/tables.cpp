@@ -311,6 +311,67 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
             }
             vtask.push_back((int64_t)visits.size() - m.visit_begin[2]);
         }
+        // set 3: the rays of one base row ib only, swept in column order, each record carrying its
+        // weights into row ib (1 - fr) and row ib + 1 (fr).  A task covers columns [jlo, jhi) of a
+        // base row and reads the rays of base columns jlo - 1 .. jhi - 1 (the first one feeds column
+        // jlo only); columns are added to a task while its visits stay within BR_VISITS (and at most
+        // VISIT_SEG_MAX columns), so tasks carry about equal work.  Every column of every row
+        // belongs to one task (rows without rays too: their tasks write zeros).
+        {
+            constexpr int64_t BR_VISITS = 40;
+            m.visit_begin[3] = (int64_t)visits.size();
+            auto rays_at = [&](int ib, int u) -> int64_t {
+                if (ib > g.n_r - 2) return 0;   // no ray has its base cell in the last row
+                const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
+                const int64_t cell = (int64_t)ib * g.n_phi + ub;
+                return cs[cell + 1] - cs[cell];
+            };
+            for (int par = 0; par < 2; ++par) {
+                std::vector<int64_t> offs, desc;
+                for (int ib = par; ib < g.n_r; ib += 2) {
+                    int jlo = 0;
+                    while (jlo < g.n_phi) {
+                        int64_t nv = rays_at(ib, jlo - 1) + rays_at(ib, jlo);
+                        int jhi = jlo + 1;
+                        while (jhi < g.n_phi && jhi - jlo < VISIT_SEG_MAX && nv + rays_at(ib, jhi) <= BR_VISITS) {
+                            nv += rays_at(ib, jhi);
+                            ++jhi;
+                        }
+                        offs.push_back((int64_t)visits.size() - m.visit_begin[3]);
+                        desc.push_back(((int64_t)ib * g.n_phi + jlo) | ((int64_t)(jhi - jlo) << 32));
+                        for (int c = 0; c <= jhi - jlo && ib <= g.n_r - 2; ++c) {
+                            const int u = jlo - 1 + c;
+                            const int ub = ((u % g.n_phi) + g.n_phi) % g.n_phi;
+                            const int64_t cell = (int64_t)ib * g.n_phi + ub;
+                            for (int32_t q = cs[cell]; q < cs[cell + 1]; ++q) {
+                                const RayRec& rr = gr[q];
+                                float wts[4];
+                                for (int lr = 0; lr < 2; ++lr) {
+                                    const double wr = lr == 0 ? 1.0 - (double)rr.fr : (double)rr.fr;
+                                    wts[2 * lr] = (float)((double)rr.w * wr * (1.0 - (double)rr.fphi));
+                                    wts[2 * lr + 1] = (float)((double)rr.w * wr * (double)rr.fphi);
+                                }
+                                VisitHead h;
+                                h.row = rr.row;
+                                h.k0 = rr.k0;
+                                h.th0 = rr.th0;
+                                h.col_order = c | (rr.order << 16);
+                                Visit raw;
+                                std::memcpy(&raw, &h, sizeof h);
+                                std::memcpy((char*)&raw + sizeof h, wts, sizeof wts);
+                                visits.push_back(raw);
+                            }
+                        }
+                        jlo = jhi;
+                    }
+                }
+                offs.push_back((int64_t)visits.size() - m.visit_begin[3]);
+                m.br_task_begin[par] = (int64_t)vtask.size();
+                m.br_ntask[par] = (int64_t)desc.size();
+                vtask.insert(vtask.end(), offs.begin(), offs.end());
+                vtask.insert(vtask.end(), desc.begin(), desc.end());
+            }
+        }
         for (const RayRec& rr : gr) {
             const int i = rr.cell / g.n_phi, j0 = rr.cell % g.n_phi;
             const int j1 = (j0 + 1 == g.n_phi) ? 0 : j0 + 1;
