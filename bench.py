@@ -745,8 +745,8 @@ def main():
     dom = "op_apply_shared" if ms_a >= ms_at else "op_apply_adjoint"
     dom_ms, dom_bytes, dom_gbps = (ms_a, b_a, gbps_a) if ms_a >= ms_at else (ms_at, b_at, gbps_at)
     modes = list(hb["modes"])
-    launches = {"op_apply_shared": 1 if modes[0] else len(G.members),
-                "op_apply_adjoint": 1 if modes[1] else len(G.members)}
+    la, lat = G.launches
+    launches = {"op_apply_shared": la, "op_apply_adjoint": lat}
     digest = source_digest()
     variants = {"op_apply_shared": sorted({v[0] for v in hb["variants"]}),
                 "op_apply_adjoint": sorted({v[1] for v in hb["variants"]})}

@@ -94,6 +94,8 @@ typedef struct {
     int64_t table_bytes;   /* device bytes held by the handle                  */
     int32_t batch_apply_mode;   /* launch mode of whole-operator op_apply (below)  */
     int32_t batch_adjoint_mode; /* launch mode of whole-operator op_apply_adjoint  */
+    int32_t apply_launches;     /* kernel launches of one whole-operator op_apply /  */
+    int32_t adjoint_launches;   /* op_apply_adjoint call with the current variants   */
 } rtt_geometry_info;
 
 /* Per-geometry layout inside a handle (geometry g of geometry_info). */
@@ -156,8 +158,10 @@ const char* variant_name(int32_t adjoint, int32_t v);
  * one launch (launch modes of geometry_set_batch_mode), keeps the fastest, and
  * records the choices in the text cache at cache_path (nullable; one "digest
  * nvec apply adjoint" line per member, one "multi digest nvec apply_mode
- * adjoint_mode apply_shared adjoint_shared" line per handle).  A cache hit
- * skips the timing.  Blocking; allocates scratch vectors.
+ * adjoint_mode apply_shared adjoint_shared" line per handle).  When every
+ * member images one source grid, the whole-operator forward is timed as
+ * op_apply_shared, the form a batch of histories uses.  A cache hit skips the
+ * timing.  Blocking; allocates scratch vectors.
  */
 int geometry_tune(rtt_geometry* geom, int32_t nvec, int32_t reps, const char* cache_path, void* stream);
 

@@ -65,7 +65,8 @@ class rtt_load_opts(ctypes.Structure):
 class rtt_geometry_info(ctypes.Structure):
     _fields_ = [("n_geometries", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("n_cols", ctypes.c_int64), ("n_rays", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
-                ("batch_apply_mode", ctypes.c_int32), ("batch_adjoint_mode", ctypes.c_int32)]
+                ("batch_apply_mode", ctypes.c_int32), ("batch_adjoint_mode", ctypes.c_int32),
+                ("apply_launches", ctypes.c_int32), ("adjoint_launches", ctypes.c_int32)]
 
 
 class rtt_member_info(ctypes.Structure):
@@ -261,6 +262,13 @@ class Geometry:
     def set_batch_mode(self, apply=-1, adjoint=-1):
         """Launch mode of whole-operator calls on several geometries (0, 1, 2; see include/rtt.h)."""
         _check(require_native().geometry_set_batch_mode(self.handle, apply, adjoint))
+
+    @property
+    def launches(self):
+        """Kernel launches of one whole-operator (op_apply, op_apply_adjoint) call."""
+        info = rtt_geometry_info()
+        _check(require_native().geometry_info(self.handle, ctypes.byref(info)))
+        return info.apply_launches, info.adjoint_launches
 
     @property
     def batch_mode(self):

@@ -2398,11 +2398,11 @@ constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 13; }
+int n_apply_variants() { return 14; }
 const char* apply_variant_name(int v)
 {
     static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8", "reg1", "reg2", "strip16",
-                                  "strip8", "lean4q", "abs4", "abs8"};
+                                  "strip8", "lean4q", "abs4", "abs8", "lean4r"};
     return names[v];
 }
 bool lean_supported(const Member& m)
@@ -2673,9 +2673,10 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
     }
     // quad gathers read 16-byte words: they need 16-byte aligned coefficient vectors
     if (variant == 10 && ((((uintptr_t)x) & 15) != 0 || (nvec > 1 && (x_stride % 4) != 0))) variant = 4;
-    if (variant == 4 || variant == 5 || variant == 10) {
+    // lean4r: the lean forward over the records in data-row order
+    if (variant == 4 || variant == 5 || variant == 10 || variant == 13) {
         LeanArgs la;
-        la.rec = g->d_fwd + m.ray_begin;
+        la.rec = (variant == 13 ? g->d_fwd_row : g->d_fwd) + m.ray_begin;
         la.n_rays = m.n_rays;
         la.K = m.grid.n_hat;
         la.F = m.grid.n_frames;
@@ -2692,11 +2693,11 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         const bool vec4 = (la.F % wa) == 0 && (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (y_stride % wa) == 0);
         if (m.Q == 1) {
             if (variant == 10) lean_launch<1, 4, true>(la, nvec, vec4, s);
-            else if (variant == 4) lean_launch<1, 4>(la, nvec, vec4, s);
+            else if (variant == 4 || variant == 13) lean_launch<1, 4>(la, nvec, vec4, s);
             else lean_launch<1, 8>(la, nvec, vec4, s);
         } else {
             if (variant == 10) lean_launch<2, 4, true>(la, nvec, vec4, s);
-            else if (variant == 4) lean_launch<2, 4>(la, nvec, vec4, s);
+            else if (variant == 4 || variant == 13) lean_launch<2, 4>(la, nvec, vec4, s);
             else lean_launch<2, 8>(la, nvec, vec4, s);
         }
         RTT_HIP(hipGetLastError());
@@ -2940,7 +2941,7 @@ static void reg_multi_dispatch(RegMulti& a, int lpr, bool vec4, bool persist, hi
 
 // Register forward of members [b, e) in one launch (all members on reg1 or all on reg2).
 static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
-                            hipStream_t s, bool persist, bool shared, int* rc)
+                            hipStream_t s, bool persist, bool shared, int* rc, bool probe = false)
 {
     const Member& m0 = g->members[b];
     const int v0 = m0.apply_variant;
@@ -2987,6 +2988,7 @@ static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x,
         nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
     }
     if (nb * nvec >= (1ll << 31)) return false;
+    if (probe) return true;
     a.per_vec = (uint32_t)nb;
     a.total = (uint32_t)(nb * nvec);
     a.x = x;
@@ -3007,12 +3009,13 @@ static bool apply_multi_reg(const rtt_geometry* g, int b, int e, const float* x,
     return true;
 }
 
+// probe: report whether the members would run in one launch, without launching
 static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, float* y, int nvec, uint32_t mask,
-                        hipStream_t s, bool persist, bool shared, int* rc)
+                        hipStream_t s, bool persist, bool shared, int* rc, bool probe = false)
 {
     const Member& m0 = g->members[b];
     if (m0.apply_variant == 6 || m0.apply_variant == 7)
-        return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, shared, rc);
+        return apply_multi_reg(g, b, e, x, y, nvec, mask, s, persist, shared, rc, probe);
     // wide output stores (8-byte aligned rows at Q = 1, 16-byte at Q = 2), decided per member
     const int wa = m0.Q == 1 ? 2 : 4;
     const bool vec4 = (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (g->n_rows % wa) == 0);
@@ -3023,9 +3026,11 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
             if (!apply_variant_ok(m, 11) || m.Q != m0.Q || m.apply_variant != 11) return false;
             continue;
         }
-        if (!lean_supported(m) || m.Q != m0.Q || (m.apply_variant != 4 && m.apply_variant != 5)) return false;
+        if (!lean_supported(m) || m.Q != m0.Q) return false;
+        if (m0.apply_variant == 13 ? m.apply_variant != 13 : (m.apply_variant != 4 && m.apply_variant != 5)) return false;
         all8 = all8 && m.apply_variant == 5;
     }
+    const FwdRec* recs = m0.apply_variant == 13 ? g->d_fwd_row : g->d_fwd;
     const int NB = all8 && !use_abs ? 8 : 4;
     LeanMulti a;
     a.G = e - b;
@@ -3033,7 +3038,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
         LeanMember& d = a.m[i - b];
-        d.rec = g->d_fwd + m.ray_begin;
+        d.rec = (use_abs ? g->d_fwd : recs) + m.ray_begin;
         d.n_rays = m.n_rays;
         d.blk_begin = (uint32_t)nb;
         d.x_off = shared ? 0 : m.col_offset;
@@ -3051,6 +3056,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
         nb += m.n_rays > 0 ? (int64_t)d.nrb * nch : 0;
     }
     if (nb * nvec >= (1ll << 31)) return false;
+    if (probe) return true;
     a.per_vec = (uint32_t)nb;
     a.total = (uint32_t)(nb * nvec);
     a.x = x;
@@ -3148,7 +3154,7 @@ static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, in
 
 // Adjoint of members [b, e) in one launch; false if they do not fit the visit multi kernel.
 static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, float* x, int nvec, uint32_t mask,
-                          hipStream_t s, bool persist, int* rc)
+                          hipStream_t s, bool persist, int* rc, bool probe = false)
 {
     const Member& m0 = g->members[b];
     bool pair = (((uintptr_t)y) & 7) == 0 && (nvec == 1 || (g->n_rows % 2) == 0);
@@ -3173,6 +3179,7 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
         most += (int64_t)((m.grid.n_r + T_WAVES - 1) / T_WAVES) * m.nseg[set] * ((m.grid.n_hat + WAVE - 3) / (WAVE - 2));
     }
     if (most * nvec >= (1ll << 31)) return false;
+    if (probe) return true;
     VisitMulti a;
     a.G = e - b;
     for (int i = b; i < e; ++i) {
@@ -3417,6 +3424,34 @@ int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, f
         }
     }
     return RTT_OK;
+}
+
+int whole_operator_launches(const rtt_geometry* g, bool adjoint)
+{
+    const int G = (int)g->members.size();
+    const int mode = adjoint ? g->batch_adjoint_mode : g->batch_apply_mode;
+    int n = 0;
+    for (int b = 0; b < G; b += MULTI_MAX) {
+        const int e = std::min(G, b + MULTI_MAX);
+        if (G > 1 && mode != 0) {
+            int rc = RTT_OK;
+            const bool one = adjoint ? adjoint_multi(g, b, e, nullptr, nullptr, 1, 0u, nullptr, mode == 2, &rc, true)
+                                     : apply_multi(g, b, e, nullptr, nullptr, 1, 0u, nullptr, mode == 2, false, &rc, true);
+            if (one) {
+                ++n;
+                continue;
+            }
+        }
+        for (int i = b; i < e; ++i) {
+            const Member& m = g->members[i];
+            if (m.n_rays == 0) continue;
+            // the base-row adjoint makes two passes (frame pairs at Q = 2; else the single-row form)
+            const bool br = adjoint && (m.adj_variant == 21 || m.adj_variant == 22) &&
+                            (m.Q == 1 || (m.grid.n_frames % 2) == 0);
+            n += br ? 2 : 1;
+        }
+    }
+    return n;
 }
 
 }  // namespace rtt

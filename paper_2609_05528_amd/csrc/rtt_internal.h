@@ -108,6 +108,7 @@ struct rtt_geometry {
     int32_t* d_cell_start = nullptr;    // per member CSR over base cells (relative to ray_begin)
     rtt::Visit* d_visits = nullptr;     // per member visit lists (cell row x segment tasks)
     rtt::FwdRec* d_fwd = nullptr;       // forward records, same order as d_rays
+    rtt::FwdRec* d_fwd_row = nullptr;   // the same records of each member in data-row order
     int64_t* d_vtask = nullptr;         // per member task offsets into the visit lists
     int64_t* d_seg = nullptr;           // [G] (col_offset, n_cols) then [G] (row_offset, n_rows)
     // grow-only scratch of the stream-ordered (graph-capturable) solver mode, kept across calls
@@ -164,6 +165,9 @@ uint32_t effective_mask(const Member& m, uint32_t mask);
 // block-diagonal operator (full-length vectors).
 int apply_op(const rtt_geometry* g, int member, bool adjoint, const float* in, float* out, int nvec,
              uint32_t mask, hipStream_t s, bool shared_x = false);
+// kernel launches one whole-operator op_apply (or op_apply_adjoint) call makes with the current
+// variants and launch modes (for one vector)
+int whole_operator_launches(const rtt_geometry* g, bool adjoint);
 
 // order mixers (mixer.hip) ---------------------------------------------------------------------
 bool mixer_ok(const rtt_mixer* m);

@@ -104,6 +104,7 @@ static void release_tables(rtt_geometry* h)
     if (h->d_visits) hipFree(h->d_visits);
     if (h->d_vtask) hipFree(h->d_vtask);
     if (h->d_fwd) hipFree(h->d_fwd);
+    if (h->d_fwd_row) hipFree(h->d_fwd_row);
     if (h->d_seg) hipFree(h->d_seg);
     delete h->solve_ws;
     h->d_rays = nullptr;
@@ -127,7 +128,7 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     std::vector<int32_t> cstart;
     std::vector<Visit> visits;
     std::vector<int64_t> vtask;
-    std::vector<FwdRec> fwd;
+    std::vector<FwdRec> fwd, fwd_row;
     int64_t row_off = 0, col_off = 0, map_idx = 0;
     const double two_pi = 6.283185307179586476925286766559;
 
@@ -392,6 +393,14 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
             fwd.push_back(f);
             (void)i;
         }
+        // the same records in data-row order: consecutive records write adjacent rows, so the
+        // cache lines two rows share are written together
+        {
+            const size_t b0 = fwd.size() - gr.size();
+            std::vector<FwdRec> byrow(fwd.begin() + b0, fwd.end());
+            std::stable_sort(byrow.begin(), byrow.end(), [](const FwdRec& a, const FwdRec& b) { return a.row < b.row; });
+            fwd_row.insert(fwd_row.end(), byrow.begin(), byrow.end());
+        }
         m.k0_min = m.k0_max = 0;
         for (size_t r = 0; r < gr.size(); ++r) {
             m.k0_min = r ? std::min(m.k0_min, gr[r].k0) : gr[r].k0;
@@ -430,6 +439,8 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
     const size_t fb = fwd.size() * sizeof(FwdRec);
     if (e == hipSuccess) e = hipMalloc((void**)&h->d_fwd, fb);
     if (e == hipSuccess) e = hipMemcpy(h->d_fwd, fwd.data(), fb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&h->d_fwd_row, fb);
+    if (e == hipSuccess) e = hipMemcpy(h->d_fwd_row, fwd_row.data(), fb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_rays, recs.data(), rb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_cell_start, cstart.data(), cb, hipMemcpyHostToDevice);
     if (e == hipSuccess && !visits.empty())
@@ -448,7 +459,7 @@ extern "C" int geometry_load(const rtt_grid* grids, const rtt_raymap* maps, int3
         delete h;
         return rc;
     }
-    h->table_bytes = (int64_t)(rb + cb + vb + tb + fb + sb);
+    h->table_bytes = (int64_t)(rb + cb + vb + tb + 2 * fb + sb);
     *out = h;
     return RTT_OK;
 }
@@ -473,6 +484,8 @@ extern "C" int geometry_info(const rtt_geometry* g, rtt_geometry_info* info)
     info->table_bytes = g->table_bytes;
     info->batch_apply_mode = g->batch_apply_mode;
     info->batch_adjoint_mode = g->batch_adjoint_mode;
+    info->apply_launches = whole_operator_launches(g, false);
+    info->adjoint_launches = whole_operator_launches(g, true);
     return RTT_OK;
 }
 

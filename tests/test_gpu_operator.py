@@ -323,7 +323,7 @@ BATCH_CASES = {
 
 
 @pytest.mark.parametrize("fwd,adj", [("lean4", "visit"), ("reg1", "visitd"), ("reg2", "visit"), ("strip16", "visitd"),
-                                     ("lean8", "visitp2v"), ("abs4", "visitp4v")])
+                                     ("lean8", "visitp2v"), ("abs4", "visitp4v"), ("lean4r", "visitb2v")])
 @pytest.mark.parametrize("name", list(BATCH_CASES))
 def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd, adj):
     """One launch for all geometries (plain and persistent) equals one launch per geometry."""
@@ -338,9 +338,16 @@ def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd,
     X = rng.random((3, G.n_cols)).astype(np.float32)
     Y = rng.standard_normal((3, G.n_rows)).astype(np.float32)
     outs = {}
+    groups = -(-len(geos) // 16)
     for mode in (0, 1, 2):
         G.set_batch_mode(apply=mode, adjoint=mode)
         assert G.batch_mode == (mode, mode)
+        # kernel launches of one call: one per group of 16 members in one-launch modes when the
+        # variant has a one-launch form, else one per member (two for the base-row adjoint)
+        one_f = mode and fwd in ("lean4", "lean8", "reg1", "reg2", "abs4", "lean4r")
+        one_a = mode and adj in ("visit", "visitd", "visitp2v")
+        per_a = 2 if adj.startswith("visitb") else 1
+        assert G.launches == (groups if one_f else len(geos), groups if one_a else per_a * len(geos)), (mode, G.launches)
         outs[mode] = (rtt.op_apply(G, to_dev(X)).cpu().numpy(), rtt.op_apply_adjoint(G, to_dev(Y)).cpu().numpy())
     for mode in (1, 2):
         assert np.array_equal(outs[mode][0], outs[0][0]), mode
