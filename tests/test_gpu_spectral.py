@@ -274,9 +274,11 @@ def test_autograd_gradient_matches_oracle_and_fd(gpu_lib):
     g = xd.grad.double().cpu().numpy()
     go = oracle.ridge_gradient(geo, x0.astype(np.float64), y32.astype(np.float64), lam)
     assert rel(g, go) <= 1e-5
-    # central differences of the FP64-accumulated loss on 64 coordinates
+    # central differences of the FP64-accumulated loss on 64 coordinates; the loss is quadratic in
+    # x, so the central difference has no truncation error and a wide step leaves only the FP32
+    # rounding of A's output, divided by 2h
     idx = rng.choice(geo.grid.n_cols, 64, replace=False)
-    h = 1e-3
+    h = 0.25
 
     def loss64(v):
         r = rtt.op_apply(G, v).double() - torch.from_numpy(y32.astype(np.float64)).cuda()
@@ -291,7 +293,7 @@ def test_autograd_gradient_matches_oracle_and_fd(gpu_lib):
         step = float(xp[i].double() - xm[i].double())
         fd = (loss64(xp) - loss64(xm)) / step
         errs.append(abs(fd - g[i]) / max(abs(g[i]), 1e-3 * np.abs(g).max()))
-    assert np.median(errs) <= 1e-3 and max(errs) <= 1e-2
+    assert np.median(errs) <= 1e-4 and max(errs) <= 1e-3, (np.median(errs), max(errs))
 
 
 def test_double_backward_is_linear(gpu_lib):

@@ -1,8 +1,8 @@
 """Representation synthesis Q_d (Sec. 3.2, Sec. 7) and the rank audit of A Q_d on the GPU against the
 FP64 oracle: the rows of Q, the synthesis and its transpose, exactly zero columns and singular
-values on a small geometry (DCT-II and compact temporal classes; singular values >= 1e-2 sigma_1 to
-1e-4, the accuracy FP32 responses allow), and the S_224 audit of the 128^2 x 128-frame Kerr workload
-(zero columns exactly, leading singular values to 1e-4).
+values on a small geometry (DCT-II and compact temporal classes; singular values >= 1e-3 sigma_1 to
+1e-4), and the S_224 audit of the 128^2 x 128-frame Kerr workload (zero columns exactly, singular
+values >= 1e-3 sigma_1 to 1e-4).
 """
 import sys
 
@@ -54,15 +54,16 @@ def test_synthesis_rows_expand_and_project_match_oracle(gpu_lib, temporal, n_rad
         want = oracle.synthesis_audit(geo, Q, order_mask=None if mask == 0 else mask)
         assert got["zero_columns"] == want["zero_columns"], (mask, len(got["zero_columns"]), len(want["zero_columns"]))
         s_w = want["sigma"]
-        keep = s_w >= 1e-2 * s_w[0]          # FP32 responses: sigma_i good to ~1e-7 sigma_1 / sigma_i
-        assert np.max(np.abs(got["sigma"][:keep.sum()] - s_w[keep]) / s_w[keep]) < 1e-4
+        keep = s_w >= 1e-3 * s_w[0]          # FP32 responses: sigma_i good to ~1e-7 sigma_1 / sigma_i
+        err = np.max(np.abs(got["sigma"][:keep.sum()] - s_w[keep]) / s_w[keep])
+        assert err < 1e-4, (mask, int(keep.sum()), err)
     if temporal == "hats":
         assert len(S.audit(G, order_mask=1)["zero_columns"]) > 0
 
 
 def test_s224_audit_on_the_kerr_128_workload(gpu_lib):
     """S_224 on the 128^2 workload: direct and resolved arms.  Zero columns against the oracle's
-    responses to every column of Q; the leading singular values against the FP64 Gram of those
+    responses to every column of Q; the singular values >= 1e-3 sigma_1 against the FP64 Gram of those
     responses."""
     rtt = gpu_lib
     geo = synth.geometry_for("cfg2")
@@ -82,7 +83,10 @@ def test_s224_audit_on_the_kerr_128_workload(gpu_lib):
             Gm = Ym @ Ym.T
             s_w = np.sqrt(np.maximum(np.linalg.eigvalsh(Gm)[::-1], 0.0))
             say(temporal, mask, "zero", len(zero), "rank", got["rank"], "sigma1", got["sigma"][0])
-            assert np.max(np.abs(got["sigma"][:10] - s_w[:10]) / s_w[:10]) < 1e-4
+            keep = int(np.sum(s_w >= 1e-3 * s_w[0]))
+            err = np.max(np.abs(got["sigma"][:keep] - s_w[:keep]) / s_w[:keep])
+            say(temporal, mask, "sigma >= 1e-3 sigma1:", keep, "max rel err", err)
+            assert err < 1e-4, (temporal, mask, keep, err)
 
 
 def test_age_fisher_matches_oracle(gpu_lib):
