@@ -572,7 +572,8 @@ def block_section(torch, rtt, synth, oracle, dev, args):
     for name, ms, b, v in (("op_apply", ms_a, b_a, names[0][0]), ("op_apply_adjoint", ms_at, b_at, names[0][1])):
         traffic = None
         for meas in MEASURED_TRAFFIC.get(name, []):
-            if meas["digest"] == digest and meas["nvec"] == nvec and meas["variant"] == v and meas.get("workload") == "cfg2":
+            if (meas.get("workload") == "cfg2" and meas["digest"] == digest and meas.get("nvec") == nvec
+                    and meas["variant"] == v):
                 traffic = meas["bytes"]
         kern[name] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9, "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                       "bytes": b, "traffic": traffic, "variant": v,
@@ -648,6 +649,7 @@ def large_section(torch, rtt, synth, dev):
     t_lz = time.perf_counter() - t0l
     conv = {str(t): int(svl.converged(t)) for t in (1e-6, 1e-4, 1e-2)}
     lz = {"seconds": t_lz, "block": 32, "steps": 16, "theta_1": float(svl.sigma[0]),
+          "theta_64": float(svl.sigma[-1]),
           "residual_1_rel": float(svl.residual[0] / svl.sigma[0]),
           "converged_of_64_by_rel_residual": conv,
           "variants": [rtt.variant_names(False)[G5.members[0]["apply_variant"]],
