@@ -43,8 +43,9 @@ template <bool VL>
 __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ A, int64_t lda,
                                                       const float* __restrict__ B, int64_t ldb, int M, int N,
                                                       int64_t L, int64_t slice, int nbn, int sym,
-                                                      float* __restrict__ part)
+                                                      float* __restrict__ part, const int* __restrict__ run_if)
 {
+    if (run_if && !*run_if) return;
     // 64 x 64 output block of one L slice; the slice runs in chunks of GK columns staged in LDS,
     // double buffered: the next chunk's global loads (16-byte when VL) are issued into registers
     // before the current chunk's MFMAs.
@@ -125,8 +126,9 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
 }
 
 __global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M, int N, int sym,
-                              double* __restrict__ G)
+                              double* __restrict__ G, const int* __restrict__ run_if)
 {
+    if (run_if && !*run_if) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)M * N) return;
     int i = (int)(e / N), j = (int)(e % N);
@@ -142,8 +144,9 @@ template <int MG, bool VY>
 __global__ __launch_bounds__(256, 2) void k_combine(const float* __restrict__ C, int K, int M, int m0,
                                                  const float* __restrict__ Y, int64_t ldy,
                                                  float* __restrict__ Out, int64_t ldo, int64_t L, float beta,
-                                                 int upper)
+                                                 int upper, const int* __restrict__ run_if)
 {
+    if (run_if && !*run_if) return;
     // The block owns 128 columns l (32 per wave) and MG 32-row blocks of Out.  k runs in chunks of
     // CK: the chunk's rows of C and Y are staged in LDS (double buffered), and the next chunk's global
     // loads are issued into registers before the current chunk's MFMAs, so they overlap.  upper:
@@ -239,8 +242,10 @@ __global__ __launch_bounds__(256, 2) void k_combine(const float* __restrict__ C,
 template <int TM>
 __global__ __launch_bounds__(256) void k_gram_skinny(const float* __restrict__ A, int64_t lda,
                                                      const float* __restrict__ B, int64_t ldb, int M, int N,
-                                                     int64_t L, int64_t slice, float* __restrict__ part)
+                                                     int64_t L, int64_t slice, float* __restrict__ part,
+                                                     const int* __restrict__ run_if)
 {
+    if (run_if && !*run_if) return;
     __shared__ float red[3][64][17];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int s = blockIdx.y;
@@ -316,8 +321,9 @@ __global__ __launch_bounds__(256) void k_gram_skinny(const float* __restrict__ A
 // (of 16) sums, in slice order, the g-th of 16 contiguous ranges of slices; the 16 group sums are
 // added in group order.  Deterministic; many slices are summed in parallel.
 __global__ __launch_bounds__(1024) void k_gram_reduce_wide(const float* __restrict__ part, int nsplit, int64_t MN,
-                                                           double* __restrict__ G)
+                                                           double* __restrict__ G, const int* __restrict__ run_if)
 {
+    if (run_if && !*run_if) return;
     __shared__ double sum[16][64];
     const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + e;
@@ -340,8 +346,10 @@ __global__ __launch_bounds__(1024) void k_gram_reduce_wide(const float* __restri
 // Y[k][l0 + 4j .. 4j + 3] for k = 2 s + h and feeds tile q (columns l0 + 4j + q) with element q.
 __global__ __launch_bounds__(256) void k_combine_skinny(const float* __restrict__ C, int K, int M,
                                                         const float* __restrict__ Y, int64_t ldy,
-                                                        float* __restrict__ Out, int64_t ldo, int64_t L, float beta)
+                                                        float* __restrict__ Out, int64_t ldo, int64_t L, float beta,
+                                                        const int* __restrict__ run_if)
 {
+    if (run_if && !*run_if) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int j = lane & 31, h = lane >> 5;
     const int64_t l0 = ((int64_t)blockIdx.x * 4 + wave) * 128;
@@ -526,7 +534,7 @@ void* Workspace::get(const char* name, size_t bytes)
 }
 
 int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb, int M, int N, int64_t L,
-         double* G_dev, hipStream_t s)
+         double* G_dev, hipStream_t s, const int* run_if)
 {
     if (M <= 0 || N <= 0) return RTT_OK;
     const bool aligned = (((uintptr_t)A) & 15) == 0 && (((uintptr_t)B) & 15) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
@@ -542,13 +550,13 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
         if (!part) return fail(RTT_ENOMEM, "gram workspace");
         if (tm == 4)
             hipLaunchKernelGGL(k_gram_skinny<4>, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s, A, lda, B, ldb,
-                               M, N, L, slice, part);
+                               M, N, L, slice, part, run_if);
         else
             hipLaunchKernelGGL(k_gram_skinny<1>, dim3((unsigned)tiles, (unsigned)nsplit), dim3(256), 0, s, A, lda, B, ldb,
-                               M, N, L, slice, part);
+                               M, N, L, slice, part, run_if);
         const int64_t tot = (int64_t)M * N;
         hipLaunchKernelGGL(k_gram_reduce_wide, dim3((unsigned)((tot + 63) / 64)), dim3(1024), 0, s, part, nsplit, tot,
-                           G_dev);
+                           G_dev, run_if);
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
@@ -567,38 +575,42 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
     // 16-byte loads need 16-byte aligned rows (slice starts are multiples of GK)
     const bool vl = (((uintptr_t)A) & 15) == 0 && (((uintptr_t)B) & 15) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
     if (vl)
-        hipLaunchKernelGGL(k_gram_partial<true>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part);
+        hipLaunchKernelGGL(k_gram_partial<true>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part,
+                           run_if);
     else
-        hipLaunchKernelGGL(k_gram_partial<false>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part);
+        hipLaunchKernelGGL(k_gram_partial<false>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part,
+                           run_if);
     const int64_t tot = (int64_t)M * N;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit, M, N,
-                       sym, G_dev);
+                       sym, G_dev, run_if);
     RTT_HIP(hipGetLastError());
     return RTT_OK;
 }
 
 template <int MG>
 static void combine_launch(const float* C, int K, int M, int m0, const float* Y, int64_t ldy, float* Out,
-                           int64_t ldo, int64_t L, float beta, int upper, hipStream_t s)
+                           int64_t ldo, int64_t L, float beta, int upper, hipStream_t s, const int* run_if)
 {
     dim3 grid((unsigned)((L + 127) / 128));
     // 16-byte loads of Y need 16-byte aligned rows
     const bool vy = (((uintptr_t)Y) & 15) == 0 && (ldy % 4) == 0;
     if (vy)
-        hipLaunchKernelGGL((k_combine<MG, true>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta, upper);
+        hipLaunchKernelGGL((k_combine<MG, true>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta, upper,
+                           run_if);
     else
-        hipLaunchKernelGGL((k_combine<MG, false>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta, upper);
+        hipLaunchKernelGGL((k_combine<MG, false>), grid, dim3(256), 0, s, C, K, M, m0, Y, ldy, Out, ldo, L, beta, upper,
+                           run_if);
 }
 
 int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Out, int64_t ldo, int64_t L,
-            float beta, hipStream_t s, bool upper)
+            float beta, hipStream_t s, bool upper, const int* run_if)
 {
     const int up = upper ? 1 : 0;
     if (M <= 0 || L <= 0) return RTT_OK;
     if (M <= 32 && (((uintptr_t)Y) & 15) == 0 && (ldy % 4) == 0 && (((uintptr_t)Out) & 15) == 0 && (ldo % 4) == 0) {
         const int64_t waves = (L + 127) / 128;
         hipLaunchKernelGGL(k_combine_skinny, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, C, K, M, Y, ldy, Out,
-                           ldo, L, beta);
+                           ldo, L, beta, run_if);
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
@@ -609,10 +621,10 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         const int mg = std::min(COMBINE_ROW_BLOCKS, (M - m0 + 31) / 32);
         static_assert(COMBINE_ROW_BLOCKS == 4, "one case per row-block count below");
         switch (mg) {
-        case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
-        default: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s); break;
+        case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
+        case 2: combine_launch<2>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
+        case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
+        default: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
         }
     }
     RTT_HIP(hipGetLastError());

@@ -1,7 +1,6 @@
-// Small dense FP64 linear algebra on the host (n <= a few hundred):
-// Cholesky with dependent-pivot handling, triangular inverse and the
+// Small dense FP64 linear algebra on the host (n <= a few hundred): the
 // one-sided Jacobi SVD (Hestenes), started from the eigenvectors of the
-// Gram matrix.  Row-major storage.
+// Gram matrix, and the host thread pool.  Row-major storage.
 #include <algorithm>
 #include <cmath>
 #include <atomic>
@@ -130,123 +129,6 @@ static void parallel_for(int n, int grain, F f)
 void host_for(int n, const std::function<void(int)>& f)
 {
     HostPool::get().run(n, [&f](int i) { f(i); });
-}
-
-int cholesky_upper(const std::vector<double>& G, int n, double shift, double dead_tol, std::vector<double>& R,
-                   std::vector<char>& dead)
-{
-    R.assign((size_t)n * n, 0.0);
-    dead.assign(n, 0);
-    double maxdiag = 0.0;
-    for (int j = 0; j < n; ++j) maxdiag = std::max(maxdiag, G[(size_t)j * n + j]);
-    // Right-looking form: S holds the upper triangle of G + shift I minus the rank-one terms of
-    // the rows of R already formed.  Each entry receives its terms in increasing row order, the
-    // order of the textbook column formula, and every update runs along a contiguous row.  Rows
-    // are formed in panels of PB: inside a panel the rows of the panel are updated at once, the
-    // rows below it afterwards (in the same order per entry), split over host threads.
-    std::vector<double> S(G.begin(), G.begin() + (size_t)n * n);
-    for (int j = 0; j < n; ++j) S[(size_t)j * n + j] += shift;
-    constexpr int PB = 32;
-    int ndead = 0;
-    for (int p0 = 0; p0 < n; p0 += PB) {
-        const int p1 = std::min(n, p0 + PB);
-        for (int j = p0; j < p1; ++j) {
-            const double d = S[(size_t)j * n + j];
-            if (!(d > dead_tol * maxdiag) || maxdiag <= 0.0) {
-                // dependent column: keep its projection coefficients R[k][j] (k < j),
-                // zero diagonal, zero row (it spans no new direction)
-                dead[j] = 1;
-                ++ndead;
-                continue;
-            }
-            const double rjj = std::sqrt(d);
-            double* rj = &R[(size_t)j * n];
-            const double* sj = &S[(size_t)j * n];
-            rj[j] = rjj;
-            for (int i = j + 1; i < n; ++i) rj[i] = sj[i] / rjj;
-            for (int i = j + 1; i < p1; ++i) {
-                const double r = rj[i];
-                double* si = &S[(size_t)i * n];
-                for (int l = i; l < n; ++l) si[l] -= r * rj[l];
-            }
-        }
-        // rows below the panel: the panel's terms in increasing row order; rows dealt out
-        // cyclically (the work per row shrinks down the matrix)
-        const int rows = n - p1;
-        if (rows <= 0) continue;
-        const int parts = rows >= 64 ? 16 : 1;
-        parallel_for(parts, 1, [&](int t0, int t1) {
-            for (int t = t0; t < t1; ++t)
-                for (int i = p1 + t; i < n; i += parts) {
-                    double* si = &S[(size_t)i * n];
-                    for (int j = p0; j < p1; ++j) {
-                        const double* rj = &R[(size_t)j * n];
-                        const double r = rj[i];
-                        if (r == 0.0) continue;
-                        for (int l = i; l < n; ++l) si[l] -= r * rj[l];
-                    }
-                }
-        });
-    }
-    return ndead;
-}
-
-void upper_inverse(const std::vector<double>& R, int n, const std::vector<char>& dead, std::vector<double>& Ri)
-{
-    Ri.assign((size_t)n * n, 0.0);
-    // column j of Ri solves R x = e_j by back substitution: x_i = -(sum_{k=i+1..j} R[i][k] x_k) / R[i][i],
-    // the sum in increasing k.  Columns are independent and are dealt out cyclically to host
-    // threads, each working in a private contiguous copy of its column.  Dependent rows and columns
-    // stay zero.
-    const int parts = n >= 64 ? 16 : 1;
-    parallel_for(parts, 1, [&](int t0, int t1) {
-        std::vector<double> x(n);
-        for (int t = t0; t < t1; ++t)
-            for (int j = t; j < n; j += parts) {
-                if (dead[j]) continue;
-                std::fill(x.begin(), x.begin() + j + 1, 0.0);
-                x[j] = 1.0 / R[(size_t)j * n + j];
-                for (int i = j - 1; i >= 0; --i) {
-                    if (dead[i]) continue;
-                    const double* ri = &R[(size_t)i * n];
-                    double v = 0.0;
-                    for (int k = i + 1; k <= j; ++k) v += ri[k] * x[k];
-                    x[i] = v == 0.0 ? 0.0 : -v / ri[i];
-                }
-                for (int i = 0; i <= j; ++i) Ri[(size_t)i * n + j] = x[i];
-            }
-    });
-}
-
-void matmul(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C)
-{
-    C.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i)
-        for (int k = 0; k < n; ++k) {
-            const double a = A[(size_t)i * n + k];
-            if (a == 0.0) continue;
-            const double* b = &B[(size_t)k * n];
-            double* c = &C[(size_t)i * n];
-            for (int j = 0; j < n; ++j) c[j] += a * b[j];
-        }
-}
-
-void matmul_upper(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C)
-{
-    C.assign((size_t)n * n, 0.0);
-    // rows of C are independent; dealt out cyclically to host threads (the work shrinks down)
-    const int parts = n >= 64 ? 16 : 1;
-    parallel_for(parts, 1, [&](int t0, int t1) {
-        for (int t = t0; t < t1; ++t)
-            for (int i = t; i < n; i += parts)
-                for (int k = i; k < n; ++k) {
-                    const double a = A[(size_t)i * n + k];
-                    if (a == 0.0) continue;
-                    const double* b = &B[(size_t)k * n];
-                    double* c = &C[(size_t)i * n];
-                    for (int j = k; j < n; ++j) c[j] += a * b[j];
-                }
-    });
 }
 
 // Eigenvectors of a symmetric n x n matrix S (row-major, destroyed): Householder reduction to

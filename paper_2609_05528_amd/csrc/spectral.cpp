@@ -5,8 +5,8 @@
 // iterations, followed by their Alg. 5.1: B^T = A^T Q, B^T = Qb R, SVD of
 // R^T = Ur S W^T, so B = Ur S (Qb W)^T.  Every block is orthonormalised by
 // Cholesky QR: the Gram matrix comes from the FP32 MFMA kernel with FP64
-// slice reduction, the Cholesky factor and its inverse are FP64 (host), the
-// triangular apply is the MFMA combine kernel.  Two passes (CholQR2) for the
+// slice reduction, the Cholesky factor and its inverse are FP64 (device, one
+// workgroup per factor), the triangular apply is the MFMA combine kernel.  Two passes (CholQR2) for the
 // final bases Q and Qb; one for the intermediate bases of the power iterations,
 // which only carry a span.  When the first Gram matrix is too ill-conditioned
 // for FP32 a diagonal shift is added in the first pass and one more pass
@@ -92,77 +92,82 @@ int upload_f32(Ctx& c, const char* name, const std::vector<double>& h, size_t n,
 }
 
 // Orthonormalise, independently on every segment, the l (padded to lp) vectors stored in *Y
-// (row stride n), using *T as ping-pong storage; on return *Y holds Q.  R_total[seg] (lp x lp,
-// row-major, upper) receives the accumulated triangular factor with Y = Q R_total on the
-// retained columns of that segment.  final_basis false: the basis only carries a span to the next
-// product (the intermediate steps of subspace iteration), so one Cholesky QR pass is made (two
-// when the first is shifted) and R_total is left as the identity.
-int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>& segs,
-         std::vector<std::vector<double>>& R_total, bool final_basis = true)
+// (row stride n), using *T as ping-pong storage; on return *Y holds Q.  Every step is queued on the
+// stream (no host synchronisation): the Gram matrices (MFMA, FP64 slice reduction), their FP64
+// Cholesky factors and inverses (cholqr.hip), the MFMA combines Q = Y R^-1.  final_basis: two
+// passes (CholQR2); otherwise one, as the basis only carries a span to the next product (the
+// intermediate steps of subspace iteration).  A first pass whose Gram matrix had to be shifted adds
+// one more pass on that segment, decided on the device: the extra pass is always queued and its
+// kernels do nothing on segments that do not need it.  R_out (optional): receives a device pointer
+// to the accumulated factors R_total (lp x lp, upper, one per segment) with Y = Q R_total on the
+// retained columns; it stays valid until the next orth call on the same context.
+int orth(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>& segs, bool final_basis,
+         double** R_out = nullptr)
 {
     const int base = final_basis ? 2 : 1;
-    const size_t ns = segs.size();
+    const int ns = (int)segs.size();
     const size_t lp2 = (size_t)lp * lp;
-    // every pass: the Gram matrices of all active segments, one download, their factors on host
-    // threads (one segment per task), one upload, the combines
     double* Gd = (double*)c.ws.get("orth_gram", sizeof(double) * lp2 * ns);
-    if (!Gd) return fail(RTT_ENOMEM, "orth gram");
-    R_total.assign(ns, std::vector<double>(lp2, 0.0));
-    std::vector<int> passes(ns, base);
-    for (size_t q = 0; q < ns; ++q)
-        for (int i = 0; i < lp; ++i) R_total[q][(size_t)i * lp + i] = 1.0;
-    std::vector<double> G, Ri_all(lp2 * ns, 0.0);
-    for (int pass = 0; pass < 3; ++pass) {
-        if (std::all_of(passes.begin(), passes.end(), [pass](int p) { return p <= pass; })) break;
-        std::vector<size_t> act;
-        int rc;
-        for (size_t q = 0; q < ns; ++q) {
-            const Seg sg = segs[q];
-            if (pass >= passes[q]) {
-                // this segment is finished: carry it over to the buffer that becomes *Y
-                if (sg.len > 0)
-                    RTT_HIP(hipMemcpy2DAsync(*T + sg.off, n * sizeof(float), *Y + sg.off, n * sizeof(float),
-                                             sg.len * sizeof(float), lp, hipMemcpyDeviceToDevice, c.s));
-                continue;
-            }
-            act.push_back(q);
-            if ((rc = gram(c.ws, *Y + sg.off, n, *Y + sg.off, n, lp, lp, sg.len, Gd + q * lp2, c.s))) return rc;
-        }
-        if ((rc = download(c, Gd, G, lp2 * ns))) return rc;
-        const double dead_tol = pass == 0 ? 1e-12 : 1e-8;
-        host_for((int)act.size(), [&](int a) {
-            const size_t q = act[a];
-            std::vector<double> Gq(G.begin() + q * lp2, G.begin() + (q + 1) * lp2), R, Ri, Rt;
-            std::vector<char> dead;
-            double maxdiag = 0.0;
-            for (int i = 0; i < lp; ++i) maxdiag = std::max(maxdiag, Gq[(size_t)i * lp + i]);
-            cholesky_upper(Gq, lp, 0.0, dead_tol, R, dead);
-            if (pass == 0) {
-                // a pivot below the FP32 Gram accuracy: shift the first pass and add one more
-                double minpiv = INFINITY;
-                for (int i = 0; i < lp; ++i)
-                    if (!dead[i]) minpiv = std::min(minpiv, R[(size_t)i * lp + i] * R[(size_t)i * lp + i]);
-                if (minpiv < 1e-5 * maxdiag) {
-                    cholesky_upper(Gq, lp, 1e-6 * maxdiag, dead_tol, R, dead);
-                    passes[q] = base + 1;
-                }
-            }
-            upper_inverse(R, lp, dead, Ri);
-            std::copy(Ri.begin(), Ri.end(), Ri_all.begin() + q * lp2);
-            if (final_basis) {
-                matmul_upper(R, R_total[q], lp, Rt);
-                R_total[q].swap(Rt);
-            }
-        });
-        float* Cd = nullptr;
-        if ((rc = upload_f32(c, "orth_rinv", Ri_all, lp2 * ns, &Cd))) return rc;
-        for (size_t q : act) {
-            const Seg sg = segs[q];
-            if ((rc = combine(Cd + q * lp2, lp, lp, *Y + sg.off, n, *T + sg.off, n, sg.len, 0.f, c.s, true))) return rc;
-        }
-        std::swap(*Y, *T);
+    double* S = (double*)c.ws.get("orth_s", sizeof(double) * lp2 * ns);
+    double* R = (double*)c.ws.get("orth_r", sizeof(double) * lp2 * ns);
+    double* Ri = (double*)c.ws.get("orth_ri", sizeof(double) * lp2 * ns);
+    float* Ri32 = (float*)c.ws.get("orth_ri32", sizeof(float) * lp2 * ns);
+    int* dead = (int*)c.ws.get("orth_dead", sizeof(int) * (size_t)lp * ns);
+    int* st = (int*)c.ws.get("orth_state", sizeof(int) * (size_t)ns);
+    double* rt[2] = {nullptr, nullptr};
+    if (R_out) {
+        rt[0] = (double*)c.ws.get("orth_rt0", sizeof(double) * lp2 * ns);
+        rt[1] = (double*)c.ws.get("orth_rt1", sizeof(double) * lp2 * ns);
     }
+    if (!Gd || !S || !R || !Ri || !Ri32 || !dead || !st || (R_out && (!rt[0] || !rt[1])))
+        return fail(RTT_ENOMEM, "orth workspace");
+    int rc, cur = 0;
+    if (R_out && (rc = identity_f64(rt[0], lp, ns, c.s))) return rc;
+    auto pass = [&](int mode, double dead_tol) -> int {
+        for (int q = 0; q < ns; ++q) {
+            const Seg sg = segs[q];
+            if ((rc = gram(c.ws, *Y + sg.off, n, *Y + sg.off, n, lp, lp, sg.len, Gd + q * lp2, c.s,
+                           mode == 2 ? st + q : nullptr)))
+                return rc;
+        }
+        if ((rc = chol_factor(Gd, lp, ns, mode, dead_tol, S, R, dead, st, c.s))) return rc;
+        if ((rc = chol_inverse(R, dead, st, lp, ns, mode, Ri, Ri32, c.s))) return rc;
+        if (R_out) {
+            if ((rc = upper_product(R, rt[cur], st, lp, ns, mode, rt[1 - cur], c.s))) return rc;
+            cur = 1 - cur;
+        }
+        for (int q = 0; q < ns; ++q) {
+            const Seg sg = segs[q];
+            if ((rc = combine(Ri32 + q * lp2, lp, lp, *Y + sg.off, n, *T + sg.off, n, sg.len, 0.f, c.s, true,
+                              mode == 2 ? st + q : nullptr)))
+                return rc;
+        }
+        if (mode != 2) {
+            std::swap(*Y, *T);
+            return RTT_OK;
+        }
+        // the conditional pass wrote its segments to *T: copy them back so that *Y holds every Q
+        for (int q = 0; q < ns; ++q) {
+            const Seg sg = segs[q];
+            if ((rc = copy_rows_if(st + q, *T + sg.off, *Y + sg.off, n, lp, sg.len, c.s))) return rc;
+        }
+        return RTT_OK;
+    };
+    // dependent-pivot thresholds: 1e-12 of the largest diagonal in the first pass, 1e-8 after
+    for (int p = 0; p < base; ++p)
+        if ((rc = pass(p == 0 ? 0 : 1, p == 0 ? 1e-12 : 1e-8))) return rc;
+    if ((rc = pass(2, 1e-8))) return rc;
+    if (R_out) *R_out = rt[cur];
     return RTT_OK;
+}
+
+// orth, then the accumulated factor of the single segment on the host (lp x lp, row-major)
+int orth_r(Ctx& c, float** Y, float** T, int lp, int64_t n, const std::vector<Seg>& segs, std::vector<double>& Rh)
+{
+    double* Rd = nullptr;
+    int rc;
+    if ((rc = orth(c, Y, T, lp, n, segs, true, &Rd))) return rc;
+    return download(c, Rd, Rh, (size_t)lp * lp * segs.size());
 }
 
 float* dev_alloc(Ctx& c, const char* name, size_t n)
@@ -195,20 +200,21 @@ int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
     if (lp > y_from && (rc = fill(Y + (size_t)y_from * m, (int64_t)(lp - y_from) * m, 0.f, c.s))) return rc;
     if (omega) RTT_HIP(hipMemcpyAsync(X, omega, sizeof(float) * l * n, hipMemcpyDeviceToDevice, c.s));
     else if ((rc = normal_fill(X, (int64_t)l * n, o.seed, c.s))) return rc;
-    std::vector<std::vector<double>> R;
     // Y = A Omega; Q = orth(Y)
     if ((rc = apply(c, false, X, Y, l))) return rc;
     // the last basis of the range (Q) is final: U = Q Ur and B^T = A^T Q need it orthonormal
-    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, o.q == 0))) return rc;
+    if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, o.q == 0))) return rc;
     for (int it = 0; it < o.q; ++it) {
         if ((rc = apply(c, true, Y, X, l))) return rc;
-        if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R, false))) return rc;
+        if ((rc = orth(c, &X, &X2, lp, n, c.cseg, false))) return rc;
         if ((rc = apply(c, false, X, Y, l))) return rc;
-        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, R, it == o.q - 1))) return rc;
+        if ((rc = orth(c, &Y, &Y2, lp, m, c.rseg, it == o.q - 1))) return rc;
     }
-    // B^T = A^T Q = Qb R
+    // B^T = A^T Q = Qb R; R of every set comes to the host for the small SVDs (the one download)
     if ((rc = apply(c, true, Y, X, l))) return rc;
-    if ((rc = orth(c, &X, &X2, lp, n, c.cseg, R))) return rc;
+    std::vector<double> Rh;
+    if ((rc = orth_r(c, &X, &X2, lp, n, c.cseg, Rh))) return rc;
+    const size_t lp2 = (size_t)lp * lp;
     const int k = o.k;
     res->k = k;
     res->sets = sets;
@@ -221,7 +227,7 @@ int run_rsvd(Ctx& c, const rtt_svd_opts& o, const float* omega, rtt_svd* res)
     host_for(sets, [&](int q) {
         std::vector<double> Mt((size_t)l * l);
         for (int i = 0; i < l; ++i)
-            for (int j = 0; j < l; ++j) Mt[(size_t)i * l + j] = R[q][(size_t)j * lp + i];
+            for (int j = 0; j < l; ++j) Mt[(size_t)i * l + j] = Rh[q * lp2 + (size_t)j * lp + i];
         jacobi_svd(Mt, l, Urs[q], svs[q], Ws[q]);
     });
     for (int q = 0; q < sets; ++q) {
@@ -296,10 +302,8 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
     if (start) RTT_HIP(hipMemcpyAsync(Z, start, sizeof(float) * b * n, hipMemcpyDeviceToDevice, c.s));
     else if ((rc = normal_fill(Z, (int64_t)b * n, o.seed, c.s))) return rc;
     std::vector<double> R, L, Rprev, T((size_t)mdim * mdim, 0.0), coef;
-    std::vector<std::vector<double>> Rs;
     const std::vector<Seg> cwhole{{0, n}}, rwhole{{0, m}};
-    if ((rc = orth(c, &Z, &Z2, b, n, cwhole, Rs))) return rc;
-    R = Rs[0];
+    if ((rc = orth_r(c, &Z, &Z2, b, n, cwhole, R))) return rc;
     RTT_HIP(hipMemcpyAsync(Vall, Z, sizeof(float) * b * n, hipMemcpyDeviceToDevice, c.s));
     bool have_prev = false;
     for (int j = 0; j < steps; ++j) {
@@ -314,8 +318,7 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
             if ((rc = upload_f32(c, "lz_c1", C, C.size(), &Cf))) return rc;
             if ((rc = combine(Cf, b, b, Up, m, W, m, m, 1.f, c.s))) return rc;
         }
-        if ((rc = orth(c, &W, &W2, b, m, rwhole, Rs))) return rc;   // W now holds U_j
-        L = Rs[0];
+        if ((rc = orth_r(c, &W, &W2, b, m, rwhole, L))) return rc;   // W now holds U_j
         for (int i = 0; i < b; ++i)
             for (int jj = 0; jj < b; ++jj) T[(size_t)(j * b + i) * mdim + j * b + jj] = L[(size_t)i * b + jj];
         // Z = A^T U_j - V_j L_j^T
@@ -338,8 +341,7 @@ int run_lanczos(Ctx& c, const rtt_svd_opts& o, const float* start, rtt_svd* res)
             if ((rc = upload_f32(c, "lz_c3", coef, coef.size(), &Cf))) return rc;
             if ((rc = combine(Cf, nv, b, Vall, n, Z, n, n, 1.f, c.s))) return rc;
         }
-        if ((rc = orth(c, &Z, &Z2, b, n, cwhole, Rs))) return rc;   // Z = V_{j+1}, R_j
-        R = Rs[0];
+        if ((rc = orth_r(c, &Z, &Z2, b, n, cwhole, R))) return rc;   // Z = V_{j+1}, R_j
         if (j + 1 < steps) {
             for (int i = 0; i < b; ++i)
                 for (int jj = 0; jj < b; ++jj)
