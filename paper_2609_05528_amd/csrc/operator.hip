@@ -2833,7 +2833,11 @@ static void visitb_dispatch(const VisitArgs& a, const int64_t* vtask0, int64_t n
         else RTT_VISITB(4, 2, 2);
         return;
     }
-    if (a.K <= 64 || waves < 16384) RTT_VISITB(1, 4, 1);
+    // at half-step frames (Q = 2) a visit feeds two frames per hat, and four hats per lane pay for
+    // the visit's set-up even when the launch has few waves (512^2 geometry, one vector: 0.204 ->
+    // 0.147 ms); at Q = 1 one hat per lane stays faster there (256^2: 0.078 against 0.14 ms)
+    if (Q == 2 && a.K > 128) RTT_VISITB(4, 2, 1);
+    else if (a.K <= 64 || waves < 16384) RTT_VISITB(1, 4, 1);
     else if (a.K <= 128) RTT_VISITB(2, 4, 1);
     else RTT_VISITB(4, 2, 1);
 #undef RTT_VISITB

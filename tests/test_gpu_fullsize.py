@@ -149,23 +149,24 @@ def _cell_support(geo, c):
     return keep, np.concatenate(sel)
 
 
-@pytest.mark.parametrize("pinned", [None, ("strip8", "visitp2v")])
-def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, pinned):
-    """The block Lanczos block of the 512^2 x 512-frame workload (32 vectors) on the variants
-    tuned for it (K = 256: the row-pair adjoint with four hat slots per lane).  Two vectors,
-    48 rays per order and 6 cells each, against the oracle evaluated on the rays concerned."""
+@pytest.mark.parametrize("nvec,pinned", [(32, None), (32, ("strip8", "visitp2v")), (1, None),
+                                         (1, ("lean4r", "visitb"))])
+def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, nvec, pinned):
+    """The block Lanczos block of the 512^2 x 512-frame workload (32 vectors), and one vector, on
+    the variants tuned for them (K = 256: the row-pair or base-row adjoint with four hat slots per
+    lane; the row-ordered forward).  The first and last vector, 48 rays per order and 6 cells each,
+    against the oracle evaluated on the rays concerned."""
     import torch
     rtt = gpu_lib
     geo = synth.geometry_for("cfg5")
     g = geo.grid
     F = g.n_frames
     G = rtt.Geometry(geo)
-    nvec = 32
     names = tuned(rtt, G, nvec)
     if pinned is not None:
         pin(rtt, G, *pinned)
         names = [pinned]
-    say("case cfg5 block 32", names)
+    say("case cfg5 block", nvec, names)
     X = to_dev(synth.gaussian_block(g.n_cols, nvec, seed=5101))
     Y = rtt.op_apply(G, X)
     rng = np.random.default_rng(56)
