@@ -75,6 +75,39 @@ def test_rsvd_of_every_geometry_in_one_call_matches_oracle(gpu_lib):
         assert np.max(np.abs(sv.residual[g] - r64)) <= 1e-5 * sv.sigma[g][0], g
 
 
+def test_rsvd_segments_with_and_without_the_shifted_pass(gpu_lib):
+    """One rSVD call over four geometries whose sketch of 340 vectors exceeds the rank of two of
+    them (their first Cholesky QR pass is shifted and takes one more pass, decided per segment on
+    the device) and not of the other two.  Every set against the oracle's rSVD on the same test
+    block (1e-4 on sigma >= 1e-3 sigma_1), and bitwise against the same member factored alone."""
+    rtt = gpu_lib
+    geos = [tiny_geometry(seed=90, rays=(40, 12, 6), n_r=4, n_phi=6, n_frames=8),
+            tiny_geometry(seed=95, rays=(80, 20, 10), n_r=4, n_phi=8, n_frames=16),
+            tiny_geometry(seed=94, rays=(30, 10, 5), n_r=4, n_phi=6, n_frames=8, delay_hi=2.0),
+            tiny_geometry(seed=92, rays=(60, 20, 10), n_r=4, n_phi=6, n_frames=12)]
+    G = rtt.Geometry(geos)
+    k, p = 300, 40
+    say("case rsvd shifted segments", [(g.n_rows, g.grid.n_cols) for g in geos])
+    om = np.random.default_rng(9).standard_normal((k + p, G.n_cols)).astype(np.float32)
+    sv = rtt.rsvd(G, k=k, p=p, q=1, omega=to_dev(om), geometry=rtt.RTT_EACH_GEOMETRY)
+    ranks = []
+    for g, geo in enumerate(geos):
+        cs, _ = blocks(G, g)
+        D = oracle.dense(geo)
+        s_true = np.linalg.svd(D, compute_uv=False)
+        rank = int(np.sum(s_true > 1e-6 * s_true[0]))
+        ranks.append(rank)
+        s_o, _, _ = oracle.rsvd(geo, om[:, cs].astype(np.float64), q=1)
+        ok = s_o[:k] >= 1e-3 * s_o[0]
+        err = np.max(np.abs(sv.sigma[g][ok] - s_o[:k][ok]) / s_o[:k][ok])
+        say("geometry", g, "rank", rank, "of sketch", k + p, "sigma err", err)
+        assert err <= 1e-4, (g, err)
+        one = rtt.rsvd(G, k=k, p=p, q=1, omega=to_dev(om[:, cs]), geometry=g)
+        assert np.array_equal(one.sigma.ravel(), sv.sigma[g]), g
+    # both kinds of segment are present: rank below the sketch (shifted) and above it
+    assert min(ranks) < k + p <= max(ranks), ranks
+
+
 def test_tsvd_of_every_geometry_matches_oracle(gpu_lib):
     rtt = gpu_lib
     geos = batch_geometries(seed=80)
