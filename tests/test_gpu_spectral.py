@@ -113,6 +113,27 @@ def test_rsvd_sketch_wider_than_one_combine_launch(gpu_lib):
     assert np.max(np.abs(V @ V.T - np.eye(k))) <= 1e-4
 
 
+def test_rsvd_sketch_of_512_vectors(gpu_lib):
+    """The widest sketch the library takes, l = k + p = 512: the device Cholesky factor runs 16
+    panels with the largest LDS panel (480 columns right of the first), the block inverse 16 block
+    columns.  The 64^2 workload (40,960 columns); singular values against the oracle on the same
+    draw, right vectors orthonormal."""
+    rtt = gpu_lib
+    geo = synth.geometry_for("cfg1")
+    say("case rsvd l=512", geo.grid.n_cols, geo.n_rows)
+    G = rtt.Geometry(geo)
+    k, p = 480, 32
+    om = np.random.default_rng(4).standard_normal((k + p, geo.grid.n_cols)).astype(np.float32)
+    sv = rtt.rsvd(G, k=k, p=p, q=1, omega=to_dev(om))
+    s_o, _, _ = oracle.rsvd(geo, om.astype(np.float64), q=1)
+    ok = s_o[:k] >= 1e-3 * s_o[0]
+    err = np.max(np.abs(sv.sigma[ok] - s_o[:k][ok]) / s_o[:k][ok])
+    say("sigma >= 1e-3 sigma_1:", int(ok.sum()), "max rel err", err)
+    assert err <= 1e-4
+    V = sv.V().double().cpu().numpy()
+    assert np.max(np.abs(V[ok] @ V[ok].T - np.eye(int(ok.sum())))) <= 1e-4
+
+
 @pytest.mark.parametrize("mask", [0b001, 0b110])
 def test_rsvd_with_order_mask_matches_oracle(gpu_lib, mask):
     """rSVD of the rows of some orders only (the other rows are never written by the operator):
