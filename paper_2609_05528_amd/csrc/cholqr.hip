@@ -7,9 +7,9 @@
 //                   factored by all threads (one column per thread, in registers), the rows below
 //                   it then updated from the panel kept in LDS.
 //                   Every entry receives its terms in increasing row order (the order of the
-//                   textbook column formula), product and difference rounded separately.  Pivots at or below
-//                   dead_tol * max diag(G) mark dependent columns: zero diagonal and row, their
-//                   projection coefficients R[k][j] (k < j) kept.  On a first pass a pivot below
+//                   textbook column formula), product and difference rounded separately.  Pivots
+//                   at or below dead_tol * max diag(G) mark dependent columns: zero diagonal and
+//                   row, their projection coefficients R[k][j] (k < j) kept.  On a first pass a pivot below
 //                   1e-5 max diag(G) (past the FP32 accuracy of the Gram matrix) re-factors
 //                   G + 1e-6 max diag(G) I and flags one more pass (shifted CholQR3, Fukaya et
 //                   al. 2020); the extra pass runs only where that flag is set.
@@ -33,14 +33,6 @@ namespace {
 constexpr int CB = 32;           // panel rows / block size
 constexpr int CQ_MAX = 512;      // largest lp
 constexpr int PW = CQ_MAX - CB;  // columns right of a panel, at most
-
-__device__ __forceinline__ double readlane_f64(double v, int lane)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 __device__ __forceinline__ double uniform_f64(double v)
 {
@@ -148,7 +140,7 @@ __global__ __launch_bounds__(512) void k_chol_factor(const double* __restrict__ 
             }
             if (tc < CB) dead[p0 + tc] = my_dead;
             __syncthreads();
-            // 3. rows below the panel: S[i][l] -= R[j][i] R[j][l] for the panel's rows j in
+            // 2. rows below the panel: S[i][l] -= R[j][i] R[j][l] for the panel's rows j in
             //    increasing order, l >= i; an item is TR rows x 64 columns of one wave, and the
             //    wave loads its next item's entries while it computes the current one
             constexpr int TR = 4;
