@@ -790,6 +790,63 @@ __device__ __forceinline__ float (*lean_lds())[NB][LEAN_ZS]
     return zs_all;
 }
 
+// Output staging rows of the lean forward at Q = 1: NB rows of up to lean_fcmax(1) frames per wave,
+// plus up to 3 floats that put the block in the same 16-byte phase as its destination.
+template <int NB>
+constexpr int lean_ob_floats() { return (NB * lean_fcmax(1) + 3 + 3) / 4 * 4; }
+
+template <int NB>
+__device__ __forceinline__ float (*lean_obuf())[lean_ob_floats<NB>()]
+{
+    __shared__ __attribute__((aligned(16))) float ob_all[A_WAVES][lean_ob_floats<NB>()];
+    return ob_all;
+}
+
+// Q = 1 output of NB rays that are consecutive data rows, their whole rows in one chunk: the values
+// (as lean_emit forms them) go to LDS at the 16-byte phase of the destination, then the contiguous
+// NB * F range goes out in 16-byte stores aligned to it, 4-byte stores only for the at most 3 + 3
+// values at its two ends.  A per-ray store starts wherever its row starts, so rows of a length that
+// is not a multiple of the sector split sectors between store instructions and waves.
+template <int NB>
+__device__ __forceinline__ void lean_emit_staged(const float* zs0, const float* th0, int row0, int F,
+                                                 float* __restrict__ y, float* ob)
+{
+    constexpr int ZS = LEAN_ZS;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const float(*zs)[ZS] = (const float(*)[ZS])zs0;
+    float* yb = y + (int64_t)row0 * F;
+    const int pad = (int)(((uintptr_t)yb >> 2) & 3);   // floats of yb past a 16-byte boundary
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const float th = th0[j];
+#pragma unroll
+        for (int t = 0; t < (lean_fcmax(1) + WAVE - 1) / WAVE; ++t) {
+            const int q = lane + t * WAVE;
+            if (q >= F) break;
+            const float za = zs[j][q], zb = zs[j][q + 1];
+            ob[pad + j * F + q] = za + th * (zb - za);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int n = NB * F;
+    const int h = (4 - pad) & 3;                  // head: values before the first 16-byte boundary
+    const int nq = (n - h) >> 2;                  // whole quads after it
+    if (lane < h && lane < n) __builtin_nontemporal_store(ob[pad + lane], yb + lane);
+    for (int g = lane; g < nq; g += WAVE) {
+        const int d = h + 4 * g;                  // yb + d and ob + pad + d are 16-byte aligned
+        const f4 v = *(const f4*)(ob + pad + d);
+        __builtin_nontemporal_store(v, (f4*)(yb + d));
+    }
+    const int tail0 = h + 4 * nq;
+    if (lane < n - tail0) __builtin_nontemporal_store(ob[pad + tail0 + lane], yb + tail0 + lane);
+    // the next task of a persistent block writes this wave's staging row again
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One block of the lean forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, frame chunk
 // `chunk`, one vector (x, y already offset to the member's blocks).
 template <int Q, int NB, bool VEC4>
@@ -882,6 +939,16 @@ __device__ __forceinline__ void lean_body(const LeanArgs& a, const float* __rest
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
+    if constexpr (Q == 1) {
+        // rays in data-row order (lean4r) that are consecutive rows: one staged contiguous range
+        bool flat = f0 == 0 && fend == a.F;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) flat = flat && on[j] && row[j] == row[0] + j;
+        if (flat) {
+            lean_emit_staged<NB>(&zs[0][0], th0, row[0], a.F, y, lean_obuf<NB>()[wave]);
+            return;
+        }
+    }
     lean_emit<Q, NB, VEC4>(&zs[0][0], th0, row, on, f0, fend, a.F, y);
 }
 
