@@ -224,10 +224,12 @@ typedef struct {
  * rsvd -- leading singular triplets of A (Sec. 3.6 eq. (19) with C = I).
  * rSVD: randomized subspace iteration (Halko, Martinsson & Tropp 2011,
  * Alg. 4.4) with block l = k + p, q power iterations, orthonormalisation by
- * Cholesky QR (FP32 MFMA Gram, FP64 factor) after every application, and the
- * FP64 SVD of the projected l x l factor.  Block Lanczos: block Golub-Kahan
+ * Cholesky QR (FP32 MFMA Gram, FP64 factor and inverse on the device, no host
+ * round trip) after every application, and the FP64 SVD of the projected
+ * l x l factor on the host (one download).  Block Lanczos: block Golub-Kahan
  * with one-sided FP64 reorthogonalisation.  omega: device FP32 [l][n_cols]
- * start block (NULL: drawn from seed).  Blocking (returns after the small SVD).
+ * start block (NULL: drawn from seed).  Blocking (returns after the small SVD);
+ * not capturable into a graph as a whole.
  * With geometry = RTT_EACH_GEOMETRY the G geometries of the handle are
  * factorised independently in one run: every application of A or A^T is one
  * batched call on the whole handle, every orthonormalisation and small SVD is
