@@ -727,8 +727,40 @@ def oracle_driver_section(oracle, synth):
     t0 = time.perf_counter()
     _, it = oracle.ridge_solve(geo3, y3, 1e-3, tol=0.0, maxit=5)
     out["ridge_256_cg_s_per_iteration"] = (time.perf_counter() - t0) / max(it, 1)
+    out["apply_per_workload"] = oracle_apply_per_workload(oracle, synth)
     log("oracle drivers: %s" % out)
     return out
+
+
+def oracle_apply_per_workload(oracle, synth):
+    """The oracle's A and A^T (plain C, FP64) on one vector at a time on one thread, and on one
+    vector per host thread on all of them, for the 64^2, 128^2, 256^2 and 512^2 workloads:
+    A+A^T applies per second (each A and each A^T counts as one apply), each figure from at least
+    about 0.3 s of work (the 512^2 one-thread figure from one vector pair)."""
+    res = {}
+    threads = oracle.host_threads()
+    for name, label in (("cfg1", "64^2"), ("cfg2", "128^2"), ("cfg3", "256^2"), ("cfg5", "512^2")):
+        geo = synth.geometry_for(name)
+        rng = np.random.default_rng(17)
+        x = rng.standard_normal(geo.grid.n_cols)
+        n1, t1 = 0, 0.0
+        t0 = time.perf_counter()
+        while t1 < 0.3 or n1 == 0:
+            oracle.adjoint(geo, oracle.forward(geo, x, threads=1), threads=1)
+            n1 += 1
+            t1 = time.perf_counter() - t0
+        X = rng.standard_normal((threads, geo.grid.n_cols))
+        nall, tall = 0, 0.0
+        t0 = time.perf_counter()
+        while tall < 0.3 or nall == 0:
+            oracle.adjoint(geo, oracle.forward(geo, X, threads=threads), threads=threads)
+            nall += threads
+            tall = time.perf_counter() - t0
+        del X
+        res[label] = {"rows": int(geo.n_rows), "cols": int(geo.grid.n_cols),
+                      "one_thread_applies_per_s": 2 * n1 / t1, "all_threads_applies_per_s": 2 * nall / tall,
+                      "threads": threads}
+    return res
 
 
 def main():
@@ -806,6 +838,17 @@ def main():
     block = None if args.no_block else block_section(torch, rtt, synth, oracle, dev, args)
     large = None if args.no_large else large_section(torch, rtt, synth, dev)
     drivers = None if args.no_oracle_drivers else oracle_driver_section(oracle, synth)
+    if drivers is not None:
+        # GPU throughput over the oracle's on all host threads, where this run measured both
+        per = drivers["apply_per_workload"]
+        ratio = {}
+        if block is not None:
+            ratio["128^2 block of %d" % block["nvec"]] = block["applies_per_s"] / per["128^2"]["all_threads_applies_per_s"]
+        if large is not None:
+            ratio["512^2 one vector"] = large["applies_per_s"] / per["512^2"]["all_threads_applies_per_s"]
+        if cpu is not None:
+            ratio["batch step"] = value / cpu["value"]
+        drivers["gpu_over_oracle_all_threads"] = ratio
 
     out = {
         "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1, "steps": steps,
