@@ -8,7 +8,9 @@
 //           64x64 output block of one slice with v_mfma_f32_32x32x2f32 (one
 //           32x32 tile per wave) and writes an FP32 partial; a second kernel
 //           sums the partials of every entry in FP64 in slice order, so the
-//           result does not depend on scheduling.
+//           result does not depend on scheduling.  The output blocks of one
+//           slice run on one XCD; for G = A A^T only the 32x32 tiles on and
+//           above the diagonal are computed and the rest is mirrored.
 //  combine: Out[m][l] = sum_k C[k][m] Y[k][l]      (Out = C^T Y; e.g. Q = Y R^-1)
 //           C (K x M, small) and the matching rows of Y are staged in LDS 16
 //           rows at a time, double buffered with the next chunk's loads in
@@ -42,7 +44,7 @@ constexpr int GK = 32;   // k-chunk staged in LDS
 template <bool VL>
 __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ A, int64_t lda,
                                                       const float* __restrict__ B, int64_t ldb, int M, int N,
-                                                      int64_t L, int64_t slice, int nbn, int sym,
+                                                      int64_t L, int64_t slice, int nsplit, int nbn, int sym,
                                                       float* __restrict__ part, const int* __restrict__ run_if)
 {
     if (run_if && !*run_if) return;
@@ -52,13 +54,36 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
     __shared__ float As[2][GB][GK + 1];
     __shared__ float Bs[2][GB][GK + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int bm = blockIdx.x / nbn, bn = blockIdx.x % nbn;
-    const int s = blockIdx.y;
+    // One workgroup per (slice, output block), output blocks on and above the diagonal only when
+    // sym.  The hardware deals workgroups round robin over the 8 XCDs; workgroup b takes output
+    // block (b / 8) % nact of slice 8 ((b / 8) / nact) + b % 8, so all blocks of a slice run one
+    // after another on one XCD and the slice's rows come into that XCD's L2 once.
+    const int nact = sym ? nbn * (nbn + 1) / 2 : (((M + GB - 1) / GB) * nbn);
+    const int kx = (int)(blockIdx.x >> 3);
+    const int s = (kx / nact) * 8 + (int)(blockIdx.x & 7);
+    if (s >= nsplit) return;
+    int bm, bn;
+    {
+        int t = kx % nact;
+        if (sym) {
+            bm = 0;
+            while (t >= nbn - bm) {
+                t -= nbn - bm;
+                ++bm;
+            }
+            bn = bm + t;
+        } else {
+            bm = t / nbn;
+            bn = t % nbn;
+        }
+    }
     float* __restrict__ out = part + (int64_t)s * M * N;
-    if (sym && bn < bm) return;   // lower blocks are mirrored from the upper ones
     const int64_t l0 = (int64_t)s * slice;
     const int64_t l1 = min(L, l0 + slice);
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    // a wave whose 32 x 32 tile lies past the last row or column, or below the diagonal of a
+    // diagonal block (mirrored when the partials are summed), only helps stage the chunks
+    const bool live = bm * GB + wm < M && bn * GB + wn < N && !(sym && bm == bn && wm > wn);
     f4v ra[2], rb[2];
     // element group e (0..511): row e / 8, columns 4 (e % 8) .. +3 of the chunk
     auto load = [&](int64_t lc) {
@@ -105,17 +130,20 @@ __global__ __launch_bounds__(256) void k_gram_partial(const float* __restrict__ 
     for (int64_t lc = l0; lc < l1; lc += GK) {
         const bool more = lc + GK < l1;
         if (more) load(lc + GK);
+        if (live) {
 #pragma unroll
-        for (int j = 0; j < GK / 2; ++j) {
-            // step j covers k = j and k = j + 16 (half selects which)
-            const float a = As[buf][wm + row][16 * half + j];
-            const float b = Bs[buf][wn + row][16 * half + j];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            for (int j = 0; j < GK / 2; ++j) {
+                // step j covers k = j and k = j + 16 (half selects which)
+                const float a = As[buf][wm + row][16 * half + j];
+                const float b = Bs[buf][wn + row][16 * half + j];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+            }
         }
         if (more) store(buf ^ 1);
         __syncthreads();
         buf ^= 1;
     }
+    if (!live) return;
     const int col = lane & 31, hi = lane >> 5;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -133,7 +161,7 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nsplit, int M,
     if (e >= (int64_t)M * N) return;
     int i = (int)(e / N), j = (int)(e % N);
     int si = i, sj = j;
-    if (sym && (j / GB) < (i / GB)) { si = j; sj = i; }   // read the mirrored upper block
+    if (sym && (j >> 5) < (i >> 5)) { si = j; sj = i; }   // below the diagonal 32 x 32 tiles: mirror
     double s = 0.0;
 #pragma unroll 8
     for (int t = 0; t < nsplit; ++t) s += (double)part[(int64_t)t * M * N + (int64_t)si * N + sj];
@@ -571,15 +599,17 @@ int gram(Workspace& ws, const float* A, int64_t lda, const float* B, int64_t ldb
     if (nsplit < 1) nsplit = 1;
     float* part = (float*)ws.get("gram_part", sizeof(float) * (size_t)nsplit * M * N);
     if (!part) return fail(RTT_ENOMEM, "gram workspace");
-    dim3 grid((unsigned)(nbm * nbn), (unsigned)nsplit);
+    // output blocks per slice (upper ones only when sym), slices rounded up to whole groups of 8
+    const int64_t nact = sym ? (int64_t)nbn * (nbn + 1) / 2 : (int64_t)nbm * nbn;
+    dim3 grid((unsigned)(nact * (((int64_t)nsplit + 7) / 8) * 8));
     // 16-byte loads need 16-byte aligned rows (slice starts are multiples of GK)
     const bool vl = (((uintptr_t)A) & 15) == 0 && (((uintptr_t)B) & 15) == 0 && (lda % 4) == 0 && (ldb % 4) == 0;
     if (vl)
-        hipLaunchKernelGGL(k_gram_partial<true>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part,
-                           run_if);
+        hipLaunchKernelGGL(k_gram_partial<true>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nsplit, nbn,
+                           sym, part, run_if);
     else
-        hipLaunchKernelGGL(k_gram_partial<false>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nbn, sym, part,
-                           run_if);
+        hipLaunchKernelGGL(k_gram_partial<false>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, L, slice, nsplit, nbn,
+                           sym, part, run_if);
     const int64_t tot = (int64_t)M * N;
     hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, nsplit, M, N,
                        sym, G_dev, run_if);
