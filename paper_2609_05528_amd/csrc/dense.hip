@@ -647,8 +647,7 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
     // at most COMBINE_ROW_BLOCKS row blocks of 32 per launch: their accumulators leave room for
     // three waves per SIMD, which cover a chunk's loads
     constexpr int COMBINE_ROW_BLOCKS = 4;
-    for (int m0 = 0; m0 < M; m0 += COMBINE_ROW_BLOCKS * 32) {
-        const int mg = std::min(COMBINE_ROW_BLOCKS, (M - m0 + 31) / 32);
+    auto launch = [&](int m0, int mg) {
         static_assert(COMBINE_ROW_BLOCKS == 4, "one case per row-block count below");
         switch (mg) {
         case 1: combine_launch<1>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
@@ -656,7 +655,14 @@ int combine(const float* C, int K, int M, const float* Y, int64_t ldy, float* Ou
         case 3: combine_launch<3>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
         default: combine_launch<4>(C, K, M, m0, Y, ldy, Out, ldo, L, beta, up, s, run_if); break;
         }
-    }
+    };
+    // upper: a launch reads the rows of Y up to its last output row, so the launch with fewer row
+    // blocks takes the top rows (a 288-row C: 32 + 160 + 288 rows of Y read, not 128 + 256 + 288).
+    // A tile's products and their order depend only on its rows, not on the launch it falls in.
+    const int nblk = (M + 31) / 32, head = upper ? nblk % COMBINE_ROW_BLOCKS : 0;
+    if (head) launch(0, head);
+    for (int m0 = head * 32; m0 < M; m0 += COMBINE_ROW_BLOCKS * 32)
+        launch(m0, std::min(COMBINE_ROW_BLOCKS, (M - m0 + 31) / 32));
     RTT_HIP(hipGetLastError());
     return RTT_OK;
 }
