@@ -23,6 +23,11 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-
          "-I" + os.path.join(HERE, "..", "include")]
 
 
+# the host FP64 kernels of the small SVD run on AVX2 + FMA (every EPYC has them); contraction stays
+# off, so every product and sum is rounded as in the plain build
+HOST_SIMD = {"smallla.cpp": ["-Xarch_host", "-march=x86-64-v3", "-Xarch_host", "-ffp-contract=off"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
@@ -31,7 +36,7 @@ def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + HOST_SIMD.get(os.path.basename(src), []) + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <functional>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <thread>
@@ -359,31 +360,56 @@ void jacobi_svd(const std::vector<double>& M, int n, std::vector<double>& U, std
     // round.  Every pair of columns is visited once per sweep.  The pairs of a round touch
     // disjoint columns and run on separate host threads; NB is fixed, so the result does not
     // depend on the number of threads.
-    constexpr int NB = 16;
+    constexpr int NB = 16, NP = NB / 2, NR = NB - 1, MAX_SWEEPS = 60;
     auto blk = [n](int b) { return (int)((int64_t)n * b / NB); };
-    std::vector<int> rot_task(NB / 2);
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        int rot = 0;
-        for (int r = 0; r < NB - 1; ++r) {
-            parallel_for(NB / 2, n >= 128 ? 1 : NB, [&](int t0, int t1) {
-                for (int t = t0; t < t1; ++t) {
-                    int P = t == 0 ? r : (r + t) % (NB - 1);
-                    int Q = t == 0 ? NB - 1 : (r - t + NB - 1) % (NB - 1);
-                    if (P > Q) std::swap(P, Q);
-                    int cnt = 0;
-                    if (r == 0)
-                        for (int B : {P, Q})
-                            for (int p = blk(B); p < blk(B + 1); ++p)
-                                for (int q = p + 1; q < blk(B + 1); ++q) cnt += rotate(p, q);
-                    for (int p = blk(P); p < blk(P + 1); ++p)
-                        for (int q = blk(Q); q < blk(Q + 1); ++q) cnt += rotate(p, q);
-                    rot_task[t] = cnt;
-                }
-            });
-            for (int c : rot_task) rot += c;
-        }
-        if (rot == 0) break;
+    auto pair_task = [&](int r, int t) {
+        int P = t == 0 ? r : (r + t) % NR;
+        int Q = t == 0 ? NB - 1 : (r - t + NR) % NR;
+        if (P > Q) std::swap(P, Q);
+        int cnt = 0;
+        if (r == 0)
+            for (int B : {P, Q})
+                for (int p = blk(B); p < blk(B + 1); ++p)
+                    for (int q = p + 1; q < blk(B + 1); ++q) cnt += rotate(p, q);
+        for (int p = blk(P); p < blk(P + 1); ++p)
+            for (int q = blk(Q); q < blk(Q + 1); ++q) cnt += rotate(p, q);
+        return cnt;
+    };
+    // All sweeps run inside one job of the host pool: the participants take the pairs of a round
+    // from a counter and wait (spinning) until every pair of the round is done before the next
+    // round, instead of one pool job per round.  A participant that starts late, or alone (the
+    // pool busy or nested), finds the taken pairs done or takes them itself, so nothing waits for a
+    // thread that is not running.  Every participant sums the same per-pair rotation counts and
+    // stops after the same sweep.
+    std::unique_ptr<std::atomic<int>[]> next(new std::atomic<int>[MAX_SWEEPS * NR]),
+        done(new std::atomic<int>[MAX_SWEEPS * NR]);
+    for (int i = 0; i < MAX_SWEEPS * NR; ++i) {
+        next[i].store(0, std::memory_order_relaxed);
+        done[i].store(0, std::memory_order_relaxed);
     }
+    std::vector<int> cnt((size_t)MAX_SWEEPS * NR * NP, 0);
+    auto participant = [&]() {
+        for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+            for (int r = 0; r < NR; ++r) {
+                const int id = sweep * NR + r;
+                for (;;) {
+                    const int t = next[id].fetch_add(1, std::memory_order_relaxed);
+                    if (t >= NP) break;
+                    cnt[(size_t)id * NP + t] = pair_task(r, t);
+                    done[id].fetch_add(1, std::memory_order_release);
+                }
+                while (done[id].load(std::memory_order_acquire) < NP) std::this_thread::yield();
+            }
+            int rot = 0;
+            for (size_t i = (size_t)sweep * NR * NP; i < (size_t)(sweep + 1) * NR * NP; ++i) rot += cnt[i];
+            if (rot == 0) return;
+        }
+    };
+    const int parts = n >= 128 ? std::min(HostPool::get().threads(), NP) : 1;
+    if (parts == 1)
+        participant();
+    else
+        HostPool::get().run(parts, [&](int) { participant(); });
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::vector<double> sv(n);
