@@ -95,12 +95,15 @@ __global__ __launch_bounds__(512) void k_chol_factor(const double* __restrict__ 
 
     double shift = 0.0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        for (int i = wave; i < lp; i += nwaves)
-            for (int l = lane; l < lp; l += 64) {
-                const size_t e = (size_t)i * lp + l;
-                S[e] = i == l ? G[e] + shift : G[e];
-                R[e] = 0.0;
-            }
+        // flat over the entries, unrolled so that a thread has eight loads of G in flight (one
+        // load-store round trip per entry had left this copy latency-bound)
+        const int n2 = lp * lp;
+#pragma unroll 8
+        for (int e = t; e < n2; e += (int)blockDim.x) {
+            const double g = G[e];
+            S[e] = e % (lp + 1) == 0 ? g + shift : g;
+            R[e] = 0.0;
+        }
         __syncthreads();
         for (int p0 = 0; p0 < lp; p0 += CB) {
             const int p1 = p0 + CB;
