@@ -1981,19 +1981,21 @@ struct VisitMember {
 struct VisitMulti {
     VisitMember m[MULTI_MAX];
     int G;
+    int nvec;                    // vectors of the launch (a task takes NVW of them)
     uint32_t per_vec, total;
     const float* y;
     float* x;
     int64_t y_stride, x_stride;
 };
 
-template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO, int RR>
+template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO, int RR, int NVW = 1>
 __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMulti a)
 {
     for (uint32_t t = blockIdx.x; t < a.total; t += gridDim.x) {
         const uint32_t lt = xcd_remap32(t, a.total);
-        const uint32_t v = lt / a.per_vec;
-        const uint32_t b = lt - v * a.per_vec;
+        const uint32_t vg = lt / a.per_vec;          // vector group
+        const uint32_t v = vg * NVW;                 // first of the group's NVW vectors
+        const uint32_t b = lt - vg * a.per_vec;
         int g = 0;
         while (g + 1 < a.G && b >= a.m[g + 1].blk_begin) ++g;
         const VisitMember& mm = a.m[g];
@@ -2012,8 +2014,9 @@ __global__ __launch_bounds__(T_WAVES * WAVE) void k_adjoint_visit_multi(VisitMul
         va.x_stride = a.x_stride;
         va.y_bytes = mm.y_bytes;
         va.x_bytes = mm.x_bytes;
-        visit_body<Q, V, NB, PAIR, 1, DPP, HALO, RR>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
-                                                 a.x + (int64_t)v * a.x_stride + mm.x_off, 1, (int64_t)(b - mm.blk_begin));
+        visit_body<Q, V, NB, PAIR, NVW, DPP, HALO, RR>(va, a.y + (int64_t)v * a.y_stride + mm.y_off,
+                                                   a.x + (int64_t)v * a.x_stride + mm.x_off,
+                                                   min(NVW, a.nvec - (int)v), (int64_t)(b - mm.blk_begin));
     }
 }
 
@@ -3171,7 +3174,7 @@ static bool apply_multi(const rtt_geometry* g, int b, int e, const float* x, flo
     return true;
 }
 
-template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO = false, int RR = 1>
+template <int Q, int V, int NB, bool PAIR, bool DPP, bool HALO = false, int RR = 1, int NVW = 1>
 static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec, bool persist,
                                hipStream_t s)
 {
@@ -3179,7 +3182,7 @@ static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int 
         bool fits = true;
         for (int i = b; i < e; ++i) fits = fits && visit_halo_fits<Q, V>(g->members[i].grid.n_hat);
         if (fits) {
-            visit_multi_launch<Q, V, NB, PAIR, true, true, RR>(a, g, b, e, set, nvec, persist, s);
+            visit_multi_launch<Q, V, NB, PAIR, true, true, RR, NVW>(a, g, b, e, set, nvec, persist, s);
             return;
         }
     }
@@ -3193,15 +3196,16 @@ static void visit_multi_launch(VisitMulti& a, const rtt_geometry* g, int b, int 
         nb += (int64_t)(((m.grid.n_r + RR - 1) / RR + T_WAVES - 1) / T_WAVES) * d.nseg * d.kchunks;
     }
     a.per_vec = (uint32_t)nb;
-    a.total = (uint32_t)(nb * nvec);   // below 2^31: checked by adjoint_multi
+    a.nvec = nvec;
+    a.total = (uint32_t)(nb * ((nvec + NVW - 1) / NVW));   // below 2^31: checked by adjoint_multi
     if (a.total == 0) return;
-    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP, HALO, RR>), dim3(multi_grid(a.total, persist)),
+    hipLaunchKernelGGL((k_adjoint_visit_multi<Q, V, NB, PAIR, DPP, HALO, RR, NVW>), dim3(multi_grid(a.total, persist)),
                        dim3(T_WAVES * WAVE), 0, s, a);
 }
 
 template <int Q, bool PAIR, bool DPP = false, int RR = 1>
 static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, int e, int set, int nvec,
-                                 bool persist, hipStream_t s)
+                                 bool persist, hipStream_t s, int vpw = 1)
 {
     constexpr int NB1 = Q == 1 ? 8 : 4;
     int64_t waves = 0;
@@ -3209,6 +3213,13 @@ static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, in
     for (int i = b; i < e; ++i) {
         waves += (int64_t)g->members[i].grid.n_r * g->members[i].nseg[set] * nvec;
         K = std::max(K, g->members[i].grid.n_hat);
+    }
+    if (RR == 2 && vpw == 2) {
+        // row pairs, two vectors per wave (record decode and tap weights shared)
+        if (K <= 64) visit_multi_launch<Q, 1, 4, PAIR, DPP, false, RR, 2>(a, g, b, e, set, nvec, persist, s);
+        else if (K <= 128) visit_multi_launch<Q, 2, 4, PAIR, DPP, false, RR, 2>(a, g, b, e, set, nvec, persist, s);
+        else visit_multi_launch<Q, 4, 2, PAIR, DPP, false, RR, 2>(a, g, b, e, set, nvec, persist, s);
+        return;
     }
     if (RR == 2) {
         // row pairs: half the (row, segment) tasks; batches as in the single-geometry pair form
@@ -3274,8 +3285,13 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     a.x = x;
     a.y_stride = g->n_rows;
     a.x_stride = g->n_cols;
-    if (rp && m0.Q == 1) visit_multi_dispatch<1, false, true, 2>(a, g, b, e, set, nvec, persist, s);
-    else if (rp) visit_multi_dispatch<2, true, true, 2>(a, g, b, e, set, nvec, persist, s);
+    // row pairs: two vectors per wave (as in the single-geometry launch) when the launch has two
+    // and every member's pair of vectors fits the buffer ranges
+    int vpw = nvec >= 2 ? 2 : 1;
+    for (int i = b; i < e; ++i)
+        if (!visit_fits(g->members[i].n_rows, g->members[i].n_cols, g->n_rows, g->n_cols, 2)) vpw = 1;
+    if (rp && m0.Q == 1) visit_multi_dispatch<1, false, true, 2>(a, g, b, e, set, nvec, persist, s, vpw);
+    else if (rp) visit_multi_dispatch<2, true, true, 2>(a, g, b, e, set, nvec, persist, s, vpw);
     else if (m0.Q == 1 && (m0.adj_variant == 16 || m0.adj_variant == 19))
         visit_multi_dispatch<1, false, true>(a, g, b, e, set, nvec, persist, s);
     else if (m0.Q == 1) visit_multi_dispatch<1, false>(a, g, b, e, set, nvec, persist, s);
