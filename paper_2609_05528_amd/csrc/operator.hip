@@ -3214,6 +3214,13 @@ static void visit_multi_dispatch(VisitMulti& a, const rtt_geometry* g, int b, in
         waves += (int64_t)g->members[i].grid.n_r * g->members[i].nseg[set] * nvec;
         K = std::max(K, g->members[i].grid.n_hat);
     }
+    if (RR == 2 && vpw == 4) {
+        // row pairs, four vectors per wave
+        if (K <= 64) visit_multi_launch<Q, 1, 2, PAIR, DPP, false, RR, 4>(a, g, b, e, set, nvec, persist, s);
+        else if (K <= 128) visit_multi_launch<Q, 2, 2, PAIR, DPP, false, RR, 4>(a, g, b, e, set, nvec, persist, s);
+        else visit_multi_launch<Q, 4, 1, PAIR, DPP, false, RR, 4>(a, g, b, e, set, nvec, persist, s);
+        return;
+    }
     if (RR == 2 && vpw == 2) {
         // row pairs, two vectors per wave (record decode and tap weights shared)
         if (K <= 64) visit_multi_launch<Q, 1, 4, PAIR, DPP, false, RR, 2>(a, g, b, e, set, nvec, persist, s);
@@ -3244,13 +3251,14 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     for (int i = b; i < e; ++i) {
         const Member& m = g->members[i];
         if (!visit_supported(m) || m.Q != m0.Q || m.adj_variant != m0.adj_variant ||
-            (m0.adj_variant != 11 && m0.adj_variant != 16 && m0.adj_variant != 19))
+            (m0.adj_variant != 11 && m0.adj_variant != 16 && m0.adj_variant != 19 && m0.adj_variant != 20))
             return false;
         pair = pair && (m.grid.n_frames % 2) == 0 && (m.row_offset % 2) == 0;
         wide += (int64_t)m.grid.n_r * m.nseg[0] * nvec;
     }
     // row pairs (lane-shifted taps; frame pairs at Q = 2) read visit set 2
-    const bool rp = m0.adj_variant == 19 && (m0.Q == 1 || pair);
+    const bool rp = (m0.adj_variant == 19 || m0.adj_variant == 20) && (m0.Q == 1 || pair);
+    if (m0.adj_variant == 20 && !rp) return false;
     const int set = rp ? 2 : wide >= 16384 ? 0 : 1;
     // task count with the narrowest hat chunk (62 hats, the largest count any V gives); every
     // member's blocks must fit the visit kernel's 31-bit buffer ranges
@@ -3285,11 +3293,13 @@ static bool adjoint_multi(const rtt_geometry* g, int b, int e, const float* y, f
     a.x = x;
     a.y_stride = g->n_rows;
     a.x_stride = g->n_cols;
-    // row pairs: two vectors per wave (as in the single-geometry launch) when the launch has two
-    // and every member's pair of vectors fits the buffer ranges
-    int vpw = nvec >= 2 ? 2 : 1;
+    // row pairs: two (visitp2v) or four (visitp4v) vectors per wave, as in the single-geometry
+    // launch, when the launch has that many and every member's group of vectors fits the buffer
+    // ranges
+    int vpw = std::min(m0.adj_variant == 20 ? 4 : 2, nvec);
+    if (vpw == 3) vpw = 2;
     for (int i = b; i < e; ++i)
-        if (!visit_fits(g->members[i].n_rows, g->members[i].n_cols, g->n_rows, g->n_cols, 2)) vpw = 1;
+        while (vpw > 1 && !visit_fits(g->members[i].n_rows, g->members[i].n_cols, g->n_rows, g->n_cols, vpw)) vpw /= 2;
     if (rp && m0.Q == 1) visit_multi_dispatch<1, false, true, 2>(a, g, b, e, set, nvec, persist, s, vpw);
     else if (rp) visit_multi_dispatch<2, true, true, 2>(a, g, b, e, set, nvec, persist, s, vpw);
     else if (m0.Q == 1 && (m0.adj_variant == 16 || m0.adj_variant == 19))

@@ -218,7 +218,7 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
                 for (const Member& m : g->members) tuned.push_back(adj ? m.adj_variant : m.apply_variant);
                 // candidates: -1 = the per-member choices; then the single-launch variants
                 std::vector<int> cands = {-1};
-                for (int v : adj ? std::vector<int>{11, 16, 19} : std::vector<int>{4, 6, 7, 11, 13}) {
+                for (int v : adj ? std::vector<int>{11, 16, 19, 20} : std::vector<int>{4, 6, 7, 11, 13}) {
                     bool ok = true;
                     for (const Member& m : g->members) ok = ok && (adj ? adjoint_variant_ok(m, v) : apply_variant_ok(m, v));
                     if (ok) cands.push_back(v);

@@ -345,7 +345,7 @@ def test_batched_launch_modes_agree_bitwise_and_match_oracle(gpu_lib, name, fwd,
         # kernel launches of one call: one per group of 16 members in one-launch modes when the
         # variant has a one-launch form, else one per member (two for the base-row adjoint)
         one_f = mode and fwd in ("lean4", "lean8", "reg1", "reg2", "abs4", "lean4r")
-        one_a = mode and adj in ("visit", "visitd", "visitp2v")
+        one_a = mode and adj in ("visit", "visitd", "visitp2v", "visitp4v")
         per_a = 2 if adj.startswith("visitb") else 1
         assert G.launches == (groups if one_f else len(geos), groups if one_a else per_a * len(geos)), (mode, G.launches)
         outs[mode] = (rtt.op_apply(G, to_dev(X)).cpu().numpy(), rtt.op_apply_adjoint(G, to_dev(Y)).cpu().numpy())
