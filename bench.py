@@ -36,10 +36,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip
 # the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only for the kernel source digest,
 # workload, variant and launch modes they were taken on (see profiles/).
 MEASURED_TRAFFIC = {
-    "op_apply_shared": [{"bytes": 10886515712, "digest": "bc1fba8286747167", "workload": "batch",
-                         "variant": ["abs4", "lean4", "lean4q", "lean4r", "reg1"], "modes": [1, 1]}],
-    "op_apply_adjoint": [{"bytes": 12178917786, "digest": "bc1fba8286747167", "workload": "batch",
-                          "variant": ["visitp2v"], "modes": [1, 1]}],
+    "op_apply_shared": [{"bytes": 10886087680, "digest": "e0983fb2350f2f62", "workload": "batch",
+                         "variant": ["abs4", "lean4", "lean4q", "lean4r", "reg1"], "modes": [2, 1]}],
+    "op_apply_adjoint": [{"bytes": 12562794496, "digest": "e0983fb2350f2f62", "workload": "batch",
+                          "variant": ["visitp2v"], "modes": [2, 1]}],
     "op_apply": [],
 }
 
