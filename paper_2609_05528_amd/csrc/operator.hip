@@ -802,6 +802,31 @@ __device__ __forceinline__ float (*lean_obuf())[lean_ob_floats<NB>()]
     return ob_all;
 }
 
+// The n values staged in ob[pad ..] leave for yb[0 .. n) (yb at the 16-byte phase pad) in 16-byte
+// stores aligned to the range, 4-byte stores only for the at most 3 + 3 values at its two ends.
+template <int NB>
+__device__ __forceinline__ void range_store(const float* ob, int pad, int n, float* __restrict__ yb)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int h = (4 - pad) & 3;                  // head: values before the first 16-byte boundary
+    const int nq = (n - h) >> 2;                  // whole quads after it
+    if (lane < h && lane < n) __builtin_nontemporal_store(ob[pad + lane], yb + lane);
+    for (int g = lane; g < nq; g += WAVE) {
+        const int d = h + 4 * g;                  // yb + d and ob + pad + d are 16-byte aligned
+        const f4 v = *(const f4*)(ob + pad + d);
+        __builtin_nontemporal_store(v, (f4*)(yb + d));
+    }
+    const int tail0 = h + 4 * nq;
+    if (lane < n - tail0) __builtin_nontemporal_store(ob[pad + tail0 + lane], yb + tail0 + lane);
+    // the next task of a persistent block writes this wave's staging row again
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Q = 1 output of NB rays that are consecutive data rows, their whole rows in one chunk: the values
 // (as lean_emit forms them) go to LDS at the 16-byte phase of the destination, then the contiguous
 // NB * F range goes out in 16-byte stores aligned to it, 4-byte stores only for the at most 3 + 3
@@ -827,24 +852,7 @@ __device__ __forceinline__ void lean_emit_staged(const float* zs0, const float* 
             ob[pad + j * F + q] = za + th * (zb - za);
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int n = NB * F;
-    const int h = (4 - pad) & 3;                  // head: values before the first 16-byte boundary
-    const int nq = (n - h) >> 2;                  // whole quads after it
-    if (lane < h && lane < n) __builtin_nontemporal_store(ob[pad + lane], yb + lane);
-    for (int g = lane; g < nq; g += WAVE) {
-        const int d = h + 4 * g;                  // yb + d and ob + pad + d are 16-byte aligned
-        const f4 v = *(const f4*)(ob + pad + d);
-        __builtin_nontemporal_store(v, (f4*)(yb + d));
-    }
-    const int tail0 = h + 4 * nq;
-    if (lane < n - tail0) __builtin_nontemporal_store(ob[pad + tail0 + lane], yb + tail0 + lane);
-    // the next task of a persistent block writes this wave's staging row again
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    range_store<NB>(ob, pad, NB * F, yb);
 }
 
 // One block of the lean forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, frame chunk
@@ -1059,7 +1067,9 @@ constexpr int ABS_KMAX = 2 * WAVE;
 
 // One block of the absolute-hat forward: rays [blk*A_WAVES*NB, +A_WAVES*NB) of one member, one
 // vector (x, y already offset to the member's blocks), every frame.
-template <int Q, int NB, bool VEC4, bool REUSE>
+// STAGE (records in data-row order, Q = 1): NB rays that are consecutive data rows with rows of at
+// most lean_fcmax(1) frames leave as one staged, 16-byte aligned range (as lean4r).
+template <int Q, int NB, bool VEC4, bool REUSE, bool STAGE = false>
 __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restrict__ x, float* __restrict__ y,
                                          int64_t blk)
 {
@@ -1129,6 +1139,30 @@ __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restr
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     const int F = a.F;
+    if constexpr (STAGE && Q == 1) {
+        bool flat = F <= lean_fcmax(1);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) flat = flat && on[j] && rc[j].row == rc[0].row + j;
+        if (flat) {
+            // the values of the per-ray path below, staged at the 16-byte phase of the range
+            float* ob = lean_obuf<NB>()[wave];
+            float* yb = y + (int64_t)rc[0].row * F;
+            const int pad = (int)(((uintptr_t)yb >> 2) & 3);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const float* zr = zs[j];
+                auto zat = [&](int k) { return (unsigned)k < (unsigned)K ? zr[k] : 0.f; };
+                const float th = rc[j].th0;
+                const int k0 = rc[j].k0;
+                for (int q = lane; q < F; q += WAVE) {
+                    const float za = zat(k0 + q), zb = zat(k0 + q + 1);
+                    ob[pad + j * F + q] = za + th * (zb - za);
+                }
+            }
+            range_store<NB>(ob, pad, NB * F, yb);
+            return;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         if (!on[j]) continue;
@@ -1182,11 +1216,11 @@ __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restr
     }
 }
 
-template <int Q, int NB, bool VEC4>
+template <int Q, int NB, bool VEC4, bool STAGE = false>
 __global__ __launch_bounds__(A_WAVES * WAVE) void k_apply_abs(LeanArgs a)
 {
-    abs_body<Q, NB, VEC4, false>(a, a.x + (int64_t)blockIdx.y * a.x_stride, a.y + (int64_t)blockIdx.y * a.y_stride,
-                                 xcd_remap(blockIdx.x, gridDim.x));
+    abs_body<Q, NB, VEC4, false, STAGE>(a, a.x + (int64_t)blockIdx.y * a.x_stride,
+                                        a.y + (int64_t)blockIdx.y * a.y_stride, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Every member of a handle (up to MULTI_MAX) in one launch.  Tasks are (vector, member, frame
@@ -2468,11 +2502,11 @@ constexpr int kNumAdj = sizeof(kAdjVariants) / sizeof(kAdjVariants[0]);
 
 int n_adjoint_variants() { return kNumAdj; }
 const char* adjoint_variant_name(int v) { return kAdjVariants[v].name; }
-int n_apply_variants() { return 14; }
+int n_apply_variants() { return 15; }
 const char* apply_variant_name(int v)
 {
     static const char* names[] = {"rpw1", "rpw2", "batch", "stream", "lean4", "lean8", "reg1", "reg2", "strip16",
-                                  "strip8", "lean4q", "abs4", "abs8", "lean4r"};
+                                  "strip8", "lean4q", "abs4", "abs8", "lean4r", "abs4r"};
     return names[v];
 }
 bool lean_supported(const Member& m)
@@ -2506,7 +2540,7 @@ bool apply_variant_ok(const Member& m, int v)
     if (v >= 4 && !lean_supported(m)) return false;      // lean / reg / strip need dt_obs/dt_src = 1 or 1/2
     if ((v == 8 || v == 9) && strip_lds_bytes(m, v == 8 ? 16 : 8) > 65536) return false;
     if (v == 10 && m.grid.n_hat % 4 != 0) return false;   // quad gathers need 16-byte aligned x rows
-    if ((v == 11 || v == 12) && m.grid.n_hat > ABS_KMAX) return false;   // absolute hats: two gather passes
+    if ((v == 11 || v == 12 || v == 14) && m.grid.n_hat > ABS_KMAX) return false;   // absolute hats: two gather passes
     return true;
 }
 
@@ -2705,10 +2739,11 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         RTT_HIP(hipGetLastError());
         return RTT_OK;
     }
-    if (variant == 11 || variant == 12) {
+    if (variant == 11 || variant == 12 || variant == 14) {
         if (m.grid.n_hat > ABS_KMAX) return fail(RTT_EINVAL, "absolute-hat forward needs n_hat <= 128");
         LeanArgs la;
-        la.rec = g->d_fwd + m.ray_begin;
+        // abs4r: the records in data-row order, consecutive rows staged (Q = 1)
+        la.rec = (variant == 14 ? g->d_fwd_row : g->d_fwd) + m.ray_begin;
         la.n_rays = m.n_rays;
         la.K = m.grid.n_hat;
         la.F = m.grid.n_frames;
@@ -2722,7 +2757,7 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         la.fc = m.grid.n_frames;
         const int wa = m.Q == 1 ? 2 : 4;
         const bool vec4 = (la.F % wa) == 0 && (((uintptr_t)y) & (4 * wa - 1)) == 0 && (nvec == 1 || (y_stride % wa) == 0);
-        const int nb = variant == 11 ? 4 : 8;
+        const int nb = variant == 12 ? 8 : 4;
         const dim3 grid((unsigned)((la.n_rays + (int64_t)A_WAVES * nb - 1) / ((int64_t)A_WAVES * nb)), (unsigned)nvec);
         const dim3 blk(A_WAVES * WAVE);
 #define RTT_ABS(Q_, NB_)                                                                      \
@@ -2730,7 +2765,10 @@ int launch_apply(const rtt_geometry* g, const Member& m, const float* x, float* 
         if (vec4) hipLaunchKernelGGL((k_apply_abs<Q_, NB_, true>), grid, blk, 0, s, la);      \
         else hipLaunchKernelGGL((k_apply_abs<Q_, NB_, false>), grid, blk, 0, s, la);          \
     } while (0)
-        if (m.Q == 1) {
+        if (variant == 14 && m.Q == 1) {
+            if (vec4) hipLaunchKernelGGL((k_apply_abs<1, 4, true, true>), grid, blk, 0, s, la);
+            else hipLaunchKernelGGL((k_apply_abs<1, 4, false, true>), grid, blk, 0, s, la);
+        } else if (m.Q == 1) {
             if (nb == 4) RTT_ABS(1, 4);
             else RTT_ABS(1, 8);
         } else {
