@@ -704,6 +704,38 @@ __device__ __forceinline__ void lean_emit(const float* zs0, const float* th0, co
     const int lane = threadIdx.x & (WAVE - 1);
     const float(*zs)[ZS] = (const float(*)[ZS])zs0;
     const int nf = fend - f0;   // frames of this chunk (at most lean_fcmax(Q))
+    if constexpr (VEC4 && Q == 1 && NB % 2 == 0) {
+        if ((F & 3) == 0 && (((uintptr_t)y) & 15) == 0) {
+            // rows of a multiple of 4 frames, 16-byte aligned (chunks start at multiples of 4): two
+            // rays per pass (lanes 0-31 ray j, lanes 32-63 ray j + 1), four frames per lane in one
+            // 16-byte store, the same values as the two-frame form below
+            const int lane2 = lane & 31;
+            const bool hi = lane >= 32;
+#pragma unroll
+            for (int j = 0; j < NB; j += 2) {
+                const int jj = hi ? j + 1 : j;
+                const bool o = hi ? on[j + 1] : on[j];
+                const float th = th0[jj];
+                float* yr = y + (int64_t)row[jj] * F;
+#pragma unroll
+                for (int p = 0; p < (lean_fcmax(1) + 127) / 128; ++p) {
+                    if (p * 128 >= nf) break;
+                    const int q = p * 128 + 4 * lane2;
+                    if (!o || q >= nf) continue;   // frames q .. q + 4 of the LDS row exist below nf
+                    const float* zr = &zs[0][0] + jj * ZS + q;
+                    const f4 za = *(const f4*)zr;
+                    const float z4 = zr[4];
+                    f4 v;
+                    v[0] = za[0] + th * (za[1] - za[0]);
+                    v[1] = za[1] + th * (za[2] - za[1]);
+                    v[2] = za[2] + th * (za[3] - za[2]);
+                    v[3] = za[3] + th * (z4 - za[3]);
+                    __builtin_nontemporal_store(v, (f4*)(yr + f0 + q));
+                }
+            }
+            return;
+        }
+    }
     if (VEC4 && Q == 1) {
         // one ray per pass of 128 frames, two frames per lane (8-byte stores): ray values stay uniform
         typedef float f2 __attribute__((ext_vector_type(2)));
@@ -1160,6 +1192,34 @@ __device__ __forceinline__ void abs_body(const LeanArgs& a, const float* __restr
                 }
             }
             range_store<NB>(ob, pad, NB * F, yb);
+            return;
+        }
+    }
+    if constexpr (VEC4 && Q == 1 && NB % 2 == 0) {
+        if ((F & 3) == 0 && (((uintptr_t)y) & 15) == 0) {
+            // rows of a multiple of 4 frames, 16-byte aligned: two rays per pass (lanes 0-31 ray j,
+            // lanes 32-63 ray j + 1), four frames per lane in one 16-byte store, the same values
+            // as the per-ray path below
+            const bool hi = lane >= 32;
+#pragma unroll
+            for (int j = 0; j < NB; j += 2) {
+                const float* zr = zs[hi ? j + 1 : j];
+                auto zat = [&](int k) { return (unsigned)k < (unsigned)K ? zr[k] : 0.f; };
+                const float th = hi ? rc[j + 1].th0 : rc[j].th0;
+                const int k0 = hi ? rc[j + 1].k0 : rc[j].k0;
+                const bool o = hi ? on[j + 1] : on[j];
+                float* yr = y + (int64_t)(hi ? rc[j + 1].row : rc[j].row) * F;
+                for (int f = 4 * (lane & 31); f < F; f += 128) {
+                    const float z0 = zat(k0 + f), z1 = zat(k0 + f + 1), z2 = zat(k0 + f + 2);
+                    const float z3 = zat(k0 + f + 3), z4 = zat(k0 + f + 4);
+                    f4 v;
+                    v[0] = z0 + th * (z1 - z0);
+                    v[1] = z1 + th * (z2 - z1);
+                    v[2] = z2 + th * (z3 - z2);
+                    v[3] = z3 + th * (z4 - z3);
+                    if (o) __builtin_nontemporal_store(v, (f4*)(yr + f));
+                }
+            }
             return;
         }
     }
