@@ -67,10 +67,36 @@ def sub_geometry(geo, keep):
     return synth.Geometry(grid=geo.grid, maps=maps)
 
 
-def tuned(rtt, G, nvec):
-    choice = G.tune(nvec=nvec, reps=3)
+def committed_tune_cache(tmp_dir):
+    """A copy of the package's tuner cache when it was made with the operator source under test
+    (its header names that source's digest), so these tests launch the kernel choices the
+    benchmark replays; None otherwise (the tuner then times the variants afresh)."""
+    import hashlib
+    import os
+    import shutil
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2609_05528_amd")
+    with open(os.path.join(pkg, "csrc", "operator.hip"), "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    src = os.path.join(pkg, "tune_cache.txt")
+    if not os.path.exists(src):
+        return None
+    with open(src) as f:
+        if f.readline().split()[:3] != ["#", "operator", digest]:
+            return None
+    dst = os.path.join(str(tmp_dir), "tune_cache.txt")
+    shutil.copyfile(src, dst)
+    return dst
+
+
+@pytest.fixture(scope="module")
+def tune_cache(tmp_path_factory):
+    return committed_tune_cache(tmp_path_factory.mktemp("tune"))
+
+
+def tuned(rtt, G, nvec, cache=None):
+    choice = G.tune(nvec=nvec, reps=3, cache_path=cache)
     names = [(rtt.variant_names(False)[a], rtt.variant_names(True)[b]) for a, b in choice]
-    say("tuned for", nvec, "vectors:", names, "launch modes", G.batch_mode)
+    say("tuned for", nvec, "vectors:", names, "launch modes", G.batch_mode, "cache", cache is not None)
     return names
 
 
@@ -80,7 +106,7 @@ def pin(rtt, G, fwd, adj):
 
 # ------------------------------------------------------------------------------ 128^2 block
 @pytest.mark.parametrize("pinned", [None, ("abs4", "visitp2v"), ("abs8", "visitp4v")])
-def test_block_of_264_on_the_128_geometry_matches_oracle(gpu_lib, pinned):
+def test_block_of_264_on_the_128_geometry_matches_oracle(gpu_lib, pinned, tune_cache):
     """The rSVD block of the 128^2 Kerr workload (l = 264 vectors): the tuned variants, and the
     absolute-hat forward with the row-pair adjoint pinned (two and four vectors per wave).  With
     K = 96 hats and 132 (or 66) vector groups the row-pair dispatch runs its two-slot form
@@ -90,7 +116,7 @@ def test_block_of_264_on_the_128_geometry_matches_oracle(gpu_lib, pinned):
     geo = synth.geometry_for("cfg2")
     G = rtt.Geometry(geo)
     nvec = 264
-    names = tuned(rtt, G, nvec)
+    names = tuned(rtt, G, nvec, tune_cache)
     if pinned is not None:
         pin(rtt, G, *pinned)
         names = [pinned]
@@ -151,7 +177,7 @@ def _cell_support(geo, c):
 
 @pytest.mark.parametrize("nvec,pinned", [(32, None), (32, ("strip8", "visitp2v")), (1, None),
                                          (1, ("lean4r", "visitb"))])
-def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, nvec, pinned):
+def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, nvec, pinned, tune_cache):
     """The block Lanczos block of the 512^2 x 512-frame workload (32 vectors), and one vector, on
     the variants tuned for them (K = 256: the row-pair or base-row adjoint with four hat slots per
     lane; the row-ordered forward).  The first and last vector, 48 rays per order and 6 cells each,
@@ -162,7 +188,7 @@ def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, nvec, pinned):
     g = geo.grid
     F = g.n_frames
     G = rtt.Geometry(geo)
-    names = tuned(rtt, G, nvec)
+    names = tuned(rtt, G, nvec, tune_cache)
     if pinned is not None:
         pin(rtt, G, *pinned)
         names = [pinned]
@@ -194,17 +220,18 @@ def test_block_of_32_on_the_512_geometry_matches_oracle(gpu_lib, nvec, pinned):
 
 
 # ------------------------------------------------------------------------------ 12 x 60 batch
-def test_full_batch_of_12_geometries_and_60_histories_matches_oracle(gpu_lib):
+def test_full_batch_of_12_geometries_and_60_histories_matches_oracle(gpu_lib, tune_cache):
     """The batched workload as the benchmark runs it: 12 geometries (96^2-256^2, 64-160 frames)
-    x 60 Gaussian-blob histories, after tuning for 60 vectors.  A and A^T of 4 (geometry,
-    history) pairs, including the smallest and the largest geometry, against the oracle; every
-    launch mode gives the same bits."""
+    x 60 Gaussian-blob histories, with the kernel choices the benchmark replays (the committed
+    tuner cache; tuned afresh for 60 vectors if it was made for another operator source).  A and
+    A^T of 4 (geometry, history) pairs, including the smallest and the largest geometry, against
+    the oracle; every launch mode gives the same bits."""
     import torch
     rtt = gpu_lib
     geos = synth.batch_geometries()
     ng, nh = len(geos), synth.BATCH_HISTORIES
     G = rtt.Geometry(geos)
-    tuned(rtt, G, nh)
+    tuned(rtt, G, nh, tune_cache)
     modes = G.batch_mode
     H = synth.blob_histories(geos[0].grid, nh, dtype=np.float32)
     X = to_dev(np.tile(H, (1, ng)))
