@@ -36,10 +36,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2609_05528_amd", "csrc", "operator.hip
 # the factor a 2 GiB plain copy reads; WRITE_SIZE by 1.0), valid only for the kernel source digest,
 # workload, variant and launch modes they were taken on (see profiles/).
 MEASURED_TRAFFIC = {
-    "op_apply_shared": [{"bytes": 10867860480, "digest": "e5d3714501f0d3e4", "workload": "batch",
-                         "variant": ["abs4", "abs4r", "lean4q", "lean4r", "reg1"], "modes": [2, 1]}],
-    "op_apply_adjoint": [{"bytes": 12559672320, "digest": "e5d3714501f0d3e4", "workload": "batch",
-                          "variant": ["visitp2v"], "modes": [2, 1]}],
+    "op_apply_shared": [{"bytes": 10856779776, "digest": "e5d3714501f0d3e4", "workload": "batch",
+                         "variant": ["abs4", "lean4", "lean4q", "lean4r", "reg1"], "modes": [1, 1]}],
+    "op_apply_adjoint": [{"bytes": 12564463616, "digest": "e5d3714501f0d3e4", "workload": "batch",
+                          "variant": ["visitp2v"], "modes": [1, 1]}],
     "op_apply": [],
 }
 

@@ -153,7 +153,10 @@ const char* variant_name(int32_t adjoint, int32_t v);
 /*
  * geometry_tune -- autotuner: times every applicable variant of both kernels
  * on nvec random vectors (HIP events on `stream`, median of `reps`) for each
- * member, keeps the fastest, then (G > 1) times the whole operator with those
+ * member at its place in the handle's [nvec][n_rows] data layout (the 128-byte
+ * phase of its rows, which row stores are sensitive to; member cache keys
+ * combine the member's content digest with that phase), keeps the fastest,
+ * then (G > 1) times the whole operator with those
  * choices launched per member against one variant shared by every member in
  * one launch (launch modes of geometry_set_batch_mode), keeps the fastest, and
  * records the choices in the text cache at cache_path (nullable; one "digest

@@ -4,9 +4,9 @@
 // persistent).
 //
 // Every applicable variant is timed with HIP events on the caller's stream
-// over `reps` launches on `nvec` random vectors (median).  Choices are cached
-// in a plain text file, one line "digest nvec apply adjoint" per entry, where
-// digest is the member's FNV-1a content hash.
+// over `reps` launches on `nvec` random vectors (median), each member at its place in the handle's
+// data layout.  Choices are cached in a plain text file, one line "digest nvec apply adjoint" per
+// entry, where digest is the member's FNV-1a content hash combined with that place.
 #include <algorithm>
 #include <cstdio>
 #include <fstream>
@@ -95,8 +95,31 @@ int time_mode(rtt_geometry* g, bool adjoint, int mode, const float* in, float* o
     return RTT_OK;
 }
 
-int time_variant(const rtt_geometry* g, const Member& m, bool adjoint, int variant, const float* in, float* out,
-                 int nvec, int reps, hipStream_t s, float* ms_out)
+// A member's place in the handle's data layout: in a handle with several members its rows start at
+// its row offset in every vector of [nvec][n_rows], so the 128-byte phase of its row block (which
+// decides how many partly written lines its row stores leave, up to twice the time of the same
+// kernel on line-aligned rows) is set by the row offset and the handle's row count.
+struct Place {
+    int64_t row_offset, y_stride;
+};
+Place member_place(const rtt_geometry* g, const Member& m)
+{
+    if (g->members.size() > 1) return {m.row_offset, g->n_rows};
+    return {0, m.n_rows};
+}
+
+// The cache key of a member: its content digest and the 128-byte phase of its place.
+uint64_t place_digest(const rtt_geometry* g, const Member& m)
+{
+    const Place p = member_place(g, m);
+    const int32_t ph[2] = {(int32_t)(p.row_offset % 32), (int32_t)(p.y_stride % 32)};
+    return fnv1a(ph, sizeof(ph), m.digest);
+}
+
+// Median time of one variant of member m: x holds [nvec][m.n_cols] (the columns a member reads in
+// the shared-grid call), y is the handle-layout buffer already offset to the member's rows.
+int time_variant(const rtt_geometry* g, const Member& m, bool adjoint, int variant, float* x, float* y,
+                 int64_t y_stride, int nvec, int reps, hipStream_t s, float* ms_out)
 {
     hipEvent_t e0, e1;
     RTT_HIP(hipEventCreate(&e0));
@@ -105,8 +128,8 @@ int time_variant(const rtt_geometry* g, const Member& m, bool adjoint, int varia
     const uint32_t mask = effective_mask(m, 0);
     for (int r = 0; r <= reps; ++r) {
         RTT_HIP(hipEventRecord(e0, s));
-        int rc = adjoint ? launch_adjoint(g, m, in, out, nvec, m.n_rows, m.n_cols, mask, s, variant)
-                         : launch_apply(g, m, in, out, nvec, m.n_cols, m.n_rows, mask, s, variant);
+        int rc = adjoint ? launch_adjoint(g, m, y, x, nvec, y_stride, m.n_cols, mask, s, variant)
+                         : launch_apply(g, m, x, y, nvec, m.n_cols, y_stride, mask, s, variant);
         if (rc) return rc;
         RTT_HIP(hipEventRecord(e1, s));
         RTT_HIP(hipEventSynchronize(e1));
@@ -130,19 +153,19 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
     hipStream_t s = (hipStream_t)stream;
     std::vector<CacheEntry> multi_cache;
     std::vector<CacheEntry> cache = read_cache(cache_path, &multi_cache);
-    int64_t max_rows = 0, max_cols = 0;
-    for (const Member& m : g->members) {
-        max_rows = std::max(max_rows, m.n_rows);
-        max_cols = std::max(max_cols, m.n_cols);
-    }
+    int64_t max_cols = 0;
+    for (const Member& m : g->members) max_cols = std::max(max_cols, m.n_cols);
+    // rows of the per-member timing buffer: the handle's layout (every member at its place)
+    const int64_t y_rows = g->members.size() > 1 ? g->n_rows : g->members[0].n_rows;
     Workspace ws;
     float* xb = nullptr;
     float* yb = nullptr;
     std::vector<CacheEntry> added;
     for (Member& m : g->members) {
         bool hit = false;
+        const uint64_t key = place_digest(g, m);
         for (const CacheEntry& e : cache)
-            if (e.digest == m.digest && e.nvec == nvec && apply_variant_ok(m, e.apply) &&
+            if (e.digest == key && e.nvec == nvec && apply_variant_ok(m, e.apply) &&
                 adjoint_variant_ok(m, e.adjoint)) {
                 m.apply_variant = e.apply;
                 m.adj_variant = e.adjoint;
@@ -151,18 +174,20 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         if (hit) continue;
         if (!xb) {
             xb = (float*)ws.get("tune_x", sizeof(float) * (size_t)nvec * max_cols);
-            yb = (float*)ws.get("tune_y", sizeof(float) * (size_t)nvec * max_rows);
+            yb = (float*)ws.get("tune_y", sizeof(float) * (size_t)nvec * y_rows);
             if (!xb || !yb) return fail(RTT_ENOMEM, "tune buffers");
             int rc = normal_fill(xb, (int64_t)nvec * max_cols, 12345, s);
-            if (!rc) rc = normal_fill(yb, (int64_t)nvec * max_rows, 54321, s);
+            if (!rc) rc = normal_fill(yb, (int64_t)nvec * y_rows, 54321, s);
             if (rc) return rc;
         }
+        const Place pl = member_place(g, m);
+        float* ym = yb + pl.row_offset;
         float best = 1e30f;
         int best_v = m.apply_variant;
         for (int v = 0; v < n_apply_variants(); ++v) {
             if (!apply_variant_ok(m, v)) continue;
             float ms;
-            int rc = time_variant(g, m, false, v, xb, yb, nvec, reps, s, &ms);
+            int rc = time_variant(g, m, false, v, xb, ym, pl.y_stride, nvec, reps, s, &ms);
             if (rc) return rc;
             if (std::getenv("RTT_LOG")) std::fprintf(stderr, "[rtt] tune apply %s: %.4f ms\n", apply_variant_name(v), ms);
             if (ms < best) { best = ms; best_v = v; }
@@ -173,13 +198,13 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         for (int v = 0; v < n_adjoint_variants(); ++v) {
             if (!adjoint_variant_ok(m, v)) continue;
             float ms;
-            int rc = time_variant(g, m, true, v, yb, xb, nvec, reps, s, &ms);
+            int rc = time_variant(g, m, true, v, xb, ym, pl.y_stride, nvec, reps, s, &ms);
             if (rc) return rc;
             if (std::getenv("RTT_LOG")) std::fprintf(stderr, "[rtt] tune adjoint %s: %.4f ms\n", adjoint_variant_name(v), ms);
             if (ms < best) { best = ms; best_v = v; }
         }
         m.adj_variant = best_v;
-        added.push_back({m.digest, nvec, m.apply_variant, m.adj_variant});
+        added.push_back({key, nvec, m.apply_variant, m.adj_variant});
     }
     // several members: the per-member choices launched one by one, or one variant shared by every
     // member (the ones with a single-launch form) launched as one launch or one persistent launch
