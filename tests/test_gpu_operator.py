@@ -457,6 +457,30 @@ def test_autotuner_on_several_geometries_caches_the_launch_choice(gpu_lib, tmp_p
         assert rel(xa[:, cs], oracle.adjoint(geo, Y[:, rs].astype(np.float64))) <= TOL
 
 
+def test_autotuner_keys_a_member_by_its_place_in_the_row_layout(gpu_lib, tmp_path):
+    """A member is timed at its place in the handle's [nvec][n_rows] layout, and its cache line
+    carries the 128-byte phase of that place: the same geometry alone (phase 0) and behind
+    another member at a row offset that is not a multiple of 32 get different member keys, and a
+    repeated tune of either handle hits its own lines."""
+    rtt = gpu_lib
+    a = tiny_geometry(seed=141, rays=(37, 5, 3), n_frames=13, n_r=4, n_phi=6)
+    b = tiny_geometry(seed=142, rays=(44, 6, 2), n_frames=16, n_r=4, n_phi=6)
+    Gab = rtt.Geometry([a, b])
+    off = Gab.members[1]["row_offset"]
+    assert off % 32 != 0, off
+    c_ab, c_b = tmp_path / "ab.txt", tmp_path / "b.txt"
+    Gab.tune(nvec=2, reps=2, cache_path=c_ab)
+    rtt.Geometry(b).tune(nvec=2, reps=2, cache_path=c_b)
+    member_keys = lambda path: [ln.split()[0] for ln in path.read_text().splitlines() if not ln.startswith("multi ")]
+    keys_ab, keys_b = member_keys(c_ab), member_keys(c_b)
+    assert len(keys_ab) == 2 and len(keys_b) == 1
+    assert keys_b[0] not in keys_ab
+    before = (c_ab.read_text(), c_b.read_text())
+    rtt.Geometry([a, b]).tune(nvec=2, reps=2, cache_path=c_ab)    # cache hits: nothing appended
+    rtt.Geometry(b).tune(nvec=2, reps=2, cache_path=c_b)
+    assert (c_ab.read_text(), c_b.read_text()) == before
+
+
 @pytest.mark.parametrize("dt_obs,n_frames", [(4.0, 110), (2.0, 132), (4.0, 45)])
 def test_absolute_hat_forward_equals_the_lean_form(gpu_lib, dt_obs, n_frames):
     """The absolute-hat forward shares one set of gathers among the rays of a base cell; on a grid
