@@ -174,7 +174,9 @@ extern "C" int geometry_tune(rtt_geometry* g, int32_t nvec, int32_t reps, const 
         if (hit) continue;
         if (!xb) {
             xb = (float*)ws.get("tune_x", sizeof(float) * (size_t)nvec * max_cols);
-            yb = (float*)ws.get("tune_y", sizeof(float) * (size_t)nvec * y_rows);
+            // a handle with several members times its whole-operator launch modes on a buffer of the
+            // same shape below: both use one allocation
+            yb = (float*)ws.get(g->members.size() > 1 ? "tune_ya" : "tune_y", sizeof(float) * (size_t)nvec * y_rows);
             if (!xb || !yb) return fail(RTT_ENOMEM, "tune buffers");
             int rc = normal_fill(xb, (int64_t)nvec * max_cols, 12345, s);
             if (!rc) rc = normal_fill(yb, (int64_t)nvec * y_rows, 54321, s);
